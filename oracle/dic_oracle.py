@@ -1,0 +1,504 @@
+"""FP64 CPU oracle for subset DIC: ZNCC brute-force integer search, IC-GN
+sub-pixel refinement (first-order shape function, bicubic interpolation) and
+the ZNSSD adjoint.
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, obviously correct
+reference that the HIP library is checked against.  Only the test-suite, the
+smoke check and the CPU-baseline leg of the benchmark may import it; the
+library itself never calls it and shares no code with it.
+
+Everything is plain NumPy in float64.  Images arrive as float32 arrays and are
+promoted.  Functions follow the paper (Thoma & Ravi, "Significance of parallel
+computing on the performance of Digital Image Correlation algorithms in
+MATLAB"):
+
+* Sec. 2, Eq. (1): the zero-normalised cross-correlation of two subsets of
+  (2M+1)x(2M+1) pixels, each centred on its mean.
+* Sec. 2.1: brute-force search evaluates every admissible integer position and
+  keeps the one with the largest coefficient.
+* Sec. 2.2: a pixel's grey level is the value at its centre; bicubic
+  interpolation; IC-GN with an affine (first-order) warp whose reference-side
+  quantities (gradients, steepest-descent images, Hessian) are precomputed.
+
+Where the paper is silent the readings listed at each function are used (the
+paper defers IC-GN details to Pan et al. and Baker & Matthews).
+
+Parity status: every function here is pinned by the CPU test-suite against
+closed forms, invariants, brute force or independent library routines, except
+the conventions that have no external value (POI grid margin, tie-break rule,
+convergence norm, seed policy of the sequence), which are "parity unpinned"
+beyond both sides implementing the same stated rule.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+
+# Per-POI status codes (shared numbering with the library's public header).
+OK = 0
+NOT_CONVERGED = 1
+OUT_OF_BOUNDS = 2
+ZERO_VARIANCE = 3
+SINGULAR_HESSIAN = 4
+NO_VALID_CANDIDATE = 5
+NAN_INPUT = 6
+
+FLAT_REL = 1e-6        # a subset is flat when sum (s - mean)^2 <= FLAT_REL * sum s^2
+TIE_EPS = 1e-12        # integer-search tie window in ZNCC units
+PIVOT_REL = 1e-10      # Cholesky pivot d_k <= PIVOT_REL * H_kk  ->  singular Hessian
+
+
+# ---------------------------------------------------------------------------
+# subset geometry (Sec. 2.1: sub-image of (2M+1)x(2M+1) pixels around a point)
+# ---------------------------------------------------------------------------
+
+def subset_offsets(M: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Offsets (dx, dy) of the (2M+1)^2 subset pixels, row-major (dy outer)."""
+    dy, dx = np.mgrid[-M:M + 1, -M:M + 1]
+    return dx.ravel().astype(np.float64), dy.ravel().astype(np.float64)
+
+
+def subset(img: np.ndarray, x0: int, y0: int, M: int) -> np.ndarray:
+    """Pixels of the square subset centred on integer (x0, y0), row-major, FP64."""
+    return img[y0 - M:y0 + M + 1, x0 - M:x0 + M + 1].astype(np.float64).ravel()
+
+
+def is_flat(s: np.ndarray) -> bool:
+    """Reading: a subset with (numerically) no grey-level variation has no
+    defined ZNCC; flat means sum (s-mean)^2 <= 1e-6 * sum s^2."""
+    d = s - s.mean()
+    return not (np.sum(d * d) > FLAT_REL * np.sum(s * s))
+
+
+# ---------------------------------------------------------------------------
+# Eq. (1): zero-normalised cross-correlation, two-pass
+# ---------------------------------------------------------------------------
+
+def zncc(fs: np.ndarray, gs: np.ndarray) -> float:
+    """C = sum (f - fbar)(g - gbar) / sqrt(sum (f - fbar)^2 * sum (g - gbar)^2)."""
+    fz = fs - fs.mean()
+    gz = gs - gs.mean()
+    return float(np.sum(fz * gz) / (np.sqrt(np.sum(fz * fz)) * np.sqrt(np.sum(gz * gz))))
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.1: brute-force integer search
+# ---------------------------------------------------------------------------
+
+def candidate_mask(width: int, height: int, x0: int, y0: int, M: int, S: int,
+                   cu: int = 0, cv: int = 0) -> np.ndarray:
+    """Admissible candidates of the (2S+1)^2 window centred on (cu, cv).
+
+    Reading: a candidate (du, dv) is admissible when its whole subset lies in
+    the deformed image.  Indexed ``[dv + S - cv, du + S - cu]``.
+    """
+    dv = np.arange(cv - S, cv + S + 1)[:, None]
+    du = np.arange(cu - S, cu + S + 1)[None, :]
+    return ((x0 + du - M >= 0) & (x0 + du + M <= width - 1)
+            & (y0 + dv - M >= 0) & (y0 + dv + M <= height - 1))
+
+
+@dataclass
+class SearchResult:
+    du: int
+    dv: int
+    zncc: float
+    status: int
+    scores: Optional[np.ndarray] = None   # [2S+1, 2S+1], -inf for inadmissible
+
+
+def integer_search(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, S: int,
+                   cu: int = 0, cv: int = 0, keep_scores: bool = False) -> SearchResult:
+    """Brute-force search (Sec. 2.1) of Eq. (1) over every admissible integer
+    displacement (du, dv) with |du - cu| <= S and |dv - cv| <= S.
+
+    Readings: inadmissible (subset leaves the image) and flat deformed subsets
+    are skipped; the winner is the lexicographically smallest (dv, du) among
+    candidates whose coefficient is within 1e-12 of the maximum.
+    """
+    fs = subset(f, x0, y0, M)
+    if not np.all(np.isfinite(fs)):
+        return SearchResult(0, 0, float("nan"), NAN_INPUT)
+    if is_flat(fs):
+        return SearchResult(0, 0, float("nan"), ZERO_VARIANCE)
+    H, W = g.shape
+    mask = candidate_mask(W, H, x0, y0, M, S, cu, cv)
+    side = 2 * S + 1
+    scores = np.full((side, side), -np.inf)
+    fz = fs - fs.mean()
+    nf = np.sqrt(np.sum(fz * fz))
+    rows = np.nonzero(mask.any(axis=1))[0]
+    for r in rows:
+        dv = cv - S + int(r)
+        cols = np.nonzero(mask[r])[0]
+        ylo = y0 + dv - M
+        band = g[ylo:ylo + 2 * M + 1].astype(np.float64)
+        for c in cols:
+            du = cu - S + int(c)
+            xlo = x0 + du - M
+            gs = band[:, xlo:xlo + 2 * M + 1].ravel()
+            if not np.all(np.isfinite(gs)) or is_flat(gs):
+                continue
+            gz = gs - gs.mean()
+            scores[r, c] = np.sum(fz * gz) / (nf * np.sqrt(np.sum(gz * gz)))
+    best = scores.max()
+    if not np.isfinite(best):
+        return SearchResult(0, 0, float("nan"), NO_VALID_CANDIDATE,
+                            scores if keep_scores else None)
+    r, c = [int(a[0]) for a in np.nonzero(scores >= best - TIE_EPS)]  # row-major first
+    return SearchResult(cu - S + c, cv - S + r, float(scores[r, c]), OK,
+                        scores if keep_scores else None)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.2: bicubic interpolation (Keys cubic convolution, a = -1/2)
+# ---------------------------------------------------------------------------
+
+def cubic_weights(t: np.ndarray) -> np.ndarray:
+    """Keys' cubic-convolution weights (a = -1/2) for taps at -1, 0, 1, 2
+    relative to floor(x), given t = x - floor(x).  Shape [..., 4]."""
+    t = np.asarray(t, dtype=np.float64)
+    t2 = t * t
+    t3 = t2 * t
+    return np.stack([(-t3 + 2 * t2 - t) / 2,
+                     (3 * t3 - 5 * t2 + 2) / 2,
+                     (-3 * t3 + 4 * t2 + t) / 2,
+                     (t3 - t2) / 2], axis=-1)
+
+
+def cubic_dweights(t: np.ndarray) -> np.ndarray:
+    """d/dt of ``cubic_weights``."""
+    t = np.asarray(t, dtype=np.float64)
+    t2 = t * t
+    return np.stack([(-3 * t2 + 4 * t - 1) / 2,
+                     (9 * t2 - 10 * t) / 2,
+                     (-9 * t2 + 8 * t + 1) / 2,
+                     (3 * t2 - 2 * t) / 2], axis=-1)
+
+
+def in_interp_bounds(xs: np.ndarray, ys: np.ndarray, width: int, height: int) -> bool:
+    """All 4x4 neighbourhoods inside the image: 1 <= floor <= size - 3."""
+    ix = np.floor(xs)
+    iy = np.floor(ys)
+    return bool(np.all(ix >= 1) and np.all(ix + 2 <= width - 1)
+                and np.all(iy >= 1) and np.all(iy + 2 <= height - 1))
+
+
+def interpolate(g: np.ndarray, xs: np.ndarray, ys: np.ndarray,
+                with_grad: bool = False):
+    """g at sub-pixel points: sum_{l,k} w_l(ty) w_k(tx) g[floor(y)+l, floor(x)+k],
+    k, l in {-1, 0, 1, 2}.  Optionally the analytic gradient of the interpolant."""
+    ix = np.floor(xs).astype(np.int64)
+    iy = np.floor(ys).astype(np.int64)
+    wx = cubic_weights(xs - ix)
+    wy = cubic_weights(ys - iy)
+    taps = np.empty(xs.shape + (4, 4))
+    for l in range(4):
+        for k in range(4):
+            taps[..., l, k] = g[iy + l - 1, ix + k - 1]
+    val = np.einsum("...l,...lk,...k->...", wy, taps, wx)
+    if not with_grad:
+        return val
+    dwx = cubic_dweights(xs - ix)
+    dwy = cubic_dweights(ys - iy)
+    gx = np.einsum("...l,...lk,...k->...", wy, taps, dwx)
+    gy = np.einsum("...l,...lk,...k->...", dwy, taps, wx)
+    return val, gx, gy
+
+
+# ---------------------------------------------------------------------------
+# first-order (affine) warp, p = (u, ux, uy, v, vx, vy)
+# ---------------------------------------------------------------------------
+
+def warp_matrix(p: Sequence[float]) -> np.ndarray:
+    u, ux, uy, v, vx, vy = [float(a) for a in p]
+    return np.array([[1.0 + ux, uy, u], [vx, 1.0 + vy, v], [0.0, 0.0, 1.0]])
+
+
+def warp_params(Wm: np.ndarray) -> np.ndarray:
+    return np.array([Wm[0, 2], Wm[0, 0] - 1.0, Wm[0, 1],
+                     Wm[1, 2], Wm[1, 0], Wm[1, 1] - 1.0])
+
+
+def warp_points(p: Sequence[float], x0: int, y0: int, dx: np.ndarray, dy: np.ndarray):
+    """Sample positions x0 + W(p) (dx, dy, 1)."""
+    u, ux, uy, v, vx, vy = [float(a) for a in p]
+    return (x0 + (1.0 + ux) * dx + uy * dy + u,
+            y0 + vx * dx + (1.0 + vy) * dy + v)
+
+
+def update_norm(dp: np.ndarray, M: int) -> float:
+    """Reading of the stop rule |dp| < tol: the change of a subset-edge point,
+    sqrt(du^2 + dv^2 + M^2 (dux^2 + duy^2 + dvx^2 + dvy^2))."""
+    return float(np.sqrt(dp[0] ** 2 + dp[3] ** 2
+                         + M * M * (dp[1] ** 2 + dp[2] ** 2 + dp[4] ** 2 + dp[5] ** 2)))
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.2: IC-GN reference-side precomputation
+# ---------------------------------------------------------------------------
+
+def central_gradients(f: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Reading: reference gradients by central difference,
+    fx = (f[y, x+1] - f[y, x-1]) / 2, fy = (f[y+1, x] - f[y-1, x]) / 2;
+    zero on the one-pixel border (never inside a subset)."""
+    f = f.astype(np.float64)
+    fx = np.zeros_like(f)
+    fy = np.zeros_like(f)
+    fx[:, 1:-1] = (f[:, 2:] - f[:, :-2]) / 2.0
+    fy[1:-1, :] = (f[2:, :] - f[:-2, :]) / 2.0
+    return fx, fy
+
+
+def cholesky6(Hm: np.ndarray) -> Optional[np.ndarray]:
+    """Plain Cholesky H = L L^T.  Returns None when a pivot fails the
+    singularity rule d_k > 1e-10 * H_kk (reading of 'singular Hessian')."""
+    n = Hm.shape[0]
+    L = np.zeros_like(Hm)
+    for k in range(n):
+        d = Hm[k, k] - np.dot(L[k, :k], L[k, :k])
+        if not (d > PIVOT_REL * Hm[k, k]):
+            return None
+        L[k, k] = np.sqrt(d)
+        for i in range(k + 1, n):
+            L[i, k] = (Hm[i, k] - np.dot(L[i, :k], L[k, :k])) / L[k, k]
+    return L
+
+
+def cholesky_solve(L: np.ndarray, b: np.ndarray) -> np.ndarray:
+    n = L.shape[0]
+    z = np.zeros(n)
+    for i in range(n):
+        z[i] = (b[i] - np.dot(L[i, :i], z[:i])) / L[i, i]
+    x = np.zeros(n)
+    for i in reversed(range(n)):
+        x[i] = (z[i] - np.dot(L[i + 1:, i], x[i + 1:])) / L[i, i]
+    return x
+
+
+@dataclass
+class RefPrep:
+    fs: np.ndarray     # subset grey levels
+    fbar: float
+    df: float          # sqrt(sum (f - fbar)^2)
+    sd: np.ndarray     # steepest-descent images [n, 6]
+    hess: np.ndarray   # [6, 6]
+    chol: Optional[np.ndarray]
+    status: int
+
+
+def reference_prep(f: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, y0: int,
+                   M: int) -> RefPrep:
+    """Quantities IC-GN precomputes once per POI (Sec. 2.2): f subset, its mean
+    and norm, steepest-descent images SD_i = grad f_i . dW/dp and the
+    Gauss-Newton Hessian H = sum (SD_i - SDbar)^T (SD_i - SDbar) with its
+    Cholesky factor."""
+    dx, dy = subset_offsets(M)
+    fs = subset(f, x0, y0, M)
+    gx = subset(fx, x0, y0, M)
+    gy = subset(fy, x0, y0, M)
+    sd = np.stack([gx, gx * dx, gx * dy, gy, gy * dx, gy * dy], axis=1)
+    if not np.all(np.isfinite(fs)):
+        return RefPrep(fs, np.nan, np.nan, sd, np.full((6, 6), np.nan), None, NAN_INPUT)
+    fbar = float(fs.mean())
+    df = float(np.sqrt(np.sum((fs - fbar) ** 2)))
+    if is_flat(fs):
+        return RefPrep(fs, fbar, df, sd, np.full((6, 6), np.nan), None, ZERO_VARIANCE)
+    # Reading: the ZNSSD criterion re-centres the warped reference subset on its
+    # own mean, so the Gauss-Newton Jacobian of (f(W(dp)) - mean) is
+    # SD_i - mean(SD).  Its normal matrix is the Hessian.  The right-hand side
+    # sum SD_i^T e_i is the same with or without centring because sum e_i = 0,
+    # so the fixed point does not depend on this choice; the convergence rate
+    # does.
+    sdc = sd - sd.mean(axis=0)
+    hess = sdc.T @ sdc
+    chol = cholesky6(hess)
+    return RefPrep(fs, fbar, df, sd, hess, chol,
+                   OK if chol is not None else SINGULAR_HESSIAN)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.2: inverse-compositional Gauss-Newton
+# ---------------------------------------------------------------------------
+
+@dataclass
+class IcgnResult:
+    p: np.ndarray
+    zncc: float
+    iters: int
+    status: int
+
+
+def icgn(f: np.ndarray, g: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, y0: int,
+         M: int, p0: Sequence[float], max_iters: int = 20, tol: float = 1e-3,
+         prep: Optional[RefPrep] = None) -> IcgnResult:
+    """IC-GN on the ZNSSD criterion with a first-order warp.
+
+    Per iteration: warp the subset with W(p), interpolate g, form
+    e_i = (f_i - fbar) - (df/dg) (g_i - gbar), solve H dp = -sum SD_i^T e_i,
+    compose W(p) <- W(p) W(dp)^-1, stop when |dp| < tol (``update_norm``).
+    Readings: fbar and df stay those of the undeformed reference subset; a
+    warp whose 4x4 neighbourhoods leave the image stops with OUT_OF_BOUNDS and
+    keeps the last p; the reported coefficient is Eq. (1) re-evaluated at the
+    final p.
+    """
+    H, W = g.shape
+    p = np.asarray(p0, dtype=np.float64).copy()
+    if prep is None:
+        prep = reference_prep(f, fx, fy, x0, y0, M)
+    if prep.status != OK:
+        return IcgnResult(p, float("nan"), 0, prep.status)
+    dx, dy = subset_offsets(M)
+    fz = prep.fs - prep.fbar
+    it = 0
+    status = NOT_CONVERGED
+    while it < max_iters:
+        it += 1
+        xs, ys = warp_points(p, x0, y0, dx, dy)
+        if not in_interp_bounds(xs, ys, W, H):
+            return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
+        gs = interpolate(g, xs, ys)
+        if not np.all(np.isfinite(gs)):
+            return IcgnResult(p, float("nan"), it, NAN_INPUT)
+        if is_flat(gs):
+            return IcgnResult(p, float("nan"), it, ZERO_VARIANCE)
+        gbar = gs.mean()
+        dg = np.sqrt(np.sum((gs - gbar) ** 2))
+        e = fz - (prep.df / dg) * (gs - gbar)
+        b = prep.sd.T @ e
+        dp = -cholesky_solve(prep.chol, b)
+        p = warp_params(warp_matrix(p) @ np.linalg.inv(warp_matrix(dp)))
+        if update_norm(dp, M) < tol:
+            status = OK
+            break
+    xs, ys = warp_points(p, x0, y0, dx, dy)
+    if not in_interp_bounds(xs, ys, W, H):
+        return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
+    gs = interpolate(g, xs, ys)
+    if not np.all(np.isfinite(gs)):
+        return IcgnResult(p, float("nan"), it, NAN_INPUT)
+    if is_flat(gs):
+        return IcgnResult(p, float("nan"), it, ZERO_VARIANCE)
+    return IcgnResult(p, zncc(prep.fs, gs), it, status)
+
+
+# ---------------------------------------------------------------------------
+# ZNSSD criterion and its adjoint (forward-additive parameters)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class ZnssdResult:
+    c: float
+    grad_p: np.ndarray          # [6]
+    rows: np.ndarray            # pixel rows touched [n, 16]
+    cols: np.ndarray            # pixel cols touched [n, 16]
+    grad_taps: np.ndarray       # dC/dG at those pixels [n, 16] (before summing)
+
+
+def znssd(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, p: Sequence[float],
+          upstream: float = 1.0) -> ZnssdResult:
+    """C = sum_i (fhat_i - ghat_i)^2 with fhat = (f - fbar)/df, ghat = (g - gbar)/dg,
+    g interpolated at x0 + W(p) xi_i.  Returns C and, scaled by ``upstream``,
+    dC/dp (through the analytic gradient of the interpolant) and the per-tap
+    contributions dC/dG[r, c] = sum_i dC/dg_i w(tx) w(ty)."""
+    dx, dy = subset_offsets(M)
+    fs = subset(f, x0, y0, M)
+    fhat = (fs - fs.mean()) / np.sqrt(np.sum((fs - fs.mean()) ** 2))
+    xs, ys = warp_points(p, x0, y0, dx, dy)
+    gs, gx, gy = interpolate(g, xs, ys, with_grad=True)
+    gbar = gs.mean()
+    dg = np.sqrt(np.sum((gs - gbar) ** 2))
+    ghat = (gs - gbar) / dg
+    r = fhat - ghat
+    c = float(np.sum(r * r))
+    zn = float(np.sum(fhat * ghat))
+    dc_dg = upstream * (2.0 / dg) * (zn * ghat - fhat)
+    jac = np.stack([gx, gx * dx, gx * dy, gy, gy * dx, gy * dy], axis=1)
+    grad_p = jac.T @ dc_dg
+    ix = np.floor(xs).astype(np.int64)
+    iy = np.floor(ys).astype(np.int64)
+    wx = cubic_weights(xs - ix)
+    wy = cubic_weights(ys - iy)
+    rows = np.empty((xs.size, 16), dtype=np.int64)
+    cols = np.empty((xs.size, 16), dtype=np.int64)
+    taps = np.empty((xs.size, 16))
+    for l in range(4):
+        for k in range(4):
+            rows[:, 4 * l + k] = iy + l - 1
+            cols[:, 4 * l + k] = ix + k - 1
+            taps[:, 4 * l + k] = dc_dg * wy[:, l] * wx[:, k]
+    return ZnssdResult(c, grad_p, rows, cols, taps)
+
+
+def znssd_batch(f: np.ndarray, g: np.ndarray, pois: np.ndarray, M: int, P: np.ndarray,
+                upstream: Optional[np.ndarray] = None):
+    """Sum over POIs: per-POI C [N], dC/dp [N, 6] and the accumulated dC/dG [H, W]."""
+    N = pois.shape[0]
+    C = np.zeros(N)
+    gp = np.zeros((N, 6))
+    gg = np.zeros(g.shape, dtype=np.float64)
+    for i in range(N):
+        up = 1.0 if upstream is None else float(upstream[i])
+        r = znssd(f, g, int(pois[i, 0]), int(pois[i, 1]), M, P[i], up)
+        C[i] = r.c
+        gp[i] = r.grad_p
+        np.add.at(gg, (r.rows.ravel(), r.cols.ravel()), r.grad_taps.ravel())
+    return C, gp, gg
+
+
+# ---------------------------------------------------------------------------
+# whole-pair drivers
+# ---------------------------------------------------------------------------
+
+def correlate(f: np.ndarray, g: np.ndarray, pois: np.ndarray, M: int, S: int,
+              centers: Optional[np.ndarray] = None, p_init: Optional[np.ndarray] = None,
+              max_iters: int = 20, tol: float = 1e-3) -> Dict[str, np.ndarray]:
+    """Integer search then IC-GN for every POI (Sec. 2: the integer result
+    seeds the sub-pixel search; initial p = (du, 0, 0, dv, 0, 0), or the
+    gradient terms of ``p_init`` when given)."""
+    N = pois.shape[0]
+    fx, fy = central_gradients(f)
+    out = dict(uv=np.zeros((N, 2), np.int32), zncc_int=np.full(N, np.nan),
+               status_int=np.zeros(N, np.int32), p=np.zeros((N, 6)),
+               zncc=np.full(N, np.nan), iters=np.zeros(N, np.int32),
+               status=np.zeros(N, np.int32))
+    for i in range(N):
+        x0, y0 = int(pois[i, 0]), int(pois[i, 1])
+        cu, cv = (0, 0) if centers is None else (int(centers[i, 0]), int(centers[i, 1]))
+        s = integer_search(f, g, x0, y0, M, S, cu, cv)
+        out["uv"][i] = (s.du, s.dv)
+        out["zncc_int"][i] = s.zncc
+        out["status_int"][i] = s.status
+        if s.status != OK:
+            out["status"][i] = s.status
+            out["p"][i] = (s.du, 0, 0, s.dv, 0, 0)
+            continue
+        p0 = np.array([s.du, 0, 0, s.dv, 0, 0], dtype=np.float64)
+        if p_init is not None:
+            p0[[1, 2, 4, 5]] = p_init[i, [1, 2, 4, 5]]
+        r = icgn(f, g, fx, fy, x0, y0, M, p0, max_iters, tol)
+        out["p"][i] = r.p
+        out["zncc"][i] = r.zncc
+        out["iters"][i] = r.iters
+        out["status"][i] = r.status
+    return out
+
+
+def correlate_sequence(frames: Sequence[np.ndarray], pois: np.ndarray, M: int, S: int,
+                       max_iters: int = 20, tol: float = 1e-3):
+    """Every frame k >= 1 against frame 0.  Reading of 'seeded by the previous
+    frame's result': the search window is centred on round(u, v) of the last
+    frame whose status was OK (frame 1: (0, 0)), and IC-GN starts from that
+    frame's gradient terms."""
+    N = pois.shape[0]
+    last_p = np.zeros((N, 6))
+    results = []
+    for k in range(1, len(frames)):
+        centers = np.stack([np.rint(last_p[:, 0]), np.rint(last_p[:, 3])], axis=1).astype(np.int64)
+        r = correlate(frames[0], frames[k], pois, M, S, centers, last_p, max_iters, tol)
+        ok = r["status"] == OK
+        last_p[ok] = r["p"][ok]
+        results.append(r)
+    return results
