@@ -65,6 +65,12 @@ def subset(img: np.ndarray, x0: int, y0: int, M: int) -> np.ndarray:
     return img[y0 - M:y0 + M + 1, x0 - M:x0 + M + 1].astype(np.float64).ravel()
 
 
+def poi_inside(x0: int, y0: int, M: int, width: int, height: int) -> bool:
+    """Reading: a POI is usable when its subset and the one-pixel border the
+    central-difference gradients need lie inside the reference image."""
+    return x0 - M >= 1 and x0 + M <= width - 2 and y0 - M >= 1 and y0 + M <= height - 2
+
+
 def is_flat(s: np.ndarray) -> bool:
     """Reading: a subset with (numerically) no grey-level variation has no
     defined ZNCC; flat means sum (s-mean)^2 <= 1e-6 * sum s^2."""
@@ -118,6 +124,8 @@ def integer_search(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, S: in
     are skipped; the winner is the lexicographically smallest (dv, du) among
     candidates whose coefficient is within 1e-12 of the maximum.
     """
+    if not poi_inside(x0, y0, M, f.shape[1], f.shape[0]):
+        return SearchResult(0, 0, float("nan"), OUT_OF_BOUNDS)
     fs = subset(f, x0, y0, M)
     if not np.all(np.isfinite(fs)):
         return SearchResult(0, 0, float("nan"), NAN_INPUT)
@@ -296,6 +304,10 @@ def reference_prep(f: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, y0: i
     Gauss-Newton Hessian H = sum (SD_i - SDbar)^T (SD_i - SDbar) with its
     Cholesky factor."""
     dx, dy = subset_offsets(M)
+    if not poi_inside(x0, y0, M, f.shape[1], f.shape[0]):
+        nan6 = np.full((6, 6), np.nan)
+        return RefPrep(np.zeros(dx.size), np.nan, np.nan, np.zeros((dx.size, 6)), nan6, None,
+                       OUT_OF_BOUNDS)
     fs = subset(f, x0, y0, M)
     gx = subset(fx, x0, y0, M)
     gy = subset(fy, x0, y0, M)
@@ -402,14 +414,29 @@ def znssd(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, p: Sequence[fl
     """C = sum_i (fhat_i - ghat_i)^2 with fhat = (f - fbar)/df, ghat = (g - gbar)/dg,
     g interpolated at x0 + W(p) xi_i.  Returns C and, scaled by ``upstream``,
     dC/dp (through the analytic gradient of the interpolant) and the per-tap
-    contributions dC/dG[r, c] = sum_i dC/dg_i w(tx) w(ty)."""
+    contributions dC/dG[r, c] = sum_i dC/dg_i w(tx) w(ty).
+
+    Reading: when the reference subset is unusable (outside the image, NaN or
+    flat) or a 4x4 neighbourhood leaves the deformed image, C is NaN and the
+    gradients are zero."""
     dx, dy = subset_offsets(M)
+    empty = ZnssdResult(float("nan"), np.zeros(6), np.zeros((0, 16), np.int64),
+                        np.zeros((0, 16), np.int64), np.zeros((0, 16)))
+    H, W = g.shape
+    if not poi_inside(x0, y0, M, f.shape[1], f.shape[0]):
+        return empty
     fs = subset(f, x0, y0, M)
-    fhat = (fs - fs.mean()) / np.sqrt(np.sum((fs - fs.mean()) ** 2))
+    if not np.all(np.isfinite(fs)) or is_flat(fs):
+        return empty
     xs, ys = warp_points(p, x0, y0, dx, dy)
+    if not in_interp_bounds(xs, ys, W, H):
+        return empty
+    fhat = (fs - fs.mean()) / np.sqrt(np.sum((fs - fs.mean()) ** 2))
     gs, gx, gy = interpolate(g, xs, ys, with_grad=True)
     gbar = gs.mean()
     dg = np.sqrt(np.sum((gs - gbar) ** 2))
+    if not (np.isfinite(dg) and dg > 0):
+        return empty
     ghat = (gs - gbar) / dg
     r = fhat - ghat
     c = float(np.sum(r * r))

@@ -1,0 +1,656 @@
+// Host implementation of the C ABI declared in include/dic.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "dic.h"
+#include "dic_internal.h"
+
+using namespace dic;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dic_status_t fail(dic_status_t code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define DIC_HIP(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(DIC_ERR_HIP, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t pairs = 0, poi_pair = 0, work = 0, counters = 0, grads = 0, recs = 0, tmpl = 0,
+         fix_off = 0, fix = 0, s_status = 0, s_zncc = 0, total = 0;
+  int64_t fix_count = 0;
+};
+
+const dic_tuning_t kDefaultTuning = {8, 256, 4, 4};
+
+bool tuning_valid(const dic_tuning_t& t) {
+  const bool blk = t.search_block == 4 || t.search_block == 6 || t.search_block == 8 ||
+                   t.search_block == 11;
+  return blk && t.search_threads >= 64 && t.search_threads <= 1024 && t.search_threads % 64 == 0 &&
+         t.icgn_waves >= 1 && t.icgn_waves <= 8 && t.icgn_slack >= 0 && t.icgn_slack <= 16;
+}
+
+}  // namespace
+
+struct dic_plan_s {
+  dic_plan_desc_t desc{};
+  std::vector<dic_pair_desc_t> pairs;
+  std::vector<DevPair> dpairs;
+  std::vector<int32_t> poi_pair, work;
+  std::vector<int64_t> fix_off;
+  int64_t N = 0;
+  int maxM = 0, maxS = 0, maxW = 0, maxH = 0;
+  Layout lay;
+  dic_tuning_t tuning = kDefaultTuning;
+  void* ws = nullptr;
+  bool bound = false;
+  int num_cu = 0;
+  DevState st{};
+  bool ref_valid = false;
+  const void* ref_img = nullptr;
+  const void* ref_poi = nullptr;
+  std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
+  std::vector<hipGraph_t> graph_objs;
+  hipStream_t cap_stream = nullptr;
+
+  bool fp32() const { return desc.precision == DIC_FP32_BATCHED; }
+  bool det() const { return (desc.flags & DIC_FLAG_DETERMINISTIC_BWD) != 0; }
+};
+
+namespace {
+
+void drop_graphs(dic_plan_s* p) {
+  for (auto& kv : p->graphs) hipGraphExecDestroy(kv.second);
+  for (auto g : p->graph_objs) hipGraphDestroy(g);
+  p->graphs.clear();
+  p->graph_objs.clear();
+}
+
+std::string tune_key(const dic_plan_s* p) {
+  std::ostringstream k;
+  k << "gfx950|" << (p->fp32() ? "f32" : "f64") << "|N" << p->N;
+  std::vector<std::pair<int, int>> ms;
+  for (auto& d : p->pairs) ms.emplace_back(d.subset_radius, d.search_radius);
+  std::sort(ms.begin(), ms.end());
+  ms.erase(std::unique(ms.begin(), ms.end()), ms.end());
+  for (auto& m : ms) k << "|M" << m.first << "S" << m.second;
+  return k.str();
+}
+
+// Minimal JSON object of arrays: {"key": [a, b, c, d], ...}.
+std::map<std::string, std::vector<int>> read_tune_cache(const char* path) {
+  std::map<std::string, std::vector<int>> out;
+  std::ifstream in(path);
+  if (!in) return out;
+  std::stringstream ss;
+  ss << in.rdbuf();
+  const std::string s = ss.str();
+  size_t i = 0;
+  while (true) {
+    const size_t q0 = s.find('"', i);
+    if (q0 == std::string::npos) break;
+    const size_t q1 = s.find('"', q0 + 1);
+    if (q1 == std::string::npos) break;
+    const std::string key = s.substr(q0 + 1, q1 - q0 - 1);
+    const size_t b0 = s.find('[', q1), b1 = s.find(']', q1);
+    if (b0 == std::string::npos || b1 == std::string::npos || b1 < b0) break;
+    std::vector<int> vals;
+    std::stringstream vs(s.substr(b0 + 1, b1 - b0 - 1));
+    std::string tok;
+    while (std::getline(vs, tok, ',')) vals.push_back(std::atoi(tok.c_str()));
+    out[key] = vals;
+    i = b1 + 1;
+  }
+  return out;
+}
+
+void write_tune_cache(const char* path, const std::map<std::string, std::vector<int>>& m) {
+  std::ofstream o(path, std::ios::trunc);
+  if (!o) return;
+  o << "{\n";
+  size_t k = 0;
+  for (auto& kv : m) {
+    o << "  \"" << kv.first << "\": [";
+    for (size_t j = 0; j < kv.second.size(); ++j) o << (j ? ", " : "") << kv.second[j];
+    o << "]" << (++k < m.size() ? "," : "") << "\n";
+  }
+  o << "}\n";
+}
+
+dic_status_t check_plan(dic_plan_t p, bool need_bound) {
+  if (!p) return fail(DIC_ERR_INVALID_ARGUMENT, "null plan");
+  if (need_bound && !p->bound) return fail(DIC_ERR_NOT_BOUND, "plan has no workspace bound");
+  return DIC_SUCCESS;
+}
+
+dic_status_t prepare(dic_plan_t p, const float* ref, const int32_t* poi, hipStream_t s,
+                     bool force) {
+  if (!force && (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->ref_valid && p->ref_img == ref &&
+      p->ref_poi == poi)
+    return DIC_SUCCESS;
+  if (p->fp32()) {
+    DIC_HIP(launch_gradients(p->st, ref, s));
+    DIC_HIP(launch_ref_prep_f32(p->st, ref, poi, s));
+  } else {
+    DIC_HIP(launch_ref_prep_f64(p->st, p->dpairs.data(), ref, poi, s));
+  }
+  p->ref_valid = true;
+  p->ref_img = ref;
+  p->ref_poi = poi;
+  return DIC_SUCCESS;
+}
+
+dic_status_t enqueue_search(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
+                            const int32_t* seed, int32_t* uv, float* zn, int32_t* status,
+                            hipStream_t s) {
+  if (p->fp32()) {
+    DIC_HIP(launch_reset_counters(p->st, s));
+    DIC_HIP(launch_search_f32(p->st, p->tuning, ref, def, poi, seed, uv, zn, status, p->num_cu, s));
+  } else {
+    DIC_HIP(launch_search_f64(p->st, p->dpairs.data(), ref, def, poi, seed, uv, zn, status, s));
+  }
+  return DIC_SUCCESS;
+}
+
+dic_status_t enqueue_refine(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
+                            const int32_t* uv, const int32_t* status_in, const double* p_init,
+                            double* p_out, float* zn, int32_t* iters, int32_t* status,
+                            hipStream_t s) {
+  if (p->fp32()) {
+    DIC_HIP(launch_reset_counters(p->st, s));
+    DIC_HIP(launch_icgn_f32(p->st, p->tuning, ref, def, poi, uv, status_in, p_init, p_out, zn,
+                            iters, status, p->num_cu, s));
+  } else {
+    DIC_HIP(launch_icgn_f64(p->st, p->dpairs.data(), ref, def, poi, uv, status_in, p_init, p_out,
+                            zn, iters, status, s));
+  }
+  return DIC_SUCCESS;
+}
+
+struct CorrArgs {
+  const float *ref, *def;
+  const int32_t* poi;
+  const int32_t* seed;
+  const double* p_init;
+  int32_t* uv;
+  float* zn_int;
+  int32_t* st_int;
+  double* p_out;
+  float* zn;
+  int32_t* iters;
+  int32_t* status;
+};
+
+dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s) {
+  dic_status_t r = prepare(p, a.ref, a.poi, s, false);
+  if (r != DIC_SUCCESS) return r;
+  r = enqueue_search(p, a.ref, a.def, a.poi, a.seed, a.uv, a.zn_int, a.st_int, s);
+  if (r != DIC_SUCCESS) return r;
+  return enqueue_refine(p, a.ref, a.def, a.poi, a.uv, a.st_int, a.p_init, a.p_out, a.zn, a.iters,
+                        a.status, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dic_last_error(void) { return g_last_error.c_str(); }
+
+const char* dic_status_string(int32_t status) {
+  switch (status) {
+    case DIC_SUCCESS: return "success";
+    case DIC_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case DIC_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case DIC_ERR_HIP: return "HIP runtime error";
+    case DIC_ERR_UNSUPPORTED: return "unsupported";
+    case DIC_ERR_INTERNAL: return "internal error";
+    case DIC_ERR_NOT_BOUND: return "plan not bound to a workspace";
+    default: return "unknown status";
+  }
+}
+
+dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
+  if (!d || !out) return fail(DIC_ERR_INVALID_ARGUMENT, "null desc or out");
+  *out = nullptr;
+  if (d->num_pairs < 1 || !d->pairs) return fail(DIC_ERR_INVALID_ARGUMENT, "num_pairs < 1 or null pairs");
+  if (d->precision != DIC_FP32_BATCHED && d->precision != DIC_FP64_PLAIN)
+    return fail(DIC_ERR_INVALID_ARGUMENT, "unknown precision");
+  if (d->max_iters < 1 || d->max_iters > 200) return fail(DIC_ERR_INVALID_ARGUMENT, "max_iters outside 1..200");
+  if (!(d->conv_tol > 0.0) || !std::isfinite(d->conv_tol))
+    return fail(DIC_ERR_INVALID_ARGUMENT, "conv_tol must be positive and finite");
+  const uint32_t known = DIC_FLAG_USE_GRAPH | DIC_FLAG_CACHE_REF_PREP | DIC_FLAG_DETERMINISTIC_BWD;
+  if (d->flags & ~known) return fail(DIC_ERR_INVALID_ARGUMENT, "unknown flag bits");
+  auto p = new dic_plan_s();
+  p->desc = *d;
+  p->pairs.assign(d->pairs, d->pairs + d->num_pairs);
+  p->desc.pairs = nullptr;
+  int64_t next = 0;
+  for (int k = 0; k < d->num_pairs; ++k) {
+    const dic_pair_desc_t& q = p->pairs[k];
+    std::ostringstream why;
+    why << "pair " << k << ": ";
+    if (q.width < 8 || q.height < 8 || q.width > 65536 || q.height > 65536) why << "width/height outside 8..65536";
+    else if (q.subset_radius < 1 || q.subset_radius > kMaxM) why << "subset_radius outside 1..20";
+    else if (q.search_radius < 0 || q.search_radius > kMaxS) why << "search_radius outside 0..32";
+    else if (2 * q.subset_radius + 3 > std::min(q.width, q.height)) why << "subset does not fit the image";
+    else if (q.ref_offset < 0 || q.def_offset < 0) why << "negative image offset";
+    else if (q.poi_count < 0) why << "negative poi_count";
+    else if (q.poi_offset != next) why << "POI ranges must be contiguous and in pair order";
+    else {
+      next += q.poi_count;
+      continue;
+    }
+    delete p;
+    return fail(DIC_ERR_INVALID_ARGUMENT, why.str());
+  }
+  if (next > INT32_MAX) {
+    delete p;
+    return fail(DIC_ERR_INVALID_ARGUMENT, "more than 2^31-1 POIs");
+  }
+  p->N = next;
+  const bool f32 = p->fp32();
+  // layout
+  Layout& L = p->lay;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  L.pairs = take(sizeof(DevPair) * d->num_pairs);
+  L.poi_pair = take(sizeof(int32_t) * p->N);
+  L.work = take(sizeof(int32_t) * p->N);
+  L.counters = take(sizeof(int32_t) * kNumCounters);
+  int64_t gfl = 0, tfl = 0, fix = 0;
+  p->dpairs.resize(d->num_pairs);
+  p->fix_off.resize(d->num_pairs);
+  for (int k = 0; k < d->num_pairs; ++k) {
+    const dic_pair_desc_t& q = p->pairs[k];
+    DevPair& P = p->dpairs[k];
+    P.width = q.width;
+    P.height = q.height;
+    P.M = q.subset_radius;
+    P.S = q.search_radius;
+    P.ref_off = q.ref_offset;
+    P.def_off = q.def_offset;
+    P.poi_off = q.poi_offset;
+    P.poi_count = q.poi_count;
+    P.grad_off = gfl;
+    P.tmpl_off = tfl;
+    const int64_t n = (int64_t)(2 * q.subset_radius + 1) * (2 * q.subset_radius + 1);
+    if (f32) {
+      gfl += 2 * (int64_t)q.width * q.height;
+      tfl += q.poi_count * n;
+    }
+    p->fix_off[k] = fix;
+    if (p->det()) fix += (int64_t)q.width * q.height;
+    p->maxM = std::max(p->maxM, (int)q.subset_radius);
+    p->maxS = std::max(p->maxS, (int)q.search_radius);
+    p->maxW = std::max(p->maxW, (int)q.width);
+    p->maxH = std::max(p->maxH, (int)q.height);
+  }
+  L.grads = take(sizeof(float) * gfl);
+  L.recs = take(sizeof(RefRec) * p->N);
+  L.tmpl = take(sizeof(float) * tfl);
+  L.fix_off = take(sizeof(int64_t) * d->num_pairs);
+  L.fix = take(sizeof(unsigned long long) * fix);
+  L.fix_count = fix;
+  L.s_status = take(sizeof(int32_t) * p->N);
+  L.s_zncc = take(sizeof(float) * p->N);
+  L.total = off;
+  // POI -> pair and the work list, largest subsets first (stable)
+  p->poi_pair.resize(p->N);
+  for (int k = 0; k < d->num_pairs; ++k)
+    for (int64_t i = 0; i < p->pairs[k].poi_count; ++i)
+      p->poi_pair[p->pairs[k].poi_offset + i] = k;
+  p->work.resize(p->N);
+  for (int64_t i = 0; i < p->N; ++i) p->work[i] = (int32_t)i;
+  std::stable_sort(p->work.begin(), p->work.end(), [&](int32_t a, int32_t b) {
+    return p->pairs[p->poi_pair[a]].subset_radius > p->pairs[p->poi_pair[b]].subset_radius;
+  });
+  if (f32 && search_lds_bytes(p->maxM, p->maxS, p->tuning.search_block) > 160 * 1024) {
+    delete p;
+    return fail(DIC_ERR_UNSUPPORTED, "search window exceeds the 160 KiB LDS of a CU");
+  }
+  *out = p;
+  return DIC_SUCCESS;
+}
+
+void dic_plan_destroy(dic_plan_t p) {
+  if (!p) return;
+  drop_graphs(p);
+  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  delete p;
+}
+
+dic_status_t dic_plan_workspace_size(dic_plan_t p, size_t* bytes) {
+  dic_status_t r = check_plan(p, false);
+  if (r) return r;
+  if (!bytes) return fail(DIC_ERR_INVALID_ARGUMENT, "null bytes");
+  *bytes = p->lay.total;
+  return DIC_SUCCESS;
+}
+
+dic_status_t dic_plan_get_tuning(dic_plan_t p, dic_tuning_t* out) {
+  dic_status_t r = check_plan(p, false);
+  if (r) return r;
+  if (!out) return fail(DIC_ERR_INVALID_ARGUMENT, "null out");
+  *out = p->tuning;
+  return DIC_SUCCESS;
+}
+
+dic_status_t dic_plan_set_tuning(dic_plan_t p, const dic_tuning_t* in) {
+  dic_status_t r = check_plan(p, false);
+  if (r) return r;
+  if (!in || !tuning_valid(*in)) return fail(DIC_ERR_INVALID_ARGUMENT, "invalid tuning");
+  if (p->fp32() && search_lds_bytes(p->maxM, p->maxS, in->search_block) > 160 * 1024)
+    return fail(DIC_ERR_UNSUPPORTED, "search tile exceeds LDS");
+  p->tuning = *in;
+  drop_graphs(p);
+  return DIC_SUCCESS;
+}
+
+dic_status_t dic_plan_bind(dic_plan_t p, void* ws, size_t bytes, dic_stream_t stream) {
+  dic_status_t r = check_plan(p, false);
+  if (r) return r;
+  if (!ws) return fail(DIC_ERR_INVALID_ARGUMENT, "null workspace");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(DIC_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+  if (bytes < p->lay.total) return fail(DIC_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than dic_plan_workspace_size");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int dev = 0;
+  DIC_HIP(hipGetDevice(&dev));
+  DIC_HIP(hipDeviceGetAttribute(&p->num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  char* base = static_cast<char*>(ws);
+  DIC_HIP(hipMemcpyAsync(base + p->lay.pairs, p->dpairs.data(), sizeof(DevPair) * p->dpairs.size(),
+                         hipMemcpyHostToDevice, s));
+  if (p->N) {
+    DIC_HIP(hipMemcpyAsync(base + p->lay.poi_pair, p->poi_pair.data(), sizeof(int32_t) * p->N,
+                           hipMemcpyHostToDevice, s));
+    DIC_HIP(hipMemcpyAsync(base + p->lay.work, p->work.data(), sizeof(int32_t) * p->N,
+                           hipMemcpyHostToDevice, s));
+  }
+  DIC_HIP(hipMemcpyAsync(base + p->lay.fix_off, p->fix_off.data(), sizeof(int64_t) * p->fix_off.size(),
+                         hipMemcpyHostToDevice, s));
+  DevState& st = p->st;
+  st.pairs = reinterpret_cast<const DevPair*>(base + p->lay.pairs);
+  st.poi_pair = reinterpret_cast<const int32_t*>(base + p->lay.poi_pair);
+  st.work = reinterpret_cast<const int32_t*>(base + p->lay.work);
+  st.counters = reinterpret_cast<int32_t*>(base + p->lay.counters);
+  st.grads = reinterpret_cast<float*>(base + p->lay.grads);
+  st.recs = reinterpret_cast<RefRec*>(base + p->lay.recs);
+  st.tmpl = reinterpret_cast<float*>(base + p->lay.tmpl);
+  st.N = p->N;
+  st.num_pairs = p->desc.num_pairs;
+  st.maxM = p->maxM;
+  st.maxS = p->maxS;
+  st.max_width = p->maxW;
+  st.max_height = p->maxH;
+  st.max_iters = p->desc.max_iters;
+  st.conv_tol = p->desc.conv_tol;
+  p->ws = ws;
+  p->bound = true;
+  p->ref_valid = false;
+  drop_graphs(p);
+  if (const char* path = std::getenv("DIC_AUTOTUNE_CACHE")) {
+    auto m = read_tune_cache(path);
+    auto it = m.find(tune_key(p));
+    if (it != m.end() && it->second.size() == 4) {
+      dic_tuning_t t = {it->second[0], it->second[1], it->second[2], it->second[3]};
+      if (tuning_valid(t)) p->tuning = t;
+    }
+  }
+  return DIC_SUCCESS;
+}
+
+dic_status_t dic_plan_invalidate_reference(dic_plan_t p) {
+  dic_status_t r = check_plan(p, false);
+  if (r) return r;
+  p->ref_valid = false;
+  drop_graphs(p);
+  return DIC_SUCCESS;
+}
+
+dic_status_t dic_prepare_reference(dic_plan_t p, const float* ref, const int32_t* poi,
+                                   dic_stream_t stream) {
+  dic_status_t r = check_plan(p, true);
+  if (r) return r;
+  if (!ref || (!poi && p->N)) return fail(DIC_ERR_INVALID_ARGUMENT, "null image or POI pointer");
+  return prepare(p, ref, poi, reinterpret_cast<hipStream_t>(stream), true);
+}
+
+dic_status_t dic_integer_search(dic_plan_t p, const float* ref, const float* def,
+                                const int32_t* poi, const int32_t* seed, int32_t* uv, float* zn,
+                                int32_t* status, dic_stream_t stream) {
+  dic_status_t r = check_plan(p, true);
+  if (r) return r;
+  if (p->N == 0) return DIC_SUCCESS;
+  if (!ref || !def || !poi || !uv || !zn || !status)
+    return fail(DIC_ERR_INVALID_ARGUMENT, "null required pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  r = prepare(p, ref, poi, s, false);
+  if (r) return r;
+  return enqueue_search(p, ref, def, poi, seed, uv, zn, status, s);
+}
+
+dic_status_t dic_icgn_refine(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
+                             const int32_t* uv_init, const int32_t* status_in,
+                             const double* p_init, double* p_out, float* zn, int32_t* iters,
+                             int32_t* status, dic_stream_t stream) {
+  dic_status_t r = check_plan(p, true);
+  if (r) return r;
+  if (p->N == 0) return DIC_SUCCESS;
+  if (!ref || !def || !poi || !uv_init || !p_out || !zn || !iters || !status)
+    return fail(DIC_ERR_INVALID_ARGUMENT, "null required pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  r = prepare(p, ref, poi, s, false);
+  if (r) return r;
+  return enqueue_refine(p, ref, def, poi, uv_init, status_in, p_init, p_out, zn, iters, status, s);
+}
+
+dic_status_t dic_correlate(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
+                           const int32_t* seed, const double* p_init, int32_t* uv,
+                           float* zn_int, int32_t* st_int, double* p_out, float* zn,
+                           int32_t* iters, int32_t* status, dic_stream_t stream) {
+  dic_status_t r = check_plan(p, true);
+  if (r) return r;
+  if (p->N == 0) return DIC_SUCCESS;
+  if (!ref || !def || !poi || !uv || !p_out || !zn || !iters || !status)
+    return fail(DIC_ERR_INVALID_ARGUMENT, "null required pointer");
+  char* base = static_cast<char*>(p->ws);
+  CorrArgs a{ref, def, poi, seed, p_init, uv,
+             zn_int ? zn_int : reinterpret_cast<float*>(base + p->lay.s_zncc),
+             st_int ? st_int : reinterpret_cast<int32_t*>(base + p->lay.s_status),
+             p_out, zn, iters, status};
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (!(p->desc.flags & DIC_FLAG_USE_GRAPH)) return enqueue_correlate(p, a, s);
+  const bool cached_ref = (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->ref_valid &&
+                          p->ref_img == ref && p->ref_poi == poi;
+  std::vector<uintptr_t> key = {
+      (uintptr_t)ref, (uintptr_t)def, (uintptr_t)poi, (uintptr_t)seed, (uintptr_t)p_init,
+      (uintptr_t)uv, (uintptr_t)a.zn_int, (uintptr_t)a.st_int, (uintptr_t)p_out, (uintptr_t)zn,
+      (uintptr_t)iters, (uintptr_t)status, (uintptr_t)cached_ref};
+  auto it = p->graphs.find(key);
+  if (it == p->graphs.end()) {
+    if (!p->cap_stream) DIC_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    DIC_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
+    r = enqueue_correlate(p, a, p->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+    if (r) {
+      if (graph) hipGraphDestroy(graph);
+      return r;
+    }
+    if (e != hipSuccess) return fail(DIC_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      hipGraphDestroy(graph);
+      return fail(DIC_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    p->graph_objs.push_back(graph);
+    it = p->graphs.emplace(key, exec).first;
+  }
+  DIC_HIP(hipGraphLaunch(it->second, s));
+  return DIC_SUCCESS;
+}
+
+dic_status_t dic_znssd_backward(dic_plan_t p, const float* ref, const float* def,
+                                const int32_t* poi, const double* pw, const float* grad_c,
+                                float* c_out, double* grad_p, float* grad_def,
+                                dic_stream_t stream) {
+  dic_status_t r = check_plan(p, true);
+  if (r) return r;
+  if (p->N == 0) return DIC_SUCCESS;
+  if (!ref || !def || !poi || !pw) return fail(DIC_ERR_INVALID_ARGUMENT, "null required pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  r = prepare(p, ref, poi, s, false);
+  if (r) return r;
+  char* base = static_cast<char*>(p->ws);
+  unsigned long long* fix = p->det() ? reinterpret_cast<unsigned long long*>(base + p->lay.fix) : nullptr;
+  const int64_t* fix_off = reinterpret_cast<const int64_t*>(base + p->lay.fix_off);
+  DIC_HIP(launch_znssd(p->st, ref, def, poi, pw, grad_c, c_out, grad_p, grad_def, fix, fix_off,
+                       p->lay.fix_count, p->num_cu, s));
+  return DIC_SUCCESS;
+}
+
+dic_status_t dic_seed_update(dic_plan_t p, const double* pw, const int32_t* status,
+                             int32_t* seed_uv, double* p_seed, dic_stream_t stream) {
+  dic_status_t r = check_plan(p, true);
+  if (r) return r;
+  if (p->N == 0) return DIC_SUCCESS;
+  if (!pw || !status || !seed_uv || !p_seed) return fail(DIC_ERR_INVALID_ARGUMENT, "null pointer");
+  DIC_HIP(launch_seed_update(p->N, pw, status, seed_uv, p_seed, reinterpret_cast<hipStream_t>(stream)));
+  return DIC_SUCCESS;
+}
+
+dic_status_t dic_poi_grid(int32_t width, int32_t height, int32_t M, int32_t S, int32_t step,
+                          int32_t* out_xy, int64_t capacity, int64_t* count) {
+  if (!count || step < 1 || M < 0 || S < 0 || width < 1 || height < 1 || capacity < 0 ||
+      (capacity > 0 && !out_xy))
+    return fail(DIC_ERR_INVALID_ARGUMENT, "invalid grid arguments");
+  const int64_t m = (int64_t)M + S + 2;
+  int64_t nx = 0, ny = 0;
+  for (int64_t x = m; x <= width - 1 - m; x += step) ++nx;
+  for (int64_t y = m; y <= height - 1 - m; y += step) ++ny;
+  *count = nx * ny;
+  int64_t k = 0;
+  for (int64_t j = 0; j < ny; ++j)
+    for (int64_t i = 0; i < nx; ++i, ++k)
+      if (k < capacity) {
+        out_xy[2 * k] = (int32_t)(m + i * step);
+        out_xy[2 * k + 1] = (int32_t)(m + j * step);
+      }
+  return DIC_SUCCESS;
+}
+
+dic_status_t dic_plan_autotune(dic_plan_t p, const float* ref, const float* def,
+                               const int32_t* poi, int32_t* uv, float* fs, int32_t* is,
+                               double* ps, dic_stream_t stream) {
+  dic_status_t r = check_plan(p, true);
+  if (r) return r;
+  if (!p->fp32() || p->N == 0) return DIC_SUCCESS;
+  if (!ref || !def || !poi || !uv || !fs || !is || !ps)
+    return fail(DIC_ERR_INVALID_ARGUMENT, "null pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  r = prepare(p, ref, poi, s, true);
+  if (r) return r;
+  hipEvent_t e0, e1;
+  DIC_HIP(hipEventCreate(&e0));
+  DIC_HIP(hipEventCreate(&e1));
+  const dic_tuning_t saved = p->tuning;
+  dic_tuning_t best = saved;
+  auto time_it = [&](auto&& fn, float* ms) -> dic_status_t {
+    dic_status_t q = fn();  // warm-up
+    if (q) return q;
+    DIC_HIP(hipEventRecord(e0, s));
+    for (int k = 0; k < 2; ++k) {
+      q = fn();
+      if (q) return q;
+    }
+    DIC_HIP(hipEventRecord(e1, s));
+    DIC_HIP(hipEventSynchronize(e1));
+    DIC_HIP(hipEventElapsedTime(ms, e0, e1));
+    return DIC_SUCCESS;
+  };
+  float best_ms = 1e30f;
+  const int blocks[] = {4, 6, 8, 11};
+  const int threads[] = {128, 256, 512};
+  for (int b : blocks)
+    for (int t : threads) {
+      dic_tuning_t c = best;
+      c.search_block = b;
+      c.search_threads = t;
+      if (search_lds_bytes(p->maxM, p->maxS, b) > 160 * 1024) continue;
+      p->tuning = c;
+      float ms = 0.f;
+      r = time_it([&] { return enqueue_search(p, ref, def, poi, nullptr, uv, fs, is, s); }, &ms);
+      if (r) continue;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best.search_block = b;
+        best.search_threads = t;
+      }
+    }
+  p->tuning = best;
+  r = enqueue_search(p, ref, def, poi, nullptr, uv, fs, is, s);
+  if (r) {
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    p->tuning = saved;
+    return r;
+  }
+  best_ms = 1e30f;
+  const int waves[] = {1, 2, 4, 8};
+  const int slacks[] = {2, 4, 6};
+  for (int w : waves)
+    for (int sl : slacks) {
+      dic_tuning_t c = best;
+      c.icgn_waves = w;
+      c.icgn_slack = sl;
+      p->tuning = c;
+      float ms = 0.f;
+      r = time_it([&] {
+        return enqueue_refine(p, ref, def, poi, uv, is, nullptr, ps, fs, is + p->N, is + p->N, s);
+      }, &ms);
+      if (r) continue;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best.icgn_waves = w;
+        best.icgn_slack = sl;
+      }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  p->tuning = best;
+  drop_graphs(p);
+  g_last_error.clear();
+  if (const char* path = std::getenv("DIC_AUTOTUNE_CACHE")) {
+    auto m = read_tune_cache(path);
+    m[tune_key(p)] = {best.search_block, best.search_threads, best.icgn_waves, best.icgn_slack};
+    write_tune_cache(path, m);
+  }
+  return DIC_SUCCESS;
+}
+
+}  // extern "C"

@@ -1,0 +1,169 @@
+// Device helpers: wave reductions, compensated sums, Keys cubic weights,
+// 6x6 Cholesky and the affine warp algebra.
+#pragma once
+
+#include <math.h>
+
+#include "dic_internal.h"
+
+namespace dic {
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Makes LDS writes of one wave visible to its other lanes (no block barrier:
+// waves of a workgroup work on different POIs).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__device__ __forceinline__ int wave_or_int(int v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Kahan-compensated FP32 accumulator.
+struct Kahan {
+  float s = 0.f, c = 0.f;
+  __device__ __forceinline__ void add(float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  // Value as FP64: the running sum minus the lost low-order part.
+  __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+};
+
+// Keys cubic-convolution weights (a = -1/2) for taps -1, 0, 1, 2 around
+// floor(x), t = x - floor(x).  Horner forms of
+//   w-1 = (-t^3 + 2t^2 - t)/2, w0 = (3t^3 - 5t^2 + 2)/2,
+//   w1 = (-3t^3 + 4t^2 + t)/2, w2 = (t^3 - t^2)/2.
+template <typename T>
+__device__ __forceinline__ void cubic_weights(T t, T w[4]) {
+  const T tm = t - T(1);
+  w[0] = T(-0.5) * t * tm * tm;
+  w[1] = fma(t * t, fma(T(1.5), t, T(-2.5)), T(1));
+  w[2] = t * fma(t, fma(T(-1.5), t, T(2)), T(0.5));
+  w[3] = T(0.5) * t * t * tm;
+}
+
+// d/dt of the weights above.
+template <typename T>
+__device__ __forceinline__ void cubic_dweights(T t, T w[4]) {
+  w[0] = T(-0.5) * fma(T(3), t, T(-1)) * (t - T(1));
+  w[1] = t * fma(T(4.5), t, T(-5));
+  w[2] = fma(t, fma(T(-4.5), t, T(4)), T(0.5));
+  w[3] = t * fma(T(1.5), t, T(-1));
+}
+
+__device__ __forceinline__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// Cholesky H = L L^T of a packed symmetric 6x6 (lower triangle, row order).
+// Fails when a pivot d_k does not exceed 1e-10 * H_kk (also for NaN).
+__device__ __forceinline__ bool cholesky6(const double* H, double* L, double* rdiag) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double d = H[tri(k, k)];
+#pragma unroll
+    for (int j = 0; j < k; ++j) d -= L[tri(k, j)] * L[tri(k, j)];
+    if (!(d > 1e-10 * H[tri(k, k)])) return false;
+    const double lkk = sqrt(d);
+    L[tri(k, k)] = lkk;
+    rdiag[k] = 1.0 / lkk;
+#pragma unroll
+    for (int i = k + 1; i < 6; ++i) {
+      double a = H[tri(i, k)];
+#pragma unroll
+      for (int j = 0; j < k; ++j) a -= L[tri(i, j)] * L[tri(k, j)];
+      L[tri(i, k)] = a * rdiag[k];
+    }
+  }
+  return true;
+}
+
+// Solve L L^T x = b.
+__device__ __forceinline__ void cholesky6_solve(const double* L, const double* rdiag,
+                                                const double* b, double* x) {
+  double z[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double a = b[i];
+#pragma unroll
+    for (int j = 0; j < i; ++j) a -= L[tri(i, j)] * z[j];
+    z[i] = a * rdiag[i];
+  }
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    double a = z[i];
+#pragma unroll
+    for (int j = i + 1; j < 6; ++j) a -= L[tri(j, i)] * x[j];
+    x[i] = a * rdiag[i];
+  }
+}
+
+// Inverse-compositional update W(p) <- W(p) W(dp)^-1 for the first-order
+// warp, p = (u, ux, uy, v, vx, vy).
+__device__ __forceinline__ void compose_inverse(double* p, const double* dp) {
+  const double a00 = 1.0 + dp[1], a01 = dp[2], a10 = dp[4], a11 = 1.0 + dp[5];
+  const double rdet = 1.0 / (a00 * a11 - a01 * a10);
+  const double i00 = a11 * rdet, i01 = -a01 * rdet, i10 = -a10 * rdet, i11 = a00 * rdet;
+  const double it0 = -(i00 * dp[0] + i01 * dp[3]);
+  const double it1 = -(i10 * dp[0] + i11 * dp[3]);
+  const double b00 = 1.0 + p[1], b01 = p[2], b10 = p[4], b11 = 1.0 + p[5];
+  const double n00 = b00 * i00 + b01 * i10, n01 = b00 * i01 + b01 * i11;
+  const double n10 = b10 * i00 + b11 * i10, n11 = b10 * i01 + b11 * i11;
+  const double t0 = b00 * it0 + b01 * it1 + p[0];
+  const double t1 = b10 * it0 + b11 * it1 + p[3];
+  p[0] = t0;
+  p[1] = n00 - 1.0;
+  p[2] = n01;
+  p[3] = t1;
+  p[4] = n10;
+  p[5] = n11 - 1.0;
+}
+
+// Stop-rule norm: displacement change at the subset edge.
+__device__ __forceinline__ double update_norm(const double* dp, int M) {
+  const double m2 = (double)M * (double)M;
+  return sqrt(dp[0] * dp[0] + dp[3] * dp[3] +
+              m2 * (dp[1] * dp[1] + dp[2] * dp[2] + dp[4] * dp[4] + dp[5] * dp[5]));
+}
+
+// Flat-subset rule shared by search, refinement and their FP64 forms:
+// sum (s - mean)^2 must exceed 1e-6 * sum s^2.
+__device__ __forceinline__ bool not_flat(double var_sum, double sq_sum) {
+  return var_sum > 1e-6 * sq_sum;
+}
+
+// A POI is usable when its subset plus the one-pixel gradient border is
+// inside the reference image.
+__device__ __forceinline__ bool poi_inside(int x0, int y0, int M, int W, int H) {
+  return x0 - M >= 1 && x0 + M <= W - 2 && y0 - M >= 1 && y0 + M <= H - 2;
+}
+
+}  // namespace dic

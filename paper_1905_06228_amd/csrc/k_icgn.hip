@@ -1,0 +1,559 @@
+// IC-GN sub-pixel refinement (Sec. 2.2) with a first-order warp and Keys
+// bicubic interpolation of the deformed image.
+//
+// FP32 batched form.  One wave per POI, persistent over a shared work counter
+// (several waves per workgroup, each independent).  Per lane: the reference
+// gradients of its samples stay in registers for the whole solve, so an
+// iteration reads only the deformed image, from a per-wave LDS patch that is
+// restaged only when the warped subset leaves it.  Sample positions are an
+// integer base (POI + rounded translation) plus an FP32 local offset below
+// ~M+slack pixels.  Eight sums per iteration (sum g, sum g^2 and the six
+// steepest-descent products) are Kahan-compensated per lane and reduced in
+// FP64; with the precomputed sum SD_i (f_i - fbar) and sum SD_i the
+// right-hand side needs no second pass:
+//   sum SD_i e_i = sum SD_i (f_i - fbar) - (df/dg) (sum SD_i g_i - gbar sum SD_i).
+// The 6x6 solve and the warp composition run in FP64.
+#include "dic_device.h"
+
+namespace dic {
+
+namespace {
+
+__host__ __device__ __forceinline__ int icgn_patch_side(int maxM, int slack) {
+  return 2 * maxM + 4 + 2 * slack;
+}
+
+__device__ __forceinline__ int pack_dxy(int dx, int dy) { return (dx + 128) | ((dy + 128) << 8); }
+__device__ __forceinline__ float unpack_dx(int v) { return (float)((v & 0xff) - 128); }
+__device__ __forceinline__ float unpack_dy(int v) { return (float)(((v >> 8) & 0xff) - 128); }
+
+struct Warp32 {
+  int bx, by;                  // integer base of the sample positions
+  float uf, vf, ux, uy, vx, vy;  // local offsets: x = bx + dx + ux dx + uy dy + uf
+};
+
+__device__ __forceinline__ Warp32 make_warp32(const double* p, int x0, int y0) {
+  Warp32 w;
+  const double ur = rint(p[0]), vr = rint(p[3]);
+  w.bx = x0 + (int)ur;
+  w.by = y0 + (int)vr;
+  w.uf = (float)(p[0] - ur);
+  w.vf = (float)(p[3] - vr);
+  w.ux = (float)p[1];
+  w.uy = (float)p[2];
+  w.vx = (float)p[4];
+  w.vy = (float)p[5];
+  return w;
+}
+
+__device__ __forceinline__ float warp_x(const Warp32& w, float dx, float dy) {
+  return dx + fmaf(w.ux, dx, fmaf(w.uy, dy, w.uf));
+}
+__device__ __forceinline__ float warp_y(const Warp32& w, float dx, float dy) {
+  return dy + fmaf(w.vx, dx, fmaf(w.vy, dy, w.vf));
+}
+
+// Bounding box (absolute pixel indices) of every 4x4 neighbourhood the
+// warped subset touches; extremes of an affine map over a square are at its
+// corners.
+__device__ __forceinline__ void tap_box(const Warp32& w, int M, int& x_lo, int& x_hi, int& y_lo,
+                                        int& y_hi) {
+  float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const float dx = a ? (float)M : -(float)M, dy = b ? (float)M : -(float)M;
+      const float xs = warp_x(w, dx, dy), ys = warp_y(w, dx, dy);
+      xmn = fminf(xmn, xs);
+      xmx = fmaxf(xmx, xs);
+      ymn = fminf(ymn, ys);
+      ymx = fmaxf(ymx, ys);
+    }
+  x_lo = w.bx + (int)floorf(xmn) - 1;
+  x_hi = w.bx + (int)floorf(xmx) + 2;
+  y_lo = w.by + (int)floorf(ymn) - 1;
+  y_hi = w.by + (int)floorf(ymx) + 2;
+}
+
+// Interpolated grey level at local offset (xs, ys).  `src` holds the image
+// (or the staged patch) with row pitch `pitch`; (ox, oy) is the position of
+// the integer base inside it.  With kClamp the 4x4 neighbourhood origin is
+// clamped to [0, maxc] x [0, maxr]: the tap box test already keeps it there,
+// the clamp only guarantees in-bounds reads for a degenerate warp.
+template <bool kClamp>
+__device__ __forceinline__ float interp32(const float* src, int pitch, int ox, int oy, float xs,
+                                          float ys, int maxc, int maxr) {
+  const float fx = floorf(xs), fy = floorf(ys);
+  float wx[4], wy[4];
+  cubic_weights(xs - fx, wx);
+  cubic_weights(ys - fy, wy);
+  int c0 = (int)fx - 1 + ox, r0 = (int)fy - 1 + oy;
+  if (kClamp) {
+    c0 = min(max(c0, 0), maxc);
+    r0 = min(max(r0, 0), maxr);
+  }
+  const float* q = src + (int64_t)r0 * pitch + c0;
+  float acc = 0.f;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const float* row = q + (int64_t)l * pitch;
+    const float r = fmaf(wx[3], row[3], fmaf(wx[2], row[2], fmaf(wx[1], row[1], wx[0] * row[0])));
+    acc = fmaf(wy[l], r, acc);
+  }
+  return acc;
+}
+
+template <int MAXS, bool kClamp>
+__device__ __forceinline__ void iter_pass(const float* src, int pitch, int ox, int oy, int maxc,
+                                          int maxr, int n, const Warp32& w, float c0,
+                                          const float* fxs, const float* fys, const int* dxy,
+                                          Kahan* K) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 0; k < MAXS; ++k) {
+    if (lane + kWave * k < n) {
+      const float dx = unpack_dx(dxy[k]), dy = unpack_dy(dxy[k]);
+      const float gs =
+          interp32<kClamp>(src, pitch, ox, oy, warp_x(w, dx, dy), warp_y(w, dx, dy), maxc, maxr) -
+          c0;
+      const float fg = fxs[k] * gs, hg = fys[k] * gs;
+      K[0].add(gs);
+      K[1].add(gs * gs);
+      K[2].add(fg);
+      K[3].add(fg * dx);
+      K[4].add(fg * dy);
+      K[5].add(hg);
+      K[6].add(hg * dx);
+      K[7].add(hg * dy);
+    }
+  }
+}
+
+template <int MAXS, bool kClamp>
+__device__ __forceinline__ void final_pass(const float* src, int pitch, int ox, int oy, int maxc,
+                                           int maxr, int n, const Warp32& w, float c0,
+                                           const int* dxy, const float* __restrict__ tm,
+                                           Kahan* K) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 0; k < MAXS; ++k) {
+    const int s = lane + kWave * k;
+    if (s < n) {
+      const float dx = unpack_dx(dxy[k]), dy = unpack_dy(dxy[k]);
+      const float gs =
+          interp32<kClamp>(src, pitch, ox, oy, warp_x(w, dx, dy), warp_y(w, dx, dy), maxc, maxr) -
+          c0;
+      K[0].add(gs);
+      K[1].add(gs * gs);
+      K[2].add(tm[s] * gs);
+    }
+  }
+}
+
+// Per-wave LDS patch of the deformed image.
+struct Patch {
+  float* buf;
+  int side;
+  int x0 = INT_MIN, y0 = INT_MIN;
+  // Makes [x_lo, x_hi] x [y_lo, y_hi] resident; false when it cannot fit.
+  __device__ __forceinline__ bool ensure(const float* __restrict__ img, int W, int H, int x_lo,
+                                         int x_hi, int y_lo, int y_hi) {
+    if (x_lo >= x0 && x_hi < x0 + side && y_lo >= y0 && y_hi < y0 + side) return true;
+    const int bw = x_hi - x_lo + 1, bh = y_hi - y_lo + 1;
+    if (bw > side || bh > side) return false;
+    x0 = x_lo - (side - bw) / 2;
+    y0 = y_lo - (side - bh) / 2;
+    const int lane = lane_id();
+    wave_lds_sync();
+    for (int idx = lane; idx < side * side; idx += kWave) {
+      const int r = idx / side, c = idx - r * side;
+      const int X = x0 + c, Y = y0 + r;
+      buf[idx] = (X >= 0 && X < W && Y >= 0 && Y < H) ? img[(int64_t)Y * W + X] : 0.f;
+    }
+    wave_lds_sync();
+    return true;
+  }
+};
+
+__device__ __forceinline__ void reduce8(const Kahan* K, double* S) {
+#pragma unroll
+  for (int a = 0; a < 8; ++a) S[a] = wave_sum(K[a].value());
+}
+
+}  // namespace
+
+size_t icgn_lds_bytes(int maxM, int slack, int waves) {
+  const int side = icgn_patch_side(maxM, slack);
+  return (size_t)waves * side * side * sizeof(float);
+}
+
+template <int MAXS>
+__global__ void __launch_bounds__(512) icgn_f32_kernel(
+    DevState st, int slack, const float* __restrict__ def, const int32_t* __restrict__ poi,
+    const int32_t* __restrict__ uv_init, const int32_t* __restrict__ status_in,
+    const double* __restrict__ p_init, double* __restrict__ p_out, float* __restrict__ zncc_out,
+    int32_t* __restrict__ iters_out, int32_t* __restrict__ status_out) {
+  extern __shared__ float lds[];
+  const int lane = lane_id(), wid = threadIdx.x / kWave;
+  const int pside = icgn_patch_side(st.maxM, slack);
+  Patch patch;
+  patch.buf = lds + (size_t)wid * pside * pside;
+  patch.side = pside;
+
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(&st.counters[kCtrIcgn], 1);
+    item = uniform(__shfl(item, 0, kWave));
+    if (item >= st.N) break;
+    const int g = uniform(st.work[item]);
+    const DevPair P = st.pairs[uniform(st.poi_pair[g])];
+    const RefRec* R = st.recs + g;
+    const int x0 = uniform(poi[2 * g]), y0 = uniform(poi[2 * g + 1]);
+    double p[6] = {(double)uv_init[2 * g], 0.0, 0.0, (double)uv_init[2 * g + 1], 0.0, 0.0};
+    if (p_init) {
+      p[1] = p_init[6 * g + 1];
+      p[2] = p_init[6 * g + 2];
+      p[4] = p_init[6 * g + 4];
+      p[5] = p_init[6 * g + 5];
+    }
+    int status = uniform(R->status);
+    if (status_in && status == DIC_POI_OK) status = uniform(status_in[g]);
+    int it = 0;
+    float zn = nanf("");
+    if (status == DIC_POI_OK) {
+      const int M = P.M, n1 = 2 * M + 1, n = n1 * n1, W = P.width, H = P.height;
+      const float* gimg = def + P.def_off;
+      const float* gx = st.grads + P.grad_off;
+      const float* gy = gx + (int64_t)W * H;
+      float fxs[MAXS], fys[MAXS];
+      int dxy[MAXS];
+#pragma unroll
+      for (int k = 0; k < MAXS; ++k) {
+        const int s = lane + kWave * k;
+        fxs[k] = fys[k] = 0.f;
+        dxy[k] = pack_dxy(0, 0);
+        if (s < n) {
+          const int r = s / n1, c = s - r * n1;
+          const int64_t idx = (int64_t)(y0 - M + r) * W + (x0 - M + c);
+          fxs[k] = gx[idx];
+          fys[k] = gy[idx];
+          dxy[k] = pack_dxy(c - M, r - M);
+        }
+      }
+      const float c0 = (float)R->fbar;
+      const double df = R->df;
+      const double nn = (double)n;
+      patch.x0 = patch.y0 = INT_MIN;
+      status = DIC_POI_NOT_CONVERGED;
+      while (it < st.max_iters) {
+        ++it;
+        const Warp32 w = make_warp32(p, x0, y0);
+        int xl, xh, yl, yh;
+        tap_box(w, M, xl, xh, yl, yh);
+        if (xl < 0 || xh > W - 1 || yl < 0 || yh > H - 1) {
+          status = DIC_POI_OUT_OF_BOUNDS;
+          break;
+        }
+        Kahan K[8];
+        if (patch.ensure(gimg, W, H, xl, xh, yl, yh))
+          iter_pass<MAXS, false>(patch.buf, pside, w.bx - patch.x0, w.by - patch.y0, 0, 0, n, w,
+                                 c0, fxs, fys, dxy, K);
+        else
+          iter_pass<MAXS, true>(gimg, W, w.bx, w.by, W - 4, H - 4, n, w, c0, fxs, fys, dxy, K);
+        double S[8];
+        reduce8(K, S);
+        if (!isfinite(S[0]) || !isfinite(S[1])) {
+          status = DIC_POI_NAN_INPUT;
+          break;
+        }
+        const double ms = S[0] / nn;
+        const double var = S[1] - S[0] * ms;
+        const double sumg2 = S[1] + 2.0 * (double)c0 * S[0] + nn * (double)c0 * (double)c0;
+        if (!not_flat(var, sumg2)) {
+          status = DIC_POI_ZERO_VARIANCE;
+          break;
+        }
+        const double ratio = df / sqrt(var);
+        double b[6], dp[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) b[a] = -(R->sdf_sum[a] - ratio * (S[2 + a] - ms * R->sd_sum[a]));
+        cholesky6_solve(R->L, R->rdiag, b, dp);
+        compose_inverse(p, dp);
+        if (update_norm(dp, M) < st.conv_tol) {
+          status = DIC_POI_OK;
+          break;
+        }
+      }
+      if (status == DIC_POI_OK || status == DIC_POI_NOT_CONVERGED) {
+        const Warp32 w = make_warp32(p, x0, y0);
+        int xl, xh, yl, yh;
+        tap_box(w, M, xl, xh, yl, yh);
+        if (xl < 0 || xh > W - 1 || yl < 0 || yh > H - 1) {
+          status = DIC_POI_OUT_OF_BOUNDS;
+        } else {
+          const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * n;
+          Kahan K[3];
+          if (patch.ensure(gimg, W, H, xl, xh, yl, yh))
+            final_pass<MAXS, false>(patch.buf, pside, w.bx - patch.x0, w.by - patch.y0, 0, 0, n, w,
+                                    c0, dxy, tm, K);
+          else
+            final_pass<MAXS, true>(gimg, W, w.bx, w.by, W - 4, H - 4, n, w, c0, dxy, tm, K);
+          const double s0 = wave_sum(K[0].value());
+          const double s1 = wave_sum(K[1].value());
+          const double s2 = wave_sum(K[2].value());
+          if (!isfinite(s0) || !isfinite(s1)) {
+            status = DIC_POI_NAN_INPUT;
+          } else {
+            const double ms = s0 / nn;
+            const double var = s1 - s0 * ms;
+            const double sumg2 = s1 + 2.0 * (double)c0 * s0 + nn * (double)c0 * (double)c0;
+            if (!not_flat(var, sumg2))
+              status = DIC_POI_ZERO_VARIANCE;
+            else
+              zn = (float)((s2 - ms * (double)R->tsum) / (df * sqrt(var)));
+          }
+        }
+      }
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int a = 0; a < 6; ++a) p_out[6 * g + a] = p[a];
+      zncc_out[g] = (status == DIC_POI_OK || status == DIC_POI_NOT_CONVERGED) ? zn : nanf("");
+      iters_out[g] = it;
+      status_out[g] = status;
+    }
+  }
+}
+
+template <int MAXS>
+static hipError_t launch_icgn_f32_t(const DevState& st, const dic_tuning_t& tu, const float* def,
+                                    const int32_t* poi, const int32_t* uv_init,
+                                    const int32_t* status_in, const double* p_init, double* p_out,
+                                    float* zncc, int32_t* iters, int32_t* status, int num_cu,
+                                    hipStream_t s) {
+  const int threads = tu.icgn_waves * kWave;
+  const size_t lds = icgn_lds_bytes(st.maxM, tu.icgn_slack, tu.icgn_waves);
+  if (lds > 65536) {
+    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&icgn_f32_kernel<MAXS>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (ea != hipSuccess) return ea;
+  }
+  int occ = 0;
+  hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, icgn_f32_kernel<MAXS>, threads, lds);
+  if (e != hipSuccess) return e;
+  if (occ < 1) return hipErrorInvalidConfiguration;
+  int64_t blocks = (int64_t)occ * num_cu;
+  const int64_t need = (st.N + tu.icgn_waves - 1) / tu.icgn_waves;
+  if (blocks > need) blocks = need;
+  hipLaunchKernelGGL(icgn_f32_kernel<MAXS>, dim3((unsigned)blocks), dim3(threads), lds, s, st,
+                     tu.icgn_slack, def, poi, uv_init, status_in, p_init, p_out, zncc, iters,
+                     status);
+  return hipGetLastError();
+}
+
+hipError_t launch_icgn_f32(const DevState& st, const dic_tuning_t& tu, const float* /*ref*/,
+                           const float* def, const int32_t* poi, const int32_t* uv_init,
+                           const int32_t* status_in, const double* p_init, double* p_out,
+                           float* zncc, int32_t* iters, int32_t* status, int num_cu,
+                           hipStream_t s) {
+  if (st.N == 0) return hipSuccess;
+  const int n = (2 * st.maxM + 1) * (2 * st.maxM + 1);
+  const int need = (n + kWave - 1) / kWave;
+#define DIC_ICGN_CASE(S_)                                                                       \
+  if (need <= S_)                                                                               \
+    return launch_icgn_f32_t<S_>(st, tu, def, poi, uv_init, status_in, p_init, p_out, zncc, iters, \
+                                 status, num_cu, s);
+  DIC_ICGN_CASE(4)
+  DIC_ICGN_CASE(8)
+  DIC_ICGN_CASE(12)
+  DIC_ICGN_CASE(16)
+  DIC_ICGN_CASE(20)
+  DIC_ICGN_CASE(28)
+#undef DIC_ICGN_CASE
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 plain form: one 64-thread workgroup per POI of one pair; FP64
+// positions, weights and sums, taps and reference gradients read from global
+// memory every iteration, two-pass statistics, residual formed per sample.
+// ---------------------------------------------------------------------------
+
+template <int MAXS>
+__global__ void __launch_bounds__(64) icgn_f64_kernel(
+    DevState st, DevPair P, const float* __restrict__ ref, const float* __restrict__ def,
+    const int32_t* __restrict__ poi, const int32_t* __restrict__ uv_init,
+    const int32_t* __restrict__ status_in, const double* __restrict__ p_init,
+    double* __restrict__ p_out, float* __restrict__ zncc_out, int32_t* __restrict__ iters_out,
+    int32_t* __restrict__ status_out) {
+  const int64_t g = P.poi_off + blockIdx.x;
+  const int lane = threadIdx.x;
+  const RefRec* R = st.recs + g;
+  const int x0 = poi[2 * g], y0 = poi[2 * g + 1];
+  double p[6] = {(double)uv_init[2 * g], 0.0, 0.0, (double)uv_init[2 * g + 1], 0.0, 0.0};
+  if (p_init) {
+    p[1] = p_init[6 * g + 1];
+    p[2] = p_init[6 * g + 2];
+    p[4] = p_init[6 * g + 4];
+    p[5] = p_init[6 * g + 5];
+  }
+  int status = R->status;
+  if (status_in && status == DIC_POI_OK) status = status_in[g];
+  int it = 0;
+  double zn = nan("");
+  const int M = P.M, n1 = 2 * M + 1, n = n1 * n1, W = P.width, H = P.height;
+  const float* f = ref + P.ref_off;
+  const float* gi = def + P.def_off;
+  const double fbar = R->fbar, df = R->df;
+  double gl[MAXS];
+
+  // Interpolates every sample at p into gl; returns 1 if any tap leaves the
+  // image (checked per sample), 2 if any value is non-finite.
+  auto sample = [&](double* mean, double* dg) -> int {
+    int oob = 0;
+#pragma unroll
+    for (int k = 0; k < MAXS; ++k) {
+      const int s = lane + kWave * k;
+      if (s >= n) continue;
+      const double dx = (double)(s % n1 - M), dy = (double)(s / n1 - M);
+      const double xs = x0 + (1.0 + p[1]) * dx + p[2] * dy + p[0];
+      const double ys = y0 + p[4] * dx + (1.0 + p[5]) * dy + p[3];
+      const double fx = floor(xs), fy = floor(ys);
+      if (fx < 1.0 || fx + 2.0 > W - 1 || fy < 1.0 || fy + 2.0 > H - 1) oob = 1;
+    }
+    if (wave_or_int(oob)) return 1;
+    double s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < MAXS; ++k) {
+      const int s = lane + kWave * k;
+      gl[k] = 0.0;
+      if (s >= n) continue;
+      const double dx = (double)(s % n1 - M), dy = (double)(s / n1 - M);
+      const double xs = x0 + (1.0 + p[1]) * dx + p[2] * dy + p[0];
+      const double ys = y0 + p[4] * dx + (1.0 + p[5]) * dy + p[3];
+      const double fx = floor(xs), fy = floor(ys);
+      double wx[4], wy[4];
+      cubic_weights(xs - fx, wx);
+      cubic_weights(ys - fy, wy);
+      const float* q = gi + (int64_t)((int)fy - 1) * W + ((int)fx - 1);
+      double v = 0.0;
+      for (int l = 0; l < 4; ++l)
+        for (int c = 0; c < 4; ++c) v += wy[l] * wx[c] * (double)q[(int64_t)l * W + c];
+      gl[k] = v;
+      s1 += v;
+    }
+    s1 = wave_sum(s1);
+    if (!isfinite(s1)) return 2;
+    *mean = s1 / (double)n;
+    double q2 = 0.0, sq = 0.0;
+#pragma unroll
+    for (int k = 0; k < MAXS; ++k) {
+      const int s = lane + kWave * k;
+      if (s >= n) continue;
+      const double d = gl[k] - *mean;
+      q2 += d * d;
+      sq += gl[k] * gl[k];
+    }
+    q2 = wave_sum(q2);
+    sq = wave_sum(sq);
+    if (!not_flat(q2, sq)) return 3;
+    *dg = sqrt(q2);
+    return 0;
+  };
+
+  if (status == DIC_POI_OK) {
+    status = DIC_POI_NOT_CONVERGED;
+    while (it < st.max_iters) {
+      ++it;
+      double gbar, dg;
+      const int r = sample(&gbar, &dg);
+      if (r) {
+        status = r == 1 ? DIC_POI_OUT_OF_BOUNDS : r == 2 ? DIC_POI_NAN_INPUT : DIC_POI_ZERO_VARIANCE;
+        break;
+      }
+      double b[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int k = 0; k < MAXS; ++k) {
+        const int s = lane + kWave * k;
+        if (s >= n) continue;
+        const int dxi = s % n1 - M, dyi = s / n1 - M;
+        const int64_t idx = (int64_t)(y0 + dyi) * W + (x0 + dxi);
+        const double fx = ((double)f[idx + 1] - (double)f[idx - 1]) / 2.0;
+        const double fy = ((double)f[idx + W] - (double)f[idx - W]) / 2.0;
+        const double e = ((double)f[idx] - fbar) - df / dg * (gl[k] - gbar);
+        const double dx = dxi, dy = dyi;
+        b[0] += fx * e;
+        b[1] += fx * dx * e;
+        b[2] += fx * dy * e;
+        b[3] += fy * e;
+        b[4] += fy * dx * e;
+        b[5] += fy * dy * e;
+      }
+      double dp[6];
+      for (int a = 0; a < 6; ++a) b[a] = -wave_sum(b[a]);
+      cholesky6_solve(R->L, R->rdiag, b, dp);
+      compose_inverse(p, dp);
+      if (update_norm(dp, M) < st.conv_tol) {
+        status = DIC_POI_OK;
+        break;
+      }
+    }
+    if (status == DIC_POI_OK || status == DIC_POI_NOT_CONVERGED) {
+      double gbar, dg;
+      const int r = sample(&gbar, &dg);
+      if (r) {
+        status = r == 1 ? DIC_POI_OUT_OF_BOUNDS : r == 2 ? DIC_POI_NAN_INPUT : DIC_POI_ZERO_VARIANCE;
+      } else {
+        double num = 0.0;
+#pragma unroll
+        for (int k = 0; k < MAXS; ++k) {
+          const int s = lane + kWave * k;
+          if (s >= n) continue;
+          const int64_t idx = (int64_t)(y0 + s / n1 - M) * W + (x0 + s % n1 - M);
+          num += ((double)f[idx] - fbar) * (gl[k] - gbar);
+        }
+        zn = wave_sum(num) / (df * dg);
+      }
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < 6; ++a) p_out[6 * g + a] = p[a];
+    zncc_out[g] = (status == DIC_POI_OK || status == DIC_POI_NOT_CONVERGED) ? (float)zn : nanf("");
+    iters_out[g] = it;
+    status_out[g] = status;
+  }
+}
+
+hipError_t launch_icgn_f64(const DevState& st, const DevPair* host_pairs, const float* ref,
+                           const float* def, const int32_t* poi, const int32_t* uv_init,
+                           const int32_t* status_in, const double* p_init, double* p_out,
+                           float* zncc, int32_t* iters, int32_t* status, hipStream_t s) {
+  for (int k = 0; k < st.num_pairs; ++k) {
+    const DevPair& P = host_pairs[k];
+    if (P.poi_count == 0) continue;
+    const int need = ((2 * P.M + 1) * (2 * P.M + 1) + kWave - 1) / kWave;
+    const dim3 grid((unsigned)P.poi_count), block(64);
+#define DIC_ICGN64_CASE(S_)                                                                    \
+  if (need <= S_) {                                                                            \
+    hipLaunchKernelGGL(icgn_f64_kernel<S_>, grid, block, 0, s, st, P, ref, def, poi, uv_init,  \
+                       status_in, p_init, p_out, zncc, iters, status);                         \
+    hipError_t e = hipGetLastError();                                                          \
+    if (e != hipSuccess) return e;                                                             \
+    continue;                                                                                  \
+  }
+    DIC_ICGN64_CASE(4)
+    DIC_ICGN64_CASE(8)
+    DIC_ICGN64_CASE(12)
+    DIC_ICGN64_CASE(16)
+    DIC_ICGN64_CASE(20)
+    DIC_ICGN64_CASE(28)
+#undef DIC_ICGN64_CASE
+    return hipErrorInvalidValue;
+  }
+  return hipSuccess;
+}
+
+}  // namespace dic

@@ -1,0 +1,276 @@
+// Reference-side precomputation: gradients of the reference images and the
+// per-POI record IC-GN precomputes (Sec. 2.2), plus small utility kernels.
+#include "dic_device.h"
+
+namespace dic {
+
+__global__ void reset_counters_kernel(int32_t* counters) {
+  if (threadIdx.x < kNumCounters) counters[threadIdx.x] = 0;
+}
+
+hipError_t launch_reset_counters(const DevState& st, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, st.counters);
+  return hipGetLastError();
+}
+
+// Central-difference gradients, fx = (f[x+1] - f[x-1]) / 2, zero on the
+// one-pixel border.  Grid: (column blocks, rows, pairs).
+__global__ void __launch_bounds__(256) gradients_kernel(const DevPair* __restrict__ pairs,
+                                                        const float* __restrict__ ref,
+                                                        float* __restrict__ grads) {
+  const DevPair P = pairs[blockIdx.z];
+  const int y = blockIdx.y;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= P.height || x >= P.width) return;
+  const int W = P.width, H = P.height;
+  const float* f = ref + P.ref_off;
+  const int64_t i = (int64_t)y * W + x;
+  float gx = 0.f, gy = 0.f;
+  if (x > 0 && x < W - 1) gx = 0.5f * (f[i + 1] - f[i - 1]);
+  if (y > 0 && y < H - 1) gy = 0.5f * (f[i + W] - f[i - W]);
+  float* out = grads + P.grad_off;
+  out[i] = gx;
+  out[i + (int64_t)W * H] = gy;
+}
+
+hipError_t launch_gradients(const DevState& st, const float* ref, hipStream_t s) {
+  dim3 grid((st.max_width + 255) / 256, st.max_height, st.num_pairs);
+  hipLaunchKernelGGL(gradients_kernel, grid, dim3(256), 0, s, st.pairs, ref, st.grads);
+  return hipGetLastError();
+}
+
+// Writes the record of a POI that cannot be processed.
+__device__ __forceinline__ void write_bad_record(RefRec* R, int status, int lane) {
+  if (lane == 0) {
+    R->fbar = nan("");
+    R->df = nan("");
+    R->tsum = 0.f;
+    R->status = status;
+  }
+}
+
+// FP32 form: one wave per POI.  Mean and norm of the subset in FP64 (they
+// decide ZERO_VARIANCE exactly as the FP64 definition does); steepest-descent
+// sums and the 21 Hessian sums in FP32 with Kahan compensation; centring,
+// factorisation and singularity test in FP64.  Also stores the float search
+// template f_i - fbar.
+__global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
+                                                           const float* __restrict__ ref,
+                                                           const int32_t* __restrict__ poi) {
+  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (g >= st.N) return;
+  const int lane = lane_id();
+  const DevPair P = st.pairs[st.poi_pair[g]];
+  RefRec* R = st.recs + g;
+  const int x0 = poi[2 * g], y0 = poi[2 * g + 1];
+  const int M = P.M, n1 = 2 * M + 1, n = n1 * n1, W = P.width;
+  if (!poi_inside(x0, y0, M, P.width, P.height)) {
+    write_bad_record(R, DIC_POI_OUT_OF_BOUNDS, lane);
+    return;
+  }
+  const float* f = ref + P.ref_off;
+  const float* gxi = st.grads + P.grad_off;
+  const float* gyi = gxi + (int64_t)P.width * P.height;
+  float* tmpl = st.tmpl + P.tmpl_off + (g - P.poi_off) * (int64_t)n;
+
+  double s1 = 0.0;
+  int bad = 0;
+  for (int k = lane; k < n; k += kWave) {
+    const int r = k / n1, c = k - r * n1;
+    const float v = f[(int64_t)(y0 - M + r) * W + (x0 - M + c)];
+    bad |= !isfinite(v);
+    s1 += (double)v;
+  }
+  s1 = wave_sum(s1);
+  bad = wave_or_int(bad);
+  if (bad) {
+    write_bad_record(R, DIC_POI_NAN_INPUT, lane);
+    return;
+  }
+  const double fbar = s1 / (double)n;
+  const float fbar_f = (float)fbar;
+
+  double q = 0.0, sq = 0.0, ts = 0.0;
+  Kahan ksd[6], ksdf[6], kh[21];
+  for (int k = lane; k < n; k += kWave) {
+    const int r = k / n1, c = k - r * n1;
+    const int64_t idx = (int64_t)(y0 - M + r) * W + (x0 - M + c);
+    const float v = f[idx];
+    const double d = (double)v - fbar;
+    q += d * d;
+    sq += (double)v * (double)v;
+    const float t = v - fbar_f;
+    tmpl[k] = t;
+    ts += (double)t;
+    const float fx = gxi[idx], fy = gyi[idx];
+    const float dx = (float)(c - M), dy = (float)(r - M);
+    const float sd[6] = {fx, fx * dx, fx * dy, fy, fy * dx, fy * dy};
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      ksd[a].add(sd[a]);
+      ksdf[a].add(sd[a] * t);
+#pragma unroll
+      for (int b = 0; b <= a; ++b) kh[tri(a, b)].add(sd[a] * sd[b]);
+    }
+  }
+  q = wave_sum(q);
+  sq = wave_sum(sq);
+  ts = wave_sum(ts);
+  double sdsum[6], sdfsum[6], h[21];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    sdsum[a] = wave_sum(ksd[a].value());
+    sdfsum[a] = wave_sum(ksdf[a].value());
+  }
+#pragma unroll
+  for (int a = 0; a < 21; ++a) h[a] = wave_sum(kh[a].value());
+
+  int status = DIC_POI_OK;
+  double L[21], rd[6];
+  if (!not_flat(q, sq)) {
+    status = DIC_POI_ZERO_VARIANCE;
+  } else {
+    // Hessian of the mean-removed steepest-descent images.
+    const double rn = 1.0 / (double)n;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+      for (int b = 0; b <= a; ++b) h[tri(a, b)] -= sdsum[a] * sdsum[b] * rn;
+    if (!cholesky6(h, L, rd)) status = DIC_POI_SINGULAR_HESSIAN;
+  }
+  if (lane == 0) {
+    R->fbar = fbar;
+    R->df = sqrt(q);
+    R->tsum = (float)ts;
+    R->status = status;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      R->sd_sum[a] = sdsum[a];
+      R->sdf_sum[a] = sdfsum[a];
+      R->rdiag[a] = status == DIC_POI_OK ? rd[a] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 21; ++a) R->L[a] = status == DIC_POI_OK ? L[a] : 0.0;
+  }
+}
+
+hipError_t launch_ref_prep_f32(const DevState& st, const float* ref, const int32_t* poi,
+                               hipStream_t s) {
+  if (st.N == 0) return hipSuccess;
+  const int64_t blocks = (st.N + 3) / 4;
+  hipLaunchKernelGGL(ref_prep_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, st, ref, poi);
+  return hipGetLastError();
+}
+
+// FP64 plain form: one 64-thread workgroup per POI of one pair, everything
+// in FP64, gradients straight from the reference image.
+__global__ void __launch_bounds__(64) ref_prep_f64_kernel(DevState st, DevPair P, int pair,
+                                                          const float* __restrict__ ref,
+                                                          const int32_t* __restrict__ poi) {
+  const int64_t g = P.poi_off + blockIdx.x;
+  const int lane = threadIdx.x;
+  RefRec* R = st.recs + g;
+  const int x0 = poi[2 * g], y0 = poi[2 * g + 1];
+  const int M = P.M, n1 = 2 * M + 1, n = n1 * n1, W = P.width;
+  if (!poi_inside(x0, y0, M, P.width, P.height)) {
+    write_bad_record(R, DIC_POI_OUT_OF_BOUNDS, lane);
+    return;
+  }
+  const float* f = ref + P.ref_off;
+  double s1 = 0.0;
+  int bad = 0;
+  for (int k = lane; k < n; k += kWave) {
+    const int r = k / n1, c = k - r * n1;
+    const float v = f[(int64_t)(y0 - M + r) * W + (x0 - M + c)];
+    bad |= !isfinite(v);
+    s1 += (double)v;
+  }
+  s1 = wave_sum(s1);
+  bad = wave_or_int(bad);
+  if (bad) {
+    write_bad_record(R, DIC_POI_NAN_INPUT, lane);
+    return;
+  }
+  const double fbar = s1 / (double)n;
+  double q = 0.0, sq = 0.0, sd_s[6] = {0}, sdf_s[6] = {0}, h[21] = {0};
+  for (int k = lane; k < n; k += kWave) {
+    const int r = k / n1, c = k - r * n1;
+    const int64_t idx = (int64_t)(y0 - M + r) * W + (x0 - M + c);
+    const double v = (double)f[idx];
+    const double d = v - fbar;
+    q += d * d;
+    sq += v * v;
+    const double fx = ((double)f[idx + 1] - (double)f[idx - 1]) / 2.0;
+    const double fy = ((double)f[idx + W] - (double)f[idx - W]) / 2.0;
+    const double dx = (double)(c - M), dy = (double)(r - M);
+    const double sd[6] = {fx, fx * dx, fx * dy, fy, fy * dx, fy * dy};
+    for (int a = 0; a < 6; ++a) {
+      sd_s[a] += sd[a];
+      sdf_s[a] += sd[a] * d;
+      for (int b = 0; b <= a; ++b) h[tri(a, b)] += sd[a] * sd[b];
+    }
+  }
+  q = wave_sum(q);
+  sq = wave_sum(sq);
+  for (int a = 0; a < 6; ++a) {
+    sd_s[a] = wave_sum(sd_s[a]);
+    sdf_s[a] = wave_sum(sdf_s[a]);
+  }
+  for (int a = 0; a < 21; ++a) h[a] = wave_sum(h[a]);
+  int status = DIC_POI_OK;
+  double L[21], rd[6];
+  if (!not_flat(q, sq)) {
+    status = DIC_POI_ZERO_VARIANCE;
+  } else {
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b <= a; ++b) h[tri(a, b)] -= sd_s[a] * sd_s[b] / (double)n;
+    if (!cholesky6(h, L, rd)) status = DIC_POI_SINGULAR_HESSIAN;
+  }
+  if (lane == 0) {
+    R->fbar = fbar;
+    R->df = sqrt(q);
+    R->tsum = 0.f;
+    R->status = status;
+    for (int a = 0; a < 6; ++a) {
+      R->sd_sum[a] = sd_s[a];
+      R->sdf_sum[a] = sdf_s[a];
+      R->rdiag[a] = status == DIC_POI_OK ? rd[a] : 0.0;
+    }
+    for (int a = 0; a < 21; ++a) R->L[a] = status == DIC_POI_OK ? L[a] : 0.0;
+  }
+}
+
+hipError_t launch_ref_prep_f64(const DevState& st, const DevPair* host_pairs, const float* ref,
+                               const int32_t* poi, hipStream_t s) {
+  for (int k = 0; k < st.num_pairs; ++k) {
+    const DevPair& P = host_pairs[k];
+    if (P.poi_count == 0) continue;
+    hipLaunchKernelGGL(ref_prep_f64_kernel, dim3((unsigned)P.poi_count), dim3(64), 0, s, st, P,
+                       k, ref, poi);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Sequence seeding: the last frame with status OK supplies the next seed.
+__global__ void seed_update_kernel(int64_t N, const double* __restrict__ p,
+                                   const int32_t* __restrict__ status, int32_t* __restrict__ seed,
+                                   double* __restrict__ p_seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N || status[i] != DIC_POI_OK) return;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) p_seed[6 * i + a] = p[6 * i + a];
+  seed[2 * i] = (int32_t)rint(p[6 * i]);
+  seed[2 * i + 1] = (int32_t)rint(p[6 * i + 3]);
+}
+
+hipError_t launch_seed_update(int64_t N, const double* p, const int32_t* status, int32_t* seed,
+                              double* p_seed, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(seed_update_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, p,
+                     status, seed, p_seed);
+  return hipGetLastError();
+}
+
+}  // namespace dic

@@ -1,0 +1,423 @@
+"""ctypes binding of libdic.so.
+
+Argument marshalling only: every step of the correlation runs in the HIP
+library.  Tensors must be CUDA tensors on the plan's device; the calls are
+asynchronous on the current torch stream.  There is no fallback: a missing
+library or a non-GPU tensor raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdic.so")
+
+FP32_BATCHED = 0
+FP64_PLAIN = 1
+FLAG_USE_GRAPH = 1
+FLAG_CACHE_REF_PREP = 2
+FLAG_DETERMINISTIC_BWD = 4
+
+POI_OK = 0
+POI_NOT_CONVERGED = 1
+POI_OUT_OF_BOUNDS = 2
+POI_ZERO_VARIANCE = 3
+POI_SINGULAR_HESSIAN = 4
+POI_NO_VALID_CANDIDATE = 5
+POI_NAN_INPUT = 6
+
+
+class PairDesc(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("subset_radius", ctypes.c_int32), ("search_radius", ctypes.c_int32),
+                ("ref_offset", ctypes.c_int64), ("def_offset", ctypes.c_int64),
+                ("poi_offset", ctypes.c_int64), ("poi_count", ctypes.c_int64)]
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("num_pairs", ctypes.c_int32), ("pairs", ctypes.POINTER(PairDesc)),
+                ("precision", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("conv_tol", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("search_block", ctypes.c_int32), ("search_threads", ctypes.c_int32),
+                ("icgn_waves", ctypes.c_int32), ("icgn_slack", ctypes.c_int32)]
+
+
+EXPORTS = [
+    "dic_plan_create", "dic_plan_workspace_size", "dic_plan_bind", "dic_plan_get_tuning",
+    "dic_plan_set_tuning", "dic_plan_autotune", "dic_plan_invalidate_reference",
+    "dic_prepare_reference", "dic_integer_search", "dic_icgn_refine", "dic_correlate",
+    "dic_znssd_backward", "dic_seed_update", "dic_poi_grid", "dic_plan_destroy",
+    "dic_status_string", "dic_last_error",
+]
+
+_lib = None
+
+
+class DicError(RuntimeError):
+    pass
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libdic.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise DicError(f"{path} is missing: build it with __graft_entry__.build() "
+                       "or python paper_1905_06228_amd/build.py")
+    L = ctypes.CDLL(path)
+    P, V, I32, I64 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.dic_plan_create.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(P)]
+    L.dic_plan_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    L.dic_plan_bind.argtypes = [P, V, ctypes.c_size_t, V]
+    L.dic_plan_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    L.dic_plan_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    L.dic_plan_autotune.argtypes = [P, V, V, V, V, V, V, V, V]
+    L.dic_plan_invalidate_reference.argtypes = [P]
+    L.dic_prepare_reference.argtypes = [P, V, V, V]
+    L.dic_integer_search.argtypes = [P, V, V, V, V, V, V, V, V]
+    L.dic_icgn_refine.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V]
+    L.dic_correlate.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V, V, V]
+    L.dic_znssd_backward.argtypes = [P, V, V, V, V, V, V, V, V, V]
+    L.dic_seed_update.argtypes = [P, V, V, V, V, V]
+    L.dic_poi_grid.argtypes = [I32, I32, I32, I32, I32, V, I64, ctypes.POINTER(I64)]
+    L.dic_plan_destroy.argtypes = [P]
+    L.dic_plan_destroy.restype = None
+    L.dic_status_string.argtypes = [I32]
+    L.dic_status_string.restype = ctypes.c_char_p
+    L.dic_last_error.argtypes = []
+    L.dic_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        fn = getattr(L, name)
+        if name not in ("dic_plan_destroy", "dic_status_string", "dic_last_error"):
+            fn.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        L = load_library()
+        raise DicError(f"{L.dic_status_string(rc).decode()} ({rc}): "
+                       f"{L.dic_last_error().decode()}")
+
+
+def _ptr(t: Optional[torch.Tensor], dtype: torch.dtype, device: torch.device,
+         name: str) -> Optional[int]:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise DicError(f"{name} must be a CUDA tensor on {device}")
+    if t.device != device:
+        raise DicError(f"{name} is on {t.device}, plan on {device}")
+    if t.dtype != dtype:
+        raise DicError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise DicError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def poi_grid(width: int, height: int, M: int, S: int, step: int) -> torch.Tensor:
+    """Host POI grid from the library (x0 = m + k step, m = M+S+2), int32 [N, 2]."""
+    L = load_library()
+    cnt = ctypes.c_int64(0)
+    _check(L.dic_poi_grid(width, height, M, S, step, None, 0, ctypes.byref(cnt)))
+    out = torch.empty((cnt.value, 2), dtype=torch.int32)
+    _check(L.dic_poi_grid(width, height, M, S, step, ctypes.c_void_p(out.data_ptr()),
+                          cnt.value, ctypes.byref(cnt)))
+    return out
+
+
+@dataclass
+class PairSpec:
+    width: int
+    height: int
+    M: int
+    S: int
+    ref_offset: int = 0
+    def_offset: int = 0
+    poi_offset: int = 0
+    poi_count: int = 0
+
+
+class Plan:
+    """A bound plan: the library's host plan plus a torch-owned workspace."""
+
+    def __init__(self, pairs: Sequence[PairSpec], precision: int = FP32_BATCHED,
+                 max_iters: int = 20, conv_tol: float = 1e-3, flags: int = 0,
+                 device: Optional[torch.device] = None):
+        self.L = load_library()
+        dev = torch.device(device) if device is not None else torch.device("cuda")
+        if dev.type != "cuda":
+            raise DicError("the library runs on a GPU; device must be cuda")
+        self.device = dev if dev.index is not None else torch.device("cuda", torch.cuda.current_device())
+        arr = (PairDesc * len(pairs))()
+        for k, q in enumerate(pairs):
+            arr[k] = PairDesc(q.width, q.height, q.M, q.S, q.ref_offset, q.def_offset,
+                              q.poi_offset, q.poi_count)
+        desc = PlanDesc(len(pairs), arr, precision, max_iters, conv_tol, flags)
+        self._h = ctypes.c_void_p()
+        _check(self.L.dic_plan_create(ctypes.byref(desc), ctypes.byref(self._h)))
+        self.pairs = list(pairs)
+        self.N = sum(q.poi_count for q in pairs)
+        self.precision = precision
+        self.flags = flags
+        nbytes = ctypes.c_size_t(0)
+        _check(self.L.dic_plan_workspace_size(self._h, ctypes.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8,
+                                         device=self.device)
+            _check(self.L.dic_plan_bind(self._h, self.workspace.data_ptr(),
+                                        self.workspace.numel(), _stream()))
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self.L.dic_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- tuning --------------------------------------------------------------
+    @property
+    def tuning(self) -> Tuple[int, int, int, int]:
+        t = Tuning()
+        _check(self.L.dic_plan_get_tuning(self._h, ctypes.byref(t)))
+        return (t.search_block, t.search_threads, t.icgn_waves, t.icgn_slack)
+
+    @tuning.setter
+    def tuning(self, v: Tuple[int, int, int, int]) -> None:
+        t = Tuning(*v)
+        _check(self.L.dic_plan_set_tuning(self._h, ctypes.byref(t)))
+
+    def autotune(self, ref: torch.Tensor, defm: torch.Tensor, pois: torch.Tensor) -> Tuple:
+        d = self.device
+        uv = torch.empty((self.N, 2), dtype=torch.int32, device=d)
+        fs = torch.empty(self.N, dtype=torch.float32, device=d)
+        is_ = torch.empty(2 * self.N, dtype=torch.int32, device=d)
+        ps = torch.empty((self.N, 6), dtype=torch.float64, device=d)
+        _check(self.L.dic_plan_autotune(
+            self._h, _ptr(ref, torch.float32, d, "ref"), _ptr(defm, torch.float32, d, "def"),
+            _ptr(pois, torch.int32, d, "pois"), uv.data_ptr(), fs.data_ptr(), is_.data_ptr(),
+            ps.data_ptr(), _stream()))
+        return self.tuning
+
+    def invalidate_reference(self) -> None:
+        _check(self.L.dic_plan_invalidate_reference(self._h))
+
+    # -- the hot path ----------------------------------------------------------
+    def prepare_reference(self, ref: torch.Tensor, pois: torch.Tensor) -> None:
+        d = self.device
+        _check(self.L.dic_prepare_reference(self._h, _ptr(ref, torch.float32, d, "ref"),
+                                            _ptr(pois, torch.int32, d, "pois"), _stream()))
+
+    def integer_search(self, ref, defm, pois, seed=None, out=None):
+        d, N = self.device, self.N
+        uv, zn, st = out if out is not None else (
+            torch.empty((N, 2), dtype=torch.int32, device=d),
+            torch.empty(N, dtype=torch.float32, device=d),
+            torch.empty(N, dtype=torch.int32, device=d))
+        _check(self.L.dic_integer_search(
+            self._h, _ptr(ref, torch.float32, d, "ref"), _ptr(defm, torch.float32, d, "def"),
+            _ptr(pois, torch.int32, d, "pois"), _ptr(seed, torch.int32, d, "seed"),
+            _ptr(uv, torch.int32, d, "uv"), _ptr(zn, torch.float32, d, "zncc"),
+            _ptr(st, torch.int32, d, "status"), _stream()))
+        return uv, zn, st
+
+    def icgn_refine(self, ref, defm, pois, uv, status_in=None, p_init=None, out=None):
+        d, N = self.device, self.N
+        p, zn, it, st = out if out is not None else (
+            torch.empty((N, 6), dtype=torch.float64, device=d),
+            torch.empty(N, dtype=torch.float32, device=d),
+            torch.empty(N, dtype=torch.int32, device=d),
+            torch.empty(N, dtype=torch.int32, device=d))
+        _check(self.L.dic_icgn_refine(
+            self._h, _ptr(ref, torch.float32, d, "ref"), _ptr(defm, torch.float32, d, "def"),
+            _ptr(pois, torch.int32, d, "pois"), _ptr(uv, torch.int32, d, "uv"),
+            _ptr(status_in, torch.int32, d, "status_in"),
+            _ptr(p_init, torch.float64, d, "p_init"), _ptr(p, torch.float64, d, "p"),
+            _ptr(zn, torch.float32, d, "zncc"), _ptr(it, torch.int32, d, "iters"),
+            _ptr(st, torch.int32, d, "status"), _stream()))
+        return p, zn, it, st
+
+    def new_outputs(self) -> dict:
+        d, N = self.device, self.N
+        return dict(uv=torch.empty((N, 2), dtype=torch.int32, device=d),
+                    zncc_int=torch.empty(N, dtype=torch.float32, device=d),
+                    status_int=torch.empty(N, dtype=torch.int32, device=d),
+                    p=torch.empty((N, 6), dtype=torch.float64, device=d),
+                    zncc=torch.empty(N, dtype=torch.float32, device=d),
+                    iters=torch.empty(N, dtype=torch.int32, device=d),
+                    status=torch.empty(N, dtype=torch.int32, device=d))
+
+    def correlate(self, ref, defm, pois, seed=None, p_init=None, out: Optional[dict] = None) -> dict:
+        """Search then refine (graph-replayed when the plan has FLAG_USE_GRAPH)."""
+        d = self.device
+        o = out if out is not None else self.new_outputs()
+        _check(self.L.dic_correlate(
+            self._h, _ptr(ref, torch.float32, d, "ref"), _ptr(defm, torch.float32, d, "def"),
+            _ptr(pois, torch.int32, d, "pois"), _ptr(seed, torch.int32, d, "seed"),
+            _ptr(p_init, torch.float64, d, "p_init"), _ptr(o["uv"], torch.int32, d, "uv"),
+            _ptr(o["zncc_int"], torch.float32, d, "zncc_int"),
+            _ptr(o["status_int"], torch.int32, d, "status_int"),
+            _ptr(o["p"], torch.float64, d, "p"), _ptr(o["zncc"], torch.float32, d, "zncc"),
+            _ptr(o["iters"], torch.int32, d, "iters"), _ptr(o["status"], torch.int32, d, "status"),
+            _stream()))
+        return o
+
+    def znssd(self, ref, defm, pois, p, grad_c=None, c_out=None, grad_p=None, grad_def=None):
+        d = self.device
+        _check(self.L.dic_znssd_backward(
+            self._h, _ptr(ref, torch.float32, d, "ref"), _ptr(defm, torch.float32, d, "def"),
+            _ptr(pois, torch.int32, d, "pois"), _ptr(p, torch.float64, d, "p"),
+            _ptr(grad_c, torch.float32, d, "grad_c"), _ptr(c_out, torch.float32, d, "c_out"),
+            _ptr(grad_p, torch.float64, d, "grad_p"),
+            _ptr(grad_def, torch.float32, d, "grad_def"), _stream()))
+
+    def seed_update(self, p, status, seed_uv, p_seed) -> None:
+        d = self.device
+        _check(self.L.dic_seed_update(
+            self._h, _ptr(p, torch.float64, d, "p"), _ptr(status, torch.int32, d, "status"),
+            _ptr(seed_uv, torch.int32, d, "seed_uv"), _ptr(p_seed, torch.float64, d, "p_seed"),
+            _stream()))
+
+
+# ---------------------------------------------------------------------------
+# convenience front ends
+# ---------------------------------------------------------------------------
+
+def single_pair_plan(width: int, height: int, M: int, S: int, n_pois: int,
+                     precision: int = FP32_BATCHED, **kw) -> Plan:
+    return Plan([PairSpec(width, height, M, S, 0, 0, 0, n_pois)], precision, **kw)
+
+
+def correlate(ref: torch.Tensor, defm: torch.Tensor, pois: torch.Tensor, M: int, S: int,
+              precision: int = FP32_BATCHED, seed=None, p_init=None, **kw) -> dict:
+    """Integer search + IC-GN for one pair of [H, W] float32 CUDA images."""
+    H, W = ref.shape
+    plan = single_pair_plan(W, H, M, S, pois.shape[0], precision, **kw)
+    out = plan.correlate(ref, defm, pois, seed, p_init)
+    out["plan"] = plan
+    return out
+
+
+def batch_layout(pairs: Sequence[Tuple[torch.Tensor, torch.Tensor, torch.Tensor, int, int]],
+                 device) -> Tuple[List[PairSpec], torch.Tensor, torch.Tensor, torch.Tensor]:
+    """Packs (ref, def, pois, M, S) tuples into two image arenas and one POI array."""
+    specs, refs, defs, pts = [], [], [], []
+    roff = doff = poff = 0
+    for f, g, q, M, S in pairs:
+        H, W = f.shape
+        specs.append(PairSpec(W, H, M, S, roff, doff, poff, q.shape[0]))
+        refs.append(f.reshape(-1))
+        defs.append(g.reshape(-1))
+        pts.append(q)
+        roff += H * W
+        doff += H * W
+        poff += q.shape[0]
+    ref = torch.cat(refs).to(device).contiguous()
+    defm = torch.cat(defs).to(device).contiguous()
+    pois = torch.cat(pts).to(device).contiguous()
+    return specs, ref, defm, pois
+
+
+def correlate_batch(pairs, precision: int = FP32_BATCHED, **kw) -> dict:
+    """Many independent pairs (mixed sizes and subset radii) in one plan."""
+    device = pairs[0][0].device
+    specs, ref, defm, pois = batch_layout(pairs, device)
+    plan = Plan(specs, precision, **kw)
+    out = plan.correlate(ref, defm, pois)
+    out.update(plan=plan, ref=ref, defm=defm, pois=pois)
+    return out
+
+
+def correlate_sequence(frames: Sequence, pois: torch.Tensor, M: int, S: int,
+                       precision: int = FP32_BATCHED, device=None, **kw) -> List[dict]:
+    """Every frame k >= 1 against frame 0; frame k is seeded by the last frame
+    whose status was OK (search centred on its rounded displacement, IC-GN
+    starting from its gradient terms).  Host frames are copied through pinned
+    memory on a side stream, one frame ahead of the compute."""
+    device = torch.device(device if device is not None else "cuda")
+    f0 = torch.as_tensor(frames[0]).to(device=device, dtype=torch.float32).contiguous()
+    H, W = f0.shape
+    N = pois.shape[0]
+    flags = kw.pop("flags", 0) | FLAG_CACHE_REF_PREP
+    plan = single_pair_plan(W, H, M, S, N, precision, flags=flags, **kw)
+    seed = torch.zeros((N, 2), dtype=torch.int32, device=device)
+    p_seed = torch.zeros((N, 6), dtype=torch.float64, device=device)
+    copy = torch.cuda.Stream(device=device)
+    bufs = [torch.empty_like(f0), torch.empty_like(f0)]
+    pinned = [torch.empty((H, W), dtype=torch.float32).pin_memory() for _ in range(2)]
+    ready = [torch.cuda.Event(), torch.cuda.Event()]
+    free = [torch.cuda.Event(), torch.cuda.Event()]
+
+    def stage(k: int) -> None:
+        slot = k % 2
+        src = frames[k]
+        if isinstance(src, torch.Tensor) and src.device.type == "cuda":
+            bufs[slot].copy_(src)
+            ready[slot].record()
+            return
+        pinned[slot].copy_(torch.as_tensor(src, dtype=torch.float32))
+        with torch.cuda.stream(copy):
+            copy.wait_event(free[slot])
+            bufs[slot].copy_(pinned[slot], non_blocking=True)
+            ready[slot].record(copy)
+
+    for e in free:
+        e.record()
+    results = []
+    if len(frames) > 1:
+        stage(1)
+    for k in range(1, len(frames)):
+        slot = k % 2
+        torch.cuda.current_stream().wait_event(ready[slot])
+        o = plan.correlate(f0, bufs[slot], pois, seed, p_seed)
+        plan.seed_update(o["p"], o["status"], seed, p_seed)
+        free[slot].record()
+        if k + 1 < len(frames):
+            free[(k + 1) % 2].synchronize()
+            stage(k + 1)
+        results.append({key: v.clone() for key, v in o.items()})
+    return results
+
+
+class ZNSSD(torch.autograd.Function):
+    """C[i] = sum over POI i's subset of (fhat - ghat)^2 as a differentiable
+    function of the warp parameters p [N, 6] (float64) and the deformed image
+    g (float32, the plan's deformed arena)."""
+
+    @staticmethod
+    def forward(ctx, p, g, plan: Plan, ref, pois):
+        c = torch.empty(plan.N, dtype=torch.float32, device=p.device)
+        plan.znssd(ref, g.detach().contiguous(), pois, p.detach().contiguous(), c_out=c)
+        ctx.plan = plan
+        ctx.save_for_backward(p, g, ref, pois)
+        return c
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        p, g, ref, pois = ctx.saved_tensors
+        plan = ctx.plan
+        gp = torch.zeros_like(p) if ctx.needs_input_grad[0] else None
+        gg = torch.zeros_like(g) if ctx.needs_input_grad[1] else None
+        plan.znssd(ref, g.detach().contiguous(), pois, p.detach().contiguous(),
+                   grad_c=grad_c.to(torch.float32).contiguous(), grad_p=gp, grad_def=gg)
+        return gp, gg, None, None, None

@@ -1,0 +1,112 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, and its host-only calls validate and lay out plans."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import dicgen
+import paper_1905_06228_amd as dic
+from paper_1905_06228_amd.dic import PairDesc, PlanDesc, Tuning
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dic.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    return dic.load_library()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dic_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported(L):
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(names) == sorted(dic.dic.EXPORTS)
+
+
+def make(L, pairs, precision=0, max_iters=20, tol=1e-3, flags=0):
+    arr = (PairDesc * max(1, len(pairs)))()
+    for k, q in enumerate(pairs):
+        arr[k] = PairDesc(*q)
+    d = PlanDesc(len(pairs), arr, precision, max_iters, tol, flags)
+    h = ctypes.c_void_p()
+    rc = L.dic_plan_create(ctypes.byref(d), ctypes.byref(h))
+    return rc, h
+
+
+def test_plan_create_and_workspace(L):
+    rc, h = make(L, [(256, 256, 10, 8, 0, 0, 0, 484)])
+    assert rc == 0 and h.value
+    nb = ctypes.c_size_t(0)
+    assert L.dic_plan_workspace_size(h, ctypes.byref(nb)) == 0
+    # gradients 2*H*W floats + 484 templates of 441 floats + 484 records, at least
+    assert nb.value >= 2 * 256 * 256 * 4 + 484 * 441 * 4 + 484 * 300
+    rc64, h64 = make(L, [(256, 256, 10, 8, 0, 0, 0, 484)], precision=1)
+    nb64 = ctypes.c_size_t(0)
+    L.dic_plan_workspace_size(h64, ctypes.byref(nb64))
+    assert nb64.value < nb.value      # the plain form keeps no gradients or templates
+    t = Tuning()
+    assert L.dic_plan_get_tuning(h, ctypes.byref(t)) == 0
+    assert (t.search_block, t.search_threads) == (8, 256)
+    bad = Tuning(5, 256, 4, 4)
+    assert L.dic_plan_set_tuning(h, ctypes.byref(bad)) == -1
+    good = Tuning(11, 512, 2, 6)
+    assert L.dic_plan_set_tuning(h, ctypes.byref(good)) == 0
+    L.dic_plan_destroy(h)
+    L.dic_plan_destroy(h64)
+
+
+@pytest.mark.parametrize("pairs,kw,why", [
+    ([(4, 256, 10, 8, 0, 0, 0, 1)], {}, "width"),
+    ([(256, 256, 21, 8, 0, 0, 0, 1)], {}, "subset_radius"),
+    ([(256, 256, 10, 33, 0, 0, 0, 1)], {}, "search_radius"),
+    ([(256, 256, 10, 8, -1, 0, 0, 1)], {}, "offset"),
+    ([(256, 256, 10, 8, 0, 0, 5, 1)], {}, "contiguous"),
+    ([(256, 256, 10, 8, 0, 0, 0, 3), (64, 64, 5, 4, 0, 0, 2, 3)], {}, "contiguous"),
+    ([(256, 256, 10, 8, 0, 0, 0, 1)], {"max_iters": 0}, "max_iters"),
+    ([(256, 256, 10, 8, 0, 0, 0, 1)], {"tol": 0.0}, "conv_tol"),
+    ([(256, 256, 10, 8, 0, 0, 0, 1)], {"precision": 7}, "precision"),
+    ([(256, 256, 10, 8, 0, 0, 0, 1)], {"flags": 64}, "flag"),
+    ([(20, 20, 9, 0, 0, 0, 0, 1)], {}, "fit"),
+])
+def test_plan_create_rejects(L, pairs, kw, why):
+    rc, h = make(L, pairs, **kw)
+    assert rc == -1 and not h.value
+    assert why in L.dic_last_error().decode()
+
+
+def test_null_arguments_and_unbound(L):
+    assert L.dic_plan_create(None, None) == -1
+    rc, h = make(L, [(64, 64, 5, 4, 0, 0, 0, 10)])
+    assert rc == 0
+    # device calls on an unbound plan fail on the host before touching a GPU
+    assert L.dic_integer_search(h, None, None, None, None, None, None, None, None) == -6
+    assert L.dic_plan_bind(h, None, 0, None) == -1
+    assert L.dic_plan_bind(h, ctypes.c_void_p(256 + 8), 1 << 30, None) == -1   # misaligned
+    assert L.dic_plan_bind(h, ctypes.c_void_p(4096), 16, None) == -2           # too small
+    L.dic_plan_destroy(h)
+    assert L.dic_status_string(-2).decode() == "workspace too small"
+
+
+def test_empty_plan_is_valid(L):
+    rc, h = make(L, [(64, 64, 5, 4, 0, 0, 0, 0)])
+    assert rc == 0
+    L.dic_plan_destroy(h)
+
+
+@pytest.mark.parametrize("W,H,M,S,step", [(256, 256, 10, 8, 10), (1024, 1024, 15, 16, 5),
+                                          (512, 512, 20, 8, 6), (4096, 3000, 14, 24, 7),
+                                          (100, 60, 7, 3, 9), (30, 30, 10, 8, 5)])
+def test_library_grid_matches_generator(W, H, M, S, step):
+    lib = dic.poi_grid(W, H, M, S, step).numpy()
+    np.testing.assert_array_equal(lib, dicgen.poi_grid(W, H, M, S, step))

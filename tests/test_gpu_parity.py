@@ -1,0 +1,222 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle on
+the same seeded inputs.  Integer displacements and statuses bit-exact,
+sub-pixel displacements within 1e-3 px, coefficients within 1e-5."""
+import numpy as np
+import pytest
+import torch
+
+import dicgen
+import paper_1905_06228_amd as dic
+from oracle import dic_oracle as O
+from tests._parity import compare, host, to_dev
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+PRECISIONS = [("fp32", dic.FP32_BATCHED), ("fp64", dic.FP64_PLAIN)]
+
+
+def run_pair(f, g, pois, M, S, precision, **kw):
+    plan = dic.single_pair_plan(f.shape[1], f.shape[0], M, S, pois.shape[0], precision, **kw)
+    F, G, Q = to_dev(f), to_dev(g), to_dev(pois)
+    out = plan.correlate(F, G, Q)
+    torch.cuda.synchronize()
+    return plan, host(out)
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def rigid():
+    pr = dicgen.rigid_pair_256()
+    ref = O.correlate(pr.ref, pr.defm, pr.pois, pr.M, pr.S)
+    return pr, ref
+
+
+@pytest.fixture(scope="module")
+def affine_small():
+    """The affine/noise workload at 256x256 (every 3rd POI: 481 POIs, a
+    ragged tail for every tile shape)."""
+    pr = dicgen.affine_pair_1024(size=256, tag=2)
+    pois = pr.pois[::3]
+    ref = O.correlate(pr.ref, pr.defm, pois, pr.M, pr.S)
+    return pr, pois, ref
+
+
+@pytest.mark.parametrize("name,prec", PRECISIONS)
+def test_rigid_256_full(rigid, name, prec):
+    pr, ref = rigid
+    print(f"case rigid_256 {name} N={len(pr.pois)}", flush=True)
+    _, got = run_pair(pr.ref, pr.defm, pr.pois, pr.M, pr.S, prec)
+    compare(got, ref, label=f"rigid_256/{name}")
+
+
+@pytest.mark.parametrize("name,prec", PRECISIONS)
+def test_affine_256_full(affine_small, name, prec):
+    pr, pois, ref = affine_small
+    print(f"case affine_256 {name} N={len(pois)}", flush=True)
+    _, got = run_pair(pr.ref, pr.defm, pois, pr.M, pr.S, prec)
+    compare(got, ref, label=f"affine_256/{name}")
+
+
+def test_affine_1024_sampled():
+    """Full 1024x1024 workload (36,864 POIs) in the benchmark's launch
+    configuration; 96 seeded POIs checked against the oracle one by one."""
+    pr = dicgen.affine_pair_1024()
+    print(f"case affine_1024 N={len(pr.pois)}", flush=True)
+    _, got = run_pair(pr.ref, pr.defm, pr.pois, pr.M, pr.S, dic.FP32_BATCHED)
+    idx = np.sort(np.random.default_rng(7).choice(len(pr.pois), 96, replace=False))
+    ref = O.correlate(pr.ref, pr.defm, pr.pois[idx], pr.M, pr.S)
+    compare(got, ref, idx=idx, label="affine_1024/fp32 sampled")
+    # properties that hold at every POI: statuses, coefficient range, truth
+    ok = got["status"] == O.OK
+    assert ok.mean() > 0.99
+    assert np.all(got["zncc"][ok] <= 1.0 + 1e-6) and np.all(got["zncc"][ok] > 0.9)
+    truth = dicgen.true_displacement(pr.field, pr.pois[ok].astype(np.float64))
+    assert np.abs(got["p"][ok][:, [0, 3]] - truth).mean() < 0.05
+
+
+def test_batch_mixed_subsets():
+    """Several pairs with every subset size of the batched workload in one
+    plan and one persistent launch."""
+    pairs = dicgen.sinusoidal_batch(n_pairs=6, size=112, S=8, step=9, first=100)
+    print("case batch subsets " + ",".join(str(p.M) for p in pairs), flush=True)
+    tens = [(to_dev(p.ref), to_dev(p.defm), to_dev(p.pois), p.M, p.S) for p in pairs]
+    for name, prec in PRECISIONS:
+        out = dic.correlate_batch(tens, prec)
+        torch.cuda.synchronize()
+        got = host({k: v for k, v in out.items() if k in ("uv", "zncc_int", "status_int", "p",
+                                                          "zncc", "iters", "status")})
+        off = 0
+        for p in pairs:
+            ref = O.correlate(p.ref, p.defm, p.pois, p.M, p.S)
+            sl = slice(off, off + len(p.pois))
+            compare({k: v[sl] for k, v in got.items()}, ref, label=f"batch M={p.M}/{name}")
+            off += len(p.pois)
+
+
+# ---------------------------------------------------------------------------
+# degenerate cases
+# ---------------------------------------------------------------------------
+
+def test_identical_images_and_integer_shift():
+    b = dicgen.make_blobs(dicgen.rng_for(77, 0, 0), 900, 160, 160)
+    big = dicgen.render_image(b, None, 160, 160)
+    f = np.ascontiguousarray(big[20:140, 20:140])
+    g = np.ascontiguousarray(big[20 + 2:140 + 2, 20 - 3:140 - 3])   # (du, dv) = (3, -2)
+    pois = dicgen.poi_grid(120, 120, 10, 6, 11)
+    for name, prec in PRECISIONS:
+        _, same = run_pair(f, f, pois, 10, 6, prec)
+        assert np.all(same["status"] == O.OK) and np.all(same["uv"] == 0)
+        np.testing.assert_array_equal(same["p"], 0.0)
+        np.testing.assert_allclose(same["zncc"], 1.0, atol=1e-6)
+        _, sh = run_pair(f, g, pois, 10, 6, prec)
+        assert np.all(sh["uv"] == [3, -2]) and np.all(sh["iters"] == 1)
+        np.testing.assert_array_equal(sh["p"], np.tile([3.0, 0, 0, -2.0, 0, 0], (len(pois), 1)))
+
+
+def test_status_codes_match_oracle():
+    rng = np.random.default_rng(5)
+    b = dicgen.make_blobs(dicgen.rng_for(78, 0, 0), 700, 128, 128)
+    f = dicgen.render_image(b, None, 128, 128)
+    g = dicgen.render_image(b, dicgen.rigid(0.4, 0.3), 128, 128)
+    f = f.copy()
+    f[40:62, 40:62] = 55.0                    # a flat reference patch
+    f[90, 95] = np.nan                       # NaN inside one reference subset
+    g = g.copy()
+    g[100, 30] = np.nan                      # NaN in the deformed image
+    x = np.arange(128, dtype=np.float32)
+    pois = np.array([[50, 50], [95, 90], [30, 100], [64, 64], [9, 64], [64, 118],
+                     [20, 20], [110, 110]], dtype=np.int32)
+    for name, prec in PRECISIONS:
+        for max_iters in (20, 1):
+            plan = dic.single_pair_plan(128, 128, 7, 6, len(pois), prec, max_iters=max_iters)
+            out = host(plan.correlate(to_dev(f), to_dev(g), to_dev(pois)))
+            ref = O.correlate(f, g, pois, 7, 6, max_iters=max_iters)
+            compare(out, ref, label=f"status/{name}/it{max_iters}")
+    # stripes along x only: singular Hessian, search still works
+    stripes = np.tile(60 + 30 * np.sin(x / 3.0) + 10 * np.cos(x / 1.7), (128, 1)).astype(np.float32)
+    for name, prec in PRECISIONS:
+        plan = dic.single_pair_plan(128, 128, 7, 4, 2, prec)
+        q = np.array([[60, 60], [70, 50]], dtype=np.int32)
+        out = host(plan.correlate(to_dev(stripes), to_dev(stripes), to_dev(q)))
+        ref = O.correlate(stripes, stripes, q, 7, 4)
+        assert np.all(ref["status"] == O.SINGULAR_HESSIAN)
+        compare(out, ref, label=f"stripes/{name}")
+
+
+def test_seeded_window_leaving_image():
+    b = dicgen.make_blobs(dicgen.rng_for(79, 0, 0), 700, 128, 128)
+    f = dicgen.render_image(b, None, 128, 128)
+    g = dicgen.render_image(b, dicgen.rigid(-1.3, 2.2), 128, 128)
+    pois = np.array([[30, 30], [64, 64], [100, 90]], dtype=np.int32)
+    seeds = np.array([[-40, 0], [1, 2], [30, 30]], dtype=np.int32)
+    for name, prec in PRECISIONS:
+        plan = dic.single_pair_plan(128, 128, 8, 5, 3, prec)
+        uv, zn, st = plan.integer_search(to_dev(f), to_dev(g), to_dev(pois), to_dev(seeds))
+        torch.cuda.synchronize()
+        for i in range(3):
+            r = O.integer_search(f, g, int(pois[i, 0]), int(pois[i, 1]), 8, 5,
+                                 int(seeds[i, 0]), int(seeds[i, 1]))
+            assert int(st[i]) == r.status, (name, i)
+            assert tuple(uv[i].tolist()) == (r.du, r.dv), (name, i)
+        assert int(st[0]) == O.NO_VALID_CANDIDATE
+
+
+def test_empty_plan():
+    plan = dic.single_pair_plan(64, 64, 5, 4, 0)
+    z = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+    img = torch.zeros((64, 64), dtype=torch.float32, device="cuda")
+    out = plan.correlate(img, img, z)
+    torch.cuda.synchronize()
+    assert out["p"].shape == (0, 6)
+
+
+# ---------------------------------------------------------------------------
+# determinism, tuning invariance, graph replay
+# ---------------------------------------------------------------------------
+
+def test_tuning_choices_bit_identical(affine_small):
+    pr, pois, _ = affine_small
+    F, G, Q = to_dev(pr.ref), to_dev(pr.defm), to_dev(pois)
+    plan = dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois))
+    base = host(plan.correlate(F, G, Q))
+    again = host(plan.correlate(F, G, Q))
+    for k in base:
+        np.testing.assert_array_equal(base[k], again[k], err_msg=k)
+    for tu in [(4, 128, 1, 2), (6, 512, 2, 4), (11, 256, 8, 6), (8, 1024, 4, 0)]:
+        plan.tuning = tu
+        o = host(plan.correlate(F, G, Q))
+        for k in base:
+            np.testing.assert_array_equal(base[k], o[k], err_msg=f"{k} {tu}")
+
+
+def test_graph_replay_matches_eager(affine_small):
+    pr, pois, _ = affine_small
+    F, G, Q = to_dev(pr.ref), to_dev(pr.defm), to_dev(pois)
+    eager = host(dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois)).correlate(F, G, Q))
+    plan = dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois), flags=dic.FLAG_USE_GRAPH)
+    out = plan.new_outputs()
+    for rep in range(4):
+        for v in out.values():
+            v.fill_(-7)
+        plan.correlate(F, G, Q, out=out)
+        torch.cuda.synchronize()
+        _ = (F * 2).sum().item()          # unrelated eager work between replays
+        got = host(out)
+        for k in eager:
+            np.testing.assert_array_equal(eager[k], got[k], err_msg=f"{k} replay {rep}")
+
+
+def test_autotune_keeps_results(affine_small):
+    pr, pois, _ = affine_small
+    F, G, Q = to_dev(pr.ref), to_dev(pr.defm), to_dev(pois)
+    plan = dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois))
+    base = host(plan.correlate(F, G, Q))
+    tu = plan.autotune(F, G, Q)
+    print(f"autotuned {tu}", flush=True)
+    o = host(plan.correlate(F, G, Q))
+    for k in base:
+        np.testing.assert_array_equal(base[k], o[k], err_msg=k)

@@ -513,3 +513,15 @@ def test_generator_deterministic_and_grid_counts():
     assert dicgen.poi_grid(1024, 1024, 15, 16, 5).shape == (36864, 2)
     assert dicgen.poi_grid(4096, 3000, 14, 24, 7).shape == (239932, 2)
     assert dicgen.gradient_grid_1024().shape == (16384, 2)
+
+
+def test_poi_border_rule(big_speckle):
+    f = big_speckle
+    fx, fy = O.central_gradients(f)
+    # the subset plus a one-pixel gradient border must fit: x0 - M >= 1, y0 + M <= H - 2
+    assert O.integer_search(f, f, 10, 50, 10, 3).status == O.OUT_OF_BOUNDS
+    assert O.integer_search(f, f, 10, 50, 9, 3).status == O.OK
+    assert O.reference_prep(f, fx, fy, 50, 130, 9).status == O.OUT_OF_BOUNDS
+    assert O.reference_prep(f, fx, fy, 50, 129, 9).status == O.OK
+    z = O.znssd(f, f, 20, 20, 8, [-11.5, 0, 0, 0, 0, 0])   # leftmost sample at x = 0.5
+    assert np.isnan(z.c) and np.all(z.grad_p == 0)
