@@ -1,0 +1,220 @@
+"""Benchmark of the subset-DIC hot path on one MI355X.
+
+A step correlates one 1024x1024 speckle pair from scratch with the images
+already in device memory: reference gradients and per-POI records, the
+brute-force ZNCC integer search and IC-GN refinement of all 36,864 POIs,
+replayed as one HIP graph.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "POIs/s to IC-GN convergence (FP32 batched vs FP64 plain) at ≤1e-3 px"
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2 (packed) x 2.4 GHz
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_PEAK_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_affine_1024.json")
+CSRC = os.path.join(ROOT, "paper_1905_06228_amd", "csrc")
+
+
+def kernel_source_hash(files=("k_search.hip", "dic_device.h", "dic_internal.h")) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; otherwise None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+        k = t["kernels"][kernel]
+        if k.get("source_hash") != kernel_source_hash(tuple(k.get("sources", []))):
+            return None
+        return float(k["bytes_per_launch"])
+    except (OSError, KeyError, ValueError, TypeError):
+        return None
+
+
+def time_launches(torch, fn, reps: int) -> float:
+    """Average ms of fn() over reps launches, HIP events on the current stream."""
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(pair, got, n_sample: int, seed: int = 11):
+    """The FP64 oracle, as it stands, on a seeded sample of POIs (one process);
+    also checks the GPU result on that sample."""
+    from oracle import dic_oracle as O
+
+    idx = np.sort(np.random.default_rng(seed).choice(len(pair.pois), n_sample, replace=False))
+    t0 = time.perf_counter()
+    ref = O.correlate(pair.ref, pair.defm, pair.pois[idx], pair.M, pair.S)
+    dt = time.perf_counter() - t0
+    ok = (ref["status"] == O.OK) & (got["status"][idx] == O.OK)
+    duv = np.abs(got["p"][idx][ok][:, [0, 3]] - ref["p"][ok][:, [0, 3]])
+    acc = dict(sample=int(n_sample),
+               integer_exact=bool(np.array_equal(got["uv"][idx], ref["uv"])),
+               status_equal=bool(np.array_equal(got["status"][idx], ref["status"])),
+               max_err_px=float(duv.max(initial=0.0)),
+               p99_err_px=float(np.percentile(duv.max(axis=1), 99)) if ok.any() else 0.0,
+               mean_err_px=float(duv.mean()) if ok.any() else 0.0,
+               max_dzncc=float(np.abs(got["zncc"][idx][ok] - ref["zncc"][ok]).max(initial=0.0)))
+    base = dict(value=n_sample / dt, unit="POIs/s", cores=1, kind="oracle",
+                sample=f"{n_sample} seeded POIs of the 36,864-POI grid, FP64 NumPy oracle, "
+                       f"one process, {dt:.1f} s",
+                seconds=dt)
+    return base, acc
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=400)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU: the hot path is a "
+                          "single-device build; --gpus must be 1"}))
+        return 2
+
+    import torch
+
+    import dicgen
+    import paper_1905_06228_amd as dic
+
+    dev = torch.device("cuda", 0)
+    pair = dicgen.affine_pair_1024()
+    N = len(pair.pois)
+    F = torch.from_numpy(pair.ref).to(dev)
+    G = torch.from_numpy(pair.defm).to(dev)
+    Q = torch.from_numpy(pair.pois).to(dev)
+    H, W = pair.ref.shape
+
+    # --- FP32 batched form, whole step as a graph ------------------------------
+    plan = dic.single_pair_plan(W, H, pair.M, pair.S, N, dic.FP32_BATCHED,
+                                flags=dic.FLAG_USE_GRAPH)
+    if not args.no_autotune:
+        plan.autotune(F, G, Q)
+    out = plan.new_outputs()
+    for _ in range(args.warmup):
+        plan.correlate(F, G, Q, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.correlate(F, G, Q, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+
+    # --- per-stage kernel times (HIP events on the launch stream) --------------
+    st = dic.single_pair_plan(W, H, pair.M, pair.S, N, dic.FP32_BATCHED,
+                              flags=dic.FLAG_CACHE_REF_PREP)
+    st.tuning = plan.tuning
+    so = st.new_outputs()
+    reps = max(5, args.steps // 2)
+    t_prep = time_launches(torch, lambda: st.prepare_reference(F, Q), reps)
+    t_search = time_launches(torch, lambda: st.integer_search(
+        F, G, Q, out=(so["uv"], so["zncc_int"], so["status_int"])), reps)
+    t_icgn = time_launches(torch, lambda: st.icgn_refine(
+        F, G, Q, so["uv"], so["status_int"],
+        out=(so["p"], so["zncc"], so["iters"], so["status"])), reps)
+    iters = got["iters"][got["status"] == 0]
+
+    # --- FP64 plain form ---------------------------------------------------------
+    p64 = dic.single_pair_plan(W, H, pair.M, pair.S, N, dic.FP64_PLAIN)
+    o64 = p64.new_outputs()
+    p64.correlate(F, G, Q, out=o64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.fp64_steps):
+        p64.correlate(F, G, Q, out=o64)
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3 / args.fp64_steps
+    g64 = {k: v.cpu().numpy() for k, v in o64.items()}
+    t64_search = time_launches(torch, lambda: p64.integer_search(
+        F, G, Q, out=(o64["uv"], o64["zncc_int"], o64["status_int"])), 1)
+    t64_icgn = time_launches(torch, lambda: p64.icgn_refine(
+        F, G, Q, o64["uv"], o64["status_int"],
+        out=(o64["p"], o64["zncc"], o64["iters"], o64["status"])), 2)
+    ok2 = (got["status"] == 0) & (g64["status"] == 0)
+    fp32_vs_fp64 = float(np.abs(got["p"][ok2][:, [0, 3]] - g64["p"][ok2][:, [0, 3]]).max(initial=0))
+
+    # --- roofline of the dominant kernel (the search) ---------------------------
+    n = (2 * pair.M + 1) ** 2
+    K = (2 * pair.S + 1) ** 2
+    flops = 2.0 * K * n * N                      # one FMA per candidate and subset pixel
+    achieved = flops / (t_search * 1e-3) / 1e12
+    traffic = measured_traffic("search_f32")
+    roofline = dict(bound="alu", achieved=round(achieved, 2), peak=FP32_VECTOR_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                    traffic=traffic, kernel="search_f32_kernel",
+                    kernel_ms=round(t_search, 4),
+                    algorithmic_flops_per_launch=flops,
+                    frac_of_nonpacked_fp32=round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 4))
+    A = (2 * pair.M + 4) ** 2
+    icgn_bytes = (12 * n + 4 * A + 70) * N
+    icgn_gbs = icgn_bytes / (t_icgn * 1e-3) / 1e9
+    roofline_icgn = dict(bound="hbm", achieved=round(icgn_gbs, 1), peak=HBM_PEAK_GBS,
+                         unit="GB/s", frac=round(icgn_gbs / HBM_PEAK_GBS, 4),
+                         traffic=measured_traffic("icgn_f32"), kernel="icgn_f32_kernel",
+                         kernel_ms=round(t_icgn, 4), algorithmic_bytes_per_launch=icgn_bytes,
+                         mean_iterations=float(iters.mean()) if iters.size else 0.0)
+
+    rec = {
+        "metric": METRIC, "value": round(N / (ms * 1e-3), 1), "unit": "POIs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "affine_1024: one 1024x1024 float32 speckle pair (16,000 "
+                               "Gaussian blobs), u = 0.005x + 1.3, v = -0.0015y - 0.6, noise "
+                               "sigma 2, subset 31x31, step 5, search +-16, 36,864 POIs, "
+                               "IC-GN stop |dp| < 1e-3 or 20 iterations",
+                   "form": "FP32 batched (compensated sums, FP64 solve), HIP graph",
+                   "tuning": list(plan.tuning)},
+        "roofline": roofline,
+        "roofline_icgn": roofline_icgn,
+        "stages_ms": {"reference_prep": round(t_prep, 4), "search": round(t_search, 4),
+                      "icgn": round(t_icgn, 4)},
+        "icgn_pois_per_s": round(N / (t_icgn * 1e-3), 1),
+        "fp64_plain": {"pois_per_s": round(N / (ms64 * 1e-3), 1), "ms_per_step": round(ms64, 3),
+                       "search_ms": round(t64_search, 3), "icgn_ms": round(t64_icgn, 3),
+                       "icgn_pois_per_s": round(N / (t64_icgn * 1e-3), 1)},
+        "fp32_over_fp64_plain": round(ms64 / ms, 2),
+        "icgn_fp32_over_fp64_plain": round(t64_icgn / t_icgn, 2),
+        "max_fp32_vs_fp64_plain_px": fp32_vs_fp64,
+    }
+    if not args.no_cpu_baseline:
+        base, acc = cpu_baseline(pair, got, args.cpu_sample)
+        rec["cpu_baseline"] = base
+        rec["accuracy_vs_oracle"] = acc
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
