@@ -115,8 +115,11 @@ typedef struct {
 /* Tile and schedule choices; dic_plan_autotune() fills them by measurement.
  * Every choice gives bit-identical results. */
 typedef struct {
-  int32_t search_block;    /* candidates per lane along du: 4, 6, 8 or 11     */
-  int32_t search_threads;  /* threads per search workgroup: 64..1024, /64     */
+  int32_t search_block;     /* candidates per lane along du: 4 or 8; a search
+                               workgroup has one lane per tile of the widest
+                               window, at most 1024                          */
+  int32_t search_occupancy; /* resident search workgroups per CU, 0 = as many
+                               as registers and LDS allow, else 1..16        */
   int32_t icgn_waves;      /* waves (POIs in flight) per IC-GN workgroup 1..8 */
   int32_t icgn_slack;      /* extra pixels around the staged deformed patch   */
 } dic_tuning_t;
@@ -170,8 +173,10 @@ dic_status_t dic_prepare_reference(dic_plan_t plan, const float* ref_images,
  * is seed_uv[i] (int32 [N,2], nullable = (0,0)); a candidate whose subset
  * leaves the image or is flat (sum (g - gbar)^2 <= 1e-6 sum g^2) is skipped.
  * The winner is the smallest (dv, du), row-major, among candidates within
- * 1e-12 of the maximum coefficient; the FP32 form scores in FP32 and
- * re-scores every candidate within 2e-5 of its maximum in FP64.
+ * 1e-12 of the maximum coefficient.  The FP32 form scores in FP32 (error
+ * ~1e-7); when two or more candidates lie within 2e-5 of its maximum they
+ * are re-scored two-pass in FP64 before the tie rule, otherwise the single
+ * one is the FP64 winner and its FP32 coefficient is reported.
  * Outputs (device, length N): uv_out int32 [N,2] integer displacement,
  * zncc_out float [N] its coefficient, status_out int32 [N] DIC_POI_* (OK,
  * ZERO_VARIANCE, NO_VALID_CANDIDATE or NAN_INPUT; uv = (0,0) unless OK). */

@@ -42,13 +42,13 @@ struct Layout {
   int64_t fix_count = 0;
 };
 
-const dic_tuning_t kDefaultTuning = {8, 256, 4, 4};
+const dic_tuning_t kDefaultTuning = {8, 0, 4, 4};  // block, occupancy, waves, slack
 
 bool tuning_valid(const dic_tuning_t& t) {
-  const bool blk = t.search_block == 4 || t.search_block == 6 || t.search_block == 8 ||
-                   t.search_block == 11;
-  return blk && t.search_threads >= 64 && t.search_threads <= 1024 && t.search_threads % 64 == 0 &&
-         t.icgn_waves >= 1 && t.icgn_waves <= 8 && t.icgn_slack >= 0 && t.icgn_slack <= 16;
+  const bool blk = t.search_block == 4 || t.search_block == 8;
+  const bool thr = t.search_occupancy >= 0 && t.search_occupancy <= 16;
+  return blk && thr && t.icgn_waves >= 1 && t.icgn_waves <= 8 && t.icgn_slack >= 0 &&
+         t.icgn_slack <= 16;
 }
 
 }  // namespace
@@ -58,6 +58,7 @@ struct dic_plan_s {
   std::vector<dic_pair_desc_t> pairs;
   std::vector<DevPair> dpairs;
   std::vector<int32_t> poi_pair, work;
+  std::vector<std::pair<int, int64_t>> m_runs;  // (M, length) runs of the work list
   std::vector<int64_t> fix_off;
   int64_t N = 0;
   int maxM = 0, maxS = 0, maxW = 0, maxH = 0;
@@ -81,8 +82,8 @@ struct dic_plan_s {
 namespace {
 
 void drop_graphs(dic_plan_s* p) {
-  for (auto& kv : p->graphs) hipGraphExecDestroy(kv.second);
-  for (auto g : p->graph_objs) hipGraphDestroy(g);
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto g : p->graph_objs) (void)hipGraphDestroy(g);
   p->graphs.clear();
   p->graph_objs.clear();
 }
@@ -161,12 +162,27 @@ dic_status_t prepare(dic_plan_t p, const float* ref, const int32_t* poi, hipStre
   return DIC_SUCCESS;
 }
 
+// Runs of the work list that share the search kernel's template row length.
+std::vector<SearchGroup> search_groups(const dic_plan_s* p, int block) {
+  std::vector<SearchGroup> g;
+  int64_t at = 0;
+  for (auto& run : p->m_runs) {
+    const int np = search_np(run.first, block);
+    if (g.empty() || g.back().np != np) g.push_back({np, at, 0});
+    g.back().count += run.second;
+    at += run.second;
+  }
+  return g;
+}
+
 dic_status_t enqueue_search(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
                             const int32_t* seed, int32_t* uv, float* zn, int32_t* status,
                             hipStream_t s) {
   if (p->fp32()) {
+    const std::vector<SearchGroup> groups = search_groups(p, p->tuning.search_block);
     DIC_HIP(launch_reset_counters(p->st, s));
-    DIC_HIP(launch_search_f32(p->st, p->tuning, ref, def, poi, seed, uv, zn, status, p->num_cu, s));
+    DIC_HIP(launch_search_f32(p->st, p->tuning, groups.data(), (int)groups.size(), ref, def, poi,
+                              seed, uv, zn, status, p->num_cu, s));
   } else {
     DIC_HIP(launch_search_f64(p->st, p->dpairs.data(), ref, def, poi, seed, uv, zn, status, s));
   }
@@ -298,10 +314,12 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
     P.poi_count = q.poi_count;
     P.grad_off = gfl;
     P.tmpl_off = tfl;
-    const int64_t n = (int64_t)(2 * q.subset_radius + 1) * (2 * q.subset_radius + 1);
+    P.tmpl_pitch = template_pitch(q.subset_radius);
+    P.pad_ = 0;
+    const int64_t tn = (int64_t)(2 * q.subset_radius + 1) * P.tmpl_pitch;
     if (f32) {
       gfl += 2 * (int64_t)q.width * q.height;
-      tfl += q.poi_count * n;
+      tfl += q.poi_count * tn;
     }
     p->fix_off[k] = fix;
     if (p->det()) fix += (int64_t)q.width * q.height;
@@ -329,7 +347,13 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
   std::stable_sort(p->work.begin(), p->work.end(), [&](int32_t a, int32_t b) {
     return p->pairs[p->poi_pair[a]].subset_radius > p->pairs[p->poi_pair[b]].subset_radius;
   });
-  if (f32 && search_lds_bytes(p->maxM, p->maxS, p->tuning.search_block) > 160 * 1024) {
+  for (int64_t i = 0; i < p->N; ++i) {
+    const int m = p->pairs[p->poi_pair[p->work[i]]].subset_radius;
+    if (p->m_runs.empty() || p->m_runs.back().first != m) p->m_runs.emplace_back(m, 0);
+    ++p->m_runs.back().second;
+  }
+  if (f32 && (search_lds_bytes(p->maxM, p->maxS, p->tuning.search_block) > 160 * 1024 ||
+              search_threads(p->maxS, p->tuning.search_block) > search_max_threads())) {
     delete p;
     return fail(DIC_ERR_UNSUPPORTED, "search window exceeds the 160 KiB LDS of a CU");
   }
@@ -340,7 +364,7 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
 void dic_plan_destroy(dic_plan_t p) {
   if (!p) return;
   drop_graphs(p);
-  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   delete p;
 }
 
@@ -364,8 +388,9 @@ dic_status_t dic_plan_set_tuning(dic_plan_t p, const dic_tuning_t* in) {
   dic_status_t r = check_plan(p, false);
   if (r) return r;
   if (!in || !tuning_valid(*in)) return fail(DIC_ERR_INVALID_ARGUMENT, "invalid tuning");
-  if (p->fp32() && search_lds_bytes(p->maxM, p->maxS, in->search_block) > 160 * 1024)
-    return fail(DIC_ERR_UNSUPPORTED, "search tile exceeds LDS");
+  if (p->fp32() && (search_lds_bytes(p->maxM, p->maxS, in->search_block) > 160 * 1024 ||
+                    search_threads(p->maxS, in->search_block) > search_max_threads()))
+    return fail(DIC_ERR_UNSUPPORTED, "search tile exceeds LDS or the widest workgroup");
   p->tuning = *in;
   drop_graphs(p);
   return DIC_SUCCESS;
@@ -498,14 +523,14 @@ dic_status_t dic_correlate(dic_plan_t p, const float* ref, const float* def, con
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
     if (r) {
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);
       return r;
     }
     if (e != hipSuccess) return fail(DIC_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-      hipGraphDestroy(graph);
+      (void)hipGraphDestroy(graph);
       return fail(DIC_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
     }
     p->graph_objs.push_back(graph);
@@ -594,29 +619,30 @@ dic_status_t dic_plan_autotune(dic_plan_t p, const float* ref, const float* def,
     return DIC_SUCCESS;
   };
   float best_ms = 1e30f;
-  const int blocks[] = {4, 6, 8, 11};
-  const int threads[] = {128, 256, 512};
+  const int blocks[] = {4, 8};
+  const int occs[] = {0, 2, 3};
   for (int b : blocks)
-    for (int t : threads) {
+    for (int o : occs) {
       dic_tuning_t c = best;
       c.search_block = b;
-      c.search_threads = t;
+      c.search_occupancy = o;
       if (search_lds_bytes(p->maxM, p->maxS, b) > 160 * 1024) continue;
+      if (search_threads(p->maxS, b) > search_max_threads()) continue;
       p->tuning = c;
       float ms = 0.f;
       r = time_it([&] { return enqueue_search(p, ref, def, poi, nullptr, uv, fs, is, s); }, &ms);
       if (r) continue;
       if (ms < best_ms) {
         best_ms = ms;
-        best.search_block = b;
-        best.search_threads = t;
+        best.search_block = c.search_block;
+        best.search_occupancy = c.search_occupancy;
       }
     }
   p->tuning = best;
   r = enqueue_search(p, ref, def, poi, nullptr, uv, fs, is, s);
   if (r) {
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     p->tuning = saved;
     return r;
   }
@@ -640,14 +666,14 @@ dic_status_t dic_plan_autotune(dic_plan_t p, const float* ref, const float* def,
         best.icgn_slack = sl;
       }
     }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   p->tuning = best;
   drop_graphs(p);
   g_last_error.clear();
   if (const char* path = std::getenv("DIC_AUTOTUNE_CACHE")) {
     auto m = read_tune_cache(path);
-    m[tune_key(p)] = {best.search_block, best.search_threads, best.icgn_waves, best.icgn_slack};
+    m[tune_key(p)] = {best.search_block, best.search_occupancy, best.icgn_waves, best.icgn_slack};
     write_tune_cache(path, m);
   }
   return DIC_SUCCESS;

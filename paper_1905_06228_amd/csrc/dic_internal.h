@@ -18,8 +18,13 @@ struct DevPair {
   int64_t ref_off, def_off;
   int64_t poi_off, poi_count;
   int64_t grad_off;  // float offset of this pair's [2, H, W] gradient block
-  int64_t tmpl_off;  // float offset of this pair's templates, n floats per POI
+  int64_t tmpl_off;  // float offset of this pair's templates
+  int32_t tmpl_pitch;  // template row pitch: 2M+1 rounded up to a multiple of 8,
+                       // zero-filled beyond the subset, (2M+1) rows per POI
+  int32_t pad_;
 };
+
+__host__ __device__ __forceinline__ int template_pitch(int M) { return (2 * M + 1 + 7) / 8 * 8; }
 
 // Per-POI reference-side record.  Everything the search and IC-GN need from
 // the reference subset, computed once.
@@ -51,7 +56,15 @@ struct DevState {
   double conv_tol;
 };
 
-enum Counter { kCtrSearch = 0, kCtrIcgn = 1, kCtrZnssd = 2, kNumCounters = 8 };
+// Persistent-launch work counters: one per search group, then IC-GN.
+enum Counter { kCtrSearch = 0, kMaxSearchGroups = 16, kCtrIcgn = 16, kNumCounters = 32 };
+
+// A run of the work list whose subsets share the search kernel's template
+// row length NP (the work list is ordered by decreasing subset size).
+struct SearchGroup {
+  int np;
+  int64_t begin, count;
+};
 
 // Kernel launchers (defined in the .hip files).  All asynchronous on `s`.
 hipError_t launch_reset_counters(const DevState& st, hipStream_t s);
@@ -60,10 +73,15 @@ hipError_t launch_ref_prep_f32(const DevState& st, const float* ref, const int32
                                hipStream_t s);
 hipError_t launch_ref_prep_f64(const DevState& st, const DevPair* host_pairs,
                                const float* ref, const int32_t* poi, hipStream_t s);
-hipError_t launch_search_f32(const DevState& st, const dic_tuning_t& tu, const float* ref,
+hipError_t launch_search_f32(const DevState& st, const dic_tuning_t& tu,
+                             const SearchGroup* groups, int ngroups, const float* ref,
                              const float* def, const int32_t* poi, const int32_t* seed,
                              int32_t* uv, float* zncc, int32_t* status, int num_cu,
                              hipStream_t s);
+// Template row length the search kernel with tile width `block` uses.
+__host__ __device__ __forceinline__ int search_np(int M, int block) {
+  return (2 * M + 1 + block - 1) / block * block;
+}
 hipError_t launch_search_f64(const DevState& st, const DevPair* host_pairs, const float* ref,
                              const float* def, const int32_t* poi, const int32_t* seed,
                              int32_t* uv, float* zncc, int32_t* status, hipStream_t s);
@@ -86,6 +104,10 @@ hipError_t launch_seed_update(int64_t N, const double* p, const int32_t* status,
 
 // Search LDS bytes per workgroup for the given radii and tile.
 size_t search_lds_bytes(int maxM, int maxS, int block);
+// Threads per search workgroup (one lane per candidate tile of the widest window).
+int search_threads(int maxS, int block);
+// Largest search workgroup the kernels are compiled for.
+int search_max_threads();
 // IC-GN LDS bytes per workgroup.
 size_t icgn_lds_bytes(int maxM, int slack, int waves);
 

@@ -133,8 +133,8 @@ __device__ __forceinline__ void iter_pass(const float* src, int pitch, int ox, i
 template <int MAXS, bool kClamp>
 __device__ __forceinline__ void final_pass(const float* src, int pitch, int ox, int oy, int maxc,
                                            int maxr, int n, const Warp32& w, float c0,
-                                           const int* dxy, const float* __restrict__ tm,
-                                           Kahan* K) {
+                                           const int* dxy, const float* __restrict__ tm, int tp,
+                                           int M, Kahan* K) {
   const int lane = lane_id();
 #pragma unroll
   for (int k = 0; k < MAXS; ++k) {
@@ -146,7 +146,7 @@ __device__ __forceinline__ void final_pass(const float* src, int pitch, int ox, 
           c0;
       K[0].add(gs);
       K[1].add(gs * gs);
-      K[2].add(tm[s] * gs);
+      K[2].add(tm[((int)dy + M) * tp + (int)dx + M] * gs);
     }
   }
 }
@@ -292,13 +292,14 @@ __global__ void __launch_bounds__(512) icgn_f32_kernel(
         if (xl < 0 || xh > W - 1 || yl < 0 || yh > H - 1) {
           status = DIC_POI_OUT_OF_BOUNDS;
         } else {
-          const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * n;
+          const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * P.tmpl_pitch;
           Kahan K[3];
           if (patch.ensure(gimg, W, H, xl, xh, yl, yh))
             final_pass<MAXS, false>(patch.buf, pside, w.bx - patch.x0, w.by - patch.y0, 0, 0, n, w,
-                                    c0, dxy, tm, K);
+                                    c0, dxy, tm, P.tmpl_pitch, M, K);
           else
-            final_pass<MAXS, true>(gimg, W, w.bx, w.by, W - 4, H - 4, n, w, c0, dxy, tm, K);
+            final_pass<MAXS, true>(gimg, W, w.bx, w.by, W - 4, H - 4, n, w, c0, dxy, tm,
+                                   P.tmpl_pitch, M, K);
           const double s0 = wave_sum(K[0].value());
           const double s1 = wave_sum(K[1].value());
           const double s2 = wave_sum(K[2].value());

@@ -71,7 +71,12 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
   const float* f = ref + P.ref_off;
   const float* gxi = st.grads + P.grad_off;
   const float* gyi = gxi + (int64_t)P.width * P.height;
-  float* tmpl = st.tmpl + P.tmpl_off + (g - P.poi_off) * (int64_t)n;
+  const int tp = P.tmpl_pitch;
+  float* tmpl = st.tmpl + P.tmpl_off + (g - P.poi_off) * (int64_t)(n1 * tp);
+  for (int k = lane; k < n1 * (tp - n1); k += kWave) {
+    const int r = k / (tp - n1);
+    tmpl[r * tp + n1 + (k - r * (tp - n1))] = 0.f;   // zero padding of every row
+  }
 
   double s1 = 0.0;
   int bad = 0;
@@ -100,7 +105,7 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
     q += d * d;
     sq += (double)v * (double)v;
     const float t = v - fbar_f;
-    tmpl[k] = t;
+    tmpl[r * tp + c] = t;
     ts += (double)t;
     const float fx = gxi[idx], fy = gyi[idx];
     const float dx = (float)(c - M), dy = (float)(r - M);

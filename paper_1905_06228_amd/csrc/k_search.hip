@@ -18,10 +18,16 @@ namespace dic {
 
 namespace {
 
+constexpr int kNearCap = 64;   // near-tie list capacity per POI (a sweep path covers more)
+constexpr int kSeg = 8;        // rows/columns per running box-sum segment
+constexpr int kSearchMaxThreads = 640;  // lanes of the widest search workgroup
+
 struct SearchGeom {
-  int M, S, n1, n, side, L, NB, n1p, Wn, P;
+  int M, S, n1, n, side, L, NB, NP, Wn, P;
 };
 
+// NP: template row length the cross-term loop runs over (2M+1 rounded up to
+// a multiple of L; the stored template is zero beyond 2M+1).
 __host__ __device__ __forceinline__ SearchGeom search_geom(int M, int S, int L) {
   SearchGeom G;
   G.M = M;
@@ -31,48 +37,58 @@ __host__ __device__ __forceinline__ SearchGeom search_geom(int M, int S, int L) 
   G.side = 2 * S + 1;
   G.L = L;
   G.NB = (G.side + L - 1) / L;
-  G.n1p = (G.n1 + L - 1) / L * L;
+  G.NP = (G.n1 + L - 1) / L * L;
   G.Wn = G.side + G.n1 - 1;
-  const int pc = G.NB * L + G.n1p - 1;
+  const int pc = G.NB * L + G.NP + L - 2;  // columns the cross-term loop touches
   G.P = pc | 1;
   return G;
 }
 
+// Window, column sums of g and g^2; the scores reuse the column sums of g^2
+// once every lane holds its box sums in registers.
 __host__ __device__ __forceinline__ size_t search_lds_floats(const SearchGeom& G) {
-  return (size_t)G.Wn * G.P + 2 * (size_t)G.side * G.Wn + 3 * (size_t)G.side * G.side;
+  return (size_t)G.Wn * G.P + 2 * (size_t)G.side * G.Wn;
 }
 
-}  // namespace
-
-size_t search_lds_bytes(int maxM, int maxS, int block) {
-  // The layout depends on M and S jointly; take the largest over the plan's
-  // range (monotone in both).
-  return search_lds_floats(search_geom(maxM, maxS, block)) * sizeof(float) + 64;
+__host__ __device__ __forceinline__ int search_items(int S, int L) {
+  const int side = 2 * S + 1;
+  return side * ((side + L - 1) / L);
 }
 
-// FP64 two-pass coefficient of one candidate, computed by a whole wave
-// exactly as Eq. (1) defines it.
+// Sum over one workgroup; every thread returns the same value.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int nw = blockDim.x / kWave, wid = threadIdx.x / kWave;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane_id() == 0) red[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < nw; ++k) t += red[k];
+  return t;
+}
+
+// FP64 two-pass coefficient of one candidate (Eq. (1) as written), computed
+// by the whole workgroup from the images in global memory.
 __device__ double rescore_f64(const float* __restrict__ f, const float* __restrict__ gimg, int W,
                               int x0, int y0, int xg, int yg, int M, double fbar, double df,
-                              bool* valid) {
-  const int lane = lane_id(), n1 = 2 * M + 1, n = n1 * n1;
-  double sg = 0.0;
-  int bad = 0;
-  for (int k = lane; k < n; k += kWave) {
+                              double* red, bool* valid) {
+  const int tid = threadIdx.x, nthr = blockDim.x, n1 = 2 * M + 1, n = n1 * n1;
+  double sg = 0.0, bad = 0.0;
+  for (int k = tid; k < n; k += nthr) {
     const int r = k / n1, c = k - r * n1;
     const float v = gimg[(int64_t)(yg - M + r) * W + (xg - M + c)];
-    bad |= !isfinite(v);
-    sg += (double)v;
+    if (!isfinite(v)) bad = 1.0;
+    else sg += (double)v;
   }
-  sg = wave_sum(sg);
-  bad = wave_or_int(bad);
-  if (bad) {
+  sg = block_sum(sg, red);
+  bad = block_sum(bad, red);
+  if (bad != 0.0) {
     *valid = false;
     return 0.0;
   }
   const double gbar = sg / (double)n;
   double num = 0.0, q = 0.0, sq = 0.0;
-  for (int k = lane; k < n; k += kWave) {
+  for (int k = tid; k < n; k += nthr) {
     const int r = k / n1, c = k - r * n1;
     const double gv = (double)gimg[(int64_t)(yg - M + r) * W + (xg - M + c)];
     const double fv = (double)f[(int64_t)(y0 - M + r) * W + (x0 - M + c)];
@@ -81,50 +97,137 @@ __device__ double rescore_f64(const float* __restrict__ f, const float* __restri
     q += d * d;
     sq += gv * gv;
   }
-  num = wave_sum(num);
-  q = wave_sum(q);
-  sq = wave_sum(sq);
+  num = block_sum(num, red);
+  q = block_sum(q, red);
+  sq = block_sum(sq, red);
   *valid = not_flat(q, sq);
   return num / (df * sqrt(q));
 }
 
-template <int L>
-__global__ void __launch_bounds__(1024) search_f32_kernel(
-    DevState st, const float* __restrict__ ref, const float* __restrict__ def,
-    const int32_t* __restrict__ poi, const int32_t* __restrict__ seed,
-    int32_t* __restrict__ uv_out, float* __restrict__ zncc_out, int32_t* __restrict__ status_out) {
+// Cross terms sum_i t_i g_i of L horizontally adjacent candidates.  Every
+// template row is fully unrolled: its NP values are wave-uniform (scalar
+// loads into SGPRs) and the NP + L - 1 window values it needs are read from
+// LDS once, so each LDS value feeds up to L FMAs.  Row partial sums (FP32,
+// at most 48 terms) are accumulated in FP64, which on this GPU costs no more
+// than an FP32 add.  The order of every candidate's sum (row by row, left to
+// right, trailing zero-template terms adding exactly 0) does not depend on L.
+template <int N>
+__device__ __forceinline__ void load_vals(const float* __restrict__ src, float* dst) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) dst[j] = src[j];
+}
+
+// part[k] += sum_{j < N} t[j] * g[j + k] for the L candidates of a lane.
+template <int L, int N>
+__device__ __forceinline__ void fma_block(const float* t, const float* g, float* part) {
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int k = 0; k < L; ++k) part[k] = fmaf(t[j], g[j + k], part[k]);
+}
+
+// One template row against the window row in g, with the next row's loads
+// interleaved: the second half of this row's template and, once the first
+// half has been used, the first half of the next row's template (SGPRs) and
+// the next window row (the other VGPR buffer) are requested before the FMAs
+// that do not need them.
+template <int L, int NP>
+__device__ __forceinline__ void row_pipelined(const float* __restrict__ trow,
+                                              const float* __restrict__ tnext,
+                                              const float* gnext_src, float* th0, float* th1,
+                                              const float* g, float* gnext, double* tot) {
+  constexpr int NH = NP / 2;
+  load_vals<NH>(trow + NH, th1);
+  float part[L];
+#pragma unroll
+  for (int k = 0; k < L; ++k) part[k] = 0.f;
+  fma_block<L, NH>(th0, g, part);
+  load_vals<NH>(tnext, th0);
+  load_vals<NP + L - 1>(gnext_src, gnext);
+  fma_block<L, NH>(th1, g + NH, part);
+#pragma unroll
+  for (int k = 0; k < L; ++k) tot[k] += (double)part[k];
+}
+
+// Cross terms sum_i t_i g_i of L horizontally adjacent candidates.  Every
+// template row is fully unrolled: its NP values are wave-uniform (scalar
+// loads into SGPRs) and the NP + L - 1 window values it needs are read from
+// LDS once, so each LDS value feeds up to L FMAs.  Loads of the next row are
+// issued ahead of the FMAs of the current one (see row_pipelined) so their
+// latency hides behind them.  Row partial sums (FP32, at most 48 terms)
+// accumulate in FP64, which on this GPU costs no more than an FP32 add.  The
+// order of every candidate's sum (row by row, left to right, trailing
+// zero-template terms adding exactly 0) does not depend on L.
+template <int L, int NP>
+__device__ __forceinline__ void cross_terms(const float* __restrict__ tm, int tp, int n1,
+                                            const float* wrow, int P, double* tot) {
+  constexpr int NH = NP / 2;
+#pragma unroll
+  for (int k = 0; k < L; ++k) tot[k] = 0.0;
+  float th0[NH], th1[NH], ga[NP + L - 1], gb[NP + L - 1];
+  load_vals<NH>(tm, th0);
+  load_vals<NP + L - 1>(wrow, ga);
+  for (int i = 0; i < n1; i += 2) {
+    // rows past the last are clamped to it: loaded, never used
+    const int i1 = min(i + 1, n1 - 1), i2 = min(i + 2, n1 - 1);
+    row_pipelined<L, NP>(tm + i * tp, tm + i1 * tp, wrow + i1 * P, th0, th1, ga, gb, tot);
+    if (i + 1 >= n1) break;
+    row_pipelined<L, NP>(tm + i1 * tp, tm + i2 * tp, wrow + i2 * P, th0, th1, gb, ga, tot);
+  }
+}
+
+}  // namespace
+
+size_t search_lds_bytes(int maxM, int maxS, int block) {
+  // The layout grows with M and S; the plan's maxima bound every pair.
+  return search_lds_floats(search_geom(maxM, maxS, block)) * sizeof(float) +
+         kNearCap * (sizeof(int) + sizeof(double)) + 64;
+}
+
+int search_threads(int maxS, int block) {
+  const int items = search_items(maxS, block);
+  return (items + kWave - 1) / kWave * kWave;  // one lane per candidate tile
+}
+
+int search_max_threads() { return kSearchMaxThreads; }
+
+template <int L, int NP>
+__global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
+    DevState st, const int32_t* __restrict__ work, int64_t count, int ctr,
+    const float* __restrict__ tmpl_arena, const float* __restrict__ ref,
+    const float* __restrict__ def, const int32_t* __restrict__ poi,
+    const int32_t* __restrict__ seed, int32_t* __restrict__ uv_out, float* __restrict__ zncc_out,
+    int32_t* __restrict__ status_out) {
   extern __shared__ float lds[];
   __shared__ int s_item;
   __shared__ float s_wmax[16];
-  __shared__ int s_pick[2];
-  __shared__ float s_zncc;
+  __shared__ double s_red[16];
+  __shared__ int s_cnt;
   const int tid = threadIdx.x, nthr = blockDim.x, lane = lane_id(), wid = tid / kWave;
   const float kNegInf = -INFINITY;
 
   for (;;) {
-    if (tid == 0) s_item = atomicAdd(&st.counters[kCtrSearch], 1);
+    if (tid == 0) s_item = atomicAdd(&st.counters[ctr], 1);
     __syncthreads();
     const int item = uniform(s_item);
-    if (item >= st.N) break;
-    const int g = uniform(st.work[item]);
+    if (item >= count) break;
+    const int g = uniform(work[item]);
     const DevPair P = st.pairs[uniform(st.poi_pair[g])];
     const RefRec* R = st.recs + g;
     const int x0 = uniform(poi[2 * g]), y0 = uniform(poi[2 * g + 1]);
     const int cu = seed ? uniform(seed[2 * g]) : 0;
     const int cv = seed ? uniform(seed[2 * g + 1]) : 0;
     const int rstat = uniform(R->status);
-    if (rstat != DIC_POI_OK) {
+    // A singular Hessian does not stop the search; every other record status does.
+    if (rstat != DIC_POI_OK && rstat != DIC_POI_SINGULAR_HESSIAN) {
       if (tid == 0) {
         uv_out[2 * g] = 0;
         uv_out[2 * g + 1] = 0;
         zncc_out[g] = nanf("");
-        status_out[g] = rstat == DIC_POI_SINGULAR_HESSIAN ? DIC_POI_OK : rstat;
+        status_out[g] = rstat;
       }
-      // A singular Hessian does not stop the search; fall through below.
-      if (rstat != DIC_POI_SINGULAR_HESSIAN) {
-        __syncthreads();
-        continue;
-      }
+      __syncthreads();
+      continue;
     }
     const SearchGeom G = search_geom(P.M, P.S, L);
     const int W = P.width, H = P.height;
@@ -135,143 +238,141 @@ __global__ void __launch_bounds__(1024) search_f32_kernel(
     float* win = lds;
     float* colS = win + G.Wn * G.P;
     float* colQ = colS + G.side * G.Wn;
-    float* boxS = colQ + G.side * G.Wn;
-    float* boxQ = boxS + G.side * G.side;
-    float* scores = boxQ + G.side * G.side;
+    float* scores = colQ;  // reused once the box sums are in registers
+    int* near_idx = reinterpret_cast<int*>(colQ + G.side * G.Wn);
+    double* near_val = reinterpret_cast<double*>(
+        (reinterpret_cast<uintptr_t>(near_idx + kNearCap) + 7) & ~uintptr_t(7));
+    const int items = G.side * G.NB;
+    const bool mine = tid < items;   // one candidate tile per lane
+    const int r = mine ? tid % G.side : 0, b = mine ? tid / G.side : 0;
 
-    // 1. stage the window; non-finite pixels become 0 and are counted.
+    // 1. stage the window (shifted by the subset mean); non-finite pixels
+    //    become 0 and are counted.  Thread t walks rows t / P0 + k * (nthr / P0)
+    //    of columns t % P0 with P0 = min(P, nthr), no per-element division.
     int nonfinite = 0;
-    for (int idx = tid; idx < G.Wn * G.P; idx += nthr) {
-      const int r = idx / G.P, c = idx - r * G.P;
-      const int X = wx0 + c, Y = wy0 + r;
-      float v = 0.f;
-      if (c < G.Wn && X >= 0 && X < W && Y >= 0 && Y < H) {
-        v = gimg[(int64_t)Y * W + X];
-        if (!isfinite(v)) {
-          nonfinite = 1;
-          v = 0.f;
-        } else {
-          v -= c0;
+    {
+      const int P0 = G.P < nthr ? G.P : nthr;
+      const int rstep = nthr / P0;
+      const int c1 = tid % P0;
+      for (int rr = tid / P0; rr < G.Wn && tid < rstep * P0; rr += rstep) {
+        const int Y = wy0 + rr;
+        const bool rowin = Y >= 0 && Y < H;
+        const float* grow = gimg + (int64_t)Y * W;
+        for (int c = c1; c < G.P; c += P0) {
+          const int X = wx0 + c;
+          float v = 0.f;
+          if (c < G.Wn && rowin && X >= 0 && X < W) {
+            v = grow[X];
+            if (!isfinite(v)) {
+              nonfinite = 1;
+              v = 0.f;
+            } else {
+              v -= c0;
+            }
+          }
+          win[rr * G.P + c] = v;
         }
       }
-      win[idx] = v;
     }
     const int has_bad = __syncthreads_or(nonfinite);
 
-    int* boxN = reinterpret_cast<int*>(scores);
+    // Rare path: exact integer counts of non-finite pixels per candidate,
+    // kept as a bit mask of the lane's tile.
+    unsigned badmask = 0;
     if (has_bad) {
-      // Exact integer box counts of non-finite pixels (rare path).
       int* colN = reinterpret_cast<int*>(colS);
       for (int c = tid; c < G.Wn; c += nthr) {
         int cnt = 0;
-        for (int r = 0; r < G.Wn; ++r) {
-          const int X = wx0 + c, Y = wy0 + r;
-          int b = 0;
-          if (X >= 0 && X < W && Y >= 0 && Y < H) b = !isfinite(gimg[(int64_t)Y * W + X]);
-          cnt += b;
-          if (r >= G.n1) {
-            const int Xo = X, Yo = wy0 + r - G.n1;
-            if (Xo >= 0 && Xo < W && Yo >= 0 && Yo < H) cnt -= !isfinite(gimg[(int64_t)Yo * W + Xo]);
+        for (int rr = 0; rr < G.Wn; ++rr) {
+          const int X = wx0 + c, Y = wy0 + rr;
+          if (X >= 0 && X < W && Y >= 0 && Y < H) cnt += !isfinite(gimg[(int64_t)Y * W + X]);
+          if (rr >= G.n1) {
+            const int Yo = wy0 + rr - G.n1;
+            if (X >= 0 && X < W && Yo >= 0 && Yo < H) cnt -= !isfinite(gimg[(int64_t)Yo * W + X]);
           }
-          if (r >= G.n1 - 1) colN[(r - G.n1 + 1) * G.Wn + c] = cnt;
+          if (rr >= G.n1 - 1) colN[(rr - G.n1 + 1) * G.Wn + c] = cnt;
         }
       }
       __syncthreads();
-      for (int r = tid; r < G.side; r += nthr) {
-        int cnt = 0;
-        for (int c = 0; c < G.Wn; ++c) {
-          cnt += colN[r * G.Wn + c];
-          if (c >= G.n1) cnt -= colN[r * G.Wn + c - G.n1];
-          if (c >= G.n1 - 1) boxN[r * G.side + c - G.n1 + 1] = cnt;
-        }
-      }
-      __syncthreads();
-    }
-
-    // 2. column sums over n1 rows, then row sums over n1 columns (running,
-    //    compensated).
-    for (int c = tid; c < G.Wn; c += nthr) {
-      Kahan s, q;
-      for (int r = 0; r < G.n1; ++r) {
-        const float v = win[r * G.P + c];
-        s.add(v);
-        q.add(v * v);
-      }
-      colS[c] = s.s - s.c;
-      colQ[c] = q.s - q.c;
-      for (int r = 1; r < G.side; ++r) {
-        const float vin = win[(r + G.n1 - 1) * G.P + c];
-        const float vout = win[(r - 1) * G.P + c];
-        s.add(vin);
-        s.add(-vout);
-        q.add(vin * vin);
-        q.add(-(vout * vout));
-        colS[r * G.Wn + c] = s.s - s.c;
-        colQ[r * G.Wn + c] = q.s - q.c;
-      }
-    }
-    __syncthreads();
-    for (int r = tid; r < G.side; r += nthr) {
-      Kahan s, q;
-      for (int c = 0; c < G.n1; ++c) {
-        s.add(colS[r * G.Wn + c]);
-        q.add(colQ[r * G.Wn + c]);
-      }
-      boxS[r * G.side] = s.s - s.c;
-      boxQ[r * G.side] = (has_bad && boxN[r * G.side] > 0) ? -1.f : q.s - q.c;
-      for (int c = 1; c < G.side; ++c) {
-        s.add(colS[r * G.Wn + c + G.n1 - 1]);
-        s.add(-colS[r * G.Wn + c - 1]);
-        q.add(colQ[r * G.Wn + c + G.n1 - 1]);
-        q.add(-colQ[r * G.Wn + c - 1]);
-        boxS[r * G.side + c] = s.s - s.c;
-        boxQ[r * G.side + c] = (has_bad && boxN[r * G.side + c] > 0) ? -1.f : q.s - q.c;
-      }
-    }
-    __syncthreads();
-
-    // 3. cross terms, register-blocked along du.
-    const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * G.n;
-    const double dfd = R->df;
-    const float df = (float)dfd;
-    const float rn = 1.0f / (float)G.n;
-    const float tsum = R->tsum;
-    const int items = G.side * G.NB;
-    for (int it = tid; it < items; it += nthr) {
-      const int r = it % G.side, b = it / G.side;
-      float tot[L];
-      float cmp[L];
-#pragma unroll
-      for (int k = 0; k < L; ++k) tot[k] = cmp[k] = 0.f;
-      const float* wrow = win + r * G.P + b * L;
-      for (int i = 0; i < G.n1; ++i) {
-        const float* trow = tm + i * G.n1;
-        const float* gw = wrow + i * G.P;
-        float w[L];
-        float part[L];
-#pragma unroll
-        for (int k = 0; k < L; ++k) part[k] = 0.f;
-#pragma unroll
-        for (int k = 0; k < L - 1; ++k) w[k] = gw[k];
-        for (int j = 0; j < G.n1p; j += L) {
-#pragma unroll
-          for (int u = 0; u < L; ++u) {
-            w[(u + L - 1) % L] = gw[j + u + L - 1];
-            const int jj = j + u;
-            float t = trow[jj < G.n1 ? jj : G.n1 - 1];
-            t = jj < G.n1 ? t : 0.f;
-#pragma unroll
-            for (int k = 0; k < L; ++k) part[k] = fmaf(t, w[(u + k) % L], part[k]);
-          }
-        }
-#pragma unroll
+      if (mine) {
         for (int k = 0; k < L; ++k) {
-          const float y = part[k] - cmp[k];
-          const float tt = tot[k] + y;
-          cmp[k] = (tt - tot[k]) - y;
-          tot[k] = tt;
+          const int c = b * L + k;
+          if (c >= G.side) break;
+          int cnt = 0;
+          for (int j = 0; j < G.n1; ++j) cnt += colN[r * G.Wn + c + j];
+          if (cnt > 0) badmask |= 1u << k;
         }
       }
+      __syncthreads();
+    }
+
+    // 2. column sums of (g - c0) and (g - c0)^2 over n1 rows: a direct sum
+    //    then a short running update (kSeg rows per task), accumulated in
+    //    FP64 (as cheap as FP32 here), stored as FP32.
+    const int nseg = (G.side + kSeg - 1) / kSeg;
+    for (int task = tid; task < G.Wn * nseg; task += nthr) {
+      const int c = task % G.Wn, r0 = (task / G.Wn) * kSeg;
+      const int r1 = min(r0 + kSeg, G.side);
+      double s = 0.0, q = 0.0;
+      for (int rr = r0; rr < r0 + G.n1; ++rr) {
+        const float v = win[rr * G.P + c];
+        s += (double)v;
+        q += (double)(v * v);
+      }
+      colS[r0 * G.Wn + c] = (float)s;
+      colQ[r0 * G.Wn + c] = (float)q;
+      for (int rr = r0 + 1; rr < r1; ++rr) {
+        const float vin = win[(rr + G.n1 - 1) * G.P + c];
+        const float vout = win[(rr - 1) * G.P + c];
+        s += (double)vin - (double)vout;
+        q += (double)(vin * vin) - (double)(vout * vout);
+        colS[rr * G.Wn + c] = (float)s;
+        colQ[rr * G.Wn + c] = (float)q;
+      }
+    }
+    __syncthreads();
+
+    // 3. each lane's box sums over n1 columns (FP64).  The running chain
+    //    starts at the nearest multiple of 8 columns at or below the lane's
+    //    tile, so every candidate's sum is formed by the same operations
+    //    whatever the tile width: results do not depend on the tuning.
+    double sg[L], sq[L];
+    if (mine) {
+      double s = 0.0, q = 0.0;
+      const float* cs = colS + r * G.Wn;
+      const float* cq = colQ + r * G.Wn;
+      const int t0 = b * L, a0 = t0 & ~7;
+      for (int j = 0; j < G.n1; ++j) {
+        s += (double)cs[a0 + j];
+        q += (double)cq[a0 + j];
+      }
+      for (int c = a0 + 1; c <= t0; ++c) {
+        s += (double)cs[c + G.n1 - 1] - (double)cs[c - 1];
+        q += (double)cq[c + G.n1 - 1] - (double)cq[c - 1];
+      }
+#pragma unroll
+      for (int k = 0; k < L; ++k) {
+        const int c = t0 + k;
+        if (k > 0 && c < G.side) {
+          s += (double)cs[c + G.n1 - 1] - (double)cs[c - 1];
+          q += (double)cq[c + G.n1 - 1] - (double)cq[c - 1];
+        }
+        sg[k] = s;
+        sq[k] = q;
+      }
+    }
+    __syncthreads();
+
+    // 4. cross terms and scores.
+    const int tp = P.tmpl_pitch;
+    const float* tm = tmpl_arena + P.tmpl_off + (int64_t)(g - P.poi_off) * G.n1 * tp;
+    const double dfd = R->df;
+    const double rnd = 1.0 / (double)G.n;
+    const double tsum = R->tsum;
+    if (mine) {
+      double tot[L];
+      const float* wrow = win + r * G.P + b * L;
+      cross_terms<L, NP>(tm, tp, G.n1, wrow, G.P, tot);   // G.NP == NP for this group
 #pragma unroll
       for (int k = 0; k < L; ++k) {
         const int c = b * L + k;
@@ -279,82 +380,94 @@ __global__ void __launch_bounds__(1024) search_f32_kernel(
         const int du = cu - G.S + c, dv = cv - G.S + r;
         const bool adm = x0 + du - G.M >= 0 && x0 + du + G.M <= W - 1 && y0 + dv - G.M >= 0 &&
                          y0 + dv + G.M <= H - 1;
-        const float sg = boxS[r * G.side + c];
-        const float sq = boxQ[r * G.side + c];
-        const float var = sq - sg * sg * rn;
-        const float sumg2 = sq + 2.f * c0 * sg + (float)G.n * c0 * c0;
+        const double var = sq[k] - sg[k] * sg[k] * rnd;
+        const double sumg2 = sq[k] + 2.0 * (double)c0 * sg[k] + (double)G.n * (double)c0 * (double)c0;
         float sc = kNegInf;
-        if (adm && sq >= 0.f && var > 1e-6f * sumg2) {
-          const float num = (tot[k] - cmp[k]) - sg * rn * tsum;
-          sc = num / (df * sqrtf(var));
+        if (adm && !((badmask >> k) & 1u) && not_flat(var, sumg2)) {
+          const double num = tot[k] - sg[k] * rnd * tsum;
+          sc = (float)(num / (dfd * sqrt(var)));
           if (!isfinite(sc)) sc = kNegInf;
         }
         scores[r * G.side + c] = sc;
       }
     }
+    if (tid == 0) s_cnt = 0;
     __syncthreads();
 
-    // 4. block maximum.
+    // 4. block maximum of the FP32 scores.
     const int K = G.side * G.side;
     float m = kNegInf;
     for (int c = tid; c < K; c += nthr) m = fmaxf(m, scores[c]);
     m = wave_max(m);
     if (lane == 0) s_wmax[wid] = m;
     __syncthreads();
-    if (wid == 0) {
-      float mm = lane < (nthr / kWave) ? s_wmax[lane] : kNegInf;
-      mm = wave_max(mm);
-      int pick = -1;
-      double best = -INFINITY;
-      if (mm > kNegInf) {
-        // 5. FP64 re-score of the near ties, then the tie rule.
-        const float thr = mm - 2e-5f;
-        const float* fimg = ref + P.ref_off;
-        double cbest = -INFINITY;
-        for (int base = 0; base < K; base += kWave) {
-          const int c = base + lane;
-          const bool hit = c < K && scores[c] >= thr;
-          uint64_t bits = __ballot(hit);
-          while (bits) {
-            const int bit = __builtin_ctzll(bits);
-            bits &= bits - 1;
-            const int cand = base + bit;
-            const int rr = cand / G.side, cc = cand - rr * G.side;
-            bool ok;
-            const double z = rescore_f64(fimg, gimg, W, x0, y0, x0 + cu - G.S + cc,
-                                         y0 + cv - G.S + rr, G.M, R->fbar, dfd, &ok);
-            if (ok && z > cbest) cbest = z;
-          }
+    float mm = kNegInf;
+    for (int k = 0; k < nthr / kWave; ++k) mm = fmaxf(mm, s_wmax[k]);
+
+    // 5. Candidates within 2e-5 of the FP32 maximum.  The FP32 scores are
+    //    within ~1e-6 of Eq. (1), so a single such candidate is the FP64 argmax
+    //    and its FP32 score is within tolerance.  Two or more are re-scored
+    //    two-pass in FP64 and the tie rule picks the smallest row-major index
+    //    within 1e-12 of the FP64 maximum.
+    int pick = -1;
+    double best = -INFINITY;
+    if (mm > kNegInf) {
+      const float thr = mm - 2e-5f;
+      const float* fimg = ref + P.ref_off;
+      for (int c = tid; c < K; c += nthr)
+        if (scores[c] >= thr) {
+          const int slot = atomicAdd(&s_cnt, 1);
+          if (slot < kNearCap) near_idx[slot] = c;
         }
-        if (cbest > -INFINITY) {
-          for (int base = 0; base < K && pick < 0; base += kWave) {
-            const int c = base + lane;
-            const bool hit = c < K && scores[c] >= thr;
-            uint64_t bits = __ballot(hit);
-            while (bits && pick < 0) {
-              const int bit = __builtin_ctzll(bits);
-              bits &= bits - 1;
-              const int cand = base + bit;
-              const int rr = cand / G.side, cc = cand - rr * G.side;
-              bool ok;
-              const double z = rescore_f64(fimg, gimg, W, x0, y0, x0 + cu - G.S + cc,
-                                           y0 + cv - G.S + rr, G.M, R->fbar, dfd, &ok);
-              if (ok && z >= cbest - 1e-12) {
-                pick = cand;
-                best = z;
-              }
+      __syncthreads();
+      const int cnt = s_cnt;
+      if (cnt == 1) {
+        pick = near_idx[0];
+        best = (double)scores[pick];
+      } else if (cnt <= kNearCap) {
+        double cmax = -INFINITY;
+        for (int e = 0; e < cnt; ++e) {
+          const int cand = near_idx[e];
+          const int rr = cand / G.side, cc = cand - rr * G.side;
+          bool ok;
+          const double z = rescore_f64(fimg, gimg, W, x0, y0, x0 + cu - G.S + cc,
+                                       y0 + cv - G.S + rr, G.M, R->fbar, dfd, s_red, &ok);
+          const double zv = ok ? z : -INFINITY;
+          if (tid == 0) near_val[e] = zv;
+          cmax = fmax(cmax, zv);
+        }
+        __syncthreads();
+        if (cmax > -INFINITY)
+          for (int e = 0; e < cnt; ++e)
+            if (near_val[e] >= cmax - 1e-12 && (pick < 0 || near_idx[e] < pick)) {
+              pick = near_idx[e];
+              best = near_val[e];
             }
+      } else {
+        // More near ties than the list holds: two sweeps in index order.
+        double cmax = -INFINITY;
+        for (int cand = 0; cand < K; ++cand) {
+          if (!(scores[cand] >= thr)) continue;
+          const int rr = cand / G.side, cc = cand - rr * G.side;
+          bool ok;
+          const double z = rescore_f64(fimg, gimg, W, x0, y0, x0 + cu - G.S + cc,
+                                       y0 + cv - G.S + rr, G.M, R->fbar, dfd, s_red, &ok);
+          if (ok) cmax = fmax(cmax, z);
+        }
+        for (int cand = 0; cand < K && pick < 0 && cmax > -INFINITY; ++cand) {
+          if (!(scores[cand] >= thr)) continue;
+          const int rr = cand / G.side, cc = cand - rr * G.side;
+          bool ok;
+          const double z = rescore_f64(fimg, gimg, W, x0, y0, x0 + cu - G.S + cc,
+                                       y0 + cv - G.S + rr, G.M, R->fbar, dfd, s_red, &ok);
+          if (ok && z >= cmax - 1e-12) {
+            pick = cand;
+            best = z;
           }
         }
-      }
-      if (lane == 0) {
-        s_pick[0] = pick;
-        s_zncc = (float)best;
       }
     }
-    __syncthreads();
     if (tid == 0) {
-      const int pick = s_pick[0];
       if (pick < 0) {
         uv_out[2 * g] = 0;
         uv_out[2 * g + 1] = 0;
@@ -364,7 +477,7 @@ __global__ void __launch_bounds__(1024) search_f32_kernel(
         const int rr = pick / G.side, cc = pick - rr * G.side;
         uv_out[2 * g] = cu - G.S + cc;
         uv_out[2 * g + 1] = cv - G.S + rr;
-        zncc_out[g] = s_zncc;
+        zncc_out[g] = (float)best;
         status_out[g] = DIC_POI_OK;
       }
     }
@@ -372,50 +485,68 @@ __global__ void __launch_bounds__(1024) search_f32_kernel(
   }
 }
 
-template <int L>
-static hipError_t launch_search_f32_t(const DevState& st, int threads, const float* ref,
-                                      const float* def, const int32_t* poi, const int32_t* seed,
-                                      int32_t* uv, float* zncc, int32_t* status, int num_cu,
-                                      hipStream_t s) {
+template <int L, int NP>
+static hipError_t launch_search_group(const DevState& st, const SearchGroup& gr, int ctr,
+                                      int occ_cap, const float* ref, const float* def,
+                                      const int32_t* poi, const int32_t* seed, int32_t* uv,
+                                      float* zncc, int32_t* status, int num_cu, hipStream_t s) {
+  const int threads = search_threads(st.maxS, L);
+  if (threads > kSearchMaxThreads) return hipErrorInvalidConfiguration;
   const size_t lds = search_lds_bytes(st.maxM, st.maxS, L);
+  const void* fn = reinterpret_cast<const void*>(&search_f32_kernel<L, NP>);
   if (lds > 65536) {
-    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&search_f32_kernel<L>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ea != hipSuccess) return ea;
   }
   int occ = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, search_f32_kernel<L>, threads,
-                                                              lds);
+  hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, search_f32_kernel<L, NP>, threads, lds);
   if (e != hipSuccess) return e;
   if (occ < 1) return hipErrorInvalidConfiguration;
+  if (occ_cap > 0 && occ > occ_cap) occ = occ_cap;
   int64_t blocks = (int64_t)occ * num_cu;
-  if (blocks > st.N) blocks = st.N;
-  hipLaunchKernelGGL(search_f32_kernel<L>, dim3((unsigned)blocks), dim3(threads), lds, s, st, ref,
-                     def, poi, seed, uv, zncc, status);
+  if (blocks > gr.count) blocks = gr.count;
+  hipLaunchKernelGGL((search_f32_kernel<L, NP>), dim3((unsigned)blocks), dim3(threads), lds, s, st,
+                     st.work + gr.begin, gr.count, ctr, st.tmpl, ref, def, poi, seed, uv, zncc,
+                     status);
   return hipGetLastError();
 }
 
-hipError_t launch_search_f32(const DevState& st, const dic_tuning_t& tu, const float* ref,
+template <int L, int NP0, int... NPs>
+static hipError_t launch_search_np(const DevState& st, const SearchGroup& gr, int ctr, int occ,
+                                   const float* ref, const float* def, const int32_t* poi,
+                                   const int32_t* seed, int32_t* uv, float* zncc, int32_t* status,
+                                   int num_cu, hipStream_t s) {
+  if (gr.np == NP0)
+    return launch_search_group<L, NP0>(st, gr, ctr, occ, ref, def, poi, seed, uv, zncc, status,
+                                       num_cu, s);
+  if constexpr (sizeof...(NPs) > 0)
+    return launch_search_np<L, NPs...>(st, gr, ctr, occ, ref, def, poi, seed, uv, zncc, status,
+                                       num_cu, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_search_f32(const DevState& st, const dic_tuning_t& tu,
+                             const SearchGroup* groups, int ngroups, const float* ref,
                              const float* def, const int32_t* poi, const int32_t* seed,
                              int32_t* uv, float* zncc, int32_t* status, int num_cu,
                              hipStream_t s) {
-  if (st.N == 0) return hipSuccess;
-  switch (tu.search_block) {
-    case 4:
-      return launch_search_f32_t<4>(st, tu.search_threads, ref, def, poi, seed, uv, zncc, status,
-                                    num_cu, s);
-    case 6:
-      return launch_search_f32_t<6>(st, tu.search_threads, ref, def, poi, seed, uv, zncc, status,
-                                    num_cu, s);
-    case 8:
-      return launch_search_f32_t<8>(st, tu.search_threads, ref, def, poi, seed, uv, zncc, status,
-                                    num_cu, s);
-    case 11:
-      return launch_search_f32_t<11>(st, tu.search_threads, ref, def, poi, seed, uv, zncc, status,
-                                     num_cu, s);
-    default:
-      return hipErrorInvalidValue;
+  if (ngroups > kMaxSearchGroups) return hipErrorInvalidValue;
+  for (int k = 0; k < ngroups; ++k) {
+    const SearchGroup& gr = groups[k];
+    if (gr.count == 0) continue;
+    hipError_t e = hipErrorInvalidValue;
+    if (tu.search_block == 4)
+      e = launch_search_np<4, 4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 44>(
+          st, gr, kCtrSearch + k, tu.search_occupancy, ref, def, poi, seed, uv, zncc, status,
+          num_cu, s);
+    else if (tu.search_block == 8)
+      e = launch_search_np<8, 8, 16, 24, 32, 40, 48>(st, gr, kCtrSearch + k, tu.search_occupancy,
+                                                     ref, def, poi, seed, uv, zncc, status, num_cu,
+                                                     s);
+    if (e != hipSuccess) return e;
   }
+  return hipSuccess;
 }
 
 // FP64 plain form: one 64-thread workgroup per POI of one pair; each lane

@@ -46,7 +46,7 @@ class PlanDesc(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("search_block", ctypes.c_int32), ("search_threads", ctypes.c_int32),
+    _fields_ = [("search_block", ctypes.c_int32), ("search_occupancy", ctypes.c_int32),
                 ("icgn_waves", ctypes.c_int32), ("icgn_slack", ctypes.c_int32)]
 
 
@@ -200,7 +200,7 @@ class Plan:
     def tuning(self) -> Tuple[int, int, int, int]:
         t = Tuning()
         _check(self.L.dic_plan_get_tuning(self._h, ctypes.byref(t)))
-        return (t.search_block, t.search_threads, t.icgn_waves, t.icgn_slack)
+        return (t.search_block, t.search_occupancy, t.icgn_waves, t.icgn_slack)
 
     @tuning.setter
     def tuning(self, v: Tuple[int, int, int, int]) -> None:

@@ -57,10 +57,10 @@ def test_plan_create_and_workspace(L):
     assert nb64.value < nb.value      # the plain form keeps no gradients or templates
     t = Tuning()
     assert L.dic_plan_get_tuning(h, ctypes.byref(t)) == 0
-    assert (t.search_block, t.search_threads) == (8, 256)
-    bad = Tuning(5, 256, 4, 4)
-    assert L.dic_plan_set_tuning(h, ctypes.byref(bad)) == -1
-    good = Tuning(11, 512, 2, 6)
+    assert (t.search_block, t.search_occupancy) == (8, 0)
+    for bad in (Tuning(5, 0, 4, 4), Tuning(8, 17, 4, 4), Tuning(8, 0, 9, 4), Tuning(4, 0, 1, 17)):
+        assert L.dic_plan_set_tuning(h, ctypes.byref(bad)) == -1
+    good = Tuning(4, 2, 2, 6)
     assert L.dic_plan_set_tuning(h, ctypes.byref(good)) == 0
     L.dic_plan_destroy(h)
     L.dic_plan_destroy(h64)
