@@ -96,6 +96,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="search_block,search_occupancy,icgn_waves,icgn_slack (skips autotuning)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU: the hot path is a "
@@ -118,7 +122,9 @@ def main() -> int:
     # --- FP32 batched form, whole step as a graph ------------------------------
     plan = dic.single_pair_plan(W, H, pair.M, pair.S, N, dic.FP32_BATCHED,
                                 flags=dic.FLAG_USE_GRAPH)
-    if not args.no_autotune:
+    if args.tuning:
+        plan.tuning = tuple(int(v) for v in args.tuning.split(","))
+    elif not args.no_autotune:
         plan.autotune(F, G, Q)
     out = plan.new_outputs()
     for _ in range(args.warmup):
@@ -208,6 +214,14 @@ def main() -> int:
         "icgn_fp32_over_fp64_plain": round(t64_icgn / t_icgn, 2),
         "max_fp32_vs_fp64_plain_px": fp32_vs_fp64,
     }
+    if args.copy_probe_mb > 0:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["copy_probe_bytes_each_way"] = n * 4
     if not args.no_cpu_baseline:
         base, acc = cpu_baseline(pair, got, args.cpu_sample)
         rec["cpu_baseline"] = base
