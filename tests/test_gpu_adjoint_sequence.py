@@ -1,0 +1,160 @@
+"""GPU parity of the ZNSSD adjoint (criterion, warp gradient, image gradient,
+deterministic mode, autograd wrapper) and of the frame-sequence driver,
+through the C ABI, against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import dicgen
+import paper_1905_06228_amd as dic
+from oracle import dic_oracle as O
+from tests._parity import compare, to_dev
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+# FP32 interpolation against an FP64 oracle: C to 2e-5 absolute (twice the
+# ZNCC tolerance, C = 2 - 2 ZNCC); gradients to 1e-4 of their largest entry.
+TOL_C = 2e-5
+TOL_GRAD_REL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def adjoint_case():
+    """Differentiation workload at 256x256: the affine field with noise,
+    subset 25x25, POIs 68 + 7k, warp = converged p* plus a seeded offset
+    (|du|, |dv| <= 0.3 px, gradient terms <= 0.01)."""
+    pr = dicgen.affine_pair_1024(size=256, tag=4)
+    c = 68 + 7 * np.arange(18)
+    c = c[c <= 256 - 1 - 40]
+    gy, gx = np.meshgrid(c, c, indexing="ij")
+    pois = np.stack([gx.ravel(), gy.ravel()], axis=1).astype(np.int32)
+    M = 12
+    fx, fy = O.central_gradients(pr.ref)
+    P = np.zeros((len(pois), 6))
+    for i, (x0, y0) in enumerate(pois):
+        s = O.integer_search(pr.ref, pr.defm, int(x0), int(y0), M, 8)
+        P[i] = O.icgn(pr.ref, pr.defm, fx, fy, int(x0), int(y0), M, [s.du, 0, 0, s.dv, 0, 0],
+                      max_iters=100, tol=1e-10).p
+    rng = np.random.default_rng(24)
+    P[:, [0, 3]] += rng.uniform(-0.3, 0.3, (len(pois), 2))
+    P[:, [1, 2, 4, 5]] += rng.uniform(-0.01, 0.01, (len(pois), 4))
+    up = rng.uniform(0.5, 2.0, len(pois))
+    C, gp, gg = O.znssd_batch(pr.ref, pr.defm, pois, M, P, upstream=up)
+    return pr, pois, M, P, up, C, gp, gg
+
+
+def run_znssd(pr, pois, M, P, up, flags=0, precision=dic.FP32_BATCHED):
+    plan = dic.single_pair_plan(256, 256, M, 8, len(pois), precision, flags=flags)
+    F, G, Q = to_dev(pr.ref), to_dev(pr.defm), to_dev(pois)
+    p = to_dev(P)
+    c = torch.empty(len(pois), dtype=torch.float32, device="cuda")
+    gp = torch.empty((len(pois), 6), dtype=torch.float64, device="cuda")
+    gg = torch.zeros((256, 256), dtype=torch.float32, device="cuda")
+    plan.znssd(F, G, Q, p, grad_c=to_dev(up.astype(np.float32)), c_out=c, grad_p=gp, grad_def=gg)
+    torch.cuda.synchronize()
+    return c.cpu().numpy(), gp.cpu().numpy(), gg.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,prec", [("fp32", dic.FP32_BATCHED), ("fp64", dic.FP64_PLAIN)])
+def test_znssd_matches_oracle(adjoint_case, name, prec):
+    pr, pois, M, P, up, C, gp, gg = adjoint_case
+    print(f"case znssd {name} N={len(pois)}", flush=True)
+    c, gpu_gp, gpu_gg = run_znssd(pr, pois, M, P, up, precision=prec)
+    dc = np.abs(c - C).max()
+    dgp = np.abs(gpu_gp - gp).max() / np.abs(gp).max()
+    dgg = np.abs(gpu_gg - gg).max() / np.abs(gg).max()
+    print(f"[parity znssd/{name}] max|dC|={dc:.2e} grad_p rel={dgp:.2e} grad_g rel={dgg:.2e}",
+          flush=True)
+    assert dc <= TOL_C
+    assert dgp <= TOL_GRAD_REL
+    assert dgg <= TOL_GRAD_REL
+    # the invariants of the criterion hold for the GPU image gradient too
+    assert abs(gpu_gg.sum()) <= 1e-4 * np.abs(gpu_gg).sum()
+
+
+def test_znssd_deterministic_mode(adjoint_case):
+    pr, pois, M, P, up, C, gp, gg = adjoint_case
+    a = run_znssd(pr, pois, M, P, up, flags=dic.FLAG_DETERMINISTIC_BWD)
+    b = run_znssd(pr, pois, M, P, up, flags=dic.FLAG_DETERMINISTIC_BWD)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    assert np.abs(a[2] - gg).max() / np.abs(gg).max() <= TOL_GRAD_REL
+
+
+def test_znssd_autograd(adjoint_case):
+    pr, pois, M, P, up, C, gp, gg = adjoint_case
+    plan = dic.single_pair_plan(256, 256, M, 8, len(pois))
+    F, Q = to_dev(pr.ref), to_dev(pois)
+    p = to_dev(P).requires_grad_(True)
+    g = to_dev(pr.defm).requires_grad_(True)
+    c = dic.ZNSSD.apply(p, g, plan, F, Q)
+    (c.double() * to_dev(up)).sum().backward()
+    torch.cuda.synchronize()
+    assert np.abs(c.detach().cpu().numpy() - C).max() <= TOL_C
+    assert np.abs(p.grad.cpu().numpy() - gp).max() / np.abs(gp).max() <= TOL_GRAD_REL
+    assert np.abs(g.grad.cpu().numpy() - gg).max() / np.abs(gg).max() <= TOL_GRAD_REL
+
+
+def test_znssd_out_of_image_and_bad_reference():
+    pr = dicgen.affine_pair_1024(size=128, tag=41)
+    f = pr.ref.copy()
+    f[30:50, 30:50] = 77.0
+    pois = np.array([[40, 40], [64, 64], [20, 64]], dtype=np.int32)
+    P = np.array([[0, 0, 0, 0, 0, 0], [1, 0, 0, 0, 0, 0], [-12, 0, 0, 0, 0, 0]], dtype=np.float64)
+    plan = dic.single_pair_plan(128, 128, 8, 4, 3)
+    c = torch.empty(3, dtype=torch.float32, device="cuda")
+    gp = torch.empty((3, 6), dtype=torch.float64, device="cuda")
+    plan.znssd(to_dev(f), to_dev(pr.defm), to_dev(pois), to_dev(P), c_out=c, grad_p=gp)
+    torch.cuda.synchronize()
+    c, gp = c.cpu().numpy(), gp.cpu().numpy()
+    for i in range(3):
+        z = O.znssd(f, pr.defm, int(pois[i, 0]), int(pois[i, 1]), 8, P[i])
+        if np.isnan(z.c):
+            assert np.isnan(c[i]) and np.all(gp[i] == 0), i
+        else:
+            assert abs(c[i] - z.c) <= TOL_C, i
+    assert np.isnan(c[0]) and np.isnan(c[2]) and np.isfinite(c[1])
+
+
+# ---------------------------------------------------------------------------
+# sequence
+# ---------------------------------------------------------------------------
+
+def test_sequence_matches_oracle():
+    """Frames under the growing heterogeneous strain, each correlated to
+    frame 0, seeded by the last OK frame."""
+    frames = dicgen.sequence_frames(5, 200, 260, 2400, noise=3.0, tag=51, pad=48.0)
+    M, S = 10, 8
+    pois = dicgen.poi_grid(260, 200, M, S, 13)
+    print(f"case sequence frames=5 N={len(pois)}", flush=True)
+    ref = O.correlate_sequence(frames, pois, M, S)
+    for name, prec in [("fp32", dic.FP32_BATCHED), ("fp64", dic.FP64_PLAIN)]:
+        got = dic.correlate_sequence([torch.from_numpy(f) for f in frames], to_dev(pois), M, S,
+                                     precision=prec)
+        assert len(got) == len(ref)
+        for k, (g, r) in enumerate(zip(got, ref), start=1):
+            h = {key: v.cpu().numpy() for key, v in g.items()}
+            compare(h, r, label=f"sequence frame {k}/{name}")
+        # the late frames move up to ~1.5 px: seeds were used
+        assert np.abs(ref[-1]["p"][:, 0]).max() > 1.0
+
+
+def test_sequence_from_device_frames_and_seed_update():
+    frames = dicgen.sequence_frames(3, 128, 160, 900, noise=0.0, tag=52, pad=40.0)
+    pois = dicgen.poi_grid(160, 128, 8, 6, 15)
+    a = dic.correlate_sequence([to_dev(f) for f in frames], to_dev(pois), 8, 6)
+    b = dic.correlate_sequence([torch.from_numpy(f) for f in frames], to_dev(pois), 8, 6)
+    for x, y in zip(a, b):
+        for k in x:
+            np.testing.assert_array_equal(x[k].cpu().numpy(), y[k].cpu().numpy(), err_msg=k)
+    # seed_update keeps the previous seed where the status is not OK
+    plan = dic.single_pair_plan(160, 128, 8, 6, 4)
+    p = to_dev(np.array([[1.4, 0, 0, -2.6, 0, 0]] * 4))
+    st = to_dev(np.array([0, 1, 0, 3], dtype=np.int32))
+    seed = to_dev(np.full((4, 2), 7, dtype=np.int32))
+    ps = to_dev(np.zeros((4, 6)))
+    plan.seed_update(p, st, seed, ps)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(seed.cpu().numpy(), [[1, -3], [7, 7], [1, -3], [7, 7]])
+    np.testing.assert_array_equal(ps.cpu().numpy()[[1, 3]], 0.0)
