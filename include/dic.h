@@ -83,8 +83,9 @@ typedef enum {
 enum {
   DIC_FLAG_USE_GRAPH = 1u << 0,       /* dic_correlate captures and replays
                                          a HIP graph                         */
-  DIC_FLAG_CACHE_REF_PREP = 1u << 1,  /* reuse the reference-side
-                                         precomputation until
+  DIC_FLAG_CACHE_REF_PREP = 1u << 1,  /* reuse the reference-side and
+                                         deformed-side precomputations for
+                                         the same image pointers until
                                          dic_plan_invalidate_reference()     */
   DIC_FLAG_DETERMINISTIC_BWD = 1u << 2 /* grad_def accumulated in a fixed
                                          order (no float atomics)            */
@@ -167,6 +168,16 @@ dic_status_t dic_plan_invalidate_reference(dic_plan_t plan);
  * the calls below unless DIC_FLAG_CACHE_REF_PREP holds a valid cache. */
 dic_status_t dic_prepare_reference(dic_plan_t plan, const float* ref_images,
                                    const int32_t* poi_xy, dic_stream_t stream);
+
+/* Deformed-side precomputation for the FP32 search: for every subset centre
+ * of every deformed image, the exact (FP64) sums of g and g^2 over the
+ * subset, so each candidate's normalisation is a lookup.  Called implicitly
+ * by dic_integer_search / dic_correlate unless DIC_FLAG_CACHE_REF_PREP holds
+ * a valid cache for this `def_images` pointer (then call it again, or
+ * dic_plan_invalidate_reference, after changing the images in place).  A
+ * no-op for the FP64 plain form. */
+dic_status_t dic_prepare_deformed(dic_plan_t plan, const float* def_images,
+                                  dic_stream_t stream);
 
 /* Brute-force integer search (Sec. 2.1, Eq. (1)).  For each POI evaluates
  * every candidate (du, dv) with |du - cu| <= S, |dv - cv| <= S, where (cu, cv)

@@ -38,7 +38,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t pairs = 0, poi_pair = 0, work = 0, counters = 0, grads = 0, recs = 0, tmpl = 0,
-         fix_off = 0, fix = 0, s_status = 0, s_zncc = 0, total = 0;
+         box = 0, fix_off = 0, fix = 0, s_status = 0, s_zncc = 0, total = 0;
   int64_t fix_count = 0;
 };
 
@@ -71,6 +71,8 @@ struct dic_plan_s {
   bool ref_valid = false;
   const void* ref_img = nullptr;
   const void* ref_poi = nullptr;
+  bool def_valid = false;
+  const void* def_img = nullptr;
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
   std::vector<hipGraph_t> graph_objs;
   hipStream_t cap_stream = nullptr;
@@ -175,11 +177,23 @@ std::vector<SearchGroup> search_groups(const dic_plan_s* p, int block) {
   return g;
 }
 
+dic_status_t prepare_deformed(dic_plan_t p, const float* def, hipStream_t s, bool force) {
+  if (!p->fp32()) return DIC_SUCCESS;
+  if (!force && (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->def_valid && p->def_img == def)
+    return DIC_SUCCESS;
+  DIC_HIP(launch_box_sums(p->st, def, s));
+  p->def_valid = true;
+  p->def_img = def;
+  return DIC_SUCCESS;
+}
+
 dic_status_t enqueue_search(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
                             const int32_t* seed, int32_t* uv, float* zn, int32_t* status,
                             hipStream_t s) {
   if (p->fp32()) {
     const std::vector<SearchGroup> groups = search_groups(p, p->tuning.search_block);
+    dic_status_t r = prepare_deformed(p, def, s, false);
+    if (r) return r;
     DIC_HIP(launch_reset_counters(p->st, s));
     DIC_HIP(launch_search_f32(p->st, p->tuning, groups.data(), (int)groups.size(), ref, def, poi,
                               seed, uv, zn, status, p->num_cu, s));
@@ -298,7 +312,7 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
   L.poi_pair = take(sizeof(int32_t) * p->N);
   L.work = take(sizeof(int32_t) * p->N);
   L.counters = take(sizeof(int32_t) * kNumCounters);
-  int64_t gfl = 0, tfl = 0, fix = 0;
+  int64_t gfl = 0, tfl = 0, bxd = 0, fix = 0;
   p->dpairs.resize(d->num_pairs);
   p->fix_off.resize(d->num_pairs);
   for (int k = 0; k < d->num_pairs; ++k) {
@@ -316,10 +330,12 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
     P.tmpl_off = tfl;
     P.tmpl_pitch = template_pitch(q.subset_radius);
     P.pad_ = 0;
+    P.box_off = bxd;
     const int64_t tn = (int64_t)(2 * q.subset_radius + 1) * P.tmpl_pitch;
     if (f32) {
       gfl += 2 * (int64_t)q.width * q.height;
       tfl += q.poi_count * tn;
+      bxd += 4 * (int64_t)q.width * q.height;
     }
     p->fix_off[k] = fix;
     if (p->det()) fix += (int64_t)q.width * q.height;
@@ -331,6 +347,7 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
   L.grads = take(sizeof(float) * gfl);
   L.recs = take(sizeof(RefRec) * p->N);
   L.tmpl = take(sizeof(float) * tfl);
+  L.box = take(sizeof(double) * bxd);
   L.fix_off = take(sizeof(int64_t) * d->num_pairs);
   L.fix = take(sizeof(unsigned long long) * fix);
   L.fix_count = fix;
@@ -425,6 +442,7 @@ dic_status_t dic_plan_bind(dic_plan_t p, void* ws, size_t bytes, dic_stream_t st
   st.grads = reinterpret_cast<float*>(base + p->lay.grads);
   st.recs = reinterpret_cast<RefRec*>(base + p->lay.recs);
   st.tmpl = reinterpret_cast<float*>(base + p->lay.tmpl);
+  st.box = reinterpret_cast<double*>(base + p->lay.box);
   st.N = p->N;
   st.num_pairs = p->desc.num_pairs;
   st.maxM = p->maxM;
@@ -436,6 +454,7 @@ dic_status_t dic_plan_bind(dic_plan_t p, void* ws, size_t bytes, dic_stream_t st
   p->ws = ws;
   p->bound = true;
   p->ref_valid = false;
+  p->def_valid = false;
   drop_graphs(p);
   if (const char* path = std::getenv("DIC_AUTOTUNE_CACHE")) {
     auto m = read_tune_cache(path);
@@ -452,6 +471,7 @@ dic_status_t dic_plan_invalidate_reference(dic_plan_t p) {
   dic_status_t r = check_plan(p, false);
   if (r) return r;
   p->ref_valid = false;
+  p->def_valid = false;
   drop_graphs(p);
   return DIC_SUCCESS;
 }
@@ -462,6 +482,13 @@ dic_status_t dic_prepare_reference(dic_plan_t p, const float* ref, const int32_t
   if (r) return r;
   if (!ref || (!poi && p->N)) return fail(DIC_ERR_INVALID_ARGUMENT, "null image or POI pointer");
   return prepare(p, ref, poi, reinterpret_cast<hipStream_t>(stream), true);
+}
+
+dic_status_t dic_prepare_deformed(dic_plan_t p, const float* def, dic_stream_t stream) {
+  dic_status_t r = check_plan(p, true);
+  if (r) return r;
+  if (!def) return fail(DIC_ERR_INVALID_ARGUMENT, "null image pointer");
+  return prepare_deformed(p, def, reinterpret_cast<hipStream_t>(stream), true);
 }
 
 dic_status_t dic_integer_search(dic_plan_t p, const float* ref, const float* def,
@@ -510,7 +537,8 @@ dic_status_t dic_correlate(dic_plan_t p, const float* ref, const float* def, con
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (!(p->desc.flags & DIC_FLAG_USE_GRAPH)) return enqueue_correlate(p, a, s);
   const bool cached_ref = (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->ref_valid &&
-                          p->ref_img == ref && p->ref_poi == poi;
+                          p->ref_img == ref && p->ref_poi == poi && p->def_valid &&
+                          p->def_img == def;
   std::vector<uintptr_t> key = {
       (uintptr_t)ref, (uintptr_t)def, (uintptr_t)poi, (uintptr_t)seed, (uintptr_t)p_init,
       (uintptr_t)uv, (uintptr_t)a.zn_int, (uintptr_t)a.st_int, (uintptr_t)p_out, (uintptr_t)zn,
@@ -599,6 +627,8 @@ dic_status_t dic_plan_autotune(dic_plan_t p, const float* ref, const float* def,
     return fail(DIC_ERR_INVALID_ARGUMENT, "null pointer");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   r = prepare(p, ref, poi, s, true);
+  if (r) return r;
+  r = prepare_deformed(p, def, s, true);
   if (r) return r;
   hipEvent_t e0, e1;
   DIC_HIP(hipEventCreate(&e0));

@@ -22,6 +22,8 @@ struct DevPair {
   int32_t tmpl_pitch;  // template row pitch: 2M+1 rounded up to a multiple of 8,
                        // zero-filled beyond the subset, (2M+1) rows per POI
   int32_t pad_;
+  int64_t box_off;   // double offset of this pair's four [H, W] box-sum planes:
+                     // column sums of g and g^2, then subset sums of g and g^2
 };
 
 __host__ __device__ __forceinline__ int template_pitch(int M) { return (2 * M + 1 + 7) / 8 * 8; }
@@ -48,6 +50,7 @@ struct DevState {
   float* grads;             // gradient arena
   RefRec* recs;             // [N]
   float* tmpl;              // template arena
+  double* box;              // box-sum arena (deformed images)
   int64_t N;
   int32_t num_pairs;
   int32_t maxM, maxS;
@@ -69,6 +72,7 @@ struct SearchGroup {
 // Kernel launchers (defined in the .hip files).  All asynchronous on `s`.
 hipError_t launch_reset_counters(const DevState& st, hipStream_t s);
 hipError_t launch_gradients(const DevState& st, const float* ref, hipStream_t s);
+hipError_t launch_box_sums(const DevState& st, const float* def, hipStream_t s);
 hipError_t launch_ref_prep_f32(const DevState& st, const float* ref, const int32_t* poi,
                                hipStream_t s);
 hipError_t launch_ref_prep_f64(const DevState& st, const DevPair* host_pairs,

@@ -39,6 +39,95 @@ hipError_t launch_gradients(const DevState& st, const float* ref, hipStream_t s)
   return hipGetLastError();
 }
 
+// Subset sums of every deformed image, for every subset centre, in FP64
+// (sums of these float grey levels are exact in FP64 for images of ordinary
+// range, and the fixed evaluation order keeps them deterministic anyway):
+// S1[y][x] = sum g, S2[y][x] = sum g^2 over the (2M+1)^2 subset centred on
+// (x, y).  A centre whose subset leaves the image or holds a non-finite
+// pixel gets S2 = -1.  Two passes: column sums (running down 64-row
+// segments), then row sums of those (direct, 2M+1 terms).
+constexpr int kBoxSeg = 64;
+
+__global__ void __launch_bounds__(256) box_cols_kernel(const DevPair* __restrict__ pairs,
+                                                       const float* __restrict__ def,
+                                                       double* __restrict__ box) {
+  const DevPair P = pairs[blockIdx.z];
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y0 = blockIdx.y * kBoxSeg;
+  const int W = P.width, H = P.height, M = P.M;
+  if (x >= W || y0 >= H) return;
+  const float* g = def + P.def_off;
+  const int64_t plane = (int64_t)W * H;
+  double* v1 = box + P.box_off;
+  double* v2 = v1 + plane;
+  const int y1 = min(y0 + kBoxSeg, H);
+  double s1 = 0.0, s2 = 0.0;
+  int bad = 0;
+  auto take = [&](int y, int sign) {
+    const float v = g[(int64_t)y * W + x];
+    if (isfinite(v)) {
+      s1 += sign * (double)v;
+      s2 += sign * (double)v * (double)v;
+    } else {
+      bad += sign;
+    }
+  };
+  bool primed = false;
+  for (int y = y0; y < y1; ++y) {
+    const int64_t o = (int64_t)y * W + x;
+    if (y - M < 0 || y + M > H - 1) {
+      v1[o] = 0.0;
+      v2[o] = -1.0;
+      continue;
+    }
+    if (!primed) {
+      for (int i = y - M; i <= y + M; ++i) take(i, 1);
+      primed = true;
+    } else {
+      take(y + M, 1);
+      take(y - M - 1, -1);
+    }
+    v1[o] = s1;
+    v2[o] = bad ? -1.0 : s2;
+  }
+}
+
+__global__ void __launch_bounds__(256) box_rows_kernel(const DevPair* __restrict__ pairs,
+                                                       double* __restrict__ box) {
+  const DevPair P = pairs[blockIdx.z];
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  const int W = P.width, H = P.height, M = P.M;
+  if (x >= W || y >= H) return;
+  const int64_t plane = (int64_t)W * H;
+  const double* v1 = box + P.box_off + (int64_t)y * W;
+  const double* v2 = v1 + plane;
+  double* o1 = box + P.box_off + 2 * plane + (int64_t)y * W;
+  double* o2 = o1 + plane;
+  double s1 = 0.0, s2 = 0.0;
+  bool bad = x - M < 0 || x + M > W - 1;
+  if (!bad)
+    for (int j = x - M; j <= x + M; ++j) {
+      const double q = v2[j];
+      bad |= q < 0.0;
+      s1 += v1[j];
+      s2 += q;
+    }
+  o1[x] = bad ? 0.0 : s1;
+  o2[x] = bad ? -1.0 : s2;
+}
+
+hipError_t launch_box_sums(const DevState& st, const float* def, hipStream_t s) {
+  const dim3 gc((st.max_width + 255) / 256, (st.max_height + kBoxSeg - 1) / kBoxSeg,
+                st.num_pairs);
+  hipLaunchKernelGGL(box_cols_kernel, gc, dim3(256), 0, s, st.pairs, def, st.box);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 gr((st.max_width + 255) / 256, st.max_height, st.num_pairs);
+  hipLaunchKernelGGL(box_rows_kernel, gr, dim3(256), 0, s, st.pairs, st.box);
+  return hipGetLastError();
+}
+
 // Writes the record of a POI that cannot be processed.
 __device__ __forceinline__ void write_bad_record(RefRec* R, int status, int lane) {
   if (lane == 0) {

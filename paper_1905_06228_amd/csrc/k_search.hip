@@ -19,7 +19,6 @@ namespace dic {
 namespace {
 
 constexpr int kNearCap = 64;   // near-tie list capacity per POI (a sweep path covers more)
-constexpr int kSeg = 8;        // rows/columns per running box-sum segment
 constexpr int kSearchMaxThreads = 640;  // lanes of the widest search workgroup
 
 struct SearchGeom {
@@ -44,10 +43,9 @@ __host__ __device__ __forceinline__ SearchGeom search_geom(int M, int S, int L) 
   return G;
 }
 
-// Window, column sums of g and g^2; the scores reuse the column sums of g^2
-// once every lane holds its box sums in registers.
+// Window and the candidate scores.
 __host__ __device__ __forceinline__ size_t search_lds_floats(const SearchGeom& G) {
-  return (size_t)G.Wn * G.P + 2 * (size_t)G.side * G.Wn;
+  return (size_t)G.Wn * G.P + (size_t)G.side * G.side;
 }
 
 __host__ __device__ __forceinline__ int search_items(int S, int L) {
@@ -194,7 +192,8 @@ int search_max_threads() { return kSearchMaxThreads; }
 template <int L, int NP>
 __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
     DevState st, const int32_t* __restrict__ work, int64_t count, int ctr,
-    const float* __restrict__ tmpl_arena, const float* __restrict__ ref,
+    const float* __restrict__ tmpl_arena, const double* __restrict__ box,
+    const float* __restrict__ ref,
     const float* __restrict__ def, const int32_t* __restrict__ poi,
     const int32_t* __restrict__ seed, int32_t* __restrict__ uv_out, float* __restrict__ zncc_out,
     int32_t* __restrict__ status_out) {
@@ -236,20 +235,18 @@ __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
     const int wx0 = x0 + cu - G.S - G.M, wy0 = y0 + cv - G.S - G.M;
 
     float* win = lds;
-    float* colS = win + G.Wn * G.P;
-    float* colQ = colS + G.side * G.Wn;
-    float* scores = colQ;  // reused once the box sums are in registers
-    int* near_idx = reinterpret_cast<int*>(colQ + G.side * G.Wn);
+    float* scores = win + G.Wn * G.P;
+    int* near_idx = reinterpret_cast<int*>(scores + G.side * G.side);
     double* near_val = reinterpret_cast<double*>(
         (reinterpret_cast<uintptr_t>(near_idx + kNearCap) + 7) & ~uintptr_t(7));
     const int items = G.side * G.NB;
     const bool mine = tid < items;   // one candidate tile per lane
     const int r = mine ? tid % G.side : 0, b = mine ? tid / G.side : 0;
 
-    // 1. stage the window (shifted by the subset mean); non-finite pixels
-    //    become 0 and are counted.  Thread t walks rows t / P0 + k * (nthr / P0)
-    //    of columns t % P0 with P0 = min(P, nthr), no per-element division.
-    int nonfinite = 0;
+    // 1. stage the window (shifted by the subset mean; non-finite pixels
+    //    become 0, the box-sum images mark their candidates invalid).
+    //    Thread t walks rows t / P0 + k * (nthr / P0) of columns t % P0 with
+    //    P0 = min(P, nthr), no per-element division.
     {
       const int P0 = G.P < nthr ? G.P : nthr;
       const int rstep = nthr / P0;
@@ -263,116 +260,28 @@ __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
           float v = 0.f;
           if (c < G.Wn && rowin && X >= 0 && X < W) {
             v = grow[X];
-            if (!isfinite(v)) {
-              nonfinite = 1;
-              v = 0.f;
-            } else {
-              v -= c0;
-            }
+            v = isfinite(v) ? v - c0 : 0.f;
           }
           win[rr * G.P + c] = v;
         }
       }
     }
-    const int has_bad = __syncthreads_or(nonfinite);
-
-    // Rare path: exact integer counts of non-finite pixels per candidate,
-    // kept as a bit mask of the lane's tile.
-    unsigned badmask = 0;
-    if (has_bad) {
-      int* colN = reinterpret_cast<int*>(colS);
-      for (int c = tid; c < G.Wn; c += nthr) {
-        int cnt = 0;
-        for (int rr = 0; rr < G.Wn; ++rr) {
-          const int X = wx0 + c, Y = wy0 + rr;
-          if (X >= 0 && X < W && Y >= 0 && Y < H) cnt += !isfinite(gimg[(int64_t)Y * W + X]);
-          if (rr >= G.n1) {
-            const int Yo = wy0 + rr - G.n1;
-            if (X >= 0 && X < W && Yo >= 0 && Yo < H) cnt -= !isfinite(gimg[(int64_t)Yo * W + X]);
-          }
-          if (rr >= G.n1 - 1) colN[(rr - G.n1 + 1) * G.Wn + c] = cnt;
-        }
-      }
-      __syncthreads();
-      if (mine) {
-        for (int k = 0; k < L; ++k) {
-          const int c = b * L + k;
-          if (c >= G.side) break;
-          int cnt = 0;
-          for (int j = 0; j < G.n1; ++j) cnt += colN[r * G.Wn + c + j];
-          if (cnt > 0) badmask |= 1u << k;
-        }
-      }
-      __syncthreads();
-    }
-
-    // 2. column sums of (g - c0) and (g - c0)^2 over n1 rows: a direct sum
-    //    then a short running update (kSeg rows per task), accumulated in
-    //    FP64 (as cheap as FP32 here), stored as FP32.
-    const int nseg = (G.side + kSeg - 1) / kSeg;
-    for (int task = tid; task < G.Wn * nseg; task += nthr) {
-      const int c = task % G.Wn, r0 = (task / G.Wn) * kSeg;
-      const int r1 = min(r0 + kSeg, G.side);
-      double s = 0.0, q = 0.0;
-      for (int rr = r0; rr < r0 + G.n1; ++rr) {
-        const float v = win[rr * G.P + c];
-        s += (double)v;
-        q += (double)(v * v);
-      }
-      colS[r0 * G.Wn + c] = (float)s;
-      colQ[r0 * G.Wn + c] = (float)q;
-      for (int rr = r0 + 1; rr < r1; ++rr) {
-        const float vin = win[(rr + G.n1 - 1) * G.P + c];
-        const float vout = win[(rr - 1) * G.P + c];
-        s += (double)vin - (double)vout;
-        q += (double)(vin * vin) - (double)(vout * vout);
-        colS[rr * G.Wn + c] = (float)s;
-        colQ[rr * G.Wn + c] = (float)q;
-      }
-    }
     __syncthreads();
 
-    // 3. each lane's box sums over n1 columns (FP64).  The running chain
-    //    starts at the nearest multiple of 8 columns at or below the lane's
-    //    tile, so every candidate's sum is formed by the same operations
-    //    whatever the tile width: results do not depend on the tuning.
-    double sg[L], sq[L];
-    if (mine) {
-      double s = 0.0, q = 0.0;
-      const float* cs = colS + r * G.Wn;
-      const float* cq = colQ + r * G.Wn;
-      const int t0 = b * L, a0 = t0 & ~7;
-      for (int j = 0; j < G.n1; ++j) {
-        s += (double)cs[a0 + j];
-        q += (double)cq[a0 + j];
-      }
-      for (int c = a0 + 1; c <= t0; ++c) {
-        s += (double)cs[c + G.n1 - 1] - (double)cs[c - 1];
-        q += (double)cq[c + G.n1 - 1] - (double)cq[c - 1];
-      }
-#pragma unroll
-      for (int k = 0; k < L; ++k) {
-        const int c = t0 + k;
-        if (k > 0 && c < G.side) {
-          s += (double)cs[c + G.n1 - 1] - (double)cs[c - 1];
-          q += (double)cq[c + G.n1 - 1] - (double)cq[c - 1];
-        }
-        sg[k] = s;
-        sq[k] = q;
-      }
-    }
-    __syncthreads();
-
-    // 4. cross terms and scores.
+    // 2. cross terms; window sums from the box-sum images; scores.
     const int tp = P.tmpl_pitch;
     const float* tm = tmpl_arena + P.tmpl_off + (int64_t)(g - P.poi_off) * G.n1 * tp;
     const double dfd = R->df;
+    const float df = (float)dfd;
     const double rnd = 1.0 / (double)G.n;
     const double tsum = R->tsum;
     if (mine) {
       double tot[L];
       const float* wrow = win + r * G.P + b * L;
       cross_terms<L, NP>(tm, tp, G.n1, wrow, G.P, tot);   // G.NP == NP for this group
+      const int64_t plane = (int64_t)W * H;
+      const double* s1img = box + P.box_off + 2 * plane;
+      const double* s2img = s1img + plane;
 #pragma unroll
       for (int k = 0; k < L; ++k) {
         const int c = b * L + k;
@@ -380,13 +289,17 @@ __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
         const int du = cu - G.S + c, dv = cv - G.S + r;
         const bool adm = x0 + du - G.M >= 0 && x0 + du + G.M <= W - 1 && y0 + dv - G.M >= 0 &&
                          y0 + dv + G.M <= H - 1;
-        const double var = sq[k] - sg[k] * sg[k] * rnd;
-        const double sumg2 = sq[k] + 2.0 * (double)c0 * sg[k] + (double)G.n * (double)c0 * (double)c0;
         float sc = kNegInf;
-        if (adm && !((badmask >> k) & 1u) && not_flat(var, sumg2)) {
-          const double num = tot[k] - sg[k] * rnd * tsum;
-          sc = (float)(num / (dfd * sqrt(var)));
-          if (!isfinite(sc)) sc = kNegInf;
+        if (adm) {
+          const int64_t o = (int64_t)(y0 + dv) * W + (x0 + du);
+          const double sg = s1img[o], sq = s2img[o];   // exact sums of g and g^2
+          const double var = sq - sg * sg * rnd;
+          if (sq >= 0.0 && not_flat(var, sq)) {
+            // sum t (g - gbar) = sum t (g - c0) - (gbar - c0) sum t
+            const double num = tot[k] - (sg * rnd - (double)c0) * tsum;
+            sc = (float)num / (df * sqrtf((float)var));
+            if (!isfinite(sc)) sc = kNegInf;
+          }
         }
         scores[r * G.side + c] = sc;
       }
@@ -507,8 +420,8 @@ static hipError_t launch_search_group(const DevState& st, const SearchGroup& gr,
   int64_t blocks = (int64_t)occ * num_cu;
   if (blocks > gr.count) blocks = gr.count;
   hipLaunchKernelGGL((search_f32_kernel<L, NP>), dim3((unsigned)blocks), dim3(threads), lds, s, st,
-                     st.work + gr.begin, gr.count, ctr, st.tmpl, ref, def, poi, seed, uv, zncc,
-                     status);
+                     st.work + gr.begin, gr.count, ctr, st.tmpl, st.box, ref, def, poi, seed, uv,
+                     zncc, status);
   return hipGetLastError();
 }
 

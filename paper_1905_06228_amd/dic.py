@@ -53,7 +53,7 @@ class Tuning(ctypes.Structure):
 EXPORTS = [
     "dic_plan_create", "dic_plan_workspace_size", "dic_plan_bind", "dic_plan_get_tuning",
     "dic_plan_set_tuning", "dic_plan_autotune", "dic_plan_invalidate_reference",
-    "dic_prepare_reference", "dic_integer_search", "dic_icgn_refine", "dic_correlate",
+    "dic_prepare_reference", "dic_prepare_deformed", "dic_integer_search", "dic_icgn_refine", "dic_correlate",
     "dic_znssd_backward", "dic_seed_update", "dic_poi_grid", "dic_plan_destroy",
     "dic_status_string", "dic_last_error",
 ]
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.dic_plan_autotune.argtypes = [P, V, V, V, V, V, V, V, V]
     L.dic_plan_invalidate_reference.argtypes = [P]
     L.dic_prepare_reference.argtypes = [P, V, V, V]
+    L.dic_prepare_deformed.argtypes = [P, V, V]
     L.dic_integer_search.argtypes = [P, V, V, V, V, V, V, V, V]
     L.dic_icgn_refine.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V]
     L.dic_correlate.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V, V, V]
@@ -227,6 +228,10 @@ class Plan:
         d = self.device
         _check(self.L.dic_prepare_reference(self._h, _ptr(ref, torch.float32, d, "ref"),
                                             _ptr(pois, torch.int32, d, "pois"), _stream()))
+
+    def prepare_deformed(self, defm: torch.Tensor) -> None:
+        _check(self.L.dic_prepare_deformed(self._h, _ptr(defm, torch.float32, self.device, "def"),
+                                           _stream()))
 
     def integer_search(self, ref, defm, pois, seed=None, out=None):
         d, N = self.device, self.N

@@ -224,3 +224,33 @@ def test_autotune_keeps_results(affine_small):
     o = host(plan.correlate(F, G, Q))
     for k in base:
         np.testing.assert_array_equal(base[k], o[k], err_msg=k)
+
+
+def test_cached_precomputation_and_invalidate(affine_small):
+    pr, pois, _ = affine_small
+    F, G, Q = to_dev(pr.ref), to_dev(pr.defm), to_dev(pois)
+    plan = dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois), flags=dic.FLAG_CACHE_REF_PREP)
+    a = host(plan.correlate(F, G, Q))
+    G2 = G.clone()
+    b = host(plan.correlate(F, G2, Q))           # new pointer: deformed sums recomputed
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    G2.mul_(1.5).add_(3.0)                        # changed in place: caches are stale ...
+    plan.invalidate_reference()                   # ... until invalidated
+    c = host(plan.correlate(F, G2, Q))
+    np.testing.assert_array_equal(a["uv"], c["uv"])   # ZNCC ignores affine intensity changes
+    np.testing.assert_allclose(a["p"], c["p"], atol=1e-5)
+
+
+def test_autotune_cache_file(affine_small, tmp_path, monkeypatch):
+    import json
+    pr, pois, _ = affine_small
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("DIC_AUTOTUNE_CACHE", str(path))
+    F, G, Q = to_dev(pr.ref), to_dev(pr.defm), to_dev(pois)
+    plan = dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois))
+    tu = plan.autotune(F, G, Q)
+    doc = json.load(open(path))
+    assert list(doc.values()) == [list(tu)]
+    again = dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois))   # bind reads the cache
+    assert again.tuning == tu
