@@ -8,8 +8,9 @@
 // restaged only when the warped subset leaves it.  Sample positions are an
 // integer base (POI + rounded translation) plus an FP32 local offset below
 // ~M+slack pixels.  Eight sums per iteration (sum g, sum g^2 and the six
-// steepest-descent products) are Kahan-compensated per lane and reduced in
-// FP64; with the precomputed sum SD_i (f_i - fbar) and sum SD_i the
+// steepest-descent products) of FP32 terms are accumulated per lane in FP64
+// (compensation for free: an FP64 add costs what an FP32 add does here) and
+// reduced across the wave with DPP; with the precomputed sum SD_i (f_i - fbar) and sum SD_i the
 // right-hand side needs no second pass:
 //   sum SD_i e_i = sum SD_i (f_i - fbar) - (df/dg) (sum SD_i g_i - gbar sum SD_i).
 // The 6x6 solve and the warp composition run in FP64.
@@ -108,7 +109,7 @@ template <int MAXS, bool kClamp>
 __device__ __forceinline__ void iter_pass(const float* src, int pitch, int ox, int oy, int maxc,
                                           int maxr, int n, const Warp32& w, float c0,
                                           const float* fxs, const float* fys, const int* dxy,
-                                          Kahan* K) {
+                                          double* K) {
   const int lane = lane_id();
 #pragma unroll
   for (int k = 0; k < MAXS; ++k) {
@@ -118,14 +119,14 @@ __device__ __forceinline__ void iter_pass(const float* src, int pitch, int ox, i
           interp32<kClamp>(src, pitch, ox, oy, warp_x(w, dx, dy), warp_y(w, dx, dy), maxc, maxr) -
           c0;
       const float fg = fxs[k] * gs, hg = fys[k] * gs;
-      K[0].add(gs);
-      K[1].add(gs * gs);
-      K[2].add(fg);
-      K[3].add(fg * dx);
-      K[4].add(fg * dy);
-      K[5].add(hg);
-      K[6].add(hg * dx);
-      K[7].add(hg * dy);
+      K[0] += (double)gs;
+      K[1] += (double)(gs * gs);
+      K[2] += (double)fg;
+      K[3] += (double)(fg * dx);
+      K[4] += (double)(fg * dy);
+      K[5] += (double)hg;
+      K[6] += (double)(hg * dx);
+      K[7] += (double)(hg * dy);
     }
   }
 }
@@ -134,7 +135,7 @@ template <int MAXS, bool kClamp>
 __device__ __forceinline__ void final_pass(const float* src, int pitch, int ox, int oy, int maxc,
                                            int maxr, int n, const Warp32& w, float c0,
                                            const int* dxy, const float* __restrict__ tm, int tp,
-                                           int M, Kahan* K) {
+                                           int M, double* K) {
   const int lane = lane_id();
 #pragma unroll
   for (int k = 0; k < MAXS; ++k) {
@@ -144,9 +145,9 @@ __device__ __forceinline__ void final_pass(const float* src, int pitch, int ox, 
       const float gs =
           interp32<kClamp>(src, pitch, ox, oy, warp_x(w, dx, dy), warp_y(w, dx, dy), maxc, maxr) -
           c0;
-      K[0].add(gs);
-      K[1].add(gs * gs);
-      K[2].add(tm[((int)dy + M) * tp + (int)dx + M] * gs);
+      K[0] += (double)gs;
+      K[1] += (double)(gs * gs);
+      K[2] += (double)(tm[((int)dy + M) * tp + (int)dx + M] * gs);
     }
   }
 }
@@ -176,9 +177,9 @@ struct Patch {
   }
 };
 
-__device__ __forceinline__ void reduce8(const Kahan* K, double* S) {
+__device__ __forceinline__ void reduce8(const double* K, double* S) {
 #pragma unroll
-  for (int a = 0; a < 8; ++a) S[a] = wave_sum(K[a].value());
+  for (int a = 0; a < 8; ++a) S[a] = wave_sum_dpp(K[a]);
 }
 
 }  // namespace
@@ -255,7 +256,7 @@ __global__ void __launch_bounds__(512) icgn_f32_kernel(
           status = DIC_POI_OUT_OF_BOUNDS;
           break;
         }
-        Kahan K[8];
+        double K[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (patch.ensure(gimg, W, H, xl, xh, yl, yh))
           iter_pass<MAXS, false>(patch.buf, pside, w.bx - patch.x0, w.by - patch.y0, 0, 0, n, w,
                                  c0, fxs, fys, dxy, K);
@@ -293,16 +294,16 @@ __global__ void __launch_bounds__(512) icgn_f32_kernel(
           status = DIC_POI_OUT_OF_BOUNDS;
         } else {
           const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * P.tmpl_pitch;
-          Kahan K[3];
+          double K[3] = {0, 0, 0};
           if (patch.ensure(gimg, W, H, xl, xh, yl, yh))
             final_pass<MAXS, false>(patch.buf, pside, w.bx - patch.x0, w.by - patch.y0, 0, 0, n, w,
                                     c0, dxy, tm, P.tmpl_pitch, M, K);
           else
             final_pass<MAXS, true>(gimg, W, w.bx, w.by, W - 4, H - 4, n, w, c0, dxy, tm,
                                    P.tmpl_pitch, M, K);
-          const double s0 = wave_sum(K[0].value());
-          const double s1 = wave_sum(K[1].value());
-          const double s2 = wave_sum(K[2].value());
+          const double s0 = wave_sum_dpp(K[0]);
+          const double s1 = wave_sum_dpp(K[1]);
+          const double s2 = wave_sum_dpp(K[2]);
           if (!isfinite(s0) || !isfinite(s1)) {
             status = DIC_POI_NAN_INPUT;
           } else {

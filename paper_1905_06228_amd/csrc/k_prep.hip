@@ -140,9 +140,9 @@ __device__ __forceinline__ void write_bad_record(RefRec* R, int status, int lane
 
 // FP32 form: one wave per POI.  Mean and norm of the subset in FP64 (they
 // decide ZERO_VARIANCE exactly as the FP64 definition does); steepest-descent
-// sums and the 21 Hessian sums in FP32 with Kahan compensation; centring,
-// factorisation and singularity test in FP64.  Also stores the float search
-// template f_i - fbar.
+// products and the 21 Hessian products in FP32, accumulated per lane in FP64
+// and reduced with DPP; centring, factorisation and singularity test in
+// FP64.  Also stores the float search template f_i - fbar.
 __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
                                                            const float* __restrict__ ref,
                                                            const int32_t* __restrict__ poi) {
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
   const float fbar_f = (float)fbar;
 
   double q = 0.0, sq = 0.0, ts = 0.0;
-  Kahan ksd[6], ksdf[6], kh[21];
+  double ksd[6] = {0}, ksdf[6] = {0}, kh[21] = {0};
   for (int k = lane; k < n; k += kWave) {
     const int r = k / n1, c = k - r * n1;
     const int64_t idx = (int64_t)(y0 - M + r) * W + (x0 - M + c);
@@ -201,23 +201,23 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
     const float sd[6] = {fx, fx * dx, fx * dy, fy, fy * dx, fy * dy};
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
-      ksd[a].add(sd[a]);
-      ksdf[a].add(sd[a] * t);
+      ksd[a] += (double)sd[a];
+      ksdf[a] += (double)(sd[a] * t);
 #pragma unroll
-      for (int b = 0; b <= a; ++b) kh[tri(a, b)].add(sd[a] * sd[b]);
+      for (int b = 0; b <= a; ++b) kh[tri(a, b)] += (double)(sd[a] * sd[b]);
     }
   }
-  q = wave_sum(q);
-  sq = wave_sum(sq);
-  ts = wave_sum(ts);
+  q = wave_sum_dpp(q);
+  sq = wave_sum_dpp(sq);
+  ts = wave_sum_dpp(ts);
   double sdsum[6], sdfsum[6], h[21];
 #pragma unroll
   for (int a = 0; a < 6; ++a) {
-    sdsum[a] = wave_sum(ksd[a].value());
-    sdfsum[a] = wave_sum(ksdf[a].value());
+    sdsum[a] = wave_sum_dpp(ksd[a]);
+    sdfsum[a] = wave_sum_dpp(ksdf[a]);
   }
 #pragma unroll
-  for (int a = 0; a < 21; ++a) h[a] = wave_sum(kh[a].value());
+  for (int a = 0; a < 21; ++a) h[a] = wave_sum_dpp(kh[a]);
 
   int status = DIC_POI_OK;
   double L[21], rd[6];

@@ -4,7 +4,8 @@
 //
 // One wave per POI.  Each lane interpolates its samples once (value and the
 // analytic gradient of the interpolant from the derivative weights), keeps
-// them in registers, reduces three compensated sums, and then scatters
+// them in registers, reduces four sums (per-lane FP64, DPP across the wave),
+// and then scatters
 //   dC/dg_i = (2/dg) (ZNCC ghat_i - fhat_i)
 // through the 16 bicubic weights into grad_def, either with float atomics or,
 // in deterministic mode, as 2^-40 fixed-point int64 atomics (integer addition
@@ -90,7 +91,7 @@ __global__ void __launch_bounds__(256) znssd_kernel(
   const float* fimg = ref + P.ref_off;
   Samp sm[MAXS];
   float tv[MAXS];
-  Kahan K[4];
+  double K[4] = {0, 0, 0, 0};
   if (ok) {
     const float c0 = (float)R->fbar;
 #pragma unroll
@@ -104,15 +105,15 @@ __global__ void __launch_bounds__(256) znssd_kernel(
                             dy + fmaf(vx, dx, fmaf(vy, dy, vf)));
         sm[k].g -= c0;
         tv[k] = fimg[(int64_t)(y0 + s / n1 - M) * W + (x0 + s % n1 - M)] - c0;
-        K[0].add(sm[k].g);
-        K[1].add(sm[k].g * sm[k].g);
-        K[2].add(tv[k] * sm[k].g);
-        K[3].add(tv[k]);
+        K[0] += (double)sm[k].g;
+        K[1] += (double)(sm[k].g * sm[k].g);
+        K[2] += (double)(tv[k] * sm[k].g);
+        K[3] += (double)tv[k];
       }
     }
   }
-  const double s0 = wave_sum(K[0].value()), s1 = wave_sum(K[1].value()),
-               s2 = wave_sum(K[2].value()), s3 = wave_sum(K[3].value());
+  const double s0 = wave_sum_dpp(K[0]), s1 = wave_sum_dpp(K[1]), s2 = wave_sum_dpp(K[2]),
+               s3 = wave_sum_dpp(K[3]);
   const double nn = (double)n;
   const double ms = s0 / nn, var = s1 - s0 * ms;
   const double df = R->df, dg = sqrt(var);
@@ -165,7 +166,7 @@ __global__ void __launch_bounds__(256) znssd_kernel(
     }
   }
 #pragma unroll
-  for (int a = 0; a < 6; ++a) gp[a] = wave_sum(gp[a]);
+  for (int a = 0; a < 6; ++a) gp[a] = wave_sum_dpp(gp[a]);
   if (lane == 0) {
     if (c_out) c_out[g] = ok ? (float)(2.0 - 2.0 * zn) : nanf("");
     if (grad_p)
