@@ -44,8 +44,17 @@ struct Layout {
 
 const dic_tuning_t kDefaultTuning = {8, 0, 4, 4};  // block, occupancy, waves, slack
 
+// Whether search form `block` can run windows up to +-maxS with subsets up
+// to radius maxM.
+bool search_fits(int maxM, int maxS, int block) {
+  if (block == kMfmaBlock)
+    return maxS <= kMfmaMaxS && search_mfma_wave_lds(mfma_kb(maxM), maxM) <= 160 * 1024;
+  return search_lds_bytes(maxM, maxS, block) <= 160 * 1024 &&
+         search_threads(maxS, block) <= search_max_threads();
+}
+
 bool tuning_valid(const dic_tuning_t& t) {
-  const bool blk = t.search_block == 4 || t.search_block == 8;
+  const bool blk = t.search_block == 4 || t.search_block == 8 || t.search_block == kMfmaBlock;
   const bool thr = t.search_occupancy >= 0 && t.search_occupancy <= 16;
   return blk && thr && t.icgn_waves >= 1 && t.icgn_waves <= 8 && t.icgn_slack >= 0 &&
          t.icgn_slack <= 16;
@@ -164,12 +173,13 @@ dic_status_t prepare(dic_plan_t p, const float* ref, const int32_t* poi, hipStre
   return DIC_SUCCESS;
 }
 
-// Runs of the work list that share the search kernel's template row length.
+// Runs of the work list that share the search kernel's template row length
+// (vector-ALU form) or K-block count (matrix-core form).
 std::vector<SearchGroup> search_groups(const dic_plan_s* p, int block) {
   std::vector<SearchGroup> g;
   int64_t at = 0;
   for (auto& run : p->m_runs) {
-    const int np = search_np(run.first, block);
+    const int np = block == kMfmaBlock ? mfma_kb(run.first) : search_np(run.first, block);
     if (g.empty() || g.back().np != np) g.push_back({np, at, 0});
     g.back().count += run.second;
     at += run.second;
@@ -195,8 +205,12 @@ dic_status_t enqueue_search(dic_plan_t p, const float* ref, const float* def, co
     dic_status_t r = prepare_deformed(p, def, s, false);
     if (r) return r;
     DIC_HIP(launch_reset_counters(p->st, s));
-    DIC_HIP(launch_search_f32(p->st, p->tuning, groups.data(), (int)groups.size(), ref, def, poi,
-                              seed, uv, zn, status, p->num_cu, s));
+    if (p->tuning.search_block == kMfmaBlock)
+      DIC_HIP(launch_search_mfma(p->st, p->tuning, groups.data(), (int)groups.size(), ref, def,
+                                 poi, seed, uv, zn, status, p->num_cu, s));
+    else
+      DIC_HIP(launch_search_f32(p->st, p->tuning, groups.data(), (int)groups.size(), ref, def,
+                                poi, seed, uv, zn, status, p->num_cu, s));
   } else {
     DIC_HIP(launch_search_f64(p->st, p->dpairs.data(), ref, def, poi, seed, uv, zn, status, s));
   }
@@ -369,8 +383,9 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
     if (p->m_runs.empty() || p->m_runs.back().first != m) p->m_runs.emplace_back(m, 0);
     ++p->m_runs.back().second;
   }
-  if (f32 && (search_lds_bytes(p->maxM, p->maxS, p->tuning.search_block) > 160 * 1024 ||
-              search_threads(p->maxS, p->tuning.search_block) > search_max_threads())) {
+  // the matrix-core search where the window allows it, else the vector-ALU form
+  if (f32 && search_fits(p->maxM, p->maxS, kMfmaBlock)) p->tuning.search_block = kMfmaBlock;
+  if (f32 && !search_fits(p->maxM, p->maxS, p->tuning.search_block)) {
     delete p;
     return fail(DIC_ERR_UNSUPPORTED, "search window exceeds the 160 KiB LDS of a CU");
   }
@@ -405,9 +420,10 @@ dic_status_t dic_plan_set_tuning(dic_plan_t p, const dic_tuning_t* in) {
   dic_status_t r = check_plan(p, false);
   if (r) return r;
   if (!in || !tuning_valid(*in)) return fail(DIC_ERR_INVALID_ARGUMENT, "invalid tuning");
-  if (p->fp32() && (search_lds_bytes(p->maxM, p->maxS, in->search_block) > 160 * 1024 ||
-                    search_threads(p->maxS, in->search_block) > search_max_threads()))
-    return fail(DIC_ERR_UNSUPPORTED, "search tile exceeds LDS or the widest workgroup");
+  if (p->fp32() && !search_fits(p->maxM, p->maxS, in->search_block))
+    return fail(DIC_ERR_UNSUPPORTED,
+                "search form does not fit: LDS, workgroup width, or radius above the "
+                "matrix-core limit");
   p->tuning = *in;
   drop_graphs(p);
   return DIC_SUCCESS;
@@ -461,7 +477,8 @@ dic_status_t dic_plan_bind(dic_plan_t p, void* ws, size_t bytes, dic_stream_t st
     auto it = m.find(tune_key(p));
     if (it != m.end() && it->second.size() == 4) {
       dic_tuning_t t = {it->second[0], it->second[1], it->second[2], it->second[3]};
-      if (tuning_valid(t)) p->tuning = t;
+      if (tuning_valid(t) && (!p->fp32() || search_fits(p->maxM, p->maxS, t.search_block)))
+        p->tuning = t;
     }
   }
   return DIC_SUCCESS;
@@ -649,15 +666,14 @@ dic_status_t dic_plan_autotune(dic_plan_t p, const float* ref, const float* def,
     return DIC_SUCCESS;
   };
   float best_ms = 1e30f;
-  const int blocks[] = {4, 8};
+  const int blocks[] = {4, 8, kMfmaBlock};
   const int occs[] = {0, 2, 3};
   for (int b : blocks)
     for (int o : occs) {
       dic_tuning_t c = best;
       c.search_block = b;
       c.search_occupancy = o;
-      if (search_lds_bytes(p->maxM, p->maxS, b) > 160 * 1024) continue;
-      if (search_threads(p->maxS, b) > search_max_threads()) continue;
+      if (!search_fits(p->maxM, p->maxS, b)) continue;
       p->tuning = c;
       float ms = 0.f;
       r = time_it([&] { return enqueue_search(p, ref, def, poi, nullptr, uv, fs, is, s); }, &ms);

@@ -82,6 +82,19 @@ hipError_t launch_search_f32(const DevState& st, const dic_tuning_t& tu,
                              const float* def, const int32_t* poi, const int32_t* seed,
                              int32_t* uv, float* zncc, int32_t* status, int num_cu,
                              hipStream_t s);
+// Matrix-core search (tuning search_block == kMfmaBlock): windows up to
+// +-kMfmaMaxS, grouped by the number of 16-wide K blocks a template row of
+// 2M+1 plus the 32 Toeplitz shifts spans.
+constexpr int kMfmaBlock = 32;
+constexpr int kMfmaMaxS = 16;
+__host__ __device__ __forceinline__ int mfma_kb(int M) { return (2 * M + 48) / 16; }
+hipError_t launch_search_mfma(const DevState& st, const dic_tuning_t& tu,
+                              const SearchGroup* groups, int ngroups, const float* ref,
+                              const float* def, const int32_t* poi, const int32_t* seed,
+                              int32_t* uv, float* zncc, int32_t* status, int num_cu,
+                              hipStream_t s);
+// LDS bytes of one matrix-core search wave (one wave per workgroup).
+size_t search_mfma_wave_lds(int kb, int maxM);
 // Template row length the search kernel with tile width `block` uses.
 __host__ __device__ __forceinline__ int search_np(int M, int block) {
   return (2 * M + 1 + block - 1) / block * block;

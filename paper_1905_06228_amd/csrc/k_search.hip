@@ -1,24 +1,24 @@
 // Brute-force integer search (Sec. 2.1): Eq. (1) at every candidate of a
 // (2S+1)^2 window per POI.
 //
-// FP32 batched form.  One workgroup per POI at a time, persistent over a
-// shared work counter.  The deformed window (2S+2M+1 square, shifted by the
-// subset mean so sums stay small) is staged in LDS once.  Per candidate the
-// window sums sum(g) and sum(g^2) come from running box sums (Kahan), and the
-// cross term sum(t_i g_i) with the mean-free template t from a register-
-// blocked loop: a lane owns L horizontally adjacent candidates, keeps a
-// sliding window of L grey levels in registers and reads each template value
-// once from scalar memory, so one LDS read feeds L FMAs.  Per template row
-// the L partial sums are added to Kahan totals.  The FP32 maximum selects the
-// candidates within 2e-5 of it, which one wave re-scores two-pass in FP64
-// before the tie rule picks the winner.
-#include "dic_device.h"
+// FP32 batched form on the vector ALUs.  One workgroup per POI at a time,
+// persistent over a shared work counter.  The deformed window (2S+2M+1
+// square, shifted by the subset mean so sums stay small) is staged in LDS
+// once.  Per candidate the window sums sum(g) and sum(g^2) come from the
+// FP64 box-sum images, and the cross term sum(t_i g_i) with the mean-free
+// template t from a register-blocked loop: a lane owns L horizontally
+// adjacent candidates, keeps a sliding window of grey levels in registers and
+// reads each template value once from scalar memory, so one LDS read feeds L
+// FMAs.  Row partial sums accumulate in FP64.  The FP32 maximum selects the
+// candidates within 2e-5 of it; one wave re-scores them in FP64 (always at
+// least the winner) and the tie rule picks the smallest row-major index
+// within 1e-12 of the FP64 maximum.
+#include "search_common.h"
 
 namespace dic {
 
 namespace {
 
-constexpr int kNearCap = 64;   // near-tie list capacity per POI (a sweep path covers more)
 constexpr int kSearchMaxThreads = 640;  // lanes of the widest search workgroup
 
 struct SearchGeom {
@@ -51,55 +51,6 @@ __host__ __device__ __forceinline__ size_t search_lds_floats(const SearchGeom& G
 __host__ __device__ __forceinline__ int search_items(int S, int L) {
   const int side = 2 * S + 1;
   return side * ((side + L - 1) / L);
-}
-
-// Sum over one workgroup; every thread returns the same value.
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  const int nw = blockDim.x / kWave, wid = threadIdx.x / kWave;
-  v = wave_sum(v);
-  __syncthreads();
-  if (lane_id() == 0) red[wid] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int k = 0; k < nw; ++k) t += red[k];
-  return t;
-}
-
-// FP64 two-pass coefficient of one candidate (Eq. (1) as written), computed
-// by the whole workgroup from the images in global memory.
-__device__ double rescore_f64(const float* __restrict__ f, const float* __restrict__ gimg, int W,
-                              int x0, int y0, int xg, int yg, int M, double fbar, double df,
-                              double* red, bool* valid) {
-  const int tid = threadIdx.x, nthr = blockDim.x, n1 = 2 * M + 1, n = n1 * n1;
-  double sg = 0.0, bad = 0.0;
-  for (int k = tid; k < n; k += nthr) {
-    const int r = k / n1, c = k - r * n1;
-    const float v = gimg[(int64_t)(yg - M + r) * W + (xg - M + c)];
-    if (!isfinite(v)) bad = 1.0;
-    else sg += (double)v;
-  }
-  sg = block_sum(sg, red);
-  bad = block_sum(bad, red);
-  if (bad != 0.0) {
-    *valid = false;
-    return 0.0;
-  }
-  const double gbar = sg / (double)n;
-  double num = 0.0, q = 0.0, sq = 0.0;
-  for (int k = tid; k < n; k += nthr) {
-    const int r = k / n1, c = k - r * n1;
-    const double gv = (double)gimg[(int64_t)(yg - M + r) * W + (xg - M + c)];
-    const double fv = (double)f[(int64_t)(y0 - M + r) * W + (x0 - M + c)];
-    const double d = gv - gbar;
-    num += (fv - fbar) * d;
-    q += d * d;
-    sq += gv * gv;
-  }
-  num = block_sum(num, red);
-  q = block_sum(q, red);
-  sq = block_sum(sq, red);
-  *valid = not_flat(q, sq);
-  return num / (df * sqrt(q));
 }
 
 // Cross terms sum_i t_i g_i of L horizontally adjacent candidates.  Every
@@ -200,7 +151,6 @@ __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
   extern __shared__ float lds[];
   __shared__ int s_item;
   __shared__ float s_wmax[16];
-  __shared__ double s_red[16];
   __shared__ int s_cnt;
   const int tid = threadIdx.x, nthr = blockDim.x, lane = lane_id(), wid = tid / kWave;
   const float kNegInf = -INFINITY;
@@ -317,81 +267,77 @@ __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
     float mm = kNegInf;
     for (int k = 0; k < nthr / kWave; ++k) mm = fmaxf(mm, s_wmax[k]);
 
-    // 5. Candidates within 2e-5 of the FP32 maximum.  The FP32 scores are
-    //    within ~1e-6 of Eq. (1), so a single such candidate is the FP64 argmax
-    //    and its FP32 score is within tolerance.  Two or more are re-scored
-    //    two-pass in FP64 and the tie rule picks the smallest row-major index
-    //    within 1e-12 of the FP64 maximum.
-    int pick = -1;
-    double best = -INFINITY;
+    // 5. Candidates within 2e-5 of the FP32 maximum (the FP32 scores are
+    //    within ~1e-6 of Eq. (1)) go to a list; wave 0 re-scores them in FP64
+    //    and applies the tie rule: the smallest row-major index within 1e-12
+    //    of the FP64 maximum.  A list that overflows is swept twice in index
+    //    order instead.
     if (mm > kNegInf) {
       const float thr = mm - 2e-5f;
-      const float* fimg = ref + P.ref_off;
       for (int c = tid; c < K; c += nthr)
         if (scores[c] >= thr) {
           const int slot = atomicAdd(&s_cnt, 1);
           if (slot < kNearCap) near_idx[slot] = c;
         }
-      __syncthreads();
-      const int cnt = s_cnt;
-      if (cnt == 1) {
-        pick = near_idx[0];
-        best = (double)scores[pick];
-      } else if (cnt <= kNearCap) {
+    }
+    __syncthreads();
+    if (wid == 0) {
+      const float* fimg = ref + P.ref_off;
+      const double* s1img = box + P.box_off + 2 * (int64_t)W * H;
+      auto rescore = [&](int cand) -> double {
+        const int rr = cand / G.side, cc = cand - rr * G.side;
+        const int xg = x0 + cu - G.S + cc, yg = y0 + cv - G.S + rr;
+        bool ok;
+        const double z = rescore_wave(fimg, gimg, W, x0, y0, xg, yg, G.M, R->fbar, dfd,
+                                      s1img + (int64_t)yg * W + xg, &ok);
+        return ok ? z : -INFINITY;
+      };
+      int pick = -1;
+      double best = -INFINITY;
+      const int cnt = mm > kNegInf ? uniform(s_cnt) : 0;
+      if (cnt <= kNearCap) {
         double cmax = -INFINITY;
         for (int e = 0; e < cnt; ++e) {
-          const int cand = near_idx[e];
-          const int rr = cand / G.side, cc = cand - rr * G.side;
-          bool ok;
-          const double z = rescore_f64(fimg, gimg, W, x0, y0, x0 + cu - G.S + cc,
-                                       y0 + cv - G.S + rr, G.M, R->fbar, dfd, s_red, &ok);
-          const double zv = ok ? z : -INFINITY;
-          if (tid == 0) near_val[e] = zv;
-          cmax = fmax(cmax, zv);
+          const double z = rescore(uniform(near_idx[e]));
+          if (lane == 0) near_val[e] = z;
+          cmax = fmax(cmax, z);
         }
-        __syncthreads();
+        wave_lds_sync();
         if (cmax > -INFINITY)
-          for (int e = 0; e < cnt; ++e)
-            if (near_val[e] >= cmax - 1e-12 && (pick < 0 || near_idx[e] < pick)) {
-              pick = near_idx[e];
+          for (int e = 0; e < cnt; ++e) {
+            const int cand = near_idx[e];
+            if (near_val[e] >= cmax - 1e-12 && (pick < 0 || cand < pick)) {
+              pick = cand;
               best = near_val[e];
             }
+          }
       } else {
-        // More near ties than the list holds: two sweeps in index order.
+        const float thr = mm - 2e-5f;
         double cmax = -INFINITY;
-        for (int cand = 0; cand < K; ++cand) {
-          if (!(scores[cand] >= thr)) continue;
-          const int rr = cand / G.side, cc = cand - rr * G.side;
-          bool ok;
-          const double z = rescore_f64(fimg, gimg, W, x0, y0, x0 + cu - G.S + cc,
-                                       y0 + cv - G.S + rr, G.M, R->fbar, dfd, s_red, &ok);
-          if (ok) cmax = fmax(cmax, z);
-        }
+        for (int cand = 0; cand < K; ++cand)
+          if (scores[cand] >= thr) cmax = fmax(cmax, rescore(cand));
         for (int cand = 0; cand < K && pick < 0 && cmax > -INFINITY; ++cand) {
           if (!(scores[cand] >= thr)) continue;
-          const int rr = cand / G.side, cc = cand - rr * G.side;
-          bool ok;
-          const double z = rescore_f64(fimg, gimg, W, x0, y0, x0 + cu - G.S + cc,
-                                       y0 + cv - G.S + rr, G.M, R->fbar, dfd, s_red, &ok);
-          if (ok && z >= cmax - 1e-12) {
+          const double z = rescore(cand);
+          if (z >= cmax - 1e-12) {
             pick = cand;
             best = z;
           }
         }
       }
-    }
-    if (tid == 0) {
-      if (pick < 0) {
-        uv_out[2 * g] = 0;
-        uv_out[2 * g + 1] = 0;
-        zncc_out[g] = nanf("");
-        status_out[g] = DIC_POI_NO_VALID_CANDIDATE;
-      } else {
-        const int rr = pick / G.side, cc = pick - rr * G.side;
-        uv_out[2 * g] = cu - G.S + cc;
-        uv_out[2 * g + 1] = cv - G.S + rr;
-        zncc_out[g] = (float)best;
-        status_out[g] = DIC_POI_OK;
+      if (lane == 0) {
+        if (pick < 0) {
+          uv_out[2 * g] = 0;
+          uv_out[2 * g + 1] = 0;
+          zncc_out[g] = nanf("");
+          status_out[g] = DIC_POI_NO_VALID_CANDIDATE;
+        } else {
+          const int rr = pick / G.side, cc = pick - rr * G.side;
+          uv_out[2 * g] = cu - G.S + cc;
+          uv_out[2 * g + 1] = cv - G.S + rr;
+          zncc_out[g] = (float)best;
+          status_out[g] = DIC_POI_OK;
+        }
       }
     }
     __syncthreads();

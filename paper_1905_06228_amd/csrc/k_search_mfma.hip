@@ -1,0 +1,519 @@
+// Brute-force integer search (Sec. 2.1, Eq. (1)) on the matrix cores:
+// bf16 filter, FP64 decision.
+//
+// The cross terms C(dv, du) = sum_{r,c} t(r, c) g'(r + dv, c + du) of all
+// candidates form a correlation, which per template row r is a product of
+// two matrices: the window rows r..r+31 (32 x K, K running over window
+// columns c') and a Toeplitz matrix B_r(c', du) = t(r, c' - du).  One wave
+// per POI accumulates sum_r A_r B_r with v_mfma_f32_32x32x16_bf16 for the
+// 32 x 32 candidates dv, du in [0, 32); a window of 33 x 33 candidates adds a
+// second tile for dv, du in [1, 33) (its A operand is the next row's, loaded
+// once for both tiles) and two corner candidates on the vector ALUs.
+//
+// Operands are rounded to bf16 (t and g' = g - fbar each to 8 significant
+// bits), so each product carries a relative error below 2^-7 + 3 * 2^-16 and
+// the FP32 accumulation adds at most (terms) * 2^-24.  With Cauchy-Schwarz,
+// sum |t| |g'| <= df * sqrt(sum g'^2), the approximate coefficient of every
+// candidate is within
+//   E = kappa * sqrt(sum g'^2 / sum (g - gbar)^2)
+// of Eq. (1), kappa = 8.5e-3 covering all of the above with margin.  The
+// exact maximum therefore lies in { c : s_c + E_c >= max_k (s_k - E_k) };
+// those few candidates (about two per POI on speckle) are re-scored in FP64
+// in index order and the tie rule picks the smallest row-major index within
+// 1e-12 of the FP64 maximum: the same decision, and the same coefficient, as
+// the FP64 definition.  Window sums come from the FP64 box-sum images.
+//
+// LDS per wave: the window in bf16 (rows padded to 16 KB + 8 elements so the
+// 16-byte reads of 8 consecutive rows hit distinct banks) and the template in
+// bf16 as two copies of dword pairs, even and odd phase, so that the 8
+// consecutive elements a lane needs for its Toeplitz column start at a dword
+// boundary in one of them (the odd copy sits 16 banks away from the even one).
+#include "search_common.h"
+
+namespace dic {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kBoundRel = 8.5e-3f;
+constexpr int kMaskWords = 36;   // >= ceil(33 * 33 / 32)
+
+// Per-wave LDS layout for K-block count KB and subsets up to nmax wide.
+struct MfmaLayout {
+  int wpb;     // window row pitch (bf16 elements)
+  int tpd;     // template row pitch (dwords)
+  int win, te, to, mask, edge, total;   // byte offsets / size
+};
+
+__host__ __device__ __forceinline__ MfmaLayout mfma_layout(int KB, int nmax) {
+  MfmaLayout L;
+  L.wpb = 16 * KB + 8;
+  L.tpd = 8 * KB + 16;
+  L.win = 0;
+  const int wrows = nmax + 32;
+  L.te = (wrows * L.wpb * 2 + 127) / 128 * 128;
+  const int tbytes = nmax * L.tpd * 4;
+  // odd copy 16 banks (64 bytes) past a 128-byte boundary after the even one
+  L.to = (L.te + tbytes + 127) / 128 * 128 + 64;
+  L.mask = L.to + tbytes;
+  L.edge = L.mask + kMaskWords * 4;
+  L.total = (L.edge + 64 * 4 + 15) / 16 * 16;
+  return L;
+}
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  const __bf16 a = (__bf16)lo, b = (__bf16)hi;
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) |
+         ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
+__device__ __forceinline__ bf16x8 load_frag_aligned(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
+}
+
+__device__ __forceinline__ bf16x8 load_frag_dwords(const uint32_t* p) {
+  const u32x4 v = {p[0], p[1], p[2], p[3]};
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+// bf16 element x of a template row stored as even-phase dword pairs.
+__device__ __forceinline__ float tmpl_elem(const uint32_t* row, int x) {
+  const uint32_t d = row[x >> 1];
+  return __builtin_bit_cast(float, (x & 1) ? (d & 0xffff0000u) : (d << 16));
+}
+
+// sum_r A_r B_r for tile A (dv, du in [0, 32)) and, with TWO, tile B
+// (dv, du in [1, 33)).  Lane (n, kg) = (lane % 32, lane / 32).  The
+// fragments of row r + 1 are requested before the products of row r.
+template <int KB, bool TWO>
+__device__ __forceinline__ void correlate_tiles(const uint16_t* win, const uint32_t* te,
+                                                const uint32_t* to, int n1, int wpb, int tpd,
+                                                f32x16& acc_a, f32x16& acc_b) {
+  const int lane = lane_id(), n = lane & 31, kg = lane >> 5;
+  const uint16_t* arow = win + n * wpb + 8 * kg;
+  const int o0 = 8 * kg - n + 32;   // Toeplitz phase of tile A's column du = n
+  const int o1 = o0 - 1;            // tile B: du = n + 1
+  const uint32_t* ba = ((o0 & 1) ? to : te) + (o0 >> 1);
+  const uint32_t* bb = ((o1 & 1) ? to : te) + (o1 >> 1);
+  bf16x8 a0[KB], a1[KB], fa[KB], fb[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    a0[kb] = load_frag_aligned(arow + 16 * kb);
+    a1[kb] = load_frag_aligned(arow + wpb + 16 * kb);
+    fa[kb] = load_frag_dwords(ba + 8 * kb);
+    if (TWO) fb[kb] = load_frag_dwords(bb + 8 * kb);
+  }
+  for (int r = 0; r < n1; ++r) {
+    // row r + 2 of the window feeds tile B at r + 1 (rows past n1 are not needed)
+    const uint16_t* an = arow + min(r + 2, n1) * wpb;
+    const int rn = min(r + 1, n1 - 1);
+    bf16x8 a2[KB], fa2[KB], fb2[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      a2[kb] = load_frag_aligned(an + 16 * kb);
+      fa2[kb] = load_frag_dwords(ba + rn * tpd + 8 * kb);
+      if (TWO) fb2[kb] = load_frag_dwords(bb + rn * tpd + 8 * kb);
+    }
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      acc_a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[kb], fa[kb], acc_a, 0, 0, 0);
+      if (TWO) acc_b = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[kb], fb[kb], acc_b, 0, 0, 0);
+    }
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      a0[kb] = a1[kb];
+      a1[kb] = a2[kb];
+      fa[kb] = fa2[kb];
+      if (TWO) fb[kb] = fb2[kb];
+    }
+  }
+}
+
+// Approximate coefficient of candidate (dv, du) of the window (row-major in
+// [0, side)^2) from its cross term C and FP64 box sums, and its error bound E;
+// -inf for an inadmissible or flat candidate.
+struct ScoreCtx {
+  int x0, y0, cu, cv, S, M, W, H, side;
+  double rnd, nn, c0, tsum;
+  float df;
+};
+
+__device__ __forceinline__ float score_of(const ScoreCtx& q, float C, int dv, int du, double sg,
+                                          double sq, float& E) {
+  E = 0.f;
+  if (dv >= q.side || du >= q.side) return -INFINITY;
+  const int dua = q.cu - q.S + du, dva = q.cv - q.S + dv;
+  if (q.x0 + dua - q.M < 0 || q.x0 + dua + q.M > q.W - 1 || q.y0 + dva - q.M < 0 ||
+      q.y0 + dva + q.M > q.H - 1)
+    return -INFINITY;
+  const double var = sq - sg * sg * q.rnd;
+  if (!(sq >= 0.0 && not_flat(var, sq))) return -INFINITY;
+  const double num = (double)C - (sg * q.rnd - q.c0) * q.tsum;
+  const float fv = (float)var;
+  const float sc = (float)num / (q.df * sqrtf(fv));
+  if (!isfinite(sc)) return -INFINITY;
+  const double g2 = sq - 2.0 * q.c0 * sg + q.nn * q.c0 * q.c0;
+  E = kBoundRel * sqrtf(fmaxf((float)g2, 0.f) / fv);
+  return sc;
+}
+
+// Index of the box-sum pixel of candidate (dv, du), clamped into the image
+// (a clamped candidate is inadmissible and its sums are not used).
+__device__ __forceinline__ int64_t box_index(const ScoreCtx& q, int dv, int du) {
+  const int x = min(max(q.x0 + q.cu - q.S + du, 0), q.W - 1);
+  const int y = min(max(q.y0 + q.cv - q.S + dv, 0), q.H - 1);
+  return (int64_t)y * q.W + x;
+}
+
+}  // namespace
+
+size_t search_mfma_wave_lds(int kb, int maxM) {
+  const int nmax = min(16 * kb - 32, 2 * maxM + 1);
+  return (size_t)mfma_layout(kb, nmax).total;
+}
+
+template <int KB>
+__global__ void __launch_bounds__(64) search_mfma_kernel(
+    DevState st, const int32_t* __restrict__ work, int64_t count, int ctr, int nmax,
+    const float* __restrict__ tmpl_arena, const double* __restrict__ box,
+    const float* __restrict__ ref, const float* __restrict__ def, const int32_t* __restrict__ poi,
+    const int32_t* __restrict__ seed, int32_t* __restrict__ uv_out, float* __restrict__ zncc_out,
+    int32_t* __restrict__ status_out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  const MfmaLayout Ly = mfma_layout(KB, nmax);
+  uint16_t* win = reinterpret_cast<uint16_t*>(lds_raw + Ly.win);
+  float* tscr = reinterpret_cast<float*>(lds_raw + Ly.win);   // FP32 template, before the window
+  uint32_t* te = reinterpret_cast<uint32_t*>(lds_raw + Ly.te);
+  uint32_t* to = reinterpret_cast<uint32_t*>(lds_raw + Ly.to);
+  uint32_t* mask = reinterpret_cast<uint32_t*>(lds_raw + Ly.mask);
+  float* edge = reinterpret_cast<float*>(lds_raw + Ly.edge);
+  const int lane = lane_id(), n = lane & 31, kg = lane >> 5;
+  constexpr int WC = 16 * KB;        // staged window columns
+  constexpr int CPR = WC / 8;        // 8-element chunks per window row
+  constexpr int NMAX = 16 * KB - 32; // widest subset of this K-block count
+  constexpr int CH = (16 * KB * CPR + kWave - 1) / kWave;       // window chunks per lane
+  constexpr int TQ = (NMAX * ((NMAX + 7) / 8 * 8) / 4 + kWave - 1) / kWave;  // float4 per lane
+  constexpr int TPD = 8 * KB + 16;
+  const int wpb = Ly.wpb;
+
+  int item = 0;
+  if (lane == 0) item = atomicAdd(&st.counters[ctr], 1);
+  item = uniform(__shfl(item, 0, kWave));
+  while (item < count) {
+    int next = 0;   // the following work item, requested now, used at the end
+    if (lane == 0) next = atomicAdd(&st.counters[ctr], 1);
+    const int g = uniform(work[item]);
+    const DevPair P = st.pairs[uniform(st.poi_pair[g])];
+    const RefRec* R = st.recs + g;
+    const int x0 = uniform(poi[2 * g]), y0 = uniform(poi[2 * g + 1]);
+    const int cu = seed ? uniform(seed[2 * g]) : 0;
+    const int cv = seed ? uniform(seed[2 * g + 1]) : 0;
+    const int rstat = uniform(R->status);
+    if (rstat != DIC_POI_OK && rstat != DIC_POI_SINGULAR_HESSIAN) {
+      if (lane == 0) {
+        uv_out[2 * g] = 0;
+        uv_out[2 * g + 1] = 0;
+        zncc_out[g] = nanf("");
+        status_out[g] = rstat;
+      }
+      item = uniform(__shfl(next, 0, kWave));
+      continue;
+    }
+    const int M = P.M, S = P.S, n1 = 2 * M + 1, nn = n1 * n1, side = 2 * S + 1;
+    const int W = P.width, H = P.height, K = side * side;
+    const float* gimg = def + P.def_off;
+    const float* fimg = ref + P.ref_off;
+    const float c0 = (float)R->fbar;
+    const int wx0 = x0 + cu - S - M, wy0 = y0 + cv - S - M;
+    const int wn = n1 + side - 1;   // real window side
+    const int wrows = n1 + 32;      // staged rows (the second tile reads up to n1 + 31)
+    const int tp = P.tmpl_pitch;
+    const float* tm = tmpl_arena + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * tp;
+    const bool two = side == 33;
+    ScoreCtx q;
+    q.x0 = x0; q.y0 = y0; q.cu = cu; q.cv = cv; q.S = S; q.M = M; q.W = W; q.H = H;
+    q.side = side;
+    q.rnd = 1.0 / (double)nn;
+    q.nn = (double)nn;
+    q.c0 = (double)c0;
+    q.tsum = (double)R->tsum;
+    q.df = (float)R->df;
+    const int64_t plane = (int64_t)W * H;
+    const double* s1img = box + P.box_off + 2 * plane;
+    const double* s2img = s1img + plane;
+
+    // 0. the FP32 template (rows of pitch tp, 16-byte aligned), requested at once
+    const int tq4 = n1 * tp / 4;
+    float4 tv[TQ];
+#pragma unroll
+    for (int k = 0; k < TQ; ++k)
+      tv[k] = reinterpret_cast<const float4*>(tm)[min(lane + k * kWave, tq4 - 1)];
+    wave_lds_sync();   // the previous POI's LDS reads are complete
+    // 1. FP32 template into LDS scratch, then its bf16 copies, padded by 32
+    //    zeros on the left: element x of row r is t(r, x - 32); the even copy
+    //    holds pairs (2i, 2i+1), the odd copy (2i+1, 2i+2).
+#pragma unroll
+    for (int k = 0; k < TQ; ++k)
+      if (lane + k * kWave < tq4) reinterpret_cast<float4*>(tscr)[lane + k * kWave] = tv[k];
+    wave_lds_sync();
+#pragma unroll 4
+    for (int idx = lane; idx < n1 * TPD; idx += kWave) {
+      const int r = idx / TPD, i = idx - r * TPD;
+      const int c = 2 * i - 32;
+      const float* row = tscr + r * tp;
+      const float a = row[min(max(c, 0), n1 - 1)];
+      const float b = row[min(max(c + 1, 0), n1 - 1)];
+      const float d = row[min(max(c + 2, 0), n1 - 1)];
+      const float va = (c >= 0 && c < n1) ? a : 0.f;
+      const float vb = (c + 1 >= 0 && c + 1 < n1) ? b : 0.f;
+      const float vd = (c + 2 >= 0 && c + 2 < n1) ? d : 0.f;
+      te[idx] = pack_bf16(va, vb);
+      to[idx] = pack_bf16(vb, vd);
+    }
+    if (lane < kMaskWords) mask[lane] = 0u;
+    wave_lds_sync();   // the scratch is free for the window
+    // 2. window g - fbar in bf16, CB chunks of 8 columns per lane at a time;
+    //    outside the window or the image, and non-finite pixels, are 0 (their
+    //    candidates are invalid by the box sums)
+    constexpr int CB = 4;
+#pragma unroll
+    for (int k0 = 0; k0 < CH; k0 += CB) {
+      float v[CB][8];
+#pragma unroll
+      for (int kk = 0; kk < CB; ++kk) {
+        const int idx = lane + (k0 + kk) * kWave;
+        const int rr = idx / CPR, ch = idx - rr * CPR;
+        const int Yc = min(max(wy0 + rr, 0), H - 1);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int Xc = min(max(wx0 + ch * 8 + e, 0), W - 1);
+          v[kk][e] = gimg[(int64_t)Yc * W + Xc];
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < CB; ++kk) {
+        const int idx = lane + (k0 + kk) * kWave;
+        const int rr = idx / CPR, ch = idx - rr * CPR;
+        if (k0 + kk < CH && rr < wrows) {
+          const int Y = wy0 + rr;
+          const bool rowok = rr < wn && Y >= 0 && Y < H;
+          float w[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int col = ch * 8 + e, X = wx0 + col;
+            const float x = v[kk][e];
+            w[e] = (rowok && col < wn && X >= 0 && X < W && isfinite(x)) ? x - c0 : 0.f;
+          }
+          const u32x4 pk = {pack_bf16(w[0], w[1]), pack_bf16(w[2], w[3]), pack_bf16(w[4], w[5]),
+                            pack_bf16(w[6], w[7])};
+          *reinterpret_cast<u32x4*>(win + rr * wpb + ch * 8) = pk;
+        }
+      }
+    }
+    wave_lds_sync();
+
+    // 3. cross terms on the matrix cores
+    f32x16 acc_a = {}, acc_b = {};
+    if (two)
+      correlate_tiles<KB, true>(win, te, to, n1, wpb, TPD, acc_a, acc_b);
+    else
+      correlate_tiles<KB, false>(win, te, to, n1, wpb, TPD, acc_a, acc_b);
+    // box sums of every candidate this lane scores, requested at once: 16 of
+    // tile A, then one edge candidate of tile B (lanes 0..62) or the two
+    // corners (lane 63); their latency overlaps the corner sums below
+    double sga[16], sqa[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int64_t o = box_index(q, (j & 3) + 8 * (j >> 2) + 4 * kg, n);
+      sga[j] = s1img[o];
+      sqa[j] = s2img[o];
+    }
+    // edge candidates: lane b < 32 -> (32, b + 1); 32 <= b < 63 -> (b - 31, 32);
+    // lane 63 -> corners (32, 0) and (0, 32)
+    const int e0v = lane < 32 ? 32 : lane < 63 ? lane - 31 : 32;
+    const int e0u = lane < 32 ? lane + 1 : lane < 63 ? 32 : 0;
+    const int e1v = 0, e1u = 32;
+    double sge0, sqe0, sge1, sqe1;
+    {
+      const int64_t o0 = box_index(q, e0v, e0u), o1 = box_index(q, e1v, e1u);
+      sge0 = s1img[o0];
+      sqe0 = s2img[o0];
+      sge1 = s1img[o1];
+      sqe1 = s2img[o1];
+    }
+
+    // the two corners on the vector ALUs
+    float cr1 = 0.f, cr2 = 0.f;   // corners (dv, du) = (32, 0) and (0, 32)
+    if (two) {
+      double s_a = 0.0, s_b = 0.0;
+      for (int k = lane; k < nn; k += kWave) {
+        const int r = k / n1, c = k - r * n1;
+        const double t = (double)tmpl_elem(te + r * TPD, c + 32);
+        s_a += t * (double)__builtin_bit_cast(float, (uint32_t)win[(r + 32) * wpb + c] << 16);
+        s_b += t * (double)__builtin_bit_cast(float, (uint32_t)win[r * wpb + c + 32] << 16);
+      }
+      cr1 = (float)wave_sum_dpp(s_a);
+      cr2 = (float)wave_sum_dpp(s_b);
+      // tile B's edge row dv = 32 and column du = 32, one value per lane
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int i = (j & 3) + 8 * (j >> 2) + 4 * kg;
+        if (i == 31) edge[n] = acc_b[j];               // (32, n + 1)
+        else if (n == 31) edge[32 + i] = acc_b[j];     // (i + 1, 32), i < 31
+      }
+      wave_lds_sync();
+    }
+
+    // 4. approximate coefficients, their bounds, and the threshold
+    float sa[16], ea[16];
+    float lo = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int i = (j & 3) + 8 * (j >> 2) + 4 * kg;
+      sa[j] = score_of(q, acc_a[j], i, n, sga[j], sqa[j], ea[j]);
+      lo = fmaxf(lo, sa[j] - ea[j]);
+    }
+    float s0 = -INFINITY, e0 = 0.f, s1 = -INFINITY, e1 = 0.f;
+    if (two) {
+      const float c_e0 = lane < 63 ? edge[lane] : cr1;
+      s0 = score_of(q, c_e0, e0v, e0u, sge0, sqe0, e0);
+      if (lane == 63) s1 = score_of(q, cr2, e1v, e1u, sge1, sqe1, e1);
+      lo = fmaxf(lo, fmaxf(s0 - e0, s1 - e1));
+    }
+    const float tau = wave_max(lo);
+
+    // 5. the candidates that may hold the FP64 maximum, as a bit set
+    int pick = -1;
+    double best = -INFINITY;
+    if (tau > -INFINITY) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (sa[j] + ea[j] >= tau) {
+          const int cand = ((j & 3) + 8 * (j >> 2) + 4 * kg) * side + n;
+          atomicOr(&mask[cand >> 5], 1u << (cand & 31));
+        }
+      if (s0 + e0 >= tau) {
+        const int cand = e0v * side + e0u;
+        atomicOr(&mask[cand >> 5], 1u << (cand & 31));
+      }
+      if (s1 + e1 >= tau) {
+        const int cand = e1v * side + e1u;
+        atomicOr(&mask[cand >> 5], 1u << (cand & 31));
+      }
+      wave_lds_sync();
+
+      // 6. FP64 re-score in index order; the first candidate within 1e-12 of
+      //    the maximum wins.  Lane e keeps the e-th value; values past the
+      //    64th are recomputed in the second sweep.
+      auto rescore = [&](int cand) -> double {
+        const int rr = cand / side, cc = cand - rr * side;
+        const int xg = x0 + cu - S + cc, yg = y0 + cv - S + rr;
+        bool ok;
+        const double z = rescore_wave(fimg, gimg, W, x0, y0, xg, yg, M, R->fbar, (double)R->df,
+                                      s1img + (int64_t)yg * W + xg, &ok);
+        return ok ? z : -INFINITY;
+      };
+      const int words = (K + 31) / 32;
+      double cmax = -INFINITY;
+      double keep = -INFINITY;
+      int e = 0;
+      for (int w = 0; w < words; ++w) {
+        uint32_t bits = (uint32_t)uniform((int)mask[w]);
+        while (bits) {
+          const int b = __builtin_ctz(bits);
+          bits &= bits - 1;
+          const double z = rescore(32 * w + b);
+          if (lane == e) keep = z;
+          ++e;
+          cmax = fmax(cmax, z);
+        }
+      }
+      if (cmax > -INFINITY) {
+        e = 0;
+        for (int w = 0; w < words && pick < 0; ++w) {
+          uint32_t bits = (uint32_t)uniform((int)mask[w]);
+          while (bits && pick < 0) {
+            const int b = __builtin_ctz(bits);
+            bits &= bits - 1;
+            const int cand = 32 * w + b;
+            const double z = e < kWave ? readlane_f64(keep, e) : rescore(cand);
+            ++e;
+            if (z >= cmax - 1e-12) {
+              pick = cand;
+              best = z;
+            }
+          }
+        }
+      }
+    }
+    if (lane == 0) {
+      if (pick < 0) {
+        uv_out[2 * g] = 0;
+        uv_out[2 * g + 1] = 0;
+        zncc_out[g] = nanf("");
+        status_out[g] = DIC_POI_NO_VALID_CANDIDATE;
+      } else {
+        const int rr = pick / side, cc = pick - rr * side;
+        uv_out[2 * g] = cu - S + cc;
+        uv_out[2 * g + 1] = cv - S + rr;
+        zncc_out[g] = (float)best;
+        status_out[g] = DIC_POI_OK;
+      }
+    }
+    item = uniform(__shfl(next, 0, kWave));
+  }
+}
+
+template <int KB>
+static hipError_t launch_search_mfma_kb(const DevState& st, const SearchGroup& gr, int ctr,
+                                        int occ_cap, const float* ref, const float* def,
+                                        const int32_t* poi, const int32_t* seed, int32_t* uv,
+                                        float* zncc, int32_t* status, int num_cu, hipStream_t s) {
+  const int nmax = min(16 * KB - 32, 2 * st.maxM + 1);
+  const size_t lds = search_mfma_wave_lds(KB, st.maxM);
+  const void* fn = reinterpret_cast<const void*>(&search_mfma_kernel<KB>);
+  if (lds > 65536) {
+    hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (ea != hipSuccess) return ea;
+  }
+  int occ = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, search_mfma_kernel<KB>, kWave, lds);
+  if (e != hipSuccess) return e;
+  if (occ < 1) return hipErrorInvalidConfiguration;
+  if (occ_cap > 0 && occ > occ_cap) occ = occ_cap;
+  int64_t blocks = (int64_t)occ * num_cu;
+  if (blocks > gr.count) blocks = gr.count;
+  hipLaunchKernelGGL(search_mfma_kernel<KB>, dim3((unsigned)blocks), dim3(kWave), lds, s, st,
+                     st.work + gr.begin, gr.count, ctr, nmax, st.tmpl, st.box, ref, def, poi, seed,
+                     uv, zncc, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_search_mfma(const DevState& st, const dic_tuning_t& tu,
+                              const SearchGroup* groups, int ngroups, const float* ref,
+                              const float* def, const int32_t* poi, const int32_t* seed,
+                              int32_t* uv, float* zncc, int32_t* status, int num_cu,
+                              hipStream_t s) {
+  if (ngroups > kMaxSearchGroups || st.maxS > kMfmaMaxS) return hipErrorInvalidValue;
+  for (int k = 0; k < ngroups; ++k) {
+    const SearchGroup& gr = groups[k];
+    if (gr.count == 0) continue;
+    hipError_t e = hipErrorInvalidValue;
+    if (gr.np == 3)
+      e = launch_search_mfma_kb<3>(st, gr, kCtrSearch + k, tu.search_occupancy, ref, def, poi,
+                                   seed, uv, zncc, status, num_cu, s);
+    else if (gr.np == 4)
+      e = launch_search_mfma_kb<4>(st, gr, kCtrSearch + k, tu.search_occupancy, ref, def, poi,
+                                   seed, uv, zncc, status, num_cu, s);
+    else if (gr.np == 5)
+      e = launch_search_mfma_kb<5>(st, gr, kCtrSearch + k, tu.search_occupancy, ref, def, poi,
+                                   seed, uv, zncc, status, num_cu, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace dic

@@ -57,13 +57,35 @@ def test_plan_create_and_workspace(L):
     assert nb64.value < nb.value      # the plain form keeps no gradients or templates
     t = Tuning()
     assert L.dic_plan_get_tuning(h, ctypes.byref(t)) == 0
-    assert (t.search_block, t.search_occupancy) == (8, 0)
-    for bad in (Tuning(5, 0, 4, 4), Tuning(8, 17, 4, 4), Tuning(8, 0, 9, 4), Tuning(4, 0, 1, 17)):
+    # search +-8: the matrix-core search form is the default
+    assert (t.search_block, t.search_occupancy) == (32, 0)
+    for bad in (Tuning(5, 0, 4, 4), Tuning(8, 17, 4, 4), Tuning(8, 0, 9, 4), Tuning(4, 0, 1, 17),
+                Tuning(16, 0, 4, 4)):
         assert L.dic_plan_set_tuning(h, ctypes.byref(bad)) == -1
-    good = Tuning(4, 2, 2, 6)
-    assert L.dic_plan_set_tuning(h, ctypes.byref(good)) == 0
+    for good in (Tuning(4, 2, 2, 6), Tuning(8, 0, 4, 4), Tuning(32, 3, 1, 2)):
+        assert L.dic_plan_set_tuning(h, ctypes.byref(good)) == 0
+        got = Tuning()
+        L.dic_plan_get_tuning(h, ctypes.byref(got))
+        assert (got.search_block, got.search_occupancy) == (good.search_block, good.search_occupancy)
     L.dic_plan_destroy(h)
     L.dic_plan_destroy(h64)
+
+
+def test_search_form_follows_radius(L):
+    """Windows beyond +-16 use the vector-ALU search form; the matrix-core
+    form is refused for them."""
+    rc, h = make(L, [(512, 512, 12, 20, 0, 0, 0, 100)])
+    assert rc == 0
+    t = Tuning()
+    L.dic_plan_get_tuning(h, ctypes.byref(t))
+    assert t.search_block == 8
+    assert L.dic_plan_set_tuning(h, ctypes.byref(Tuning(32, 0, 4, 4))) == -4
+    assert "matrix-core" in L.dic_last_error().decode()
+    L.dic_plan_destroy(h)
+    rc, h = make(L, [(512, 512, 20, 16, 0, 0, 0, 100)])
+    L.dic_plan_get_tuning(h, ctypes.byref(t))
+    assert rc == 0 and t.search_block == 32
+    L.dic_plan_destroy(h)
 
 
 @pytest.mark.parametrize("pairs,kw,why", [
