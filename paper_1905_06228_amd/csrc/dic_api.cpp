@@ -349,7 +349,7 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
     if (f32) {
       gfl += 2 * (int64_t)q.width * q.height;
       tfl += q.poi_count * tn;
-      bxd += 4 * (int64_t)q.width * q.height;
+      bxd += 5 * (int64_t)q.width * q.height;
     }
     p->fix_off[k] = fix;
     if (p->det()) fix += (int64_t)q.width * q.height;

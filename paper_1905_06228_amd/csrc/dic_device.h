@@ -4,6 +4,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "dic_internal.h"
 
 namespace dic {
@@ -51,6 +53,24 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   v += dpp_f64<0x141>(v);  // row_half_mirror
   v += dpp_f64<0x140>(v);  // row_mirror
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+// Maximum over the 64 lanes of a wave by DPP within rows of 16, then the
+// four row maxima; every lane returns the same value.  All lanes active.
+__device__ __forceinline__ float wave_max_dpp(float v) {
+  const auto mv = [](float x, auto ctrl) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), decltype(ctrl)::value, 0xF,
+                                        0xF, true));
+  };
+  v = fmaxf(v, mv(v, std::integral_constant<int, 0xB1>{}));
+  v = fmaxf(v, mv(v, std::integral_constant<int, 0x4E>{}));
+  v = fmaxf(v, mv(v, std::integral_constant<int, 0x141>{}));
+  v = fmaxf(v, mv(v, std::integral_constant<int, 0x140>{}));
+  const auto rl = [](float x, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+  };
+  return fmaxf(fmaxf(rl(v, 0), rl(v, 16)), fmaxf(rl(v, 32), rl(v, 48)));
 }
 
 template <typename T>

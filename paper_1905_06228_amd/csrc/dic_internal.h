@@ -22,8 +22,9 @@ struct DevPair {
   int32_t tmpl_pitch;  // template row pitch: 2M+1 rounded up to a multiple of 8,
                        // zero-filled beyond the subset, (2M+1) rows per POI
   int32_t pad_;
-  int64_t box_off;   // double offset of this pair's four [H, W] box-sum planes:
-                     // column sums of g and g^2, then subset sums of g and g^2
+  int64_t box_off;   // double offset of this pair's five [H, W] box-sum planes:
+                     // column sums of g and g^2, subset sums of g and g^2, and
+                     // float pairs (subset mean, 1/sqrt(sum (g - mean)^2))
 };
 
 __host__ __device__ __forceinline__ int template_pitch(int M) { return (2 * M + 1 + 7) / 8 * 8; }

@@ -45,7 +45,10 @@ hipError_t launch_gradients(const DevState& st, const float* ref, hipStream_t s)
 // S1[y][x] = sum g, S2[y][x] = sum g^2 over the (2M+1)^2 subset centred on
 // (x, y).  A centre whose subset leaves the image or holds a non-finite
 // pixel gets S2 = -1.  Two passes: column sums (running down 64-row
-// segments), then row sums of those (direct, 2M+1 terms).
+// segments), then row sums of those (direct, 2M+1 terms).  The second pass
+// also stores per centre the float pair (mean, 1/sqrt(sum (g - mean)^2)) that
+// the matrix-core search scores with, (0, 0) where the subset is inadmissible
+// or flat by the FP64 rule.
 constexpr int kBoxSeg = 64;
 
 __global__ void __launch_bounds__(256) box_cols_kernel(const DevPair* __restrict__ pairs,
@@ -104,6 +107,7 @@ __global__ void __launch_bounds__(256) box_rows_kernel(const DevPair* __restrict
   const double* v2 = v1 + plane;
   double* o1 = box + P.box_off + 2 * plane + (int64_t)y * W;
   double* o2 = o1 + plane;
+  float2* o3 = reinterpret_cast<float2*>(o2 + plane);
   double s1 = 0.0, s2 = 0.0;
   bool bad = x - M < 0 || x + M > W - 1;
   if (!bad)
@@ -115,6 +119,10 @@ __global__ void __launch_bounds__(256) box_rows_kernel(const DevPair* __restrict
     }
   o1[x] = bad ? 0.0 : s1;
   o2[x] = bad ? -1.0 : s2;
+  const double n = (double)(2 * M + 1) * (double)(2 * M + 1);
+  const double var = s2 - s1 * s1 / n;
+  const bool ok = !bad && not_flat(var, s2);
+  o3[x] = ok ? make_float2((float)(s1 / n), (float)(1.0 / sqrt(var))) : make_float2(0.f, 0.f);
 }
 
 hipError_t launch_box_sums(const DevState& st, const float* def, hipStream_t s) {

@@ -287,10 +287,9 @@ __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
       auto rescore = [&](int cand) -> double {
         const int rr = cand / G.side, cc = cand - rr * G.side;
         const int xg = x0 + cu - G.S + cc, yg = y0 + cv - G.S + rr;
-        bool ok;
-        const double z = rescore_wave(fimg, gimg, W, x0, y0, xg, yg, G.M, R->fbar, dfd,
-                                      s1img + (int64_t)yg * W + xg, &ok);
-        return ok ? z : -INFINITY;
+        double z;
+        rescore_wave<1>(fimg, gimg, W, x0, y0, &xg, &yg, 1, G.M, R->fbar, dfd, s1img, &z);
+        return z;
       };
       int pick = -1;
       double best = -INFINITY;

@@ -39,6 +39,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr float kBoundRel = 8.5e-3f;
+constexpr int kXcds = 8;   // accelerator complex dies of the MI355X
 constexpr int kMaskWords = 36;   // >= ceil(33 * 33 / 32)
 
 // Per-wave LDS layout for K-block count KB and subsets up to nmax wide.
@@ -86,8 +87,30 @@ __device__ __forceinline__ float tmpl_elem(const uint32_t* row, int x) {
 }
 
 // sum_r A_r B_r for tile A (dv, du in [0, 32)) and, with TWO, tile B
-// (dv, du in [1, 33)).  Lane (n, kg) = (lane % 32, lane / 32).  The
-// fragments of row r + 1 are requested before the products of row r.
+// (dv, du in [1, 33)).  Lane (n, kg) = (lane % 32, lane / 32).  Tile B's
+// term for template row r - 1 pairs window rows r.. (tile B's dv is one
+// larger) with the Toeplitz fragment of row r - 1 shifted by one column, so
+// both tiles read the same window fragment A(r) at step r:
+//   step r:  acc_a += A(r) B(r)      (r < n1)
+//            acc_b += A(r) B'(r - 1) (r >= 1)
+// The fragments of step r + 1 are requested before the products of step r,
+// in two alternating register sets (no copies between steps).
+template <int KB>
+struct Frags {
+  bf16x8 a[KB], b[KB], bp[KB];
+};
+
+template <int KB, bool TWO>
+__device__ __forceinline__ void mfma_step(const bf16x8* a, const bf16x8* b, const bf16x8* bp,
+                                          bool do_a, bool do_b, f32x16& acc_a, f32x16& acc_b) {
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    if (do_a) acc_a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kb], b[kb], acc_a, 0, 0, 0);
+    if (TWO && do_b)
+      acc_b = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kb], bp[kb], acc_b, 0, 0, 0);
+  }
+}
+
 template <int KB, bool TWO>
 __device__ __forceinline__ void correlate_tiles(const uint16_t* win, const uint32_t* te,
                                                 const uint32_t* to, int n1, int wpb, int tpd,
@@ -98,66 +121,58 @@ __device__ __forceinline__ void correlate_tiles(const uint16_t* win, const uint3
   const int o1 = o0 - 1;            // tile B: du = n + 1
   const uint32_t* ba = ((o0 & 1) ? to : te) + (o0 >> 1);
   const uint32_t* bb = ((o1 & 1) ? to : te) + (o1 >> 1);
-  bf16x8 a0[KB], a1[KB], fa[KB], fb[KB];
+  // window rows r.. (r <= n1), template row rb for tile A and rp for tile B
+  auto load = [&](Frags<KB>& f, int r, int rb, int rp) {
 #pragma unroll
-  for (int kb = 0; kb < KB; ++kb) {
-    a0[kb] = load_frag_aligned(arow + 16 * kb);
-    a1[kb] = load_frag_aligned(arow + wpb + 16 * kb);
-    fa[kb] = load_frag_dwords(ba + 8 * kb);
-    if (TWO) fb[kb] = load_frag_dwords(bb + 8 * kb);
+    for (int kb = 0; kb < KB; ++kb) {
+      f.a[kb] = load_frag_aligned(arow + r * wpb + 16 * kb);
+      f.b[kb] = load_frag_dwords(ba + rb * tpd + 8 * kb);
+      if (TWO) f.bp[kb] = load_frag_dwords(bb + rp * tpd + 8 * kb);
+    }
+  };
+  Frags<KB> x, y;
+  load(x, 0, 0, 0);
+  load(y, 1, min(1, n1 - 1), 0);
+  mfma_step<KB, TWO>(x.a, x.b, x.bp, true, false, acc_a, acc_b);   // step 0
+  // entering step r: y = (A(r), B(r), B'(r - 1))
+  int r = 1;
+  for (; r + 1 < n1; r += 2) {
+    load(x, r + 1, r + 1, r);
+    mfma_step<KB, TWO>(y.a, y.b, y.bp, true, true, acc_a, acc_b);
+    load(y, r + 2, min(r + 2, n1 - 1), r + 1);
+    mfma_step<KB, TWO>(x.a, x.b, x.bp, true, true, acc_a, acc_b);
   }
-  for (int r = 0; r < n1; ++r) {
-    // row r + 2 of the window feeds tile B at r + 1 (rows past n1 are not needed)
-    const uint16_t* an = arow + min(r + 2, n1) * wpb;
-    const int rn = min(r + 1, n1 - 1);
-    bf16x8 a2[KB], fa2[KB], fb2[KB];
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      a2[kb] = load_frag_aligned(an + 16 * kb);
-      fa2[kb] = load_frag_dwords(ba + rn * tpd + 8 * kb);
-      if (TWO) fb2[kb] = load_frag_dwords(bb + rn * tpd + 8 * kb);
-    }
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      acc_a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[kb], fa[kb], acc_a, 0, 0, 0);
-      if (TWO) acc_b = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[kb], fb[kb], acc_b, 0, 0, 0);
-    }
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      a0[kb] = a1[kb];
-      a1[kb] = a2[kb];
-      fa[kb] = fa2[kb];
-      if (TWO) fb[kb] = fb2[kb];
-    }
+  if (r < n1) {   // r == n1 - 1: one full step, then the last tile-B step
+    load(x, n1, n1 - 1, n1 - 1);
+    mfma_step<KB, TWO>(y.a, y.b, y.bp, true, true, acc_a, acc_b);
+    mfma_step<KB, TWO>(x.a, x.b, x.bp, false, true, acc_a, acc_b);
+  } else {        // r == n1: y = (A(n1), -, B'(n1 - 1))
+    mfma_step<KB, TWO>(y.a, y.b, y.bp, false, true, acc_a, acc_b);
   }
 }
 
 // Approximate coefficient of candidate (dv, du) of the window (row-major in
-// [0, side)^2) from its cross term C and FP64 box sums, and its error bound E;
-// -inf for an inadmissible or flat candidate.
+// [0, side)^2) from its cross term C and the window statistics st = (mean,
+// 1/sqrt(sum (g - mean)^2)) of the box-sum pass, and its error bound E (the
+// ratio sum g'^2 / sum (g - mean)^2 is 1 + n ((mean - fbar) / sd)^2); -inf for
+// an inadmissible or flat candidate.
 struct ScoreCtx {
   int x0, y0, cu, cv, S, M, W, H, side;
-  double rnd, nn, c0, tsum;
-  float df;
+  float c0, tsum, rdf, nn;
 };
 
-__device__ __forceinline__ float score_of(const ScoreCtx& q, float C, int dv, int du, double sg,
-                                          double sq, float& E) {
-  E = 0.f;
-  if (dv >= q.side || du >= q.side) return -INFINITY;
+__device__ __forceinline__ float score_of(const ScoreCtx& q, float C, int dv, int du, float2 st,
+                                          float& E) {
   const int dua = q.cu - q.S + du, dva = q.cv - q.S + dv;
-  if (q.x0 + dua - q.M < 0 || q.x0 + dua + q.M > q.W - 1 || q.y0 + dva - q.M < 0 ||
-      q.y0 + dva + q.M > q.H - 1)
-    return -INFINITY;
-  const double var = sq - sg * sg * q.rnd;
-  if (!(sq >= 0.0 && not_flat(var, sq))) return -INFINITY;
-  const double num = (double)C - (sg * q.rnd - q.c0) * q.tsum;
-  const float fv = (float)var;
-  const float sc = (float)num / (q.df * sqrtf(fv));
-  if (!isfinite(sc)) return -INFINITY;
-  const double g2 = sq - 2.0 * q.c0 * sg + q.nn * q.c0 * q.c0;
-  E = kBoundRel * sqrtf(fmaxf((float)g2, 0.f) / fv);
-  return sc;
+  bool ok = dv < q.side && du < q.side && q.x0 + dua - q.M >= 0 && q.x0 + dua + q.M <= q.W - 1 &&
+            q.y0 + dva - q.M >= 0 && q.y0 + dva + q.M <= q.H - 1 && st.y > 0.f;
+  // sum t (g - mean) = sum t (g - fbar) - (mean - fbar) sum t
+  const float dm = st.x - q.c0;
+  const float sc = fmaf(-dm, q.tsum, C) * st.y * q.rdf;
+  const float z = dm * st.y;
+  ok = ok && isfinite(sc);
+  E = ok ? kBoundRel * sqrtf(fmaf(q.nn * z, z, 1.f)) : 0.f;
+  return ok ? sc : -INFINITY;
 }
 
 // Index of the box-sum pixel of candidate (dv, du), clamped into the image
@@ -176,8 +191,8 @@ size_t search_mfma_wave_lds(int kb, int maxM) {
 }
 
 template <int KB>
-__global__ void __launch_bounds__(64) search_mfma_kernel(
-    DevState st, const int32_t* __restrict__ work, int64_t count, int ctr, int nmax,
+__global__ void __launch_bounds__(64, 2) search_mfma_kernel(
+    DevState st, const int32_t* __restrict__ work, int64_t count, int nmax,
     const float* __restrict__ tmpl_arena, const double* __restrict__ box,
     const float* __restrict__ ref, const float* __restrict__ def, const int32_t* __restrict__ poi,
     const int32_t* __restrict__ seed, int32_t* __restrict__ uv_out, float* __restrict__ zncc_out,
@@ -185,7 +200,6 @@ __global__ void __launch_bounds__(64) search_mfma_kernel(
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   const MfmaLayout Ly = mfma_layout(KB, nmax);
   uint16_t* win = reinterpret_cast<uint16_t*>(lds_raw + Ly.win);
-  float* tscr = reinterpret_cast<float*>(lds_raw + Ly.win);   // FP32 template, before the window
   uint32_t* te = reinterpret_cast<uint32_t*>(lds_raw + Ly.te);
   uint32_t* to = reinterpret_cast<uint32_t*>(lds_raw + Ly.to);
   uint32_t* mask = reinterpret_cast<uint32_t*>(lds_raw + Ly.mask);
@@ -195,16 +209,34 @@ __global__ void __launch_bounds__(64) search_mfma_kernel(
   constexpr int CPR = WC / 8;        // 8-element chunks per window row
   constexpr int NMAX = 16 * KB - 32; // widest subset of this K-block count
   constexpr int CH = (16 * KB * CPR + kWave - 1) / kWave;       // window chunks per lane
-  constexpr int TQ = (NMAX * ((NMAX + 7) / 8 * 8) / 4 + kWave - 1) / kWave;  // float4 per lane
   constexpr int TPD = 8 * KB + 16;
+  constexpr int TG = (TPD - 16) / 2;   // 4-column groups of a template row past the left pad
+  constexpr int TGL = (NMAX * TG + kWave - 1) / kWave;   // groups per lane
   const int wpb = Ly.wpb;
+  // the 32 zero elements left of every template row, in both copies, once
+  for (int idx = lane; idx < nmax * 16; idx += kWave) {
+    const int r = idx >> 4, i = idx & 15;
+    te[r * TPD + i] = 0u;
+    to[r * TPD + i] = 0u;
+  }
 
-  int item = 0;
-  if (lane == 0) item = atomicAdd(&st.counters[ctr], 1);
-  item = uniform(__shfl(item, 0, kWave));
-  while (item < count) {
-    int next = 0;   // the following work item, requested now, used at the end
-    if (lane == 0) next = atomicAdd(&st.counters[ctr], 1);
+  // Static assignment: every POI costs about the same, and a device-wide
+  // counter would serialise an atomic per POI across the XCDs.  Workgroups
+  // are dispatched round-robin over the XCDs, so with a grid that is a
+  // multiple of kXcds, XCD x takes the x-th contiguous part of the work list
+  // (neighbouring POIs, whose windows and box sums then share its L2).
+  int64_t item, end, step;
+  if (gridDim.x % kXcds == 0) {
+    const int x = blockIdx.x % kXcds, per = gridDim.x / kXcds;
+    item = count * x / kXcds + blockIdx.x / kXcds;
+    end = count * (x + 1) / kXcds;
+    step = per;
+  } else {
+    item = blockIdx.x;
+    end = count;
+    step = gridDim.x;
+  }
+  for (; item < end; item += step) {
     const int g = uniform(work[item]);
     const DevPair P = st.pairs[uniform(st.poi_pair[g])];
     const RefRec* R = st.recs + g;
@@ -219,7 +251,6 @@ __global__ void __launch_bounds__(64) search_mfma_kernel(
         zncc_out[g] = nanf("");
         status_out[g] = rstat;
       }
-      item = uniform(__shfl(next, 0, kWave));
       continue;
     }
     const int M = P.M, S = P.S, n1 = 2 * M + 1, nn = n1 * n1, side = 2 * S + 1;
@@ -236,45 +267,53 @@ __global__ void __launch_bounds__(64) search_mfma_kernel(
     ScoreCtx q;
     q.x0 = x0; q.y0 = y0; q.cu = cu; q.cv = cv; q.S = S; q.M = M; q.W = W; q.H = H;
     q.side = side;
-    q.rnd = 1.0 / (double)nn;
-    q.nn = (double)nn;
-    q.c0 = (double)c0;
-    q.tsum = (double)R->tsum;
-    q.df = (float)R->df;
+    q.c0 = c0;
+    q.tsum = R->tsum;
+    q.rdf = (float)(1.0 / R->df);
+    q.nn = (float)nn;
     const int64_t plane = (int64_t)W * H;
     const double* s1img = box + P.box_off + 2 * plane;
-    const double* s2img = s1img + plane;
+    const float2* stimg = reinterpret_cast<const float2*>(box + P.box_off + 4 * plane);
 
-    // 0. the FP32 template (rows of pitch tp, 16-byte aligned), requested at once
-    const int tq4 = n1 * tp / 4;
-    float4 tv[TQ];
+    // 0. the FP32 template as 4-column groups (rows of pitch tp, 16-byte
+    //    aligned; groups past tp are zero), requested at once
+    const int tq = tp / 4;
+    float4 tv[TGL];
 #pragma unroll
-    for (int k = 0; k < TQ; ++k)
-      tv[k] = reinterpret_cast<const float4*>(tm)[min(lane + k * kWave, tq4 - 1)];
+    for (int k = 0; k < TGL; ++k) {
+      const int idx = lane + k * kWave, r = idx / TG, qq = idx - r * TG;
+      const bool in = idx < n1 * TG && qq < tq;
+      tv[k] = reinterpret_cast<const float4*>(tm)[in ? r * tq + qq : 0];
+    }
+
     wave_lds_sync();   // the previous POI's LDS reads are complete
-    // 1. FP32 template into LDS scratch, then its bf16 copies, padded by 32
-    //    zeros on the left: element x of row r is t(r, x - 32); the even copy
-    //    holds pairs (2i, 2i+1), the odd copy (2i+1, 2i+2).
+    // 1. template rows in bf16 after 32 zeros: element x of row r is
+    //    t(r, x - 32); the even copy holds pairs (2i, 2i+1), the odd copy
+    //    (2i+1, 2i+2).  A group's odd pair (3, 4) takes element 4 from the
+    //    next group, which the next lane holds.
 #pragma unroll
-    for (int k = 0; k < TQ; ++k)
-      if (lane + k * kWave < tq4) reinterpret_cast<float4*>(tscr)[lane + k * kWave] = tv[k];
-    wave_lds_sync();
-#pragma unroll 4
-    for (int idx = lane; idx < n1 * TPD; idx += kWave) {
-      const int r = idx / TPD, i = idx - r * TPD;
-      const int c = 2 * i - 32;
-      const float* row = tscr + r * tp;
-      const float a = row[min(max(c, 0), n1 - 1)];
-      const float b = row[min(max(c + 1, 0), n1 - 1)];
-      const float d = row[min(max(c + 2, 0), n1 - 1)];
-      const float va = (c >= 0 && c < n1) ? a : 0.f;
-      const float vb = (c + 1 >= 0 && c + 1 < n1) ? b : 0.f;
-      const float vd = (c + 2 >= 0 && c + 2 < n1) ? d : 0.f;
-      te[idx] = pack_bf16(va, vb);
-      to[idx] = pack_bf16(vb, vd);
+    for (int k = 0; k < TGL; ++k) {
+      const int idx = lane + k * kWave, r = idx / TG, qq = idx - r * TG;
+      const bool in = idx < n1 * TG && qq < tq;
+      const float4 v = in ? tv[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+      float nxt = __builtin_bit_cast(
+          float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v.x), 0x130, 0xF, 0xF, true));
+      if (k + 1 < TGL) {
+        const int idx1 = (k + 1) * kWave, r1 = idx1 / TG, q1 = idx1 - r1 * TG;
+        const float x1 = (idx1 < n1 * TG && q1 < tq) ? tv[k + 1 < TGL ? k + 1 : k].x : 0.f;
+        const float lane0 = __builtin_bit_cast(
+            float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x1), 0));
+        if (lane == kWave - 1) nxt = lane0;
+      }
+      if (qq == TG - 1) nxt = 0.f;
+      if (idx < n1 * TG) {
+        const int base = r * TPD + 16 + 2 * qq;
+        *reinterpret_cast<uint2*>(te + base) = make_uint2(pack_bf16(v.x, v.y), pack_bf16(v.z, v.w));
+        *reinterpret_cast<uint2*>(to + base) = make_uint2(pack_bf16(v.y, v.z), pack_bf16(v.w, nxt));
+        if (qq == 0) to[base - 1] = pack_bf16(0.f, v.x);
+      }
     }
     if (lane < kMaskWords) mask[lane] = 0u;
-    wave_lds_sync();   // the scratch is free for the window
     // 2. window g - fbar in bf16, CB chunks of 8 columns per lane at a time;
     //    outside the window or the image, and non-finite pixels, are 0 (their
     //    candidates are invalid by the box sums)
@@ -324,36 +363,34 @@ __global__ void __launch_bounds__(64) search_mfma_kernel(
     // box sums of every candidate this lane scores, requested at once: 16 of
     // tile A, then one edge candidate of tile B (lanes 0..62) or the two
     // corners (lane 63); their latency overlaps the corner sums below
-    double sga[16], sqa[16];
+    float2 sta[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int64_t o = box_index(q, (j & 3) + 8 * (j >> 2) + 4 * kg, n);
-      sga[j] = s1img[o];
-      sqa[j] = s2img[o];
-    }
+    for (int j = 0; j < 16; ++j) sta[j] = stimg[box_index(q, (j & 3) + 8 * (j >> 2) + 4 * kg, n)];
     // edge candidates: lane b < 32 -> (32, b + 1); 32 <= b < 63 -> (b - 31, 32);
     // lane 63 -> corners (32, 0) and (0, 32)
     const int e0v = lane < 32 ? 32 : lane < 63 ? lane - 31 : 32;
     const int e0u = lane < 32 ? lane + 1 : lane < 63 ? 32 : 0;
     const int e1v = 0, e1u = 32;
-    double sge0, sqe0, sge1, sqe1;
-    {
-      const int64_t o0 = box_index(q, e0v, e0u), o1 = box_index(q, e1v, e1u);
-      sge0 = s1img[o0];
-      sqe0 = s2img[o0];
-      sge1 = s1img[o1];
-      sqe1 = s2img[o1];
-    }
+    const float2 ste0 = stimg[box_index(q, e0v, e0u)];
+    const float2 ste1 = stimg[box_index(q, e1v, e1u)];
 
     // the two corners on the vector ALUs
     float cr1 = 0.f, cr2 = 0.f;   // corners (dv, du) = (32, 0) and (0, 32)
     if (two) {
       double s_a = 0.0, s_b = 0.0;
+      const int dr = kWave / n1, dc = kWave - dr * n1;
+      int r = lane / n1, c = lane - r * n1;
+#pragma unroll 4
       for (int k = lane; k < nn; k += kWave) {
-        const int r = k / n1, c = k - r * n1;
         const double t = (double)tmpl_elem(te + r * TPD, c + 32);
         s_a += t * (double)__builtin_bit_cast(float, (uint32_t)win[(r + 32) * wpb + c] << 16);
         s_b += t * (double)__builtin_bit_cast(float, (uint32_t)win[r * wpb + c + 32] << 16);
+        c += dc;
+        r += dr;
+        if (c >= n1) {
+          c -= n1;
+          ++r;
+        }
       }
       cr1 = (float)wave_sum_dpp(s_a);
       cr2 = (float)wave_sum_dpp(s_b);
@@ -373,19 +410,20 @@ __global__ void __launch_bounds__(64) search_mfma_kernel(
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int i = (j & 3) + 8 * (j >> 2) + 4 * kg;
-      sa[j] = score_of(q, acc_a[j], i, n, sga[j], sqa[j], ea[j]);
+      sa[j] = score_of(q, acc_a[j], i, n, sta[j], ea[j]);
       lo = fmaxf(lo, sa[j] - ea[j]);
     }
     float s0 = -INFINITY, e0 = 0.f, s1 = -INFINITY, e1 = 0.f;
     if (two) {
       const float c_e0 = lane < 63 ? edge[lane] : cr1;
-      s0 = score_of(q, c_e0, e0v, e0u, sge0, sqe0, e0);
-      if (lane == 63) s1 = score_of(q, cr2, e1v, e1u, sge1, sqe1, e1);
+      s0 = score_of(q, c_e0, e0v, e0u, ste0, e0);
+      if (lane == 63) s1 = score_of(q, cr2, e1v, e1u, ste1, e1);
       lo = fmaxf(lo, fmaxf(s0 - e0, s1 - e1));
     }
-    const float tau = wave_max(lo);
+    const float tau = wave_max_dpp(lo);
 
-    // 5. the candidates that may hold the FP64 maximum, as a bit set
+    // 5. the candidates that may hold the FP64 maximum: a bit set, then the
+    //    list of its members in index order (lane e holds the e-th)
     int pick = -1;
     double best = -INFINITY;
     if (tau > -INFINITY) {
@@ -404,48 +442,84 @@ __global__ void __launch_bounds__(64) search_mfma_kernel(
         atomicOr(&mask[cand >> 5], 1u << (cand & 31));
       }
       wave_lds_sync();
-
-      // 6. FP64 re-score in index order; the first candidate within 1e-12 of
-      //    the maximum wins.  Lane e keeps the e-th value; values past the
-      //    64th are recomputed in the second sweep.
-      auto rescore = [&](int cand) -> double {
-        const int rr = cand / side, cc = cand - rr * side;
-        const int xg = x0 + cu - S + cc, yg = y0 + cv - S + rr;
-        bool ok;
-        const double z = rescore_wave(fimg, gimg, W, x0, y0, xg, yg, M, R->fbar, (double)R->df,
-                                      s1img + (int64_t)yg * W + xg, &ok);
-        return ok ? z : -INFINITY;
-      };
       const int words = (K + 31) / 32;
-      double cmax = -INFINITY;
-      double keep = -INFINITY;
-      int e = 0;
-      for (int w = 0; w < words; ++w) {
-        uint32_t bits = (uint32_t)uniform((int)mask[w]);
-        while (bits) {
-          const int b = __builtin_ctz(bits);
-          bits &= bits - 1;
-          const double z = rescore(32 * w + b);
-          if (lane == e) keep = z;
-          ++e;
-          cmax = fmax(cmax, z);
+      const uint32_t myword = lane < words ? mask[lane] : 0u;
+      const uint64_t nonempty = __ballot(myword != 0u);
+      int count = 0, mycand = 0;
+      for (uint64_t ws = nonempty; ws; ws &= ws - 1) {
+        const int w = __builtin_ctzll(ws);
+        for (uint32_t bits = (uint32_t)__builtin_amdgcn_readlane((int)myword, w); bits;
+             bits &= bits - 1) {
+          if (lane == count) mycand = 32 * w + __builtin_ctz(bits);
+          ++count;
         }
       }
+
+      // 6. FP64 re-score, two candidates per pass over the subset; the
+      //    first candidate in index order within 1e-12 of the maximum wins.
+      //    Members past the 64th (many exact ties) are walked in the bit set.
+      const double fbar = R->fbar, dfd = R->df;
+      auto centre = [&](int cand, int& xg, int& yg) {
+        const int rr = cand / side, cc = cand - rr * side;
+        xg = x0 + cu - S + cc;
+        yg = y0 + cv - S + rr;
+      };
+      auto rescore1 = [&](int cand) -> double {
+        int xg, yg;
+        centre(cand, xg, yg);
+        double z;
+        rescore_wave<1>(fimg, gimg, W, x0, y0, &xg, &yg, 1, M, fbar, dfd, s1img, &z);
+        return z;
+      };
+      // calls fn(cand) for the members past the 64th, in index order, while it returns true
+      auto walk_rest = [&](auto&& fn) {
+        int e = 0;
+        for (uint64_t ws = nonempty; ws; ws &= ws - 1) {
+          const int w = __builtin_ctzll(ws);
+          for (uint32_t bits = (uint32_t)__builtin_amdgcn_readlane((int)myword, w); bits;
+               bits &= bits - 1, ++e)
+            if (e >= kWave && !fn(32 * w + __builtin_ctz(bits))) return;
+        }
+      };
+      const int listed = min(count, kWave);
+      double keep = -INFINITY, cmax = -INFINITY;
+      constexpr int kB = 2;
+      for (int e0 = 0; e0 < listed; e0 += kB) {
+        const int nb = min(kB, listed - e0);
+        int xs[kB], ys[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b)
+          centre(__builtin_amdgcn_readlane(mycand, e0 + min(b, nb - 1)), xs[b], ys[b]);
+        double z[kB];
+        rescore_wave<kB>(fimg, gimg, W, x0, y0, xs, ys, nb, M, fbar, dfd, s1img, z);
+#pragma unroll
+        for (int b = 0; b < kB; ++b)
+          if (b < nb) {
+            if (lane == e0 + b) keep = z[b];
+            cmax = fmax(cmax, z[b]);
+          }
+      }
+      if (count > listed)
+        walk_rest([&](int cand) {
+          cmax = fmax(cmax, rescore1(cand));
+          return true;
+        });
       if (cmax > -INFINITY) {
-        e = 0;
-        for (int w = 0; w < words && pick < 0; ++w) {
-          uint32_t bits = (uint32_t)uniform((int)mask[w]);
-          while (bits && pick < 0) {
-            const int b = __builtin_ctz(bits);
-            bits &= bits - 1;
-            const int cand = 32 * w + b;
-            const double z = e < kWave ? readlane_f64(keep, e) : rescore(cand);
-            ++e;
+        const uint64_t hit = __ballot(lane < listed && keep >= cmax - 1e-12);
+        if (hit) {
+          const int e = __builtin_ctzll(hit);
+          pick = __builtin_amdgcn_readlane(mycand, e);
+          best = readlane_f64(keep, e);
+        } else {
+          walk_rest([&](int cand) {
+            const double z = rescore1(cand);
             if (z >= cmax - 1e-12) {
               pick = cand;
               best = z;
+              return false;
             }
-          }
+            return true;
+          });
         }
       }
     }
@@ -463,13 +537,11 @@ __global__ void __launch_bounds__(64) search_mfma_kernel(
         status_out[g] = DIC_POI_OK;
       }
     }
-    item = uniform(__shfl(next, 0, kWave));
   }
 }
 
 template <int KB>
-static hipError_t launch_search_mfma_kb(const DevState& st, const SearchGroup& gr, int ctr,
-                                        int occ_cap, const float* ref, const float* def,
+static hipError_t launch_search_mfma_kb(const DevState& st, const SearchGroup& gr, int occ_cap, const float* ref, const float* def,
                                         const int32_t* poi, const int32_t* seed, int32_t* uv,
                                         float* zncc, int32_t* status, int num_cu, hipStream_t s) {
   const int nmax = min(16 * KB - 32, 2 * st.maxM + 1);
@@ -486,8 +558,9 @@ static hipError_t launch_search_mfma_kb(const DevState& st, const SearchGroup& g
   if (occ_cap > 0 && occ > occ_cap) occ = occ_cap;
   int64_t blocks = (int64_t)occ * num_cu;
   if (blocks > gr.count) blocks = gr.count;
+  if (blocks >= kXcds) blocks -= blocks % kXcds;
   hipLaunchKernelGGL(search_mfma_kernel<KB>, dim3((unsigned)blocks), dim3(kWave), lds, s, st,
-                     st.work + gr.begin, gr.count, ctr, nmax, st.tmpl, st.box, ref, def, poi, seed,
+                     st.work + gr.begin, gr.count, nmax, st.tmpl, st.box, ref, def, poi, seed,
                      uv, zncc, status);
   return hipGetLastError();
 }
@@ -503,13 +576,13 @@ hipError_t launch_search_mfma(const DevState& st, const dic_tuning_t& tu,
     if (gr.count == 0) continue;
     hipError_t e = hipErrorInvalidValue;
     if (gr.np == 3)
-      e = launch_search_mfma_kb<3>(st, gr, kCtrSearch + k, tu.search_occupancy, ref, def, poi,
+      e = launch_search_mfma_kb<3>(st, gr, tu.search_occupancy, ref, def, poi,
                                    seed, uv, zncc, status, num_cu, s);
     else if (gr.np == 4)
-      e = launch_search_mfma_kb<4>(st, gr, kCtrSearch + k, tu.search_occupancy, ref, def, poi,
+      e = launch_search_mfma_kb<4>(st, gr, tu.search_occupancy, ref, def, poi,
                                    seed, uv, zncc, status, num_cu, s);
     else if (gr.np == 5)
-      e = launch_search_mfma_kb<5>(st, gr, kCtrSearch + k, tu.search_occupancy, ref, def, poi,
+      e = launch_search_mfma_kb<5>(st, gr, tu.search_occupancy, ref, def, poi,
                                    seed, uv, zncc, status, num_cu, s);
     if (e != hipSuccess) return e;
   }
