@@ -8,9 +8,10 @@
 // restaged only when the warped subset leaves it.  Sample positions are an
 // integer base (POI + rounded translation) plus an FP32 local offset below
 // ~M+slack pixels.  Eight sums per iteration (sum g, sum g^2 and the six
-// steepest-descent products) of FP32 terms are accumulated per lane in FP64
-// (compensation for free: an FP64 add costs what an FP32 add does here) and
-// reduced across the wave with DPP; with the precomputed sum SD_i (f_i - fbar) and sum SD_i the
+// steepest-descent products) are blocked: each lane sums its at most MAXS
+// samples in FP32 (fused multiply-adds), and the 64 lane partials are added
+// in FP64 by DPP, so the relative error stays near MAXS * 2^-24 of the sum of
+// magnitudes; with the precomputed sum SD_i (f_i - fbar) and sum SD_i the
 // right-hand side needs no second pass:
 //   sum SD_i e_i = sum SD_i (f_i - fbar) - (df/dg) (sum SD_i g_i - gbar sum SD_i).
 // The 6x6 solve and the warp composition run in FP64.
@@ -24,9 +25,10 @@ __host__ __device__ __forceinline__ int icgn_patch_side(int maxM, int slack) {
   return 2 * maxM + 4 + 2 * slack;
 }
 
-__device__ __forceinline__ int pack_dxy(int dx, int dy) { return (dx + 128) | ((dy + 128) << 8); }
-__device__ __forceinline__ float unpack_dx(int v) { return (float)((v & 0xff) - 128); }
-__device__ __forceinline__ float unpack_dy(int v) { return (float)(((v >> 8) & 0xff) - 128); }
+
+// A sample's subset offsets (dx, dy): small integers, exact in fp16, one
+// register per sample.
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 
 struct Warp32 {
   int bx, by;                  // integer base of the sample positions
@@ -94,11 +96,12 @@ __device__ __forceinline__ float interp32(const float* src, int pitch, int ox, i
     c0 = min(max(c0, 0), maxc);
     r0 = min(max(r0, 0), maxr);
   }
-  const float* q = src + (int64_t)r0 * pitch + c0;
+  // patch offsets fit 24 bits: a full-rate multiply
+  const float* q = kClamp ? src + (int64_t)r0 * pitch + c0 : src + (__umul24(r0, pitch) + c0);
   float acc = 0.f;
 #pragma unroll
   for (int l = 0; l < 4; ++l) {
-    const float* row = q + (int64_t)l * pitch;
+    const float* row = q + l * pitch;
     const float r = fmaf(wx[3], row[3], fmaf(wx[2], row[2], fmaf(wx[1], row[1], wx[0] * row[0])));
     acc = fmaf(wy[l], r, acc);
   }
@@ -108,25 +111,25 @@ __device__ __forceinline__ float interp32(const float* src, int pitch, int ox, i
 template <int MAXS, bool kClamp>
 __device__ __forceinline__ void iter_pass(const float* src, int pitch, int ox, int oy, int maxc,
                                           int maxr, int n, const Warp32& w, float c0,
-                                          const float* fxs, const float* fys, const int* dxy,
-                                          double* K) {
+                                          const float* fxs, const float* fys, const half2v* dxy,
+                                          float* K) {
   const int lane = lane_id();
 #pragma unroll
   for (int k = 0; k < MAXS; ++k) {
     if (lane + kWave * k < n) {
-      const float dx = unpack_dx(dxy[k]), dy = unpack_dy(dxy[k]);
+      const float dx = (float)dxy[k].x, dy = (float)dxy[k].y;
       const float gs =
           interp32<kClamp>(src, pitch, ox, oy, warp_x(w, dx, dy), warp_y(w, dx, dy), maxc, maxr) -
           c0;
       const float fg = fxs[k] * gs, hg = fys[k] * gs;
-      K[0] += (double)gs;
-      K[1] += (double)(gs * gs);
-      K[2] += (double)fg;
-      K[3] += (double)(fg * dx);
-      K[4] += (double)(fg * dy);
-      K[5] += (double)hg;
-      K[6] += (double)(hg * dx);
-      K[7] += (double)(hg * dy);
+      K[0] += gs;
+      K[1] = fmaf(gs, gs, K[1]);
+      K[2] += fg;
+      K[3] = fmaf(fg, dx, K[3]);
+      K[4] = fmaf(fg, dy, K[4]);
+      K[5] += hg;
+      K[6] = fmaf(hg, dx, K[6]);
+      K[7] = fmaf(hg, dy, K[7]);
     }
   }
 }
@@ -134,20 +137,19 @@ __device__ __forceinline__ void iter_pass(const float* src, int pitch, int ox, i
 template <int MAXS, bool kClamp>
 __device__ __forceinline__ void final_pass(const float* src, int pitch, int ox, int oy, int maxc,
                                            int maxr, int n, const Warp32& w, float c0,
-                                           const int* dxy, const float* __restrict__ tm, int tp,
-                                           int M, double* K) {
+                                           const half2v* dxy, const float* __restrict__ tm,
+                                           int tp, int M, float* K) {
   const int lane = lane_id();
 #pragma unroll
   for (int k = 0; k < MAXS; ++k) {
-    const int s = lane + kWave * k;
-    if (s < n) {
-      const float dx = unpack_dx(dxy[k]), dy = unpack_dy(dxy[k]);
+    if (lane + kWave * k < n) {
+      const float dx = (float)dxy[k].x, dy = (float)dxy[k].y;
       const float gs =
           interp32<kClamp>(src, pitch, ox, oy, warp_x(w, dx, dy), warp_y(w, dx, dy), maxc, maxr) -
           c0;
-      K[0] += (double)gs;
-      K[1] += (double)(gs * gs);
-      K[2] += (double)(tm[((int)dy + M) * tp + (int)dx + M] * gs);
+      K[0] += gs;
+      K[1] = fmaf(gs, gs, K[1]);
+      K[2] = fmaf(tm[((int)dy + M) * tp + (int)dx + M], gs, K[2]);
     }
   }
 }
@@ -177,9 +179,9 @@ struct Patch {
   }
 };
 
-__device__ __forceinline__ void reduce8(const double* K, double* S) {
+__device__ __forceinline__ void reduce8(const float* K, double* S) {
 #pragma unroll
-  for (int a = 0; a < 8; ++a) S[a] = wave_sum_dpp(K[a]);
+  for (int a = 0; a < 8; ++a) S[a] = wave_sum_dpp((double)K[a]);
 }
 
 }  // namespace
@@ -190,7 +192,8 @@ size_t icgn_lds_bytes(int maxM, int slack, int waves) {
 }
 
 template <int MAXS>
-__global__ void __launch_bounds__(512) icgn_f32_kernel(
+__global__ void __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
     DevState st, int slack, const float* __restrict__ def, const int32_t* __restrict__ poi,
     const int32_t* __restrict__ uv_init, const int32_t* __restrict__ status_in,
     const double* __restrict__ p_init, double* __restrict__ p_out, float* __restrict__ zncc_out,
@@ -228,18 +231,18 @@ __global__ void __launch_bounds__(512) icgn_f32_kernel(
       const float* gx = st.grads + P.grad_off;
       const float* gy = gx + (int64_t)W * H;
       float fxs[MAXS], fys[MAXS];
-      int dxy[MAXS];
+      half2v dxy[MAXS];
 #pragma unroll
       for (int k = 0; k < MAXS; ++k) {
         const int s = lane + kWave * k;
         fxs[k] = fys[k] = 0.f;
-        dxy[k] = pack_dxy(0, 0);
+        dxy[k] = half2v{(_Float16)0.f, (_Float16)0.f};
         if (s < n) {
           const int r = s / n1, c = s - r * n1;
           const int64_t idx = (int64_t)(y0 - M + r) * W + (x0 - M + c);
           fxs[k] = gx[idx];
           fys[k] = gy[idx];
-          dxy[k] = pack_dxy(c - M, r - M);
+          dxy[k] = half2v{(_Float16)(c - M), (_Float16)(r - M)};
         }
       }
       const float c0 = (float)R->fbar;
@@ -256,7 +259,7 @@ __global__ void __launch_bounds__(512) icgn_f32_kernel(
           status = DIC_POI_OUT_OF_BOUNDS;
           break;
         }
-        double K[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        float K[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (patch.ensure(gimg, W, H, xl, xh, yl, yh))
           iter_pass<MAXS, false>(patch.buf, pside, w.bx - patch.x0, w.by - patch.y0, 0, 0, n, w,
                                  c0, fxs, fys, dxy, K);
@@ -294,16 +297,16 @@ __global__ void __launch_bounds__(512) icgn_f32_kernel(
           status = DIC_POI_OUT_OF_BOUNDS;
         } else {
           const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * P.tmpl_pitch;
-          double K[3] = {0, 0, 0};
+          float K[3] = {0.f, 0.f, 0.f};
           if (patch.ensure(gimg, W, H, xl, xh, yl, yh))
             final_pass<MAXS, false>(patch.buf, pside, w.bx - patch.x0, w.by - patch.y0, 0, 0, n, w,
                                     c0, dxy, tm, P.tmpl_pitch, M, K);
           else
             final_pass<MAXS, true>(gimg, W, w.bx, w.by, W - 4, H - 4, n, w, c0, dxy, tm,
                                    P.tmpl_pitch, M, K);
-          const double s0 = wave_sum_dpp(K[0]);
-          const double s1 = wave_sum_dpp(K[1]);
-          const double s2 = wave_sum_dpp(K[2]);
+          const double s0 = wave_sum_dpp((double)K[0]);
+          const double s1 = wave_sum_dpp((double)K[1]);
+          const double s2 = wave_sum_dpp((double)K[2]);
           if (!isfinite(s0) || !isfinite(s1)) {
             status = DIC_POI_NAN_INPUT;
           } else {
