@@ -45,7 +45,9 @@ hipError_t launch_gradients(const DevState& st, const float* ref, hipStream_t s)
 // S1[y][x] = sum g, S2[y][x] = sum g^2 over the (2M+1)^2 subset centred on
 // (x, y).  A centre whose subset leaves the image or holds a non-finite
 // pixel gets S2 = -1.  Two passes: column sums (running down 64-row
-// segments), then row sums of those (direct, 2M+1 terms).  The second pass
+// segments, one term in and one out per step), then row sums of those
+// (direct, 2M+1 terms from an LDS tile); the order is fixed, so the results
+// are deterministic.  The second pass
 // also stores per centre the float pair (mean, 1/sqrt(sum (g - mean)^2)) that
 // the matrix-core search scores with, (0, 0) where the subset is inadmissible
 // or flat by the FP64 rule.
@@ -95,34 +97,47 @@ __global__ void __launch_bounds__(256) box_cols_kernel(const DevPair* __restrict
   }
 }
 
-__global__ void __launch_bounds__(256) box_rows_kernel(const DevPair* __restrict__ pairs,
-                                                       double* __restrict__ box) {
+// Row pass: a workgroup stages one row segment of the column sums (with the
+// 2M-column halo) in LDS; each thread then sums its 2M+1 columns directly.
+constexpr int kBoxRowTile = 256;
+
+__global__ void __launch_bounds__(kBoxRowTile) box_rows_kernel(const DevPair* __restrict__ pairs,
+                                                               double* __restrict__ box) {
+  __shared__ double l1[kBoxRowTile + 2 * kMaxM];
+  __shared__ double l2[kBoxRowTile + 2 * kMaxM];
   const DevPair P = pairs[blockIdx.z];
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
+  const int x0 = blockIdx.x * kBoxRowTile, y = blockIdx.y;
   const int W = P.width, H = P.height, M = P.M;
-  if (x >= W || y >= H) return;
+  if (x0 >= W || y >= H) return;   // uniform over the workgroup
   const int64_t plane = (int64_t)W * H;
   const double* v1 = box + P.box_off + (int64_t)y * W;
   const double* v2 = v1 + plane;
+  for (int i = threadIdx.x; i < kBoxRowTile + 2 * M; i += kBoxRowTile) {
+    const int j = x0 - M + i;
+    const bool in = j >= 0 && j < W;
+    l1[i] = in ? v1[j] : 0.0;
+    l2[i] = in ? v2[j] : -1.0;
+  }
+  __syncthreads();
+  const int x = x0 + threadIdx.x;
+  if (x >= W) return;
   double* o1 = box + P.box_off + 2 * plane + (int64_t)y * W;
   double* o2 = o1 + plane;
   float2* o3 = reinterpret_cast<float2*>(o2 + plane);
   double s1 = 0.0, s2 = 0.0;
   bool bad = x - M < 0 || x + M > W - 1;
-  if (!bad)
-    for (int j = x - M; j <= x + M; ++j) {
-      const double q = v2[j];
-      bad |= q < 0.0;
-      s1 += v1[j];
-      s2 += q;
-    }
+  for (int i = threadIdx.x; i <= threadIdx.x + 2 * M; ++i) {
+    const double q = l2[i];
+    bad |= q < 0.0;
+    s1 += l1[i];
+    s2 += q;
+  }
   o1[x] = bad ? 0.0 : s1;
   o2[x] = bad ? -1.0 : s2;
   const double n = (double)(2 * M + 1) * (double)(2 * M + 1);
   const double var = s2 - s1 * s1 / n;
-  const bool ok = !bad && not_flat(var, s2);
-  o3[x] = ok ? make_float2((float)(s1 / n), (float)(1.0 / sqrt(var))) : make_float2(0.f, 0.f);
+  o3[x] = !bad && not_flat(var, s2) ? make_float2((float)(s1 / n), (float)(1.0 / sqrt(var)))
+                                    : make_float2(0.f, 0.f);
 }
 
 hipError_t launch_box_sums(const DevState& st, const float* def, hipStream_t s) {
@@ -131,8 +146,8 @@ hipError_t launch_box_sums(const DevState& st, const float* def, hipStream_t s) 
   hipLaunchKernelGGL(box_cols_kernel, gc, dim3(256), 0, s, st.pairs, def, st.box);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const dim3 gr((st.max_width + 255) / 256, st.max_height, st.num_pairs);
-  hipLaunchKernelGGL(box_rows_kernel, gr, dim3(256), 0, s, st.pairs, st.box);
+  const dim3 gr((st.max_width + kBoxRowTile - 1) / kBoxRowTile, st.max_height, st.num_pairs);
+  hipLaunchKernelGGL(box_rows_kernel, gr, dim3(kBoxRowTile), 0, s, st.pairs, st.box);
   return hipGetLastError();
 }
 
@@ -146,10 +161,14 @@ __device__ __forceinline__ void write_bad_record(RefRec* R, int status, int lane
   }
 }
 
-// FP32 form: one wave per POI.  Mean and norm of the subset in FP64 (they
-// decide ZERO_VARIANCE exactly as the FP64 definition does); steepest-descent
-// products and the 21 Hessian products in FP32, accumulated per lane in FP64
-// and reduced with DPP; centring, factorisation and singularity test in
+// FP32 form: one wave per POI, two passes over the subset (pixel k on lane
+// k mod 64, its row and column stepped without division).  Pass 1, in FP64:
+// sum f (the mean decides ZERO_VARIANCE exactly as the FP64 definition does)
+// and the six steepest-descent sums sum SD.  Pass 2: sum (f - fbar)^2 and
+// sum f^2 in FP64; the 21 products of the mean-removed steepest-descent
+// images (the Hessian, no cancellation left) and the six sum SD (f - fbar)
+// in FP32 per lane with fused multiply-adds (at most a few tens of terms),
+// added across lanes in FP64 by DPP.  Factorisation and singularity test in
 // FP64.  Also stores the float search template f_i - fbar.
 __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
                                                            const float* __restrict__ ref,
@@ -165,8 +184,8 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
     write_bad_record(R, DIC_POI_OUT_OF_BOUNDS, lane);
     return;
   }
-  const float* f = ref + P.ref_off;
-  const float* gxi = st.grads + P.grad_off;
+  const float* f = ref + P.ref_off + (int64_t)(y0 - M) * W + (x0 - M);
+  const float* gxi = st.grads + P.grad_off + (int64_t)(y0 - M) * W + (x0 - M);
   const float* gyi = gxi + (int64_t)P.width * P.height;
   const int tp = P.tmpl_pitch;
   float* tmpl = st.tmpl + P.tmpl_off + (g - P.poi_off) * (int64_t)(n1 * tp);
@@ -174,70 +193,110 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
     const int r = k / (tp - n1);
     tmpl[r * tp + n1 + (k - r * (tp - n1))] = 0.f;   // zero padding of every row
   }
+  const int dr = kWave / n1, dc = kWave - dr * n1;
+  auto step = [&](int& r, int& c) {
+    c += dc;
+    r += dr;
+    if (c >= n1) {
+      c -= n1;
+      ++r;
+    }
+  };
+  auto sd_of = [&](float fx, float fy, int r, int c, float* sd) {
+    const float dx = (float)(c - M), dy = (float)(r - M);
+    sd[0] = fx;
+    sd[1] = fx * dx;
+    sd[2] = fx * dy;
+    sd[3] = fy;
+    sd[4] = fy * dx;
+    sd[5] = fy * dy;
+  };
 
-  double s1 = 0.0;
+  double s1 = 0.0, ssd[6] = {0, 0, 0, 0, 0, 0};
   int bad = 0;
-  for (int k = lane; k < n; k += kWave) {
-    const int r = k / n1, c = k - r * n1;
-    const float v = f[(int64_t)(y0 - M + r) * W + (x0 - M + c)];
-    bad |= !isfinite(v);
-    s1 += (double)v;
+  {
+    int r = lane / n1, c = lane - r * n1;
+    for (int k = lane; k < n; k += kWave) {
+      const int o = r * W + c;
+      const float v = f[o];
+      bad |= !isfinite(v);
+      s1 += (double)v;
+      float sd[6];
+      sd_of(gxi[o], gyi[o], r, c, sd);
+#pragma unroll
+      for (int a = 0; a < 6; ++a) ssd[a] += (double)sd[a];
+      step(r, c);
+    }
   }
-  s1 = wave_sum(s1);
+  s1 = wave_sum_dpp(s1);
   bad = wave_or_int(bad);
   if (bad) {
     write_bad_record(R, DIC_POI_NAN_INPUT, lane);
     return;
   }
+  double sdsum[6];
+  float sdm[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    sdsum[a] = wave_sum_dpp(ssd[a]);
+    sdm[a] = (float)(sdsum[a] / (double)n);
+  }
   const double fbar = s1 / (double)n;
   const float fbar_f = (float)fbar;
 
   double q = 0.0, sq = 0.0, ts = 0.0;
-  double ksd[6] = {0}, ksdf[6] = {0}, kh[21] = {0};
-  for (int k = lane; k < n; k += kWave) {
-    const int r = k / n1, c = k - r * n1;
-    const int64_t idx = (int64_t)(y0 - M + r) * W + (x0 - M + c);
-    const float v = f[idx];
-    const double d = (double)v - fbar;
-    q += d * d;
-    sq += (double)v * (double)v;
-    const float t = v - fbar_f;
-    tmpl[r * tp + c] = t;
-    ts += (double)t;
-    const float fx = gxi[idx], fy = gyi[idx];
-    const float dx = (float)(c - M), dy = (float)(r - M);
-    const float sd[6] = {fx, fx * dx, fx * dy, fy, fy * dx, fy * dy};
+  float ksdf[6] = {0, 0, 0, 0, 0, 0}, kh[21];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) {
-      ksd[a] += (double)sd[a];
-      ksdf[a] += (double)(sd[a] * t);
+  for (int a = 0; a < 21; ++a) kh[a] = 0.f;
+  {
+    int r = lane / n1, c = lane - r * n1;
+    for (int k = lane; k < n; k += kWave) {
+      const int o = r * W + c;
+      const float v = f[o];
+      const double d = (double)v - fbar;
+      q += d * d;
+      sq += (double)v * (double)v;
+      const float t = v - fbar_f;
+      tmpl[r * tp + c] = t;
+      ts += (double)t;
+      float sd[6];
+      sd_of(gxi[o], gyi[o], r, c, sd);
 #pragma unroll
-      for (int b = 0; b <= a; ++b) kh[tri(a, b)] += (double)(sd[a] * sd[b]);
+      for (int a = 0; a < 6; ++a) {
+        ksdf[a] = fmaf(sd[a], t, ksdf[a]);
+        sd[a] -= sdm[a];
+      }
+#pragma unroll
+      for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) kh[tri(a, b)] = fmaf(sd[a], sd[b], kh[tri(a, b)]);
+      step(r, c);
     }
   }
   q = wave_sum_dpp(q);
   sq = wave_sum_dpp(sq);
   ts = wave_sum_dpp(ts);
-  double sdsum[6], sdfsum[6], h[21];
+  double sdfsum[6], h[21];
 #pragma unroll
-  for (int a = 0; a < 6; ++a) {
-    sdsum[a] = wave_sum_dpp(ksd[a]);
-    sdfsum[a] = wave_sum_dpp(ksdf[a]);
-  }
+  for (int a = 0; a < 6; ++a) sdfsum[a] = wave_sum_dpp((double)ksdf[a]);
 #pragma unroll
-  for (int a = 0; a < 21; ++a) h[a] = wave_sum_dpp(kh[a]);
+  for (int a = 0; a < 21; ++a) h[a] = wave_sum_dpp((double)kh[a]);
 
   int status = DIC_POI_OK;
   double L[21], rd[6];
   if (!not_flat(q, sq)) {
     status = DIC_POI_ZERO_VARIANCE;
   } else {
-    // Hessian of the mean-removed steepest-descent images.
-    const double rn = 1.0 / (double)n;
+    // Hessian of the mean-removed steepest-descent images (centred in pass 2
+    // by the FP32 rounding of the means: the residual mean m' gives n m' m'^T,
+    // which is removed here)
+    double mres[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) mres[a] = sdsum[a] / (double)n - (double)sdm[a];
 #pragma unroll
     for (int a = 0; a < 6; ++a)
 #pragma unroll
-      for (int b = 0; b <= a; ++b) h[tri(a, b)] -= sdsum[a] * sdsum[b] * rn;
+      for (int b = 0; b <= a; ++b) h[tri(a, b)] -= (double)n * mres[a] * mres[b];
     if (!cholesky6(h, L, rd)) status = DIC_POI_SINGULAR_HESSIAN;
   }
   if (lane == 0) {
