@@ -1,6 +1,6 @@
 """FP64 CPU oracle for subset DIC: ZNCC brute-force integer search, IC-GN
-sub-pixel refinement (first-order shape function, bicubic interpolation) and
-the ZNSSD adjoint.
+and Newton-Raphson sub-pixel refinement (first-order shape function, bicubic
+interpolation) and the ZNSSD adjoint.
 
 TEST INFRASTRUCTURE ONLY.  This module is the slow, obviously correct
 reference that the HIP library is checked against.  Only the test-suite, the
@@ -18,7 +18,8 @@ MATLAB"):
   keeps the one with the largest coefficient.
 * Sec. 2.2: a pixel's grey level is the value at its centre; bicubic
   interpolation; IC-GN with an affine (first-order) warp whose reference-side
-  quantities (gradients, steepest-descent images, Hessian) are precomputed.
+  quantities (gradients, steepest-descent images, Hessian) are precomputed;
+  Newton-Raphson, whose quantities are recomputed at every iteration.
 
 Where the paper is silent the readings listed at each function are used (the
 paper defers IC-GN details to Pan et al. and Baker & Matthews).
@@ -397,6 +398,100 @@ def icgn(f: np.ndarray, g: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, 
 
 
 # ---------------------------------------------------------------------------
+# Sec. 2.2: Newton-Raphson sub-pixel refinement
+# ---------------------------------------------------------------------------
+
+@dataclass
+class NrStep:
+    zncc: float
+    grad: np.ndarray            # dC/dp, C = ZNSSD
+    hess: np.ndarray            # Gauss-Newton approximation of d2C/dp2
+    dg: float
+
+
+def nr_terms(fs: np.ndarray, gs: np.ndarray, gx: np.ndarray, gy: np.ndarray,
+             dx: np.ndarray, dy: np.ndarray) -> NrStep:
+    """Gradient and Gauss-Newton Hessian of the ZNSSD criterion
+    C(p) = sum (fhat_i - ghat_i)^2, fhat = (f - fbar)/df, ghat = (g - gbar)/dg,
+    with g_i = g(x0 + W(p) xi_i) and the forward warp's Jacobian
+    J_i = [gx, gx dx, gx dy, gy, gy dx, gy dy] (gradient of the interpolant at
+    the sample).  With Jc = J - mean(J):
+      dC/dp = -(2/dg) sum Jc_i (fhat_i - ZNCC ghat_i)          (exact)
+      H     =  (2/dg^2) sum Jc_i^T Jc_i                          (Gauss-Newton:
+    the second derivatives of the interpolant and of the normalisation are
+    neglected, the Hessian approximation of the Newton-Raphson method as DIC
+    uses it)."""
+    fbar, gbar = fs.mean(), gs.mean()
+    df = np.sqrt(np.sum((fs - fbar) ** 2))
+    dg = np.sqrt(np.sum((gs - gbar) ** 2))
+    fh, gh = (fs - fbar) / df, (gs - gbar) / dg
+    z = float(np.sum(fh * gh))
+    J = np.stack([gx, gx * dx, gx * dy, gy, gy * dx, gy * dy], axis=1)
+    Jc = J - J.mean(axis=0)
+    grad = -(2.0 / dg) * (Jc.T @ (fh - z * gh))
+    hess = (2.0 / dg ** 2) * (Jc.T @ Jc)
+    return NrStep(z, grad, hess, float(dg))
+
+
+def nr(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, p0: Sequence[float],
+       max_iters: int = 20, tol: float = 1e-3) -> IcgnResult:
+    """Newton-Raphson refinement (Sec. 2.2: the method whose parameters are
+    recomputed at every iteration, in contrast to IC-GN) on the ZNSSD
+    criterion with the first-order warp applied forward, x_i = x0 + W(p) xi_i,
+    and updated additively.
+
+    Per iteration: warp, interpolate g and its gradient, form dC/dp and the
+    Gauss-Newton Hessian (``nr_terms``), p <- p - H^-1 dC/dp, stop when
+    |dp| < tol (``update_norm``).  The fixed point is a stationary point of
+    ZNSSD itself.  Readings: the POI must pass the same reference checks as
+    IC-GN (subset and one-pixel border inside, finite, not flat); a warp whose
+    4x4 neighbourhoods leave the image stops with OUT_OF_BOUNDS, a Hessian
+    whose Cholesky pivot fails (``cholesky6``) with SINGULAR_HESSIAN, both
+    keeping the last p; the reported coefficient is Eq. (1) at the final p.
+    """
+    H, W = g.shape
+    p = np.asarray(p0, dtype=np.float64).copy()
+    if not poi_inside(x0, y0, M, f.shape[1], f.shape[0]):
+        return IcgnResult(p, float("nan"), 0, OUT_OF_BOUNDS)
+    fs = subset(f, x0, y0, M)
+    if not np.all(np.isfinite(fs)):
+        return IcgnResult(p, float("nan"), 0, NAN_INPUT)
+    if is_flat(fs):
+        return IcgnResult(p, float("nan"), 0, ZERO_VARIANCE)
+    dx, dy = subset_offsets(M)
+    it = 0
+    status = NOT_CONVERGED
+    while it < max_iters:
+        it += 1
+        xs, ys = warp_points(p, x0, y0, dx, dy)
+        if not in_interp_bounds(xs, ys, W, H):
+            return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
+        gs, gx, gy = interpolate(g, xs, ys, with_grad=True)
+        if not (np.all(np.isfinite(gs)) and np.all(np.isfinite(gx)) and np.all(np.isfinite(gy))):
+            return IcgnResult(p, float("nan"), it, NAN_INPUT)
+        if is_flat(gs):
+            return IcgnResult(p, float("nan"), it, ZERO_VARIANCE)
+        t = nr_terms(fs, gs, gx, gy, dx, dy)
+        L = cholesky6(t.hess)
+        if L is None:
+            return IcgnResult(p, float("nan"), it, SINGULAR_HESSIAN)
+        dp = -cholesky_solve(L, t.grad)
+        p = p + dp
+        if update_norm(dp, M) < tol:
+            status = OK
+            break
+    xs, ys = warp_points(p, x0, y0, dx, dy)
+    if not in_interp_bounds(xs, ys, W, H):
+        return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
+    gs = interpolate(g, xs, ys)
+    if not np.all(np.isfinite(gs)):
+        return IcgnResult(p, float("nan"), it, NAN_INPUT)
+    if is_flat(gs):
+        return IcgnResult(p, float("nan"), it, ZERO_VARIANCE)
+    return IcgnResult(p, zncc(fs, gs), it, status)
+
+
+# ---------------------------------------------------------------------------
 # ZNSSD criterion and its adjoint (forward-additive parameters)
 # ---------------------------------------------------------------------------
 
@@ -481,10 +576,12 @@ def znssd_batch(f: np.ndarray, g: np.ndarray, pois: np.ndarray, M: int, P: np.nd
 
 def correlate(f: np.ndarray, g: np.ndarray, pois: np.ndarray, M: int, S: int,
               centers: Optional[np.ndarray] = None, p_init: Optional[np.ndarray] = None,
-              max_iters: int = 20, tol: float = 1e-3) -> Dict[str, np.ndarray]:
-    """Integer search then IC-GN for every POI (Sec. 2: the integer result
-    seeds the sub-pixel search; initial p = (du, 0, 0, dv, 0, 0), or the
-    gradient terms of ``p_init`` when given)."""
+              max_iters: int = 20, tol: float = 1e-3,
+              refine: str = "icgn") -> Dict[str, np.ndarray]:
+    """Integer search then IC-GN (or Newton-Raphson, ``refine="nr"``) for
+    every POI (Sec. 2: the integer result seeds the sub-pixel search; initial
+    p = (du, 0, 0, dv, 0, 0), or the gradient terms of ``p_init`` when
+    given)."""
     N = pois.shape[0]
     fx, fy = central_gradients(f)
     out = dict(uv=np.zeros((N, 2), np.int32), zncc_int=np.full(N, np.nan),
@@ -505,7 +602,10 @@ def correlate(f: np.ndarray, g: np.ndarray, pois: np.ndarray, M: int, S: int,
         p0 = np.array([s.du, 0, 0, s.dv, 0, 0], dtype=np.float64)
         if p_init is not None:
             p0[[1, 2, 4, 5]] = p_init[i, [1, 2, 4, 5]]
-        r = icgn(f, g, fx, fy, x0, y0, M, p0, max_iters, tol)
+        if refine == "nr":
+            r = nr(f, g, x0, y0, M, p0, max_iters, tol)
+        else:
+            r = icgn(f, g, fx, fy, x0, y0, M, p0, max_iters, tol)
         out["p"][i] = r.p
         out["zncc"][i] = r.zncc
         out["iters"][i] = r.iters
