@@ -87,8 +87,11 @@ enum {
                                          deformed-side precomputations for
                                          the same image pointers until
                                          dic_plan_invalidate_reference()     */
-  DIC_FLAG_DETERMINISTIC_BWD = 1u << 2 /* grad_def accumulated in a fixed
+  DIC_FLAG_DETERMINISTIC_BWD = 1u << 2, /* grad_def accumulated in a fixed
                                          order (no float atomics)            */
+  DIC_FLAG_REFINE_NR = 1u << 3        /* dic_correlate (and the autotuner)
+                                         refine with Newton-Raphson instead
+                                         of IC-GN                            */
 };
 
 typedef struct {
@@ -214,7 +217,29 @@ dic_status_t dic_icgn_refine(dic_plan_t plan, const float* ref_images,
                              float* zncc_out, int32_t* iters_out,
                              int32_t* status_out, dic_stream_t stream);
 
-/* Search then refine in one call (the two entries above, in order).
+/* Newton-Raphson sub-pixel refinement (Sec. 2.2: the alternative to IC-GN
+ * whose quantities are recomputed at every iteration), on the ZNSSD
+ * criterion with the first-order warp applied forward,
+ * x_i = x0 + W(p) xi_i, and updated additively.  Each iteration interpolates
+ * g and its gradient (Keys, a = -1/2) at the warped samples, forms
+ * J_i = [gx, gx dx, gx dy, gy, gy dx, gy dy], Jc = J - mean(J), and takes
+ *   dp = Hc^-1 sum Jc_i [(dg/df)(f_i - fbar) - ZNCC (g_i - gbar)],
+ *   Hc = sum Jc_i^T Jc_i,
+ * i.e. p <- p - H^-1 dC/dp with the exact gradient of ZNSSD and its
+ * Gauss-Newton Hessian; a Cholesky pivot failure stops with
+ * SINGULAR_HESSIAN (last p kept).  Arguments, outputs, stop rule and the
+ * other statuses are those of dic_icgn_refine; the reference-side Hessian
+ * of the plan's records is not used (a POI whose reference Hessian is
+ * singular is refined). */
+dic_status_t dic_nr_refine(dic_plan_t plan, const float* ref_images,
+                           const float* def_images, const int32_t* poi_xy,
+                           const int32_t* uv_init, const int32_t* status_in,
+                           const double* p_init, double* p_out,
+                           float* zncc_out, int32_t* iters_out,
+                           int32_t* status_out, dic_stream_t stream);
+
+/* Search then refine in one call (the two entries above, in order; the
+ * refinement is Newton-Raphson when the plan has DIC_FLAG_REFINE_NR).
  * zncc_int_out / status_int_out receive the search results (nullable).  With
  * DIC_FLAG_USE_GRAPH the enqueued work is captured once per distinct set of
  * pointers and replayed as a HIP graph afterwards. */

@@ -14,9 +14,10 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdic.so")
 
 SOURCES = [
-    "k_prep.hip", "k_search.hip", "k_search_mfma.hip", "k_icgn.hip", "k_znssd.hip", "dic_api.cpp"
+    "k_prep.hip", "k_search.hip", "k_search_mfma.hip", "k_icgn.hip", "k_nr.hip", "k_znssd.hip",
+    "dic_api.cpp",
 ]
-HEADERS = ["dic_internal.h", "dic_device.h", "search_common.h"]
+HEADERS = ["dic_internal.h", "dic_device.h", "search_common.h", "refine_common.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -88,6 +88,7 @@ struct dic_plan_s {
 
   bool fp32() const { return desc.precision == DIC_FP32_BATCHED; }
   bool det() const { return (desc.flags & DIC_FLAG_DETERMINISTIC_BWD) != 0; }
+  bool nr() const { return (desc.flags & DIC_FLAG_REFINE_NR) != 0; }
 };
 
 namespace {
@@ -217,14 +218,22 @@ dic_status_t enqueue_search(dic_plan_t p, const float* ref, const float* def, co
   return DIC_SUCCESS;
 }
 
+// Sub-pixel refinement: IC-GN, or Newton-Raphson when `nr`.
 dic_status_t enqueue_refine(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
                             const int32_t* uv, const int32_t* status_in, const double* p_init,
                             double* p_out, float* zn, int32_t* iters, int32_t* status,
-                            hipStream_t s) {
+                            hipStream_t s, bool nr) {
   if (p->fp32()) {
     DIC_HIP(launch_reset_counters(p->st, s));
-    DIC_HIP(launch_icgn_f32(p->st, p->tuning, ref, def, poi, uv, status_in, p_init, p_out, zn,
-                            iters, status, p->num_cu, s));
+    if (nr)
+      DIC_HIP(launch_nr_f32(p->st, p->tuning, def, poi, uv, status_in, p_init, p_out, zn, iters,
+                            status, p->num_cu, s));
+    else
+      DIC_HIP(launch_icgn_f32(p->st, p->tuning, ref, def, poi, uv, status_in, p_init, p_out, zn,
+                              iters, status, p->num_cu, s));
+  } else if (nr) {
+    DIC_HIP(launch_nr_f64(p->st, p->dpairs.data(), ref, def, poi, uv, status_in, p_init, p_out,
+                          zn, iters, status, s));
   } else {
     DIC_HIP(launch_icgn_f64(p->st, p->dpairs.data(), ref, def, poi, uv, status_in, p_init, p_out,
                             zn, iters, status, s));
@@ -252,7 +261,7 @@ dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s) {
   r = enqueue_search(p, a.ref, a.def, a.poi, a.seed, a.uv, a.zn_int, a.st_int, s);
   if (r != DIC_SUCCESS) return r;
   return enqueue_refine(p, a.ref, a.def, a.poi, a.uv, a.st_int, a.p_init, a.p_out, a.zn, a.iters,
-                        a.status, s);
+                        a.status, s, p->nr());
 }
 
 }  // namespace
@@ -283,7 +292,8 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
   if (d->max_iters < 1 || d->max_iters > 200) return fail(DIC_ERR_INVALID_ARGUMENT, "max_iters outside 1..200");
   if (!(d->conv_tol > 0.0) || !std::isfinite(d->conv_tol))
     return fail(DIC_ERR_INVALID_ARGUMENT, "conv_tol must be positive and finite");
-  const uint32_t known = DIC_FLAG_USE_GRAPH | DIC_FLAG_CACHE_REF_PREP | DIC_FLAG_DETERMINISTIC_BWD;
+  const uint32_t known = DIC_FLAG_USE_GRAPH | DIC_FLAG_CACHE_REF_PREP |
+                         DIC_FLAG_DETERMINISTIC_BWD | DIC_FLAG_REFINE_NR;
   if (d->flags & ~known) return fail(DIC_ERR_INVALID_ARGUMENT, "unknown flag bits");
   auto p = new dic_plan_s();
   p->desc = *d;
@@ -534,7 +544,24 @@ dic_status_t dic_icgn_refine(dic_plan_t p, const float* ref, const float* def, c
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   r = prepare(p, ref, poi, s, false);
   if (r) return r;
-  return enqueue_refine(p, ref, def, poi, uv_init, status_in, p_init, p_out, zn, iters, status, s);
+  return enqueue_refine(p, ref, def, poi, uv_init, status_in, p_init, p_out, zn, iters, status, s,
+                        false);
+}
+
+dic_status_t dic_nr_refine(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
+                           const int32_t* uv_init, const int32_t* status_in,
+                           const double* p_init, double* p_out, float* zn, int32_t* iters,
+                           int32_t* status, dic_stream_t stream) {
+  dic_status_t r = check_plan(p, true);
+  if (r) return r;
+  if (p->N == 0) return DIC_SUCCESS;
+  if (!ref || !def || !poi || !uv_init || !p_out || !zn || !iters || !status)
+    return fail(DIC_ERR_INVALID_ARGUMENT, "null required pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  r = prepare(p, ref, poi, s, false);
+  if (r) return r;
+  return enqueue_refine(p, ref, def, poi, uv_init, status_in, p_init, p_out, zn, iters, status, s,
+                        true);
 }
 
 dic_status_t dic_correlate(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
@@ -703,7 +730,8 @@ dic_status_t dic_plan_autotune(dic_plan_t p, const float* ref, const float* def,
       p->tuning = c;
       float ms = 0.f;
       r = time_it([&] {
-        return enqueue_refine(p, ref, def, poi, uv, is, nullptr, ps, fs, is + p->N, is + p->N, s);
+        return enqueue_refine(p, ref, def, poi, uv, is, nullptr, ps, fs, is + p->N, is + p->N, s,
+                              p->nr());
       }, &ms);
       if (r) continue;
       if (ms < best_ms) {

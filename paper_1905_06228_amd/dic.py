@@ -22,6 +22,7 @@ FP64_PLAIN = 1
 FLAG_USE_GRAPH = 1
 FLAG_CACHE_REF_PREP = 2
 FLAG_DETERMINISTIC_BWD = 4
+FLAG_REFINE_NR = 8
 
 POI_OK = 0
 POI_NOT_CONVERGED = 1
@@ -53,7 +54,7 @@ class Tuning(ctypes.Structure):
 EXPORTS = [
     "dic_plan_create", "dic_plan_workspace_size", "dic_plan_bind", "dic_plan_get_tuning",
     "dic_plan_set_tuning", "dic_plan_autotune", "dic_plan_invalidate_reference",
-    "dic_prepare_reference", "dic_prepare_deformed", "dic_integer_search", "dic_icgn_refine", "dic_correlate",
+    "dic_prepare_reference", "dic_prepare_deformed", "dic_integer_search", "dic_icgn_refine", "dic_nr_refine", "dic_correlate",
     "dic_znssd_backward", "dic_seed_update", "dic_poi_grid", "dic_plan_destroy",
     "dic_status_string", "dic_last_error",
 ]
@@ -86,6 +87,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.dic_prepare_deformed.argtypes = [P, V, V]
     L.dic_integer_search.argtypes = [P, V, V, V, V, V, V, V, V]
     L.dic_icgn_refine.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V]
+    L.dic_nr_refine.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V]
     L.dic_correlate.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V, V, V]
     L.dic_znssd_backward.argtypes = [P, V, V, V, V, V, V, V, V, V]
     L.dic_seed_update.argtypes = [P, V, V, V, V, V]
@@ -247,13 +249,20 @@ class Plan:
         return uv, zn, st
 
     def icgn_refine(self, ref, defm, pois, uv, status_in=None, p_init=None, out=None):
+        return self._refine(self.L.dic_icgn_refine, ref, defm, pois, uv, status_in, p_init, out)
+
+    def nr_refine(self, ref, defm, pois, uv, status_in=None, p_init=None, out=None):
+        """Newton-Raphson refinement (same arguments and outputs as icgn_refine)."""
+        return self._refine(self.L.dic_nr_refine, ref, defm, pois, uv, status_in, p_init, out)
+
+    def _refine(self, fn, ref, defm, pois, uv, status_in, p_init, out):
         d, N = self.device, self.N
         p, zn, it, st = out if out is not None else (
             torch.empty((N, 6), dtype=torch.float64, device=d),
             torch.empty(N, dtype=torch.float32, device=d),
             torch.empty(N, dtype=torch.int32, device=d),
             torch.empty(N, dtype=torch.int32, device=d))
-        _check(self.L.dic_icgn_refine(
+        _check(fn(
             self._h, _ptr(ref, torch.float32, d, "ref"), _ptr(defm, torch.float32, d, "def"),
             _ptr(pois, torch.int32, d, "pois"), _ptr(uv, torch.int32, d, "uv"),
             _ptr(status_in, torch.int32, d, "status_in"),
