@@ -168,6 +168,12 @@ def main() -> int:
         F, G, Q, so["uv"], so["status_int"],
         out=(so["p"], so["zncc"], so["iters"], so["status"])), reps)
     iters = got["iters"][got["status"] == 0]
+    # Newton-Raphson refinement of the same search result (Sec. 2.2's other
+    # sub-pixel method), both precisions
+    nro = (so["p"].clone(), so["zncc"].clone(), so["iters"].clone(), so["status"].clone())
+    t_nr = time_launches(torch, lambda: st.nr_refine(F, G, Q, so["uv"], so["status_int"], out=nro),
+                         reps)
+    nr_p, nr_it, nr_st = nro[0].cpu().numpy(), nro[2].cpu().numpy(), nro[3].cpu().numpy()
 
     # --- FP64 plain form ---------------------------------------------------------
     p64 = dic.single_pair_plan(W, H, pair.M, pair.S, N, dic.FP64_PLAIN)
@@ -185,6 +191,12 @@ def main() -> int:
     t64_icgn = time_launches(torch, lambda: p64.icgn_refine(
         F, G, Q, o64["uv"], o64["status_int"],
         out=(o64["p"], o64["zncc"], o64["iters"], o64["status"])), 2)
+    n64 = (o64["p"].clone(), o64["zncc"].clone(), o64["iters"].clone(), o64["status"].clone())
+    t64_nr = time_launches(torch, lambda: p64.nr_refine(F, G, Q, o64["uv"], o64["status_int"],
+                                                        out=n64), 2)
+    nr64_p, nr64_st = n64[0].cpu().numpy(), n64[3].cpu().numpy()
+    okn = (nr_st == 0) & (nr64_st == 0)
+    nr_fp32_vs_fp64 = float(np.abs(nr_p[okn][:, [0, 3]] - nr64_p[okn][:, [0, 3]]).max(initial=0))
     ok2 = (got["status"] == 0) & (g64["status"] == 0)
     fp32_vs_fp64 = float(np.abs(got["p"][ok2][:, [0, 3]] - g64["p"][ok2][:, [0, 3]]).max(initial=0))
 
@@ -245,6 +257,17 @@ def main() -> int:
         "fp32_over_fp64_plain": round(ms64 / ms, 2),
         "icgn_fp32_over_fp64_plain": round(t64_icgn / t_icgn, 2),
         "max_fp32_vs_fp64_plain_px": fp32_vs_fp64,
+        "newton_raphson": {
+            "refine_ms": round(t_nr, 4), "pois_per_s": round(N / (t_nr * 1e-3), 1),
+            "fp64_plain_refine_ms": round(t64_nr, 3),
+            "fp32_over_fp64_plain": round(t64_nr / t_nr, 2),
+            "mean_iterations": float(nr_it[nr_st == 0].mean()) if (nr_st == 0).any() else 0.0,
+            "ok_fraction": float((nr_st == 0).mean()),
+            "max_fp32_vs_fp64_plain_px": nr_fp32_vs_fp64,
+            "max_vs_icgn_px": float(np.abs(nr_p[okn & (got["status"] == 0)][:, [0, 3]]
+                                           - got["p"][okn & (got["status"] == 0)][:, [0, 3]]
+                                           ).max(initial=0)),
+        },
     }
     if args.copy_probe_mb > 0:
         n = args.copy_probe_mb * (1 << 20) // 4
