@@ -57,7 +57,7 @@ bool tuning_valid(const dic_tuning_t& t) {
   const bool blk = t.search_block == 4 || t.search_block == 8 || t.search_block == kMfmaBlock;
   const bool thr = t.search_occupancy >= 0 && t.search_occupancy <= 16;
   return blk && thr && t.icgn_waves >= 1 && t.icgn_waves <= 8 && t.icgn_slack >= 0 &&
-         t.icgn_slack <= 16;
+         t.icgn_slack <= kMaxRefineSlack;
 }
 
 }  // namespace

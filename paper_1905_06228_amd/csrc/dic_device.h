@@ -1,4 +1,4 @@
-// Device helpers: wave reductions, compensated sums, Keys cubic weights,
+// Device helpers: wave reductions, Keys cubic weights,
 // 6x6 Cholesky and the affine warp algebra.
 #pragma once
 
@@ -13,6 +13,16 @@ namespace dic {
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Next item of a work counter shared by persistent waves, the same in every
+// lane.  Every lane takes part in one atomic (lane 0 adds 1, the others 0) and
+// the wave reads lane 0's result, so no lane-dependent branch surrounds the
+// fetch: a branch there would let the compiler route the other lanes back to
+// the cross-lane read without lane 0.  All lanes must be active.
+__device__ __forceinline__ int wave_next_item(int* counter) {
+  const int old = atomicAdd(counter, lane_id() == 0 ? 1 : 0);
+  return __builtin_amdgcn_readlane(old, 0);
+}
 
 // Makes LDS writes of one wave visible to its other lanes (no block barrier:
 // waves of a workgroup work on different POIs).
@@ -55,6 +65,63 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
+// DPP move of a 32-bit float inside rows of 16 lanes, every source lane valid.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ float readlane_f32(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// Sums over the 64 lanes of N per-lane FP32 values, each returned as FP64
+// with identical bits in every lane; FP32 additions in a fixed order.  Inside
+// each row of 16 lanes the DPP butterfly of wave_sum_dpp leaves the row sum
+// in every lane.  Then two values share a register: a permlane32 swap (lanes
+// 32-63 of the first with lanes 0-31 of the second) and an add put rows 0+2
+// and 1+3 of value 2j in lanes 0-31 and of value 2j+1 in lanes 32-63; a
+// permlane16 swap (odd rows of the first with even rows of the second) and an
+// add of two such registers leave the totals of values 4i, 4i+2, 4i+1, 4i+3
+// in rows 0, 1, 2, 3, read from lanes 0, 16, 32, 48.  All lanes must be
+// active.
+template <int N>
+__device__ __forceinline__ void wave_sums_f32(const float* v, double* out) {
+  constexpr int N2 = (N + 1) / 2, N4 = (N2 + 1) / 2;
+  float r[2 * N2], h[2 * N4];
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    float x = v[a];
+    x += dpp_f32<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dpp_f32<0x4E>(x);   // quad_perm [2,3,0,1]
+    x += dpp_f32<0x141>(x);  // row_half_mirror
+    x += dpp_f32<0x140>(x);  // row_mirror
+    r[a] = x;
+  }
+  if constexpr ((N & 1) != 0) r[N] = 0.f;
+#pragma unroll
+  for (int j = 0; j < N2; ++j) {
+    const auto q = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, r[2 * j]),
+                                                    __builtin_bit_cast(unsigned, r[2 * j + 1]),
+                                                    false, false);
+    h[j] = __builtin_bit_cast(float, (unsigned)q[0]) + __builtin_bit_cast(float, (unsigned)q[1]);
+  }
+  if constexpr ((N2 & 1) != 0) h[N2] = 0.f;
+#pragma unroll
+  for (int i = 0; i < N4; ++i) {
+    const auto q = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, h[2 * i]),
+                                                    __builtin_bit_cast(unsigned, h[2 * i + 1]),
+                                                    false, false);
+    const float t =
+        __builtin_bit_cast(float, (unsigned)q[0]) + __builtin_bit_cast(float, (unsigned)q[1]);
+    constexpr int kLane[4] = {0, 32, 16, 48};
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (4 * i + u < N) out[4 * i + u] = (double)readlane_f32(t, kLane[u]);
+  }
+}
+
 // Maximum over the 64 lanes of a wave by DPP within rows of 16, then the
 // four row maxima; every lane returns the same value.  All lanes active.
 __device__ __forceinline__ float wave_max_dpp(float v) {
@@ -91,19 +158,6 @@ __device__ __forceinline__ int wave_or_int(int v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
   return v;
 }
-
-// Kahan-compensated FP32 accumulator.
-struct Kahan {
-  float s = 0.f, c = 0.f;
-  __device__ __forceinline__ void add(float x) {
-    const float y = x - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
-  }
-  // Value as FP64: the running sum minus the lost low-order part.
-  __device__ __forceinline__ double value() const { return (double)s - (double)c; }
-};
 
 // Keys cubic-convolution weights (a = -1/2) for taps -1, 0, 1, 2 around
 // floor(x), t = x - floor(x).  Horner forms of

@@ -11,6 +11,7 @@ namespace dic {
 constexpr int kMaxM = 20;
 constexpr int kMaxS = 32;
 constexpr int kWave = 64;
+constexpr int kMaxRefineSlack = 16;  // largest tuning icgn_slack
 
 // Device copy of a pair description plus derived offsets.
 struct DevPair {
@@ -134,7 +135,5 @@ size_t search_lds_bytes(int maxM, int maxS, int block);
 int search_threads(int maxS, int block);
 // Largest search workgroup the kernels are compiled for.
 int search_max_threads();
-// IC-GN LDS bytes per workgroup.
-size_t icgn_lds_bytes(int maxM, int slack, int waves);
 
 }  // namespace dic

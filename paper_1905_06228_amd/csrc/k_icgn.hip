@@ -4,15 +4,16 @@
 // FP32 batched form.  One wave per POI, persistent over a shared work counter
 // (several waves per workgroup, each independent).  Per lane: the reference
 // gradients of its samples stay in registers for the whole solve, so an
-// iteration reads only the deformed image, from a per-wave LDS patch that is
-// restaged only when the warped subset leaves it.  Sample positions are an
-// integer base (POI + rounded translation) plus an FP32 local offset below
-// ~M+slack pixels.  Eight sums per iteration (sum g, sum g^2 and the six
-// steepest-descent products) are blocked: each lane sums its at most MAXS
-// samples in FP32 (fused multiply-adds), and the 64 lane partials are added
-// in FP64 by DPP, so the relative error stays near MAXS * 2^-24 of the sum of
-// magnitudes; with the precomputed sum SD_i (f_i - fbar) and sum SD_i the
-// right-hand side needs no second pass:
+// iteration reads only the deformed image, from a per-wave LDS patch (holding
+// g - fbar, compile-time row pitch) that is restaged only when the warped
+// subset leaves it.  Sample positions are an integer base (POI + rounded
+// translation) plus an FP32 local offset below ~M+slack pixels.  Eight sums
+// per iteration (sum g, sum g^2 and the six steepest-descent products, g
+// taken relative to fbar) are blocked: each lane sums its at most MAXS
+// samples in FP32 (fused multiply-adds) and the 64 lane partials are added in
+// FP32 in a fixed tree of six levels, so the relative error stays near
+// (MAXS + 6) * 2^-24 of the sum of magnitudes; with the precomputed
+// sum SD_i (f_i - fbar) and sum SD_i the right-hand side needs no second pass:
 //   sum SD_i e_i = sum SD_i (f_i - fbar) - (df/dg) (sum SD_i g_i - gbar sum SD_i).
 // The 6x6 solve and the warp composition run in FP64.
 #include "refine_common.h"
@@ -21,43 +22,31 @@ namespace dic {
 
 namespace {
 
-template <int MAXS, bool kClamp>
-__device__ __forceinline__ void iter_pass(const float* src, int pitch, int ox, int oy, int maxc,
-                                          int maxr, int n, const Warp32& w, float c0,
+template <int MAXS, class Smp>
+__device__ __forceinline__ void iter_pass(const Smp& smp, int n, const Warp32& w,
                                           const float* fxs, const float* fys, const half2v* dxy,
                                           float* K) {
-  const int lane = lane_id();
+  const Slots sl(n);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) K[a] = 0.f;
 #pragma unroll
   for (int k = 0; k < MAXS; ++k) {
-    if (lane + kWave * k < n) {
-      const float dx = (float)dxy[k].x, dy = (float)dxy[k].y;
-      const float gs =
-          interp32<kClamp>(src, pitch, ox, oy, warp_x(w, dx, dy), warp_y(w, dx, dy), maxc, maxr) -
-          c0;
-      const float fg = fxs[k] * gs, hg = fys[k] * gs;
-      K[0] += gs;
-      K[1] = fmaf(gs, gs, K[1]);
-      K[2] += fg;
-      K[3] = fmaf(fg, dx, K[3]);
-      K[4] = fmaf(fg, dy, K[4]);
-      K[5] += hg;
-      K[6] = fmaf(hg, dx, K[6]);
-      K[7] = fmaf(hg, dy, K[7]);
-    }
+    if (!sl.used(k)) continue;
+    const float dx = (float)dxy[k].x, dy = (float)dxy[k].y;
+    const float gs = sl.mask(k, sample_value(smp, warp_x(w, dx, dy), warp_y(w, dx, dy)));
+    const float fg = fxs[k] * gs, hg = fys[k] * gs;
+    K[0] += gs;
+    K[1] = fmaf(gs, gs, K[1]);
+    K[2] += fg;
+    K[3] = fmaf(fg, dx, K[3]);
+    K[4] = fmaf(fg, dy, K[4]);
+    K[5] += hg;
+    K[6] = fmaf(hg, dx, K[6]);
+    K[7] = fmaf(hg, dy, K[7]);
   }
 }
 
-__device__ __forceinline__ void reduce8(const float* K, double* S) {
-#pragma unroll
-  for (int a = 0; a < 8; ++a) S[a] = wave_sum_dpp((double)K[a]);
-}
-
 }  // namespace
-
-size_t icgn_lds_bytes(int maxM, int slack, int waves) {
-  const int side = icgn_patch_side(maxM, slack);
-  return (size_t)waves * side * side * sizeof(float);
-}
 
 template <int MAXS>
 __global__ void __launch_bounds__(512)
@@ -66,17 +55,16 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
     const int32_t* __restrict__ uv_init, const int32_t* __restrict__ status_in,
     const double* __restrict__ p_init, double* __restrict__ p_out, float* __restrict__ zncc_out,
     int32_t* __restrict__ iters_out, int32_t* __restrict__ status_out) {
+  constexpr int PP = refine_patch_pitch(MAXS);
   extern __shared__ float lds[];
   const int lane = lane_id(), wid = threadIdx.x / kWave;
   const int pside = icgn_patch_side(st.maxM, slack);
-  Patch patch;
-  patch.buf = lds + (size_t)wid * pside * pside;
+  LdsPatch<PP> patch;
+  patch.buf = lds + (size_t)wid * pside * PP;
   patch.side = pside;
 
   for (;;) {
-    int item = 0;
-    if (lane == 0) item = atomicAdd(&st.counters[kCtrIcgn], 1);
-    item = uniform(__shfl(item, 0, kWave));
+    const int item = wave_next_item(&st.counters[kCtrIcgn]);
     if (item >= st.N) break;
     const int g = uniform(st.work[item]);
     const DevPair P = st.pairs[uniform(st.poi_pair[g])];
@@ -96,23 +84,12 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
     if (status == DIC_POI_OK) {
       const int M = P.M, n1 = 2 * M + 1, n = n1 * n1, W = P.width, H = P.height;
       const float* gimg = def + P.def_off;
-      const float* gx = st.grads + P.grad_off;
+      const int64_t corner = (int64_t)(y0 - M) * W + (x0 - M);
+      const float* gx = st.grads + P.grad_off + corner;
       const float* gy = gx + (int64_t)W * H;
       float fxs[MAXS], fys[MAXS];
       half2v dxy[MAXS];
-#pragma unroll
-      for (int k = 0; k < MAXS; ++k) {
-        const int s = lane + kWave * k;
-        fxs[k] = fys[k] = 0.f;
-        dxy[k] = half2v{(_Float16)0.f, (_Float16)0.f};
-        if (s < n) {
-          const int r = s / n1, c = s - r * n1;
-          const int64_t idx = (int64_t)(y0 - M + r) * W + (x0 - M + c);
-          fxs[k] = gx[idx];
-          fys[k] = gy[idx];
-          dxy[k] = half2v{(_Float16)(c - M), (_Float16)(r - M)};
-        }
-      }
+      load_slots<MAXS>(M, n, gx, gy, W, dxy, fxs, fys);
       const float c0 = (float)R->fbar;
       const double df = R->df;
       const double nn = (double)n;
@@ -127,14 +104,14 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
           status = DIC_POI_OUT_OF_BOUNDS;
           break;
         }
-        float K[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (patch.ensure(gimg, W, H, xl, xh, yl, yh))
-          iter_pass<MAXS, false>(patch.buf, pside, w.bx - patch.x0, w.by - patch.y0, 0, 0, n, w,
-                                 c0, fxs, fys, dxy, K);
+        float K[8];
+        if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
+          iter_pass<MAXS>(patch.sampler(w.bx, w.by), n, w, fxs, fys, dxy, K);
         else
-          iter_pass<MAXS, true>(gimg, W, w.bx, w.by, W - 4, H - 4, n, w, c0, fxs, fys, dxy, K);
+          iter_pass<MAXS>(ImageSampler{gimg, W, w.bx, w.by, W - 4, H - 4, c0}, n, w, fxs, fys,
+                          dxy, K);
         double S[8];
-        reduce8(K, S);
+        wave_sums_f32<8>(K, S);
         if (!isfinite(S[0]) || !isfinite(S[1])) {
           status = DIC_POI_NAN_INPUT;
           break;
@@ -164,38 +141,41 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
         if (xl < 0 || xh > W - 1 || yl < 0 || yh > H - 1) {
           status = DIC_POI_OUT_OF_BOUNDS;
         } else {
-          const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * P.tmpl_pitch;
-          float K[3] = {0.f, 0.f, 0.f};
-          if (patch.ensure(gimg, W, H, xl, xh, yl, yh))
-            final_pass<MAXS, false>(patch.buf, pside, w.bx - patch.x0, w.by - patch.y0, 0, 0, n, w,
-                                    c0, dxy, tm, P.tmpl_pitch, M, K);
+          const int tp = P.tmpl_pitch;
+          const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * tp +
+                            (int64_t)M * tp + M;
+          const auto tval = [&](int, float dx, float dy) {
+            return tm[__mul24((int)dy, tp) + (int)dx];
+          };
+          float K[3];
+          if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
+            final_pass<MAXS>(patch.sampler(w.bx, w.by), n, w, dxy, tval, K);
           else
-            final_pass<MAXS, true>(gimg, W, w.bx, w.by, W - 4, H - 4, n, w, c0, dxy, tm,
-                                   P.tmpl_pitch, M, K);
-          const double s0 = wave_sum_dpp((double)K[0]);
-          const double s1 = wave_sum_dpp((double)K[1]);
-          const double s2 = wave_sum_dpp((double)K[2]);
-          if (!isfinite(s0) || !isfinite(s1)) {
+            final_pass<MAXS>(ImageSampler{gimg, W, w.bx, w.by, W - 4, H - 4, c0}, n, w, dxy,
+                             tval, K);
+          double S[3];
+          wave_sums_f32<3>(K, S);
+          if (!isfinite(S[0]) || !isfinite(S[1])) {
             status = DIC_POI_NAN_INPUT;
           } else {
-            const double ms = s0 / nn;
-            const double var = s1 - s0 * ms;
-            const double sumg2 = s1 + 2.0 * (double)c0 * s0 + nn * (double)c0 * (double)c0;
+            const double ms = S[0] / nn;
+            const double var = S[1] - S[0] * ms;
+            const double sumg2 = S[1] + 2.0 * (double)c0 * S[0] + nn * (double)c0 * (double)c0;
             if (!not_flat(var, sumg2))
               status = DIC_POI_ZERO_VARIANCE;
             else
-              zn = (float)((s2 - ms * (double)R->tsum) / (df * sqrt(var)));
+              zn = (float)((S[2] - ms * (double)R->tsum) / (df * sqrt(var)));
           }
         }
       }
     }
-    if (lane == 0) {
+    // every lane stores the same (wave-uniform) results: no lane-dependent
+    // branch at the end of the persistent loop either
 #pragma unroll
-      for (int a = 0; a < 6; ++a) p_out[6 * g + a] = p[a];
-      zncc_out[g] = (status == DIC_POI_OK || status == DIC_POI_NOT_CONVERGED) ? zn : nanf("");
-      iters_out[g] = it;
-      status_out[g] = status;
-    }
+    for (int a = 0; a < 6; ++a) p_out[6 * g + a] = p[a];
+    zncc_out[g] = (status == DIC_POI_OK || status == DIC_POI_NOT_CONVERGED) ? zn : nanf("");
+    iters_out[g] = it;
+    status_out[g] = status;
   }
 }
 
@@ -206,7 +186,8 @@ static hipError_t launch_icgn_f32_t(const DevState& st, const dic_tuning_t& tu, 
                                     float* zncc, int32_t* iters, int32_t* status, int num_cu,
                                     hipStream_t s) {
   const int threads = tu.icgn_waves * kWave;
-  const size_t lds = icgn_lds_bytes(st.maxM, tu.icgn_slack, tu.icgn_waves);
+  const size_t lds = refine_lds_bytes(refine_patch_pitch(MAXS),
+                                      icgn_patch_side(st.maxM, tu.icgn_slack), tu.icgn_waves);
   if (lds > 65536) {
     hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&icgn_f32_kernel<MAXS>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

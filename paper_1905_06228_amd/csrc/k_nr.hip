@@ -14,76 +14,54 @@
 // f_i - fbar and sample offsets stay in registers; the deformed patch is
 // staged per wave in LDS as for IC-GN.  One pass per iteration accumulates
 // sum g, sum g^2, sum (f - fbar) g, sum J, sum J J^T, sum J (f - fbar) and
-// sum J g (42 sums) in FP32 per lane and FP64 across lanes; the centring by
-// the means is applied to the FP64 sums.  Hessian, solve and update in FP64.
+// sum J g (42 sums, g taken relative to fbar) in FP32 per lane and in a fixed
+// FP32 tree across lanes; the centring by the means is applied to the sums in
+// FP64.  Hessian, solve and update in FP64.
 #include "refine_common.h"
 
 namespace dic {
 
 namespace {
 
-// Grey level and gradient of the Keys interpolant at local offset (xs, ys);
-// same addressing and clamping as interp32.
-template <bool kClamp>
-__device__ __forceinline__ void interp_grad32(const float* src, int pitch, int ox, int oy,
-                                              float xs, float ys, int maxc, int maxr, float& v,
-                                              float& gx, float& gy) {
-  const float fx = floorf(xs), fy = floorf(ys);
-  float wx[4], wy[4], dwx[4], dwy[4];
-  cubic_weights(xs - fx, wx);
-  cubic_weights(ys - fy, wy);
-  cubic_dweights(xs - fx, dwx);
-  cubic_dweights(ys - fy, dwy);
-  int c0 = (int)fx - 1 + ox, r0 = (int)fy - 1 + oy;
-  if (kClamp) {
-    c0 = min(max(c0, 0), maxc);
-    r0 = min(max(r0, 0), maxr);
-  }
-  const float* q = kClamp ? src + (int64_t)r0 * pitch + c0 : src + (__umul24(r0, pitch) + c0);
-  v = gx = gy = 0.f;
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    const float* row = q + l * pitch;
-    const float r = fmaf(wx[3], row[3], fmaf(wx[2], row[2], fmaf(wx[1], row[1], wx[0] * row[0])));
-    const float rd =
-        fmaf(dwx[3], row[3], fmaf(dwx[2], row[2], fmaf(dwx[1], row[1], dwx[0] * row[0])));
-    v = fmaf(wy[l], r, v);
-    gx = fmaf(wy[l], rd, gx);
-    gy = fmaf(dwy[l], r, gy);
-  }
-}
-
-// Per-lane partial sums of one iteration (g taken relative to c0).
+// Per-lane partial sums of one iteration (g taken relative to c0), in the
+// order they are reduced.
 struct NrSums {
   float g, gg, fg;
-  float J[6], JJ[21], Jf[6], Jg[6];
+  float J[6], Jf[6], Jg[6], JJ[21];
 };
 
-template <int MAXS, bool kClamp>
-__device__ __forceinline__ void nr_pass(const float* src, int pitch, int ox, int oy, int maxc,
-                                        int maxr, int n, const Warp32& w, float c0,
-                                        const float* tv, const half2v* dxy, NrSums& A) {
-  const int lane = lane_id();
+template <int MAXS, class Smp>
+__device__ __forceinline__ void nr_pass(const Smp& smp, int n, const Warp32& w, const float* tv,
+                                        const half2v* dxy, NrSums& A) {
+  const Slots sl(n);
+  A.g = A.gg = A.fg = 0.f;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) A.J[a] = A.Jf[a] = A.Jg[a] = 0.f;
+#pragma unroll
+  for (int a = 0; a < 21; ++a) A.JJ[a] = 0.f;
 #pragma unroll
   for (int k = 0; k < MAXS; ++k) {
-    if (lane + kWave * k < n) {
-      const float dx = (float)dxy[k].x, dy = (float)dxy[k].y;
-      float v, gx, gy;
-      interp_grad32<kClamp>(src, pitch, ox, oy, warp_x(w, dx, dy), warp_y(w, dx, dy), maxc, maxr,
-                            v, gx, gy);
-      const float gs = v - c0, t = tv[k];
-      const float J[6] = {gx, gx * dx, gx * dy, gy, gy * dx, gy * dy};
-      A.g += gs;
-      A.gg = fmaf(gs, gs, A.gg);
-      A.fg = fmaf(t, gs, A.fg);
+    if (!sl.used(k)) continue;
+    const float dx = (float)dxy[k].x, dy = (float)dxy[k].y;
+    float v, gx, gy;
+    sample_value_grad(smp, warp_x(w, dx, dy), warp_y(w, dx, dy), v, gx, gy);
+    // a missing sample of the partial slot has zero template value and
+    // offsets; zeroing its value and gradient removes it from every sum
+    const float gs = sl.mask(k, v);
+    gx = sl.mask(k, gx);
+    gy = sl.mask(k, gy);
+    const float t = tv[k];
+    const float J[6] = {gx, gx * dx, gx * dy, gy, gy * dx, gy * dy};
+    A.g += gs;
+    A.gg = fmaf(gs, gs, A.gg);
+    A.fg = fmaf(t, gs, A.fg);
 #pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        A.J[a] += J[a];
-        A.Jf[a] = fmaf(J[a], t, A.Jf[a]);
-        A.Jg[a] = fmaf(J[a], gs, A.Jg[a]);
+    for (int a = 0; a < 6; ++a) {
+      A.J[a] += J[a];
+      A.Jf[a] = fmaf(J[a], t, A.Jf[a]);
+      A.Jg[a] = fmaf(J[a], gs, A.Jg[a]);
 #pragma unroll
-        for (int b = 0; b <= a; ++b) A.JJ[tri(a, b)] = fmaf(J[a], J[b], A.JJ[tri(a, b)]);
-      }
+      for (int b = 0; b <= a; ++b) A.JJ[tri(a, b)] = fmaf(J[a], J[b], A.JJ[tri(a, b)]);
     }
   }
 }
@@ -96,17 +74,16 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
     const int32_t* __restrict__ uv_init, const int32_t* __restrict__ status_in,
     const double* __restrict__ p_init, double* __restrict__ p_out, float* __restrict__ zncc_out,
     int32_t* __restrict__ iters_out, int32_t* __restrict__ status_out) {
+  constexpr int PP = refine_patch_pitch(MAXS);
   extern __shared__ float lds[];
   const int lane = lane_id(), wid = threadIdx.x / kWave;
   const int pside = icgn_patch_side(st.maxM, slack);
-  Patch patch;
-  patch.buf = lds + (size_t)wid * pside * pside;
+  LdsPatch<PP> patch;
+  patch.buf = lds + (size_t)wid * pside * PP;
   patch.side = pside;
 
   for (;;) {
-    int item = 0;
-    if (lane == 0) item = atomicAdd(&st.counters[kCtrIcgn], 1);
-    item = uniform(__shfl(item, 0, kWave));
+    const int item = wave_next_item(&st.counters[kCtrIcgn]);
     if (item >= st.N) break;
     const int g = uniform(st.work[item]);
     const DevPair P = st.pairs[uniform(st.poi_pair[g])];
@@ -132,17 +109,7 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
       const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * tp;
       float tv[MAXS];
       half2v dxy[MAXS];
-#pragma unroll
-      for (int k = 0; k < MAXS; ++k) {
-        const int s = lane + kWave * k;
-        tv[k] = 0.f;
-        dxy[k] = half2v{(_Float16)0.f, (_Float16)0.f};
-        if (s < n) {
-          const int r = s / n1, c = s - r * n1;
-          tv[k] = tm[r * tp + c];
-          dxy[k] = half2v{(_Float16)(c - M), (_Float16)(r - M)};
-        }
-      }
+      load_slots<MAXS>(M, n, tm, nullptr, tp, dxy, tv, nullptr);
       const float c0 = (float)R->fbar;
       const double df = R->df, tsum = (double)R->tsum;
       const double nn = (double)n;
@@ -158,27 +125,21 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
           break;
         }
         NrSums A;
-        A.g = A.gg = A.fg = 0.f;
-#pragma unroll
-        for (int a = 0; a < 6; ++a) A.J[a] = A.Jf[a] = A.Jg[a] = 0.f;
-#pragma unroll
-        for (int a = 0; a < 21; ++a) A.JJ[a] = 0.f;
-        if (patch.ensure(gimg, W, H, xl, xh, yl, yh))
-          nr_pass<MAXS, false>(patch.buf, pside, w.bx - patch.x0, w.by - patch.y0, 0, 0, n, w, c0,
-                               tv, dxy, A);
+        if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
+          nr_pass<MAXS>(patch.sampler(w.bx, w.by), n, w, tv, dxy, A);
         else
-          nr_pass<MAXS, true>(gimg, W, w.bx, w.by, W - 4, H - 4, n, w, c0, tv, dxy, A);
-        const double sg = wave_sum_dpp((double)A.g), sgg = wave_sum_dpp((double)A.gg);
-        const double sfg = wave_sum_dpp((double)A.fg);
-        double sJ[6], sJf[6], sJg[6], hc[21];
+          nr_pass<MAXS>(ImageSampler{gimg, W, w.bx, w.by, W - 4, H - 4, c0}, n, w, tv, dxy, A);
+        // all 42 sums in one reduction, in struct order
+        static_assert(sizeof(NrSums) == 42 * sizeof(float), "NrSums layout");
+        double S[42];
+        wave_sums_f32<42>(&A.g, S);
+        const double sg = S[0], sgg = S[1], sfg = S[2];
+        const double* sJ = S + 3;
+        const double* sJf = S + 9;
+        const double* sJg = S + 15;
+        double hc[21];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) {
-          sJ[a] = wave_sum_dpp((double)A.J[a]);
-          sJf[a] = wave_sum_dpp((double)A.Jf[a]);
-          sJg[a] = wave_sum_dpp((double)A.Jg[a]);
-        }
-#pragma unroll
-        for (int a = 0; a < 21; ++a) hc[a] = wave_sum_dpp((double)A.JJ[a]);
+        for (int a = 0; a < 21; ++a) hc[a] = S[21 + a];
         bool fin = isfinite(sg) && isfinite(sgg);
 #pragma unroll
         for (int a = 0; a < 6; ++a) fin = fin && isfinite(sJ[a]);
@@ -223,36 +184,36 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
         if (xl < 0 || xh > W - 1 || yl < 0 || yh > H - 1) {
           status = DIC_POI_OUT_OF_BOUNDS;
         } else {
-          float K[3] = {0.f, 0.f, 0.f};
-          if (patch.ensure(gimg, W, H, xl, xh, yl, yh))
-            final_pass<MAXS, false>(patch.buf, pside, w.bx - patch.x0, w.by - patch.y0, 0, 0, n, w,
-                                    c0, dxy, tm, tp, M, K);
+          const auto tval = [&](int k, float, float) { return tv[k]; };
+          float K[3];
+          if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
+            final_pass<MAXS>(patch.sampler(w.bx, w.by), n, w, dxy, tval, K);
           else
-            final_pass<MAXS, true>(gimg, W, w.bx, w.by, W - 4, H - 4, n, w, c0, dxy, tm, tp, M, K);
-          const double s0 = wave_sum_dpp((double)K[0]);
-          const double s1 = wave_sum_dpp((double)K[1]);
-          const double s2 = wave_sum_dpp((double)K[2]);
-          if (!isfinite(s0) || !isfinite(s1)) {
+            final_pass<MAXS>(ImageSampler{gimg, W, w.bx, w.by, W - 4, H - 4, c0}, n, w, dxy,
+                             tval, K);
+          double S[3];
+          wave_sums_f32<3>(K, S);
+          if (!isfinite(S[0]) || !isfinite(S[1])) {
             status = DIC_POI_NAN_INPUT;
           } else {
-            const double ms = s0 / nn;
-            const double var = s1 - s0 * ms;
-            const double sumg2 = s1 + 2.0 * (double)c0 * s0 + nn * (double)c0 * (double)c0;
+            const double ms = S[0] / nn;
+            const double var = S[1] - S[0] * ms;
+            const double sumg2 = S[1] + 2.0 * (double)c0 * S[0] + nn * (double)c0 * (double)c0;
             if (!not_flat(var, sumg2))
               status = DIC_POI_ZERO_VARIANCE;
             else
-              zn = (float)((s2 - ms * tsum) / (df * sqrt(var)));
+              zn = (float)((S[2] - ms * tsum) / (df * sqrt(var)));
           }
         }
       }
     }
-    if (lane == 0) {
+    // every lane stores the same (wave-uniform) results: no lane-dependent
+    // branch at the end of the persistent loop either
 #pragma unroll
-      for (int a = 0; a < 6; ++a) p_out[6 * g + a] = p[a];
-      zncc_out[g] = (status == DIC_POI_OK || status == DIC_POI_NOT_CONVERGED) ? zn : nanf("");
-      iters_out[g] = it;
-      status_out[g] = status;
-    }
+    for (int a = 0; a < 6; ++a) p_out[6 * g + a] = p[a];
+    zncc_out[g] = (status == DIC_POI_OK || status == DIC_POI_NOT_CONVERGED) ? zn : nanf("");
+    iters_out[g] = it;
+    status_out[g] = status;
   }
 }
 
@@ -263,7 +224,8 @@ static hipError_t launch_nr_f32_t(const DevState& st, const dic_tuning_t& tu, co
                                   float* zncc, int32_t* iters, int32_t* status, int num_cu,
                                   hipStream_t s) {
   const int threads = tu.icgn_waves * kWave;
-  const size_t lds = icgn_lds_bytes(st.maxM, tu.icgn_slack, tu.icgn_waves);
+  const size_t lds = refine_lds_bytes(refine_patch_pitch(MAXS),
+                                      icgn_patch_side(st.maxM, tu.icgn_slack), tu.icgn_waves);
   if (lds > 65536) {
     hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&nr_f32_kernel<MAXS>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -1,8 +1,14 @@
 // Pieces shared by the sub-pixel refinements of Sec. 2.2 (IC-GN and
 // Newton-Raphson, FP32 batched forms): the first-order warp in FP32 local
-// form, the bounding box of the taps it touches, Keys bicubic interpolation
-// from an image or a per-wave LDS patch, and the final pass that evaluates
-// Eq. (1) at the converged warp.
+// form, the bounding box of the taps it touches, the per-wave LDS patch of
+// the deformed image, Keys bicubic interpolation from that patch or from the
+// image, and the final pass that evaluates Eq. (1) at the converged warp.
+//
+// Sample layout: lane l holds samples s = l + 64 k (slot k) of the subset in
+// row-major order; slots below n / 64 are full, the next one is partial and
+// the rest are empty and skipped.  The empty samples of the partial slot have
+// offsets (0, 0) and zero reference data, so only their interpolated value
+// has to be masked for every sum to ignore them.
 #pragma once
 
 #include "dic_device.h"
@@ -13,14 +19,38 @@ __host__ __device__ __forceinline__ int icgn_patch_side(int maxM, int slack) {
   return 2 * maxM + 4 + 2 * slack;
 }
 
+// Largest subset radius M with (2M + 1)^2 <= 64 * maxs samples.
+__host__ __device__ constexpr int refine_max_radius(int maxs) {
+  int m = 0;
+  while ((2 * m + 3) * (2 * m + 3) <= kWave * maxs) ++m;
+  return m;
+}
 
-// A sample's subset offsets (dx, dy): small integers, exact in fp16, one
-// register per sample.
+// Row pitch (floats) of the LDS patch of a kernel built for at most 64 * maxs
+// samples per subset: odd, and at least the widest patch side such a subset
+// can need.  A compile-time pitch lets the 16 taps of a sample be read from
+// one address with immediate offsets (at most 3 * pitch + 3 dwords).
+__host__ __device__ constexpr int refine_patch_pitch(int maxs) {
+  return (2 * refine_max_radius(maxs) + 4 + 2 * kMaxRefineSlack) | 1;
+}
+static_assert(3 * refine_patch_pitch(28) + 3 <= 255, "tap offsets exceed the LDS read2 range");
+static_assert(refine_max_radius(28) >= kMaxM, "largest kernel does not cover kMaxM");
+
+// LDS bytes of a refinement workgroup: one patch of `side` rows per wave.
+__host__ __device__ constexpr size_t refine_lds_bytes(int pitch, int side, int waves) {
+  return (size_t)waves * side * pitch * sizeof(float);
+}
+
+// A sample's subset offsets (dx, dy): small integers, exact in fp16.
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 
+// Warp W(p) in local FP32 form around an integer base:
+//   x = bx + ax dx + uy dy + uf,  y = by + vx dx + ay dy + vf,
+// ax = 1 + du/dx and ay = 1 + dv/dy rounded once to FP32, (uf, vf) the
+// translation minus its rounded integer part (bx - x0, by - y0).
 struct Warp32 {
-  int bx, by;                  // integer base of the sample positions
-  float uf, vf, ux, uy, vx, vy;  // local offsets: x = bx + dx + ux dx + uy dy + uf
+  int bx, by;
+  float ax, uy, uf, vx, ay, vf;
 };
 
 __device__ __forceinline__ Warp32 make_warp32(const double* p, int x0, int y0) {
@@ -30,18 +60,18 @@ __device__ __forceinline__ Warp32 make_warp32(const double* p, int x0, int y0) {
   w.by = y0 + (int)vr;
   w.uf = (float)(p[0] - ur);
   w.vf = (float)(p[3] - vr);
-  w.ux = (float)p[1];
+  w.ax = (float)(1.0 + p[1]);
   w.uy = (float)p[2];
   w.vx = (float)p[4];
-  w.vy = (float)p[5];
+  w.ay = (float)(1.0 + p[5]);
   return w;
 }
 
 __device__ __forceinline__ float warp_x(const Warp32& w, float dx, float dy) {
-  return dx + fmaf(w.ux, dx, fmaf(w.uy, dy, w.uf));
+  return fmaf(w.ax, dx, fmaf(w.uy, dy, w.uf));
 }
 __device__ __forceinline__ float warp_y(const Warp32& w, float dx, float dy) {
-  return dy + fmaf(w.vx, dx, fmaf(w.vy, dy, w.vf));
+  return fmaf(w.vx, dx, fmaf(w.ay, dy, w.vf));
 }
 
 // Bounding box (absolute pixel indices) of every 4x4 neighbourhood the
@@ -67,77 +97,223 @@ __device__ __forceinline__ void tap_box(const Warp32& w, int M, int& x_lo, int& 
   y_hi = w.by + (int)floorf(ymx) + 2;
 }
 
-// Interpolated grey level at local offset (xs, ys).  `src` holds the image
-// (or the staged patch) with row pitch `pitch`; (ox, oy) is the position of
-// the integer base inside it.  With kClamp the 4x4 neighbourhood origin is
-// clamped to [0, maxc] x [0, maxr]: the tap box test already keeps it there,
-// the clamp only guarantees in-bounds reads for a degenerate warp.
-template <bool kClamp>
-__device__ __forceinline__ float interp32(const float* src, int pitch, int ox, int oy, float xs,
-                                          float ys, int maxc, int maxr) {
-  const float fx = floorf(xs), fy = floorf(ys);
-  float wx[4], wy[4];
-  cubic_weights(xs - fx, wx);
-  cubic_weights(ys - fy, wy);
-  int c0 = (int)fx - 1 + ox, r0 = (int)fy - 1 + oy;
-  if (kClamp) {
-    c0 = min(max(c0, 0), maxc);
-    r0 = min(max(r0, 0), maxr);
+// Keys weights (a = -1/2) of taps -1, 0, 1, 2 at fractional offset t; with
+// s = 1 - t: w-1 = -t s^2 / 2, w2 = -s t^2 / 2, w0 = 1 + t^2 (3t - 5) / 2 and
+// w1 = 1 - w-1 - w0 - w2 (the four sum to one and w-1 + w2 = -t s / 2).
+__device__ __forceinline__ void keys_weights32(float t, float* w) {
+  const float s = 1.f - t;
+  const float q = -0.5f * (t * s);
+  w[0] = q * s;
+  w[3] = q * t;
+  w[1] = fmaf(t * t, fmaf(1.5f, t, -2.5f), 1.f);
+  w[2] = (1.f - q) - w[1];
+}
+
+// d/dt of the weights above: w-1' = -s (s - 2t) / 2, w0' = t (9t - 10) / 2,
+// w2' = -t (2s - t) / 2 and w1' = -(w-1' + w0' + w2').
+__device__ __forceinline__ void keys_dweights32(float t, float* w) {
+  const float s = 1.f - t;
+  w[0] = (-0.5f * s) * fmaf(-2.f, t, s);
+  w[3] = (-0.5f * t) * fmaf(2.f, s, -t);
+  w[1] = t * fmaf(4.5f, t, -5.f);
+  w[2] = -((w[0] + w[1]) + w[3]);
+}
+
+// Interpolation of one sample at local offset (xs, ys) from the integer
+// base.  PatchSampler reads a wave's LDS patch, which holds g - c0; q0
+// addresses its element at offset (-1, -1) from the base.
+template <int P>
+struct PatchSampler {
+  const float* q0;
+
+  __device__ __forceinline__ const float* taps(float xs, float ys, float* wx, float* wy,
+                                               float& tx, float& ty) const {
+    const float fx = floorf(xs), fy = floorf(ys);
+    tx = xs - fx;
+    ty = ys - fy;
+    keys_weights32(tx, wx);
+    keys_weights32(ty, wy);
+    return q0 + (__mul24((int)fy, P) + (int)fx);
   }
-  // patch offsets fit 24 bits: a full-rate multiply
-  const float* q = kClamp ? src + (int64_t)r0 * pitch + c0 : src + (__umul24(r0, pitch) + c0);
+  static constexpr int pitch() { return P; }
+  __device__ __forceinline__ float tap(const float* q) const { return *q; }
+};
+
+// The same from the deformed image itself (row pitch W), each tap centred as
+// the patch stores it (g - c0 in FP32), so both paths give the same bits; the
+// 4x4 neighbourhood origin is clamped into the image: the tap box test
+// already keeps it there, the clamp only guards the reads of a degenerate
+// warp.
+struct ImageSampler {
+  const float* img;
+  int W, bx, by, maxc, maxr;
+  float c0;
+
+  __device__ __forceinline__ const float* taps(float xs, float ys, float* wx, float* wy,
+                                               float& tx, float& ty) const {
+    const float fx = floorf(xs), fy = floorf(ys);
+    tx = xs - fx;
+    ty = ys - fy;
+    keys_weights32(tx, wx);
+    keys_weights32(ty, wy);
+    const int c = min(max(bx + (int)fx - 1, 0), maxc), r = min(max(by + (int)fy - 1, 0), maxr);
+    return img + (int64_t)r * W + c;
+  }
+  __device__ __forceinline__ int pitch() const { return W; }
+  __device__ __forceinline__ float tap(const float* q) const { return *q - c0; }
+};
+
+// g - c0 at local offset (xs, ys).
+template <class Smp>
+__device__ __forceinline__ float sample_value(const Smp& smp, float xs, float ys) {
+  float wx[4], wy[4], tx, ty;
+  const float* q = smp.taps(xs, ys, wx, wy, tx, ty);
+  const int P = smp.pitch();
   float acc = 0.f;
 #pragma unroll
   for (int l = 0; l < 4; ++l) {
-    const float* row = q + l * pitch;
-    const float r = fmaf(wx[3], row[3], fmaf(wx[2], row[2], fmaf(wx[1], row[1], wx[0] * row[0])));
-    acc = fmaf(wy[l], r, acc);
+    const float* row = q + l * P;
+    const float r =
+        fmaf(wx[3], smp.tap(row + 3),
+             fmaf(wx[2], smp.tap(row + 2), fmaf(wx[1], smp.tap(row + 1), wx[0] * smp.tap(row))));
+    acc = l == 0 ? wy[0] * r : fmaf(wy[l], r, acc);
   }
   return acc;
 }
 
-template <int MAXS, bool kClamp>
-__device__ __forceinline__ void final_pass(const float* src, int pitch, int ox, int oy, int maxc,
-                                           int maxr, int n, const Warp32& w, float c0,
-                                           const half2v* dxy, const float* __restrict__ tm,
-                                           int tp, int M, float* K) {
-  const int lane = lane_id();
+// g - c0 and the interpolant's gradient (d/dx, d/dy) at local offset (xs, ys).
+template <class Smp>
+__device__ __forceinline__ void sample_value_grad(const Smp& smp, float xs, float ys, float& v,
+                                                  float& gx, float& gy) {
+  float wx[4], wy[4], tx, ty, dwx[4], dwy[4];
+  const float* q = smp.taps(xs, ys, wx, wy, tx, ty);
+  keys_dweights32(tx, dwx);
+  keys_dweights32(ty, dwy);
+  const int P = smp.pitch();
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const float* row = q + l * P;
+    float t[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) t[c] = smp.tap(row + c);
+    const float r = fmaf(wx[3], t[3], fmaf(wx[2], t[2], fmaf(wx[1], t[1], wx[0] * t[0])));
+    const float rd = fmaf(dwx[3], t[3], fmaf(dwx[2], t[2], fmaf(dwx[1], t[1], dwx[0] * t[0])));
+    v = l == 0 ? wy[0] * r : fmaf(wy[l], r, v);
+    gx = l == 0 ? wy[0] * rd : fmaf(wy[l], rd, gx);
+    gy = l == 0 ? dwy[0] * r : fmaf(dwy[l], r, gy);
+  }
+}
+
+// Offsets and one per-sample reference value of every slot of this lane,
+// stepping (row, column) of the subset by 64 samples per slot.  `ref`
+// addresses the subset's top-left sample with row pitch `pitch` (nullable:
+// the values are then zero).
+template <int MAXS>
+__device__ __forceinline__ void load_slots(int M, int n, const float* __restrict__ ref0,
+                                           const float* __restrict__ ref1, int pitch,
+                                           half2v* dxy, float* v0, float* v1) {
+  const int n1 = 2 * M + 1, lane = lane_id();
+  const int dr = kWave / n1, dc = kWave - dr * n1;
+  int r = lane / n1, c = lane - r * n1;
 #pragma unroll
   for (int k = 0; k < MAXS; ++k) {
+    dxy[k] = half2v{(_Float16)0.f, (_Float16)0.f};
+    v0[k] = 0.f;
+    if (v1) v1[k] = 0.f;
     if (lane + kWave * k < n) {
-      const float dx = (float)dxy[k].x, dy = (float)dxy[k].y;
-      const float gs =
-          interp32<kClamp>(src, pitch, ox, oy, warp_x(w, dx, dy), warp_y(w, dx, dy), maxc, maxr) -
-          c0;
-      K[0] += gs;
-      K[1] = fmaf(gs, gs, K[1]);
-      K[2] = fmaf(tm[((int)dy + M) * tp + (int)dx + M], gs, K[2]);
+      const int o = __umul24(r, pitch) + c;
+      v0[k] = ref0[o];
+      if (v1) v1[k] = ref1[o];
+      dxy[k] = half2v{(_Float16)(c - M), (_Float16)(r - M)};
+    }
+    c += dc;
+    r += dr;
+    if (c >= n1) {
+      c -= n1;
+      ++r;
     }
   }
 }
 
-// Per-wave LDS patch of the deformed image.
-struct Patch {
+// Slot bookkeeping of one pass: whether slot k holds samples, and the mask
+// for the missing samples of the partial slot.  The sample count is made
+// opaque at the start of every pass so the per-slot tests stay scalar
+// compares inside the pass instead of masks kept live across the solve.
+struct Slots {
+  int n;
+  bool tail_valid;
+  __device__ __forceinline__ explicit Slots(int n_) : n(__builtin_amdgcn_readfirstlane(n_)) {
+    tail_valid = lane_id() < n % kWave;
+  }
+  __device__ __forceinline__ bool used(int k) const { return kWave * k < n; }
+  // v, or 0 for a missing sample of slot k
+  __device__ __forceinline__ float mask(int k, float v) const {
+    return (kWave * (k + 1) > n && !tail_valid) ? 0.f : v;
+  }
+};
+
+// Sums over this lane's samples at the final warp: sum (g - c0),
+// sum (g - c0)^2 and sum (f - fbar)(g - c0), with f - fbar of slot k at
+// offsets (dx, dy) given by tval(k, dx, dy).
+template <int MAXS, class Smp, class TV>
+__device__ __forceinline__ void final_pass(const Smp& smp, int n, const Warp32& w,
+                                           const half2v* dxy, const TV& tval, float* K) {
+  const Slots sl(n);
+  K[0] = K[1] = K[2] = 0.f;
+#pragma unroll
+  for (int k = 0; k < MAXS; ++k) {
+    if (!sl.used(k)) continue;
+    const float dx = (float)dxy[k].x, dy = (float)dxy[k].y;
+    const float gs = sl.mask(k, sample_value(smp, warp_x(w, dx, dy), warp_y(w, dx, dy)));
+    K[0] += gs;
+    K[1] = fmaf(gs, gs, K[1]);
+    K[2] = fmaf(tval(k, dx, dy), gs, K[2]);
+  }
+}
+
+// Per-wave LDS patch of the deformed image: `side` rows of pitch P holding
+// g - c0 (zero outside the image).
+template <int P>
+struct LdsPatch {
   float* buf;
   int side;
   int x0 = INT_MIN, y0 = INT_MIN;
-  // Makes [x_lo, x_hi] x [y_lo, y_hi] resident; false when it cannot fit.
+
+  // Makes [x_lo, x_hi] x [y_lo, y_hi] resident, centred in the patch; false
+  // when it cannot fit.  One column per lane (two passes when the side
+  // exceeds 64), eight rows per batch of loads; the loads read clamped, always
+  // valid addresses so a batch is issued back to back, and the pixels outside
+  // the image are replaced by zero afterwards.
   __device__ __forceinline__ bool ensure(const float* __restrict__ img, int W, int H, int x_lo,
-                                         int x_hi, int y_lo, int y_hi) {
+                                         int x_hi, int y_lo, int y_hi, float c0) {
     if (x_lo >= x0 && x_hi < x0 + side && y_lo >= y0 && y_hi < y0 + side) return true;
     const int bw = x_hi - x_lo + 1, bh = y_hi - y_lo + 1;
     if (bw > side || bh > side) return false;
     x0 = x_lo - (side - bw) / 2;
     y0 = y_lo - (side - bh) / 2;
-    const int lane = lane_id();
     wave_lds_sync();
-    for (int idx = lane; idx < side * side; idx += kWave) {
-      const int r = idx / side, c = idx - r * side;
-      const int X = x0 + c, Y = y0 + r;
-      buf[idx] = (X >= 0 && X < W && Y >= 0 && Y < H) ? img[(int64_t)Y * W + X] : 0.f;
+    for (int c = lane_id(); c < side; c += kWave) {
+      const int X = x0 + c;
+      const bool col_in = X >= 0 && X < W;
+      const float* col = img + min(max(X, 0), W - 1);
+      for (int r0 = 0; r0 < side; r0 += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = col[(int64_t)min(max(y0 + r0 + u, 0), H - 1) * W];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int Y = y0 + r0 + u;
+          if (r0 + u < side) buf[(r0 + u) * P + c] = (col_in && Y >= 0 && Y < H) ? v[u] - c0 : 0.f;
+        }
+      }
     }
     wave_lds_sync();
     return true;
+  }
+
+  // Sampler for a warp whose integer base is (bx, by).
+  __device__ __forceinline__ PatchSampler<P> sampler(int bx, int by) const {
+    return PatchSampler<P>{buf + (by - y0 - 1) * P + (bx - x0 - 1)};
   }
 };
 

@@ -122,6 +122,7 @@ def test_identical_images_and_integer_shift():
 
 
 def test_status_codes_match_oracle():
+    print("case status codes M=7 S=6 N=8 (subset radius 7: smallest refinement kernel)", flush=True)
     rng = np.random.default_rng(5)
     b = dicgen.make_blobs(dicgen.rng_for(78, 0, 0), 700, 128, 128)
     f = dicgen.render_image(b, None, 128, 128)
