@@ -119,13 +119,17 @@ typedef struct {
 /* Tile and schedule choices; dic_plan_autotune() fills them by measurement.
  * Every choice gives bit-identical results. */
 typedef struct {
-  int32_t search_block;     /* candidates per lane along du: 4 or 8; a search
+  int32_t search_block;     /* integer-search form: 4 or 8 = vector-ALU form
+                               with that many candidates per lane along du (a
                                workgroup has one lane per tile of the widest
-                               window, at most 1024                          */
+                               window, at most 1024); 32 = matrix-core form
+                               (bf16 filter, FP64 decision; radii up to 16)  */
   int32_t search_occupancy; /* resident search workgroups per CU, 0 = as many
                                as registers and LDS allow, else 1..16        */
-  int32_t icgn_waves;      /* waves (POIs in flight) per IC-GN workgroup 1..8 */
-  int32_t icgn_slack;      /* extra pixels around the staged deformed patch   */
+  int32_t icgn_waves;      /* waves (POIs in flight) per refinement workgroup
+                              1..8 (IC-GN and Newton-Raphson)                 */
+  int32_t icgn_slack;      /* extra pixels around the staged deformed patch,
+                              0..16                                           */
 } dic_tuning_t;
 
 /* Validate a plan description and build the POI work list (host only, no
@@ -187,10 +191,13 @@ dic_status_t dic_prepare_deformed(dic_plan_t plan, const float* def_images,
  * is seed_uv[i] (int32 [N,2], nullable = (0,0)); a candidate whose subset
  * leaves the image or is flat (sum (g - gbar)^2 <= 1e-6 sum g^2) is skipped.
  * The winner is the smallest (dv, du), row-major, among candidates within
- * 1e-12 of the maximum coefficient.  The FP32 form scores in FP32 (error
- * ~1e-7); when two or more candidates lie within 2e-5 of its maximum they
- * are re-scored two-pass in FP64 before the tie rule, otherwise the single
- * one is the FP64 winner and its FP32 coefficient is reported.
+ * 1e-12 of the maximum coefficient.  The FP32 batched form first scores
+ * every candidate approximately (bf16 matrix-core products with a rigorous
+ * error bound for radii up to 16 and subsets up to 41 x 41, FP32 vector
+ * sums otherwise), keeps every candidate whose bound still reaches the
+ * maximum, and evaluates Eq. (1) for those in FP64 before the tie rule; the
+ * winner and its FP64 coefficient (rounded to float) do not depend on the
+ * form.  The FP64 plain form scores every candidate in FP64.
  * Outputs (device, length N): uv_out int32 [N,2] integer displacement,
  * zncc_out float [N] its coefficient, status_out int32 [N] DIC_POI_* (OK,
  * ZERO_VARIANCE, NO_VALID_CANDIDATE or NAN_INPUT; uv = (0,0) unless OK). */
