@@ -288,3 +288,95 @@ def sequence_frames(n_frames: int, height: int, width: int, n_blobs: int,
         fld = None if k == 0 else heterogeneous_strain(k)
         frames.append(render_image(blobs, fld, height, width, noise, rng_for(tag, k, 1)))
     return frames
+
+
+# ---------------------------------------------------------------------------
+# camera-scale frames rendered with torch (same recipe, any torch device)
+# ---------------------------------------------------------------------------
+
+def heterogeneous_strain_torch(k: int):
+    """``heterogeneous_strain(k)`` on torch tensors."""
+    import torch
+    w = 2.0 * math.pi / 1500.0
+    return lambda X, Y: (0.002 * k * X * (1.0 + 0.5 * torch.sin(w * Y)), -0.0006 * k * Y)
+
+
+def heterogeneous_strain_lipschitz(k: int, width: float) -> float:
+    """Bound on the operator norm of the displacement gradient of
+    ``heterogeneous_strain(k)`` for reference x in [0, width]."""
+    w = 2.0 * math.pi / 1500.0
+    return math.sqrt((0.003 * k) ** 2 + (0.001 * k * width * w) ** 2 + (0.0006 * k) ** 2)
+
+
+def render_image_torch(blobs: Blobs, fld, height: int, width: int, lipschitz: float = 0.0,
+                       noise_sigma: float = 0.0, noise_rng: Optional[np.random.Generator] = None,
+                       device="cuda", chunk: int = 4096):
+    """``render_image`` with torch: the reference coordinates of every pixel by
+    the same fixed-point iteration, then each blob added (FP64) to the pixels
+    of a window around its deformed centre that contains every pixel whose
+    reference coordinates lie within its truncation radius (the window grows
+    with ``lipschitz``, a bound on the displacement gradient).  Agrees with
+    the NumPy renderer up to the order of the additions.  Noise is drawn with
+    NumPy from ``noise_rng`` as there.  Returns a float32 tensor on
+    ``device``."""
+    import torch
+    dev = torch.device(device)
+    f64 = torch.float64
+    y, x = torch.meshgrid(torch.arange(height, dtype=f64, device=dev),
+                          torch.arange(width, dtype=f64, device=dev), indexing="ij")
+    if fld is None:
+        X, Y = x, y
+    else:
+        X, Y = x.clone(), y.clone()
+        for _ in range(500):
+            u, v = fld(X, Y)
+            Xn, Yn = x - u, y - v
+            err = max(float((Xn - X).abs().max()), float((Yn - Y).abs().max()))
+            X, Y = Xn, Yn
+            if err < 1e-12:
+                break
+    Xf, Yf = X.reshape(-1), Y.reshape(-1)
+    out = torch.full((height * width,), BACKGROUND, dtype=f64, device=dev)
+    cx = torch.as_tensor(blobs.cx, dtype=f64, device=dev)
+    cy = torch.as_tensor(blobs.cy, dtype=f64, device=dev)
+    sg = torch.as_tensor(blobs.sigma, dtype=f64, device=dev)
+    pk = torch.as_tensor(blobs.peak, dtype=f64, device=dev)
+    if fld is None:
+        xc, yc = cx, cy
+    else:
+        u, v = fld(cx, cy)
+        xc, yc = cx + u, cy + v
+    R = int(math.ceil(TRUNC_SIGMAS * float(blobs.sigma.max()) * (1.0 + lipschitz))) + 1
+    offs = torch.arange(-R, R + 1, device=dev)
+    for i in range(0, len(blobs), chunk):
+        j = min(len(blobs), i + chunk)
+        bx = torch.round(xc[i:j]).long()
+        by = torch.round(yc[i:j]).long()
+        px = (bx[:, None, None] + offs[None, None, :]).expand(-1, 2 * R + 1, -1)
+        py = (by[:, None, None] + offs[None, :, None]).expand(-1, -1, 2 * R + 1)
+        inside = ((px >= 0) & (px < width) & (py >= 0) & (py < height)).reshape(j - i, -1)
+        idx = (py.clamp(0, height - 1) * width + px.clamp(0, width - 1)).reshape(j - i, -1)
+        dX = Xf[idx] - cx[i:j, None]
+        dY = Yf[idx] - cy[i:j, None]
+        r2 = dX * dX + dY * dY
+        val = pk[i:j, None] * torch.exp(-r2 / (2.0 * sg[i:j, None] ** 2))
+        keep = inside & (r2 <= (TRUNC_SIGMAS * sg[i:j, None]) ** 2)
+        out.index_add_(0, idx[keep], val[keep])
+    img = out.reshape(height, width)
+    if noise_sigma > 0.0:
+        img = img + torch.from_numpy(noise_rng.normal(0.0, noise_sigma, (height, width))).to(dev)
+    return img.to(torch.float32)
+
+
+def sequence_frames_torch(n_frames: int, height: int, width: int, n_blobs: int,
+                          noise: float = 3.0, tag: int = 5, pad: float = 96.0, device="cuda"):
+    """``sequence_frames`` rendered with ``render_image_torch`` (same blobs,
+    fields and noise streams), as float32 tensors on ``device``."""
+    blobs = make_blobs(rng_for(tag, 0, 0), n_blobs, height, width, pad=pad)
+    frames = []
+    for k in range(n_frames):
+        fld = None if k == 0 else heterogeneous_strain_torch(k)
+        lip = 0.0 if k == 0 else heterogeneous_strain_lipschitz(k, width + pad)
+        frames.append(render_image_torch(blobs, fld, height, width, lip, noise,
+                                         rng_for(tag, k, 1), device=device))
+    return frames

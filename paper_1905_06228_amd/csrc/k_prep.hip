@@ -168,8 +168,8 @@ __device__ __forceinline__ void write_bad_record(RefRec* R, int status, int lane
 // sum f^2 in FP64; the 21 products of the mean-removed steepest-descent
 // images (the Hessian, no cancellation left) and the six sum SD (f - fbar)
 // in FP32 per lane with fused multiply-adds (at most a few tens of terms),
-// added across lanes in FP64 by DPP.  Factorisation and singularity test in
-// FP64.  Also stores the float search template f_i - fbar.
+// added across lanes in a fixed FP32 tree (six levels).  Factorisation and
+// singularity test in FP64.  Also stores the float search template f_i - fbar.
 __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
                                                            const float* __restrict__ ref,
                                                            const int32_t* __restrict__ poi) {
@@ -277,10 +277,8 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
   sq = wave_sum_dpp(sq);
   ts = wave_sum_dpp(ts);
   double sdfsum[6], h[21];
-#pragma unroll
-  for (int a = 0; a < 6; ++a) sdfsum[a] = wave_sum_dpp((double)ksdf[a]);
-#pragma unroll
-  for (int a = 0; a < 21; ++a) h[a] = wave_sum_dpp((double)kh[a]);
+  wave_sums_f32<6>(ksdf, sdfsum);
+  wave_sums_f32<21>(kh, h);
 
   int status = DIC_POI_OK;
   double L[21], rd[6];

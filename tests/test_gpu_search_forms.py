@@ -105,3 +105,15 @@ def test_forms_exact_ties_beyond_list():
     ref = oracle_search(f, f, pois, M, S)
     assert np.all(ref["uv"][:, 0] == -S)
     both_forms(f, f, pois, M, S, ref, "ties")
+
+
+def test_valu_form_wide_seeded_window():
+    """Radius 24 (beyond the matrix-core form): the vector-ALU form alone, on
+    seeded windows as the frame sequence uses them."""
+    pr = dicgen.affine_pair_1024(size=200, M=14, S=24, step=9, tag=73)
+    pois = pr.pois[::2]
+    rng = np.random.default_rng(74)
+    seeds = rng.integers(-4, 5, size=(len(pois), 2)).astype(np.int32)
+    print(f"case valu wide window M=14 S=24 N={len(pois)}", flush=True)
+    ref = oracle_search(pr.ref, pr.defm, pois, 14, 24, seeds)
+    check(gpu_search(pr.ref, pr.defm, pois, 14, 24, VALU, seeds), ref, "M14S24/valu")
