@@ -31,9 +31,16 @@ MFMA_BLOCK = 32          # tuning search_block of the matrix-core search form
 KERNEL_SOURCES = {
     "search_mfma": ("k_search_mfma.hip", "search_common.h", "dic_device.h", "dic_internal.h"),
     "search_f32": ("k_search.hip", "search_common.h", "dic_device.h", "dic_internal.h"),
-    "icgn_f32": ("k_icgn.hip", "dic_device.h", "dic_internal.h"),
+    "icgn_f32": ("k_icgn.hip", "refine_common.h", "dic_device.h", "dic_internal.h"),
+    "nr_f32": ("k_nr.hip", "refine_common.h", "dic_device.h", "dic_internal.h"),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_affine_1024.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "sq_counters_affine_1024.json")
+SIMDS = 256 * 4          # compute units x SIMDs
+CLOCK_HZ = 2.4e9         # peak engine clock
+# issue cycles of one wave64 instruction on a SIMD: vector ALU (16 lanes, 4
+# passes) and v_mfma_f32_32x32x16_bf16 (8 passes of 4 cycles)
+VALU_CYCLES, MFMA_CYCLES = 4, 32
 CSRC = os.path.join(ROOT, "paper_1905_06228_amd", "csrc")
 
 
@@ -56,6 +63,26 @@ def measured_traffic(kernel: str):
         if list(srcs) != list(k.get("sources", [])) or k.get("source_hash") != kernel_source_hash(srcs):
             return None
         return float(k["bytes_per_launch"])
+    except (OSError, KeyError, ValueError, TypeError):
+        return None
+
+
+def measured_issue(kernel: str, kernel_ms: float):
+    """Fractions of the kernel's time the SIMDs spend issuing its vector-ALU
+    and matrix-core instructions: instruction counts per launch from the
+    committed rocprofv3 SQ counter summary (if taken on the current source)
+    times the issue cycles of one instruction, over SIMDs x clock x time."""
+    try:
+        with open(COUNTERS_FILE) as fh:
+            t = json.load(fh)
+        k = t["kernels"][kernel]
+        srcs = KERNEL_SOURCES.get(kernel, tuple(k.get("sources", [])))
+        if list(srcs) != list(k.get("sources", [])) or k.get("source_hash") != kernel_source_hash(srcs):
+            return None
+        cyc = SIMDS * CLOCK_HZ * kernel_ms * 1e-3
+        return dict(valu_issue_frac=round(k["valu_insts_per_launch"] * VALU_CYCLES / cyc, 3),
+                    mfma_issue_frac=round(k["mfma_insts_per_launch"] * MFMA_CYCLES / cyc, 3),
+                    valu_insts_per_launch=k["valu_insts_per_launch"])
     except (OSError, KeyError, ValueError, TypeError):
         return None
 
@@ -276,7 +303,8 @@ def main() -> int:
                            algorithmic_flops_per_launch=flops,
                            executed_mfma_flops_per_launch=mfma_flops,
                            executed_mfma_tflops=round(mfma_flops / (t_search * 1e-3) / 1e12, 1),
-                           frac_of_fp32_vector_peak=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4))
+                           frac_of_fp32_vector_peak=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                           issue=measured_issue("search_mfma", t_search))
     else:
         roof_search = dict(bound="alu", achieved=round(achieved, 2), peak=FP32_VECTOR_PEAK_TFLOPS,
                            unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
@@ -290,7 +318,8 @@ def main() -> int:
                      unit="GB/s", frac=round(icgn_gbs / HBM_PEAK_GBS, 4),
                      traffic=measured_traffic("icgn_f32"), kernel="icgn_f32_kernel",
                      kernel_ms=round(t_icgn, 4), algorithmic_bytes_per_launch=icgn_bytes,
-                     mean_iterations=float(iters.mean()) if iters.size else 0.0)
+                     mean_iterations=float(iters.mean()) if iters.size else 0.0,
+                     issue=measured_issue("icgn_f32", t_icgn))
     roofline = roof_search if t_search >= t_icgn else roof_icgn
 
     rec = {
@@ -326,6 +355,7 @@ def main() -> int:
             "max_vs_icgn_px": float(np.abs(nr_p[okn & (got["status"] == 0)][:, [0, 3]]
                                            - got["p"][okn & (got["status"] == 0)][:, [0, 3]]
                                            ).max(initial=0)),
+            "issue": measured_issue("nr_f32", t_nr),
         },
     }
     if args.copy_probe_mb > 0:
