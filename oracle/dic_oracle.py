@@ -15,7 +15,9 @@ MATLAB"):
 * Sec. 2, Eq. (1): the zero-normalised cross-correlation of two subsets of
   (2M+1)x(2M+1) pixels, each centred on its mean.
 * Sec. 2.1: brute-force search evaluates every admissible integer position and
-  keeps the one with the largest coefficient.
+  keeps the one with the largest coefficient; particle swarm optimisation
+  (Eqs. 2-4) and its modified form with a star step evaluate at most
+  250 / 1250 positions (Sec. 5.2).
 * Sec. 2.2: a pixel's grey level is the value at its centre; bicubic
   interpolation; IC-GN with an affine (first-order) warp whose reference-side
   quantities (gradients, steepest-descent images, Hessian) are precomputed;
@@ -159,6 +161,167 @@ def integer_search(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, S: in
     r, c = [int(a[0]) for a in np.nonzero(scores >= best - TIE_EPS)]  # row-major first
     return SearchResult(cu - S + c, cv - S + r, float(scores[r, c]), OK,
                         scores if keep_scores else None)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.1, Eqs. (2)-(4): particle swarm integer search, and its modified form
+# with a star (four-neighbour) step
+# ---------------------------------------------------------------------------
+
+PSO_PARTICLES = 50     # swarm size (Sec. 5.2)
+PSO_GENERATIONS = 5    # G_max (Sec. 2.1 after Wu et al.; Sec. 5.2)
+PSO_STOP_CC = 0.995    # the swarm stops once its best coefficient reaches this (Sec. 5.2)
+PSO_C1 = 2.0           # cognitive and social acceleration coefficients: not given in
+PSO_C2 = 2.0           # the paper; the canonical values
+STAR_STEPS = ((1, 0), (-1, 0), (0, 1), (0, -1))
+
+
+def pso_weight(t: int, generations: int) -> float:
+    """Eq. (4): w(t) = 0.9 - t / (2 G_max)."""
+    return 0.9 - t / (2.0 * generations)
+
+
+@dataclass
+class PsoResult:
+    du: int
+    dv: int
+    zncc: float
+    status: int
+    generations: int                  # generations evaluated
+    evaluations: int                  # distinct positions whose coefficient was computed
+    trace: Optional[list] = None      # per generation: (positions [P,2] int, gbest (kx, ky))
+
+
+def _pso_better(ca: float, ia: int, cb: float, ib: int) -> bool:
+    """Whether (coefficient ca, window index ia) beats (cb, ib): larger by more
+    than the tie window, or within it with the smaller row-major index (the
+    brute-force tie rule); a position with no admissible subset never wins."""
+    if not np.isfinite(ca):
+        return False
+    if not np.isfinite(cb):
+        return True
+    if ca > cb + TIE_EPS:
+        return True
+    return ca >= cb - TIE_EPS and ia < ib
+
+
+def pso_search(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, S: int,
+               rand: np.ndarray, cu: int = 0, cv: int = 0, modified: bool = False,
+               generations: int = PSO_GENERATIONS, stop_cc: float = PSO_STOP_CC,
+               c1: float = PSO_C1, c2: float = PSO_C2, memo: bool = True,
+               keep_trace: bool = False) -> PsoResult:
+    """Particle swarm maximisation of Eq. (1) over the integer window
+    |du - cu| <= S, |dv - cv| <= S (Sec. 2.1, Eqs. 2-4).
+
+    ``rand`` holds the swarm's random numbers, float32 uniforms in [0, 1) of
+    shape [generations, particles, 4]: rand[0, i] = (x, y of the position,
+    x, y of the velocity) at initialisation, rand[t + 1, i] = (r1 for x, r1
+    for y, r2 for x, r2 for y) of the update that follows generation t.
+
+    Readings (the paper gives Eqs. 2-4, 50 particles, at most 5 generations,
+    the stop at 0.995 and the modified form's four neighbours, nothing else):
+    positions q and velocities v are window offsets from (cu, cv), both
+    initialised uniformly in [-S, S]; a particle's coefficient is Eq. (1) at
+    its rounded position rint(q) (ties to even) clipped to the window;
+    a position whose subset leaves the image, is not finite or is flat has
+    no coefficient (it never becomes a best); p_best and g_best follow the
+    brute-force tie rule (larger by more than 1e-12, else the smaller
+    row-major index), g_best is taken over the particles in index order;
+    after generation t the swarm stops when g_best >= stop_cc or t = G_max - 1,
+    else per direction d
+        v = w(t) v + c1 r1 (p_best - q) + c2 r2 (g_best - q),  w(t) = 0.9 - t / (2 G_max),
+    evaluated in exactly that order ((w v + c1 r1 (..)) + c2 r2 (..)), a term
+    whose best does not exist yet taken as zero, v clipped to [-S, S], then
+    q = q + v clipped to [-S, S].  The modified form
+    also evaluates the four neighbours of rint(q) that lie in the window and
+    moves the particle to the best of the five (a star step) before the
+    update.  Coefficients already computed are looked up, not recomputed
+    (Sec. 5.2), which changes nothing in the result.  Status as the
+    brute-force search, NO_VALID_CANDIDATE when no evaluated position had a
+    coefficient.
+    """
+    rand = np.asarray(rand, dtype=np.float32).astype(np.float64)
+    P = rand.shape[1]
+    if not poi_inside(x0, y0, M, f.shape[1], f.shape[0]):
+        return PsoResult(0, 0, float("nan"), OUT_OF_BOUNDS, 0, 0)
+    fs = subset(f, x0, y0, M)
+    if not np.all(np.isfinite(fs)):
+        return PsoResult(0, 0, float("nan"), NAN_INPUT, 0, 0)
+    if is_flat(fs):
+        return PsoResult(0, 0, float("nan"), ZERO_VARIANCE, 0, 0)
+    H, W = g.shape
+    side = 2 * S + 1
+    inside = candidate_mask(W, H, x0, y0, M, S, cu, cv)
+    lut: Dict[Tuple[int, int], float] = {}
+    n_eval = [0]
+
+    def coeff(kx: int, ky: int) -> float:
+        if memo and (kx, ky) in lut:
+            return lut[(kx, ky)]
+        n_eval[0] += 0 if (kx, ky) in lut else 1
+        c = -np.inf
+        if inside[ky + S, kx + S]:
+            gs = subset(g, x0 + cu + kx, y0 + cv + ky, M)
+            if np.all(np.isfinite(gs)) and not is_flat(gs):
+                c = zncc(fs, gs)
+        lut[(kx, ky)] = c
+        return c
+
+    def index(kx: int, ky: int) -> int:
+        return (ky + S) * side + (kx + S)
+
+    span = 2.0 * S
+    q = span * rand[0, :, 0:2] - S
+    v = span * rand[0, :, 2:4] - S
+    pb = [(-np.inf, side * side, 0, 0)] * P          # (coefficient, index, kx, ky)
+    trace = [] if keep_trace else None
+    t = 0
+    while True:
+        ks = np.clip(np.rint(q), -S, S).astype(np.int64)
+        for i in range(P):
+            kx, ky = int(ks[i, 0]), int(ks[i, 1])
+            best = (coeff(kx, ky), index(kx, ky), kx, ky)
+            if modified:
+                for sx, sy in STAR_STEPS:
+                    nx, ny = kx + sx, ky + sy
+                    if -S <= nx <= S and -S <= ny <= S:
+                        cand = (coeff(nx, ny), index(nx, ny), nx, ny)
+                        if _pso_better(cand[0], cand[1], best[0], best[1]):
+                            best = cand
+                q[i] = (best[2], best[3])
+            if _pso_better(best[0], best[1], pb[i][0], pb[i][1]):
+                pb[i] = best
+        gb = (-np.inf, side * side, 0, 0)
+        for i in range(P):
+            if _pso_better(pb[i][0], pb[i][1], gb[0], gb[1]):
+                gb = pb[i]
+        if keep_trace:
+            trace.append((ks.copy(), (gb[2], gb[3])))
+        if (np.isfinite(gb[0]) and gb[0] >= stop_cc) or t == generations - 1:
+            break
+        w = pso_weight(t, generations)
+        r = rand[t + 1]
+        for i in range(P):
+            for d in range(2):
+                target_p = float(pb[i][2 + d]) if np.isfinite(pb[i][0]) else q[i, d]
+                target_g = float(gb[2 + d]) if np.isfinite(gb[0]) else q[i, d]
+                a = w * v[i, d]
+                b = (c1 * r[i, d]) * (target_p - q[i, d])
+                c = (c2 * r[i, 2 + d]) * (target_g - q[i, d])
+                vn = min(max((a + b) + c, -float(S)), float(S))
+                v[i, d] = vn
+                q[i, d] = min(max(q[i, d] + vn, -float(S)), float(S))
+        t += 1
+    if not np.isfinite(gb[0]):
+        return PsoResult(0, 0, float("nan"), NO_VALID_CANDIDATE, t + 1, n_eval[0], trace)
+    return PsoResult(cu + gb[2], cv + gb[3], float(gb[0]), OK, t + 1, n_eval[0], trace)
+
+
+def pso_random(n_pois: int, seed: int, particles: int = PSO_PARTICLES,
+               generations: int = PSO_GENERATIONS) -> np.ndarray:
+    """Seeded swarm random numbers for n_pois POIs, float32 [N, G, P, 4]."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 7]))
+    return rng.random((n_pois, generations, particles, 4), dtype=np.float32)
 
 
 # ---------------------------------------------------------------------------
@@ -577,11 +740,13 @@ def znssd_batch(f: np.ndarray, g: np.ndarray, pois: np.ndarray, M: int, P: np.nd
 def correlate(f: np.ndarray, g: np.ndarray, pois: np.ndarray, M: int, S: int,
               centers: Optional[np.ndarray] = None, p_init: Optional[np.ndarray] = None,
               max_iters: int = 20, tol: float = 1e-3,
-              refine: str = "icgn") -> Dict[str, np.ndarray]:
-    """Integer search then IC-GN (or Newton-Raphson, ``refine="nr"``) for
-    every POI (Sec. 2: the integer result seeds the sub-pixel search; initial
-    p = (du, 0, 0, dv, 0, 0), or the gradient terms of ``p_init`` when
-    given)."""
+              refine: str = "icgn", search: str = "bfs",
+              rand: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+    """Integer search (brute force, or ``search="pso"`` / ``"mpso"`` with the
+    swarm random numbers ``rand`` [N, G, P, 4]) then IC-GN (or
+    Newton-Raphson, ``refine="nr"``) for every POI (Sec. 2: the integer result
+    seeds the sub-pixel search; initial p = (du, 0, 0, dv, 0, 0), or the
+    gradient terms of ``p_init`` when given)."""
     N = pois.shape[0]
     fx, fy = central_gradients(f)
     out = dict(uv=np.zeros((N, 2), np.int32), zncc_int=np.full(N, np.nan),
@@ -591,7 +756,10 @@ def correlate(f: np.ndarray, g: np.ndarray, pois: np.ndarray, M: int, S: int,
     for i in range(N):
         x0, y0 = int(pois[i, 0]), int(pois[i, 1])
         cu, cv = (0, 0) if centers is None else (int(centers[i, 0]), int(centers[i, 1]))
-        s = integer_search(f, g, x0, y0, M, S, cu, cv)
+        if search == "bfs":
+            s = integer_search(f, g, x0, y0, M, S, cu, cv)
+        else:
+            s = pso_search(f, g, x0, y0, M, S, rand[i], cu, cv, modified=(search == "mpso"))
         out["uv"][i] = (s.du, s.dv)
         out["zncc_int"][i] = s.zncc
         out["status_int"][i] = s.status
