@@ -245,6 +245,35 @@ dic_status_t dic_nr_refine(dic_plan_t plan, const float* ref_images,
                            float* zncc_out, int32_t* iters_out,
                            int32_t* status_out, dic_stream_t stream);
 
+/* Particle swarm integer search (Sec. 2.1, Eqs. 2-4) with the settings of
+ * Sec. 5.2: 50 particles, at most 5 generations, stop once the swarm's best
+ * coefficient reaches 0.995; acceleration coefficients c1 = c2 = 2 (not
+ * given in the paper), inertia w(t) = 0.9 - t / 10 (Eq. 4).  With
+ * modified = 1 every particle also evaluates the four neighbours of its
+ * position and moves to the best of the five before the update (the
+ * modified swarm with star search).  Positions and velocities are window
+ * offsets from seed_uv[i] (nullable = (0,0)), initialised uniformly in
+ * [-S, S]; a particle's coefficient is Eq. (1) at its rounded position
+ * clipped to the window, candidates whose subset leaves the image, is not
+ * finite or is flat having none; personal and swarm bests follow the
+ * brute-force tie rule; velocities are clipped to [-S, S], positions to the
+ * window.  swarm_random (device, float32 [N, 5, 50, 4], uniforms in [0, 1))
+ * holds the swarm's random numbers: [i, 0, j] = (x, y of particle j's
+ * position, x, y of its velocity) at initialisation, [i, t + 1, j] = (r1 for
+ * x, r1 for y, r2 for x, r2 for y) of the update after generation t.  Each
+ * coefficient is computed once per POI (a look-up table).  Outputs as
+ * dic_integer_search (status NO_VALID_CANDIDATE when no evaluated position
+ * had a coefficient), plus generations_out and evaluations_out (int32 [N],
+ * nullable): generations run and distinct positions evaluated (at most 250,
+ * or 1250 with modified = 1).  FP32 batched plans only (it reads the
+ * deformed-side box sums); DIC_ERR_UNSUPPORTED otherwise. */
+dic_status_t dic_pso_search(dic_plan_t plan, const float* ref_images,
+                            const float* def_images, const int32_t* poi_xy,
+                            const int32_t* seed_uv, const float* swarm_random,
+                            int32_t modified, int32_t* uv_out, float* zncc_out,
+                            int32_t* status_out, int32_t* generations_out,
+                            int32_t* evaluations_out, dic_stream_t stream);
+
 /* Search then refine in one call (the two entries above, in order; the
  * refinement is Newton-Raphson when the plan has DIC_FLAG_REFINE_NR).
  * zncc_int_out / status_int_out receive the search results (nullable).  With

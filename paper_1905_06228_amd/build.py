@@ -15,6 +15,7 @@ LIB = os.path.join(PKG, "libdic.so")
 
 SOURCES = [
     "k_prep.hip", "k_search.hip", "k_search_mfma.hip", "k_icgn.hip", "k_nr.hip", "k_znssd.hip",
+    "k_pso.hip",
     "dic_api.cpp",
 ]
 HEADERS = ["dic_internal.h", "dic_device.h", "search_common.h", "refine_common.h"]

@@ -564,6 +564,30 @@ dic_status_t dic_nr_refine(dic_plan_t p, const float* ref, const float* def, con
                         true);
 }
 
+dic_status_t dic_pso_search(dic_plan_t p, const float* ref, const float* def,
+                            const int32_t* poi, const int32_t* seed, const float* swarm_random,
+                            int32_t modified, int32_t* uv, float* zn, int32_t* status,
+                            int32_t* generations, int32_t* evaluations, dic_stream_t stream) {
+  dic_status_t r = check_plan(p, true);
+  if (r) return r;
+  if (p->N == 0) return DIC_SUCCESS;
+  if (!ref || !def || !poi || !swarm_random || !uv || !zn || !status)
+    return fail(DIC_ERR_INVALID_ARGUMENT, "null required pointer");
+  if (modified != 0 && modified != 1)
+    return fail(DIC_ERR_INVALID_ARGUMENT, "modified must be 0 or 1");
+  if (!p->fp32())
+    return fail(DIC_ERR_UNSUPPORTED, "the swarm search uses the FP32 batched form's box sums");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  r = prepare(p, ref, poi, s, false);
+  if (r) return r;
+  r = prepare_deformed(p, def, s, false);
+  if (r) return r;
+  DIC_HIP(launch_reset_counters(p->st, s));
+  DIC_HIP(launch_pso(p->st, modified != 0, ref, def, poi, seed, swarm_random, uv, zn, status,
+                     generations, evaluations, p->num_cu, s));
+  return DIC_SUCCESS;
+}
+
 dic_status_t dic_correlate(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
                            const int32_t* seed, const double* p_init, int32_t* uv,
                            float* zn_int, int32_t* st_int, double* p_out, float* zn,

@@ -12,6 +12,12 @@ constexpr int kMaxM = 20;
 constexpr int kMaxS = 32;
 constexpr int kWave = 64;
 constexpr int kMaxRefineSlack = 16;  // largest tuning icgn_slack
+// Particle swarm search (Sec. 2.1, Eqs. 2-4; settings of Sec. 5.2)
+constexpr int kPsoParticles = 50;
+constexpr int kPsoGenerations = 5;
+constexpr int kPsoStar = 5;            // positions per particle and generation, modified form
+constexpr double kPsoC1 = 2.0, kPsoC2 = 2.0;
+constexpr double kPsoStopCC = 0.995;
 
 // Device copy of a pair description plus derived offsets.
 struct DevPair {
@@ -75,6 +81,10 @@ struct SearchGroup {
 hipError_t launch_reset_counters(const DevState& st, hipStream_t s);
 hipError_t launch_gradients(const DevState& st, const float* ref, hipStream_t s);
 hipError_t launch_box_sums(const DevState& st, const float* def, hipStream_t s);
+hipError_t launch_pso(const DevState& st, bool modified, const float* ref, const float* def,
+                      const int32_t* poi, const int32_t* seed, const float* rand, int32_t* uv,
+                      float* zn, int32_t* status, int32_t* gens, int32_t* evals, int num_cu,
+                      hipStream_t s);
 hipError_t launch_ref_prep_f32(const DevState& st, const float* ref, const int32_t* poi,
                                hipStream_t s);
 hipError_t launch_ref_prep_f64(const DevState& st, const DevPair* host_pairs,

@@ -51,10 +51,14 @@ class Tuning(ctypes.Structure):
                 ("icgn_waves", ctypes.c_int32), ("icgn_slack", ctypes.c_int32)]
 
 
+PSO_PARTICLES = 50      # swarm size of dic_pso_search
+PSO_GENERATIONS = 5     # its maximum number of generations
+
 EXPORTS = [
     "dic_plan_create", "dic_plan_workspace_size", "dic_plan_bind", "dic_plan_get_tuning",
     "dic_plan_set_tuning", "dic_plan_autotune", "dic_plan_invalidate_reference",
-    "dic_prepare_reference", "dic_prepare_deformed", "dic_integer_search", "dic_icgn_refine", "dic_nr_refine", "dic_correlate",
+    "dic_prepare_reference", "dic_prepare_deformed", "dic_integer_search", "dic_pso_search",
+    "dic_icgn_refine", "dic_nr_refine", "dic_correlate",
     "dic_znssd_backward", "dic_seed_update", "dic_poi_grid", "dic_plan_destroy",
     "dic_status_string", "dic_last_error",
 ]
@@ -86,6 +90,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.dic_prepare_reference.argtypes = [P, V, V, V]
     L.dic_prepare_deformed.argtypes = [P, V, V]
     L.dic_integer_search.argtypes = [P, V, V, V, V, V, V, V, V]
+    L.dic_pso_search.argtypes = [P, V, V, V, V, V, I32, V, V, V, V, V, V]
     L.dic_icgn_refine.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V]
     L.dic_nr_refine.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V]
     L.dic_correlate.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V, V, V]
@@ -247,6 +252,28 @@ class Plan:
             _ptr(uv, torch.int32, d, "uv"), _ptr(zn, torch.float32, d, "zncc"),
             _ptr(st, torch.int32, d, "status"), _stream()))
         return uv, zn, st
+
+    def pso_search(self, ref, defm, pois, swarm_random, modified=False, seed=None, out=None):
+        """Particle swarm integer search (modified=True: with the star step).
+        swarm_random: float32 [N, 5, 50, 4] uniforms in [0, 1).  Returns
+        (uv, zncc, status, generations, evaluations)."""
+        d, N = self.device, self.N
+        if tuple(swarm_random.shape) != (N, PSO_GENERATIONS, PSO_PARTICLES, 4):
+            raise DicError(f"swarm_random must have shape {(N, PSO_GENERATIONS, PSO_PARTICLES, 4)}")
+        uv, zn, st, gen, ev = out if out is not None else (
+            torch.empty((N, 2), dtype=torch.int32, device=d),
+            torch.empty(N, dtype=torch.float32, device=d),
+            torch.empty(N, dtype=torch.int32, device=d),
+            torch.empty(N, dtype=torch.int32, device=d),
+            torch.empty(N, dtype=torch.int32, device=d))
+        _check(self.L.dic_pso_search(
+            self._h, _ptr(ref, torch.float32, d, "ref"), _ptr(defm, torch.float32, d, "def"),
+            _ptr(pois, torch.int32, d, "pois"), _ptr(seed, torch.int32, d, "seed"),
+            _ptr(swarm_random, torch.float32, d, "swarm_random"), 1 if modified else 0,
+            _ptr(uv, torch.int32, d, "uv"), _ptr(zn, torch.float32, d, "zncc"),
+            _ptr(st, torch.int32, d, "status"), _ptr(gen, torch.int32, d, "generations"),
+            _ptr(ev, torch.int32, d, "evaluations"), _stream()))
+        return uv, zn, st, gen, ev
 
     def icgn_refine(self, ref, defm, pois, uv, status_in=None, p_init=None, out=None):
         return self._refine(self.L.dic_icgn_refine, ref, defm, pois, uv, status_in, p_init, out)
