@@ -260,6 +260,32 @@ def main() -> int:
     t_nr = time_launches(torch, lambda: st.nr_refine(F, G, Q, so["uv"], so["status_int"], out=nro),
                          reps)
     nr_p, nr_it, nr_st = nro[0].cpu().numpy(), nro[2].cpu().numpy(), nro[3].cpu().numpy()
+    # particle swarm searches (Sec. 2.1, Eqs. 2-4) on the same pair, and the
+    # modified swarm + Newton-Raphson pipeline (the paper's fastest combination)
+    Rs = torch.from_numpy(dicgen.swarm_random(N, 7)).to(dev)
+    swarm = {}
+    uv_bfs, st_bfs = so["uv"].cpu().numpy(), so["status_int"].cpu().numpy()
+    for name, mod in (("pso", False), ("modified_pso", True)):
+        po = tuple(torch.empty_like(x) for x in (so["uv"], so["zncc_int"], so["status_int"],
+                                                  so["iters"], so["iters"]))
+        t_sw = time_launches(torch, lambda: st.pso_search(F, G, Q, Rs, modified=mod, out=po), reps)
+        puv, pst, pgen, pev = (po[0].cpu().numpy(), po[2].cpu().numpy(), po[3].cpu().numpy(),
+                               po[4].cpu().numpy())
+        okp = (pst == 0) & (st_bfs == 0)
+        swarm[name] = {"search_ms": round(t_sw, 4), "pois_per_s": round(N / (t_sw * 1e-3), 1),
+                       "mean_evaluations": float(pev[pst == 0].mean()),
+                       "mean_generations": float(pgen[pst == 0].mean()),
+                       "integer_equal_to_brute_force": float(np.all(puv[okp] == uv_bfs[okp],
+                                                                    axis=1).mean())}
+        if mod:
+            so2 = tuple(torch.empty_like(x) for x in (so["p"], so["zncc"], so["iters"], so["status"]))
+            t_nr2 = time_launches(torch, lambda: st.nr_refine(F, G, Q, po[0], po[2], out=so2), reps)
+            p2, s2 = so2[0].cpu().numpy(), so2[3].cpu().numpy()
+            ok3 = (s2 == 0) & (nr_st == 0)
+            swarm["modified_pso_then_nr"] = {
+                "ms": round(t_sw + t_nr2, 4), "pois_per_s": round(N / ((t_sw + t_nr2) * 1e-3), 1),
+                "final_within_1e-3px_of_brute_force_then_nr": float(
+                    (np.abs(p2[ok3][:, [0, 3]] - nr_p[ok3][:, [0, 3]]).max(axis=1) <= 1e-3).mean())}
 
     # --- FP64 plain form ---------------------------------------------------------
     p64 = dic.single_pair_plan(W, H, pair.M, pair.S, N, dic.FP64_PLAIN)
@@ -357,6 +383,7 @@ def main() -> int:
                                            ).max(initial=0)),
             "issue": measured_issue("nr_f32", t_nr),
         },
+        "particle_swarm": swarm,
     }
     if args.copy_probe_mb > 0:
         n = args.copy_probe_mb * (1 << 20) // 4

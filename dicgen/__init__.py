@@ -203,6 +203,16 @@ def poi_grid(width: int, height: int, M: int, S: int, step: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# random numbers of the particle swarm search (an input of the method)
+# ---------------------------------------------------------------------------
+
+def swarm_random(n_pois: int, seed: int, particles: int = 50, generations: int = 5) -> np.ndarray:
+    """Seeded uniforms in [0, 1) for the swarm searches, float32
+    [n_pois, generations, particles, 4]."""
+    return rng_for(seed, 7).random((n_pois, generations, particles, 4), dtype=np.float32)
+
+
+# ---------------------------------------------------------------------------
 # the five workloads
 # ---------------------------------------------------------------------------
 

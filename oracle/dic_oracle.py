@@ -317,13 +317,6 @@ def pso_search(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, S: int,
     return PsoResult(cu + gb[2], cv + gb[3], float(gb[0]), OK, t + 1, n_eval[0], trace)
 
 
-def pso_random(n_pois: int, seed: int, particles: int = PSO_PARTICLES,
-               generations: int = PSO_GENERATIONS) -> np.ndarray:
-    """Seeded swarm random numbers for n_pois POIs, float32 [N, G, P, 4]."""
-    rng = np.random.default_rng(np.random.SeedSequence([seed, 7]))
-    return rng.random((n_pois, generations, particles, 4), dtype=np.float32)
-
-
 # ---------------------------------------------------------------------------
 # Sec. 2.2: bicubic interpolation (Keys cubic convolution, a = -1/2)
 # ---------------------------------------------------------------------------

@@ -56,7 +56,7 @@ def check(got, ref, label):
 def test_pso_matches_oracle(modified):
     pr = dicgen.affine_pair_1024(size=256, tag=2)
     pois = pr.pois[::6]
-    R = O.pso_random(len(pois), 31)
+    R = dicgen.swarm_random(len(pois), 31)
     print(f"case pso modified={modified} M={pr.M} S={pr.S} N={len(pois)}", flush=True)
     ref = oracle_pso(pr.ref, pr.defm, pois, pr.M, pr.S, R, modified)
     check(gpu_pso(pr.ref, pr.defm, pois, pr.M, pr.S, R, modified), ref, f"affine_256/mod={modified}")
@@ -74,7 +74,7 @@ def test_pso_seeded_border_nan_and_small_subsets(modified):
     rng = np.random.default_rng(72)
     seeds = rng.integers(-6, 7, size=(len(pois), 2)).astype(np.int32)
     seeds[3] = (200, 0)                     # every window position outside the image
-    R = O.pso_random(len(pois), 32)
+    R = dicgen.swarm_random(len(pois), 32)
     print(f"case pso border/nan modified={modified} N={len(pois)}", flush=True)
     ref = oracle_pso(pr.ref, g, pois, 7, 5, R, modified, seeds)
     assert ref["status"][3] == O.NO_VALID_CANDIDATE
@@ -86,7 +86,7 @@ def test_pso_exact_shift_stops_early():
     f = dicgen.render_image(b, None, 150, 150)
     g = np.roll(np.roll(f, -2, axis=0), 3, axis=1)
     pois = np.array([[75, 75], [60, 90], [90, 60]], dtype=np.int32)
-    R = O.pso_random(len(pois), 21)
+    R = dicgen.swarm_random(len(pois), 21)
     print("case pso exact shift N=3", flush=True)
     for mod in (False, True):
         ref = oracle_pso(f, g, pois, 10, 8, R, mod)
@@ -101,7 +101,7 @@ def test_pso_then_nr_pipeline():
     the oracle's same pipeline."""
     pr = dicgen.affine_pair_1024(size=256, tag=2)
     pois = pr.pois[::9]
-    R = O.pso_random(len(pois), 33)
+    R = dicgen.swarm_random(len(pois), 33)
     print(f"case pso+nr N={len(pois)}", flush=True)
     ref = O.correlate(pr.ref, pr.defm, pois, pr.M, pr.S, refine="nr", search="mpso", rand=R)
     plan = dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois))
@@ -127,4 +127,4 @@ def test_pso_argument_errors():
         plan.pso_search(F, G, Q, torch.zeros((len(pois), 4, 50, 4), device="cuda"))
     plan64 = dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois), dic.FP64_PLAIN)
     with pytest.raises(dic.DicError):
-        plan64.pso_search(F, G, Q, to_dev(O.pso_random(len(pois), 1)))
+        plan64.pso_search(F, G, Q, to_dev(dicgen.swarm_random(len(pois), 1)))

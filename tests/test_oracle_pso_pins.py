@@ -33,7 +33,7 @@ def test_evaluations_within_paper_bounds(pair):
     1250."""
     g = json.load(open(GOLDEN))
     pois = pair.pois[::61]
-    R = O.pso_random(len(pois), 3)
+    R = dicgen.swarm_random(len(pois), 3)
     for i, (x0, y0) in enumerate(pois):
         a = O.pso_search(pair.ref, pair.defm, int(x0), int(y0), pair.M, pair.S, R[i])
         m = O.pso_search(pair.ref, pair.defm, int(x0), int(y0), pair.M, pair.S, R[i], modified=True)
@@ -90,7 +90,7 @@ def test_star_step_is_greedy_ascent(pair):
 @pytest.mark.parametrize("modified", [False, True])
 def test_reported_coefficient_is_eq1_and_swarm_maximum(pair, modified):
     pois = pair.pois[::97]
-    R = O.pso_random(len(pois), 9)
+    R = dicgen.swarm_random(len(pois), 9)
     for i, (x0, y0) in enumerate(pois):
         r = O.pso_search(pair.ref, pair.defm, int(x0), int(y0), pair.M, pair.S, R[i],
                          modified=modified, keep_trace=True)
@@ -110,7 +110,7 @@ def test_exact_shift_found_and_early_stop():
     b = dicgen.make_blobs(dicgen.rng_for(904, 1, 0), 1500, 150, 150)
     f = dicgen.render_image(b, None, 150, 150)
     g = np.roll(np.roll(f, -2, axis=0), 3, axis=1)
-    R = O.pso_random(1, 21)[0]
+    R = dicgen.swarm_random(1, 21)[0]
     r = O.pso_search(f, g, 75, 75, 10, 8, R, modified=True, keep_trace=True)
     assert (r.du, r.dv, r.status) == (3, -2, O.OK)
     assert abs(r.zncc - 1.0) < 1e-12
@@ -118,7 +118,7 @@ def test_exact_shift_found_and_early_stop():
 
 
 def test_memo_changes_nothing(pair):
-    R = O.pso_random(3, 4)
+    R = dicgen.swarm_random(3, 4)
     for i, (x0, y0) in enumerate(pair.pois[[5, 200, 400]]):
         for mod in (False, True):
             a = O.pso_search(pair.ref, pair.defm, int(x0), int(y0), pair.M, pair.S, R[i], modified=mod)
@@ -129,7 +129,7 @@ def test_memo_changes_nothing(pair):
 
 def test_statuses_and_radius_zero(pair):
     f, g, M = pair.ref, pair.defm, pair.M
-    R = O.pso_random(1, 2)[0]
+    R = dicgen.swarm_random(1, 2)[0]
     assert O.pso_search(f, g, 5, 120, M, 4, R).status == O.OUT_OF_BOUNDS
     fn = f.copy()
     fn[121, 123] = np.nan
