@@ -343,18 +343,48 @@ def cubic_dweights(t: np.ndarray) -> np.ndarray:
                      (3 * t2 - 2 * t) / 2], axis=-1)
 
 
-def in_interp_bounds(xs: np.ndarray, ys: np.ndarray, width: int, height: int) -> bool:
-    """All 4x4 neighbourhoods inside the image: 1 <= floor <= size - 3."""
+def in_interp_bounds(xs: np.ndarray, ys: np.ndarray, width: int, height: int,
+                     method: str = "bicubic") -> bool:
+    """All interpolation neighbourhoods inside the image: 4x4 for bicubic
+    (1 <= floor <= size - 3), 2x2 for bilinear (0 <= floor <= size - 2)."""
     ix = np.floor(xs)
     iy = np.floor(ys)
-    return bool(np.all(ix >= 1) and np.all(ix + 2 <= width - 1)
-                and np.all(iy >= 1) and np.all(iy + 2 <= height - 1))
+    lo, hi = (0, 1) if method == "bilinear" else (1, 2)
+    return bool(np.all(ix >= lo) and np.all(ix + hi <= width - 1)
+                and np.all(iy >= lo) and np.all(iy + hi <= height - 1))
+
+
+def bilinear(g: np.ndarray, xs: np.ndarray, ys: np.ndarray, with_grad: bool = False):
+    """Eq. (5): G(x*, y*) = a00 + a10 x' + a01 y' + a11 x' y', with x', y' the
+    distances from the integer pixel (floor(x*), floor(y*)) and the
+    coefficients fixed by the grey levels of the four surrounding pixels
+    (G = g00 at (0, 0), g10 at (1, 0), g01 at (0, 1), g11 at (1, 1)).
+    Optionally the gradient (a10 + a11 y', a01 + a11 x')."""
+    ix = np.floor(xs).astype(np.int64)
+    iy = np.floor(ys).astype(np.int64)
+    x1 = xs - ix
+    y1 = ys - iy
+    g00 = g[iy, ix].astype(np.float64)
+    g10 = g[iy, ix + 1].astype(np.float64)
+    g01 = g[iy + 1, ix].astype(np.float64)
+    g11 = g[iy + 1, ix + 1].astype(np.float64)
+    a00 = g00
+    a10 = g10 - g00
+    a01 = g01 - g00
+    a11 = g11 - g10 - g01 + g00
+    val = a00 + a10 * x1 + a01 * y1 + a11 * x1 * y1
+    if not with_grad:
+        return val
+    return val, a10 + a11 * y1, a01 + a11 * x1
 
 
 def interpolate(g: np.ndarray, xs: np.ndarray, ys: np.ndarray,
-                with_grad: bool = False):
+                with_grad: bool = False, method: str = "bicubic"):
     """g at sub-pixel points: sum_{l,k} w_l(ty) w_k(tx) g[floor(y)+l, floor(x)+k],
-    k, l in {-1, 0, 1, 2}.  Optionally the analytic gradient of the interpolant."""
+    k, l in {-1, 0, 1, 2} (Keys bicubic), or Eq. (5) with method="bilinear".
+    Optionally the analytic gradient of the interpolant."""
+    if method == "bilinear":
+        return bilinear(g, xs, ys, with_grad)
     ix = np.floor(xs).astype(np.int64)
     iy = np.floor(ys).astype(np.int64)
     wx = cubic_weights(xs - ix)
@@ -502,7 +532,7 @@ class IcgnResult:
 
 def icgn(f: np.ndarray, g: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, y0: int,
          M: int, p0: Sequence[float], max_iters: int = 20, tol: float = 1e-3,
-         prep: Optional[RefPrep] = None) -> IcgnResult:
+         prep: Optional[RefPrep] = None, interp: str = "bicubic") -> IcgnResult:
     """IC-GN on the ZNSSD criterion with a first-order warp.
 
     Per iteration: warp the subset with W(p), interpolate g, form
@@ -526,9 +556,9 @@ def icgn(f: np.ndarray, g: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, 
     while it < max_iters:
         it += 1
         xs, ys = warp_points(p, x0, y0, dx, dy)
-        if not in_interp_bounds(xs, ys, W, H):
+        if not in_interp_bounds(xs, ys, W, H, interp):
             return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
-        gs = interpolate(g, xs, ys)
+        gs = interpolate(g, xs, ys, method=interp)
         if not np.all(np.isfinite(gs)):
             return IcgnResult(p, float("nan"), it, NAN_INPUT)
         if is_flat(gs):
@@ -543,9 +573,9 @@ def icgn(f: np.ndarray, g: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, 
             status = OK
             break
     xs, ys = warp_points(p, x0, y0, dx, dy)
-    if not in_interp_bounds(xs, ys, W, H):
+    if not in_interp_bounds(xs, ys, W, H, interp):
         return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
-    gs = interpolate(g, xs, ys)
+    gs = interpolate(g, xs, ys, method=interp)
     if not np.all(np.isfinite(gs)):
         return IcgnResult(p, float("nan"), it, NAN_INPUT)
     if is_flat(gs):
@@ -590,7 +620,7 @@ def nr_terms(fs: np.ndarray, gs: np.ndarray, gx: np.ndarray, gy: np.ndarray,
 
 
 def nr(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, p0: Sequence[float],
-       max_iters: int = 20, tol: float = 1e-3) -> IcgnResult:
+       max_iters: int = 20, tol: float = 1e-3, interp: str = "bicubic") -> IcgnResult:
     """Newton-Raphson refinement (Sec. 2.2: the method whose parameters are
     recomputed at every iteration, in contrast to IC-GN) on the ZNSSD
     criterion with the first-order warp applied forward, x_i = x0 + W(p) xi_i,
@@ -620,9 +650,9 @@ def nr(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, p0: Sequence[floa
     while it < max_iters:
         it += 1
         xs, ys = warp_points(p, x0, y0, dx, dy)
-        if not in_interp_bounds(xs, ys, W, H):
+        if not in_interp_bounds(xs, ys, W, H, interp):
             return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
-        gs, gx, gy = interpolate(g, xs, ys, with_grad=True)
+        gs, gx, gy = interpolate(g, xs, ys, with_grad=True, method=interp)
         if not (np.all(np.isfinite(gs)) and np.all(np.isfinite(gx)) and np.all(np.isfinite(gy))):
             return IcgnResult(p, float("nan"), it, NAN_INPUT)
         if is_flat(gs):
@@ -637,9 +667,9 @@ def nr(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, p0: Sequence[floa
             status = OK
             break
     xs, ys = warp_points(p, x0, y0, dx, dy)
-    if not in_interp_bounds(xs, ys, W, H):
+    if not in_interp_bounds(xs, ys, W, H, interp):
         return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
-    gs = interpolate(g, xs, ys)
+    gs = interpolate(g, xs, ys, method=interp)
     if not np.all(np.isfinite(gs)):
         return IcgnResult(p, float("nan"), it, NAN_INPUT)
     if is_flat(gs):
@@ -734,7 +764,8 @@ def correlate(f: np.ndarray, g: np.ndarray, pois: np.ndarray, M: int, S: int,
               centers: Optional[np.ndarray] = None, p_init: Optional[np.ndarray] = None,
               max_iters: int = 20, tol: float = 1e-3,
               refine: str = "icgn", search: str = "bfs",
-              rand: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+              rand: Optional[np.ndarray] = None,
+              interp: str = "bicubic") -> Dict[str, np.ndarray]:
     """Integer search (brute force, or ``search="pso"`` / ``"mpso"`` with the
     swarm random numbers ``rand`` [N, G, P, 4]) then IC-GN (or
     Newton-Raphson, ``refine="nr"``) for every POI (Sec. 2: the integer result
@@ -764,9 +795,9 @@ def correlate(f: np.ndarray, g: np.ndarray, pois: np.ndarray, M: int, S: int,
         if p_init is not None:
             p0[[1, 2, 4, 5]] = p_init[i, [1, 2, 4, 5]]
         if refine == "nr":
-            r = nr(f, g, x0, y0, M, p0, max_iters, tol)
+            r = nr(f, g, x0, y0, M, p0, max_iters, tol, interp=interp)
         else:
-            r = icgn(f, g, fx, fy, x0, y0, M, p0, max_iters, tol)
+            r = icgn(f, g, fx, fy, x0, y0, M, p0, max_iters, tol, interp=interp)
         out["p"][i] = r.p
         out["zncc"][i] = r.zncc
         out["iters"][i] = r.iters
