@@ -260,6 +260,30 @@ def main() -> int:
     t_nr = time_launches(torch, lambda: st.nr_refine(F, G, Q, so["uv"], so["status_int"], out=nro),
                          reps)
     nr_p, nr_it, nr_st = nro[0].cpu().numpy(), nro[2].cpu().numpy(), nro[3].cpu().numpy()
+    # bilinear interpolation (Eq. 5) in both refinements of the same search
+    # result, and the accuracy of each interpolant against the true field
+    bp = dic.single_pair_plan(W, H, pair.M, pair.S, N, dic.FP32_BATCHED,
+                              flags=dic.FLAG_CACHE_REF_PREP | dic.FLAG_INTERP_BILINEAR)
+    bp.tuning = plan.tuning
+    bil = {}
+    truth = dicgen.true_displacement(pair.field, pair.pois.astype(np.float64))
+    ref_err = {"icgn": (so["p"], so["status"]), "nr": (nro[0], nro[3])}
+    for name, fn in (("icgn", bp.icgn_refine), ("nr", bp.nr_refine)):
+        bo = tuple(torch.empty_like(x) for x in (so["p"], so["zncc"], so["iters"], so["status"]))
+        t_b = time_launches(torch, lambda: fn(F, G, Q, so["uv"], so["status_int"], out=bo), reps)
+        bpn, bit, bst = bo[0].cpu().numpy(), bo[2].cpu().numpy(), bo[3].cpu().numpy()
+        cp, cst = ref_err[name][0].cpu().numpy(), ref_err[name][1].cpu().numpy()
+        okb, okc = bst == 0, cst == 0
+        eb = np.abs(bpn[okb][:, [0, 3]] - truth[okb])
+        ec = np.abs(cp[okc][:, [0, 3]] - truth[okc])
+        bil[name] = {"refine_ms": round(t_b, 4), "pois_per_s": round(N / (t_b * 1e-3), 1),
+                     "bicubic_refine_ms": round(t_icgn if name == "icgn" else t_nr, 4),
+                     "mean_iterations": float(bit[okb].mean()) if okb.any() else 0.0,
+                     "ok_fraction": float(okb.mean()),
+                     "mean_abs_error_px": float(eb.mean()) if okb.any() else None,
+                     "bicubic_mean_abs_error_px": float(ec.mean()) if okc.any() else None,
+                     "p99_abs_error_px": float(np.percentile(eb.max(axis=1), 99)) if okb.any() else None,
+                     "bicubic_p99_abs_error_px": float(np.percentile(ec.max(axis=1), 99)) if okc.any() else None}
     # particle swarm searches (Sec. 2.1, Eqs. 2-4) on the same pair, and the
     # modified swarm + Newton-Raphson pipeline (the paper's fastest combination)
     Rs = torch.from_numpy(dicgen.swarm_random(N, 7)).to(dev)
@@ -384,6 +408,7 @@ def main() -> int:
             "issue": measured_issue("nr_f32", t_nr),
         },
         "particle_swarm": swarm,
+        "bilinear": bil,
     }
     if args.copy_probe_mb > 0:
         n = args.copy_probe_mb * (1 << 20) // 4

@@ -89,9 +89,16 @@ enum {
                                          dic_plan_invalidate_reference()     */
   DIC_FLAG_DETERMINISTIC_BWD = 1u << 2, /* grad_def accumulated in a fixed
                                          order (no float atomics)            */
-  DIC_FLAG_REFINE_NR = 1u << 3        /* dic_correlate (and the autotuner)
+  DIC_FLAG_REFINE_NR = 1u << 3,       /* dic_correlate (and the autotuner)
                                          refine with Newton-Raphson instead
                                          of IC-GN                            */
+  DIC_FLAG_INTERP_BILINEAR = 1u << 4  /* IC-GN and Newton-Raphson interpolate
+                                         g bilinearly (Eq. (5), 2x2 taps,
+                                         out of bounds when a 2x2
+                                         neighbourhood leaves the image)
+                                         instead of bicubically; FP32
+                                         batched plans only; the ZNSSD
+                                         adjoint rejects such plans         */
 };
 
 typedef struct {

@@ -2,7 +2,8 @@
 ZNCC integer searches, IC-GN and Newton-Raphson sub-pixel refinement and the
 ZNSSD adjoint, as HIP kernels behind the C ABI in include/dic.h (libdic.so),
 with a thin ctypes binding."""
-from .dic import (FLAG_CACHE_REF_PREP, FLAG_DETERMINISTIC_BWD, FLAG_REFINE_NR, FLAG_USE_GRAPH,  # noqa: F401
+from .dic import (FLAG_CACHE_REF_PREP, FLAG_DETERMINISTIC_BWD, FLAG_INTERP_BILINEAR,  # noqa: F401
+                  FLAG_REFINE_NR, FLAG_USE_GRAPH,
                   FP32_BATCHED, FP64_PLAIN, POI_NAN_INPUT, POI_NO_VALID_CANDIDATE,
                   PSO_GENERATIONS, PSO_PARTICLES,
                   POI_NOT_CONVERGED, POI_OK, POI_OUT_OF_BOUNDS, POI_SINGULAR_HESSIAN,

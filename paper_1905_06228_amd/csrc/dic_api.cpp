@@ -89,6 +89,7 @@ struct dic_plan_s {
   bool fp32() const { return desc.precision == DIC_FP32_BATCHED; }
   bool det() const { return (desc.flags & DIC_FLAG_DETERMINISTIC_BWD) != 0; }
   bool nr() const { return (desc.flags & DIC_FLAG_REFINE_NR) != 0; }
+  bool bilinear() const { return (desc.flags & DIC_FLAG_INTERP_BILINEAR) != 0; }
 };
 
 namespace {
@@ -227,10 +228,10 @@ dic_status_t enqueue_refine(dic_plan_t p, const float* ref, const float* def, co
     DIC_HIP(launch_reset_counters(p->st, s));
     if (nr)
       DIC_HIP(launch_nr_f32(p->st, p->tuning, def, poi, uv, status_in, p_init, p_out, zn, iters,
-                            status, p->num_cu, s));
+                            status, p->num_cu, s, p->bilinear()));
     else
       DIC_HIP(launch_icgn_f32(p->st, p->tuning, ref, def, poi, uv, status_in, p_init, p_out, zn,
-                              iters, status, p->num_cu, s));
+                              iters, status, p->num_cu, s, p->bilinear()));
   } else if (nr) {
     DIC_HIP(launch_nr_f64(p->st, p->dpairs.data(), ref, def, poi, uv, status_in, p_init, p_out,
                           zn, iters, status, s));
@@ -293,8 +294,11 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
   if (!(d->conv_tol > 0.0) || !std::isfinite(d->conv_tol))
     return fail(DIC_ERR_INVALID_ARGUMENT, "conv_tol must be positive and finite");
   const uint32_t known = DIC_FLAG_USE_GRAPH | DIC_FLAG_CACHE_REF_PREP |
-                         DIC_FLAG_DETERMINISTIC_BWD | DIC_FLAG_REFINE_NR;
+                         DIC_FLAG_DETERMINISTIC_BWD | DIC_FLAG_REFINE_NR |
+                         DIC_FLAG_INTERP_BILINEAR;
   if (d->flags & ~known) return fail(DIC_ERR_INVALID_ARGUMENT, "unknown flag bits");
+  if ((d->flags & DIC_FLAG_INTERP_BILINEAR) && d->precision != DIC_FP32_BATCHED)
+    return fail(DIC_ERR_UNSUPPORTED, "bilinear interpolation needs the FP32 batched form");
   auto p = new dic_plan_s();
   p->desc = *d;
   p->pairs.assign(d->pairs, d->pairs + d->num_pairs);
@@ -644,6 +648,8 @@ dic_status_t dic_znssd_backward(dic_plan_t p, const float* ref, const float* def
   if (r) return r;
   if (p->N == 0) return DIC_SUCCESS;
   if (!ref || !def || !poi || !pw) return fail(DIC_ERR_INVALID_ARGUMENT, "null required pointer");
+  if (p->bilinear())
+    return fail(DIC_ERR_UNSUPPORTED, "the ZNSSD adjoint interpolates bicubically only");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   r = prepare(p, ref, poi, s, false);
   if (r) return r;

@@ -118,11 +118,11 @@ hipError_t launch_icgn_f32(const DevState& st, const dic_tuning_t& tu, const flo
                            const float* def, const int32_t* poi, const int32_t* uv_init,
                            const int32_t* status_in, const double* p_init, double* p_out,
                            float* zncc, int32_t* iters, int32_t* status, int num_cu,
-                           hipStream_t s);
+                           hipStream_t s, bool bilinear);
 hipError_t launch_nr_f32(const DevState& st, const dic_tuning_t& tu, const float* def,
                          const int32_t* poi, const int32_t* uv_init, const int32_t* status_in,
                          const double* p_init, double* p_out, float* zncc, int32_t* iters,
-                         int32_t* status, int num_cu, hipStream_t s);
+                         int32_t* status, int num_cu, hipStream_t s, bool bilinear);
 hipError_t launch_nr_f64(const DevState& st, const DevPair* host_pairs, const float* ref,
                          const float* def, const int32_t* poi, const int32_t* uv_init,
                          const int32_t* status_in, const double* p_init, double* p_out,

@@ -48,7 +48,7 @@ __device__ __forceinline__ void iter_pass(const Smp& smp, int n, const Warp32& w
 
 }  // namespace
 
-template <int MAXS>
+template <int MAXS, int NT>
 __global__ void __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
     DevState st, int slack, const float* __restrict__ def, const int32_t* __restrict__ poi,
@@ -99,16 +99,16 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
         ++it;
         const Warp32 w = make_warp32(p, x0, y0);
         int xl, xh, yl, yh;
-        tap_box(w, M, xl, xh, yl, yh);
+        tap_box<NT>(w, M, xl, xh, yl, yh);
         if (xl < 0 || xh > W - 1 || yl < 0 || yh > H - 1) {
           status = DIC_POI_OUT_OF_BOUNDS;
           break;
         }
         float K[8];
         if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
-          iter_pass<MAXS>(patch.sampler(w.bx, w.by), n, w, fxs, fys, dxy, K);
+          iter_pass<MAXS>(patch.template sampler<NT>(w.bx, w.by), n, w, fxs, fys, dxy, K);
         else
-          iter_pass<MAXS>(ImageSampler{gimg, W, w.bx, w.by, W - 4, H - 4, c0}, n, w, fxs, fys,
+          iter_pass<MAXS>(ImageSampler<NT>{gimg, W, H, w.bx, w.by, c0}, n, w, fxs, fys,
                           dxy, K);
         double S[8];
         wave_sums_f32<8>(K, S);
@@ -137,7 +137,7 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
       if (status == DIC_POI_OK || status == DIC_POI_NOT_CONVERGED) {
         const Warp32 w = make_warp32(p, x0, y0);
         int xl, xh, yl, yh;
-        tap_box(w, M, xl, xh, yl, yh);
+        tap_box<NT>(w, M, xl, xh, yl, yh);
         if (xl < 0 || xh > W - 1 || yl < 0 || yh > H - 1) {
           status = DIC_POI_OUT_OF_BOUNDS;
         } else {
@@ -149,9 +149,9 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
           };
           float K[3];
           if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
-            final_pass<MAXS>(patch.sampler(w.bx, w.by), n, w, dxy, tval, K);
+            final_pass<MAXS>(patch.template sampler<NT>(w.bx, w.by), n, w, dxy, tval, K);
           else
-            final_pass<MAXS>(ImageSampler{gimg, W, w.bx, w.by, W - 4, H - 4, c0}, n, w, dxy,
+            final_pass<MAXS>(ImageSampler<NT>{gimg, W, H, w.bx, w.by, c0}, n, w, dxy,
                              tval, K);
           double S[3];
           wave_sums_f32<3>(K, S);
@@ -179,7 +179,7 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
   }
 }
 
-template <int MAXS>
+template <int MAXS, int NT>
 static hipError_t launch_icgn_f32_t(const DevState& st, const dic_tuning_t& tu, const float* def,
                                     const int32_t* poi, const int32_t* uv_init,
                                     const int32_t* status_in, const double* p_init, double* p_out,
@@ -189,19 +189,19 @@ static hipError_t launch_icgn_f32_t(const DevState& st, const dic_tuning_t& tu, 
   const size_t lds = refine_lds_bytes(refine_patch_pitch(MAXS),
                                       icgn_patch_side(st.maxM, tu.icgn_slack), tu.icgn_waves);
   if (lds > 65536) {
-    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&icgn_f32_kernel<MAXS>),
+    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&icgn_f32_kernel<MAXS, NT>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ea != hipSuccess) return ea;
   }
   int occ = 0;
   hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, icgn_f32_kernel<MAXS>, threads, lds);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, icgn_f32_kernel<MAXS, NT>, threads, lds);
   if (e != hipSuccess) return e;
   if (occ < 1) return hipErrorInvalidConfiguration;
   int64_t blocks = (int64_t)occ * num_cu;
   const int64_t need = (st.N + tu.icgn_waves - 1) / tu.icgn_waves;
   if (blocks > need) blocks = need;
-  hipLaunchKernelGGL(icgn_f32_kernel<MAXS>, dim3((unsigned)blocks), dim3(threads), lds, s, st,
+  hipLaunchKernelGGL((icgn_f32_kernel<MAXS, NT>), dim3((unsigned)blocks), dim3(threads), lds, s, st,
                      tu.icgn_slack, def, poi, uv_init, status_in, p_init, p_out, zncc, iters,
                      status);
   return hipGetLastError();
@@ -211,14 +211,16 @@ hipError_t launch_icgn_f32(const DevState& st, const dic_tuning_t& tu, const flo
                            const float* def, const int32_t* poi, const int32_t* uv_init,
                            const int32_t* status_in, const double* p_init, double* p_out,
                            float* zncc, int32_t* iters, int32_t* status, int num_cu,
-                           hipStream_t s) {
+                           hipStream_t s, bool bilinear) {
   if (st.N == 0) return hipSuccess;
   const int n = (2 * st.maxM + 1) * (2 * st.maxM + 1);
   const int need = (n + kWave - 1) / kWave;
 #define DIC_ICGN_CASE(S_)                                                                       \
   if (need <= S_)                                                                               \
-    return launch_icgn_f32_t<S_>(st, tu, def, poi, uv_init, status_in, p_init, p_out, zncc, iters, \
-                                 status, num_cu, s);
+    return bilinear ? launch_icgn_f32_t<S_, 2>(st, tu, def, poi, uv_init, status_in, p_init, p_out, \
+                                               zncc, iters, status, num_cu, s)                     \
+                    : launch_icgn_f32_t<S_, 4>(st, tu, def, poi, uv_init, status_in, p_init, p_out, \
+                                               zncc, iters, status, num_cu, s);
   DIC_ICGN_CASE(4)
   DIC_ICGN_CASE(8)
   DIC_ICGN_CASE(12)

@@ -1,8 +1,9 @@
 // Pieces shared by the sub-pixel refinements of Sec. 2.2 (IC-GN and
 // Newton-Raphson, FP32 batched forms): the first-order warp in FP32 local
 // form, the bounding box of the taps it touches, the per-wave LDS patch of
-// the deformed image, Keys bicubic interpolation from that patch or from the
-// image, and the final pass that evaluates Eq. (1) at the converged warp.
+// the deformed image, interpolation from that patch or from the image (Keys
+// bicubic, NT = 4 taps per direction, or Eq. (5)'s bilinear, NT = 2), and the
+// final pass that evaluates Eq. (1) at the converged warp.
 //
 // Sample layout: lane l holds samples s = l + 64 k (slot k) of the subset in
 // row-major order; slots below n / 64 are full, the next one is partial and
@@ -74,9 +75,10 @@ __device__ __forceinline__ float warp_y(const Warp32& w, float dx, float dy) {
   return fmaf(w.vx, dx, fmaf(w.ay, dy, w.vf));
 }
 
-// Bounding box (absolute pixel indices) of every 4x4 neighbourhood the
-// warped subset touches; extremes of an affine map over a square are at its
-// corners.
+// Bounding box (absolute pixel indices) of every NT x NT neighbourhood the
+// warped subset touches (bicubic: floor - 1 .. floor + 2, bilinear: floor ..
+// floor + 1); extremes of an affine map over a square are at its corners.
+template <int NT>
 __device__ __forceinline__ void tap_box(const Warp32& w, int M, int& x_lo, int& x_hi, int& y_lo,
                                         int& y_hi) {
   float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
@@ -91,10 +93,11 @@ __device__ __forceinline__ void tap_box(const Warp32& w, int M, int& x_lo, int& 
       ymn = fminf(ymn, ys);
       ymx = fmaxf(ymx, ys);
     }
-  x_lo = w.bx + (int)floorf(xmn) - 1;
-  x_hi = w.bx + (int)floorf(xmx) + 2;
-  y_lo = w.by + (int)floorf(ymn) - 1;
-  y_hi = w.by + (int)floorf(ymx) + 2;
+  constexpr int lo = NT == 4 ? 1 : 0, hi = NT == 4 ? 2 : 1;
+  x_lo = w.bx + (int)floorf(xmn) - lo;
+  x_hi = w.bx + (int)floorf(xmx) + hi;
+  y_lo = w.by + (int)floorf(ymn) - lo;
+  y_hi = w.by + (int)floorf(ymx) + hi;
 }
 
 // Keys weights (a = -1/2) of taps -1, 0, 1, 2 at fractional offset t; with
@@ -119,10 +122,32 @@ __device__ __forceinline__ void keys_dweights32(float t, float* w) {
   w[2] = -((w[0] + w[1]) + w[3]);
 }
 
+// Interpolation weights of NT taps at fractional offset t: Keys (taps -1..2)
+// or Eq. (5)'s bilinear (taps 0, 1: G = a00 + a10 x' + ... is the weighted
+// sum (1 - x') g0 + x' g1 along each direction).
+template <int NT>
+__device__ __forceinline__ void interp_weights(float t, float* w) {
+  if constexpr (NT == 4) {
+    keys_weights32(t, w);
+  } else {
+    w[0] = 1.f - t;
+    w[1] = t;
+  }
+}
+template <int NT>
+__device__ __forceinline__ void interp_dweights(float t, float* w) {
+  if constexpr (NT == 4) {
+    keys_dweights32(t, w);
+  } else {
+    w[0] = -1.f;
+    w[1] = 1.f;
+  }
+}
+
 // Interpolation of one sample at local offset (xs, ys) from the integer
 // base.  PatchSampler reads a wave's LDS patch, which holds g - c0; q0
 // addresses its element at offset (-1, -1) from the base.
-template <int P>
+template <int P, int NT = 4>
 struct PatchSampler {
   const float* q0;
 
@@ -131,22 +156,25 @@ struct PatchSampler {
     const float fx = floorf(xs), fy = floorf(ys);
     tx = xs - fx;
     ty = ys - fy;
-    keys_weights32(tx, wx);
-    keys_weights32(ty, wy);
-    return q0 + (__mul24((int)fy, P) + (int)fx);
+    interp_weights<NT>(tx, wx);
+    interp_weights<NT>(ty, wy);
+    constexpr int first = NT == 4 ? 0 : P + 1;   // the 2x2 neighbourhood starts at (0, 0)
+    return q0 + (first + __mul24((int)fy, P) + (int)fx);
   }
   static constexpr int pitch() { return P; }
+  static constexpr int ntaps() { return NT; }
   __device__ __forceinline__ float tap(const float* q) const { return *q; }
 };
 
 // The same from the deformed image itself (row pitch W), each tap centred as
 // the patch stores it (g - c0 in FP32), so both paths give the same bits; the
-// 4x4 neighbourhood origin is clamped into the image: the tap box test
-// already keeps it there, the clamp only guards the reads of a degenerate
-// warp.
+// NT x NT neighbourhood origin is clamped to [0, W - NT] x [0, H - NT]: the
+// tap box test already keeps it there, the clamp only guards the reads of a
+// degenerate warp.
+template <int NT = 4>
 struct ImageSampler {
   const float* img;
-  int W, bx, by, maxc, maxr;
+  int W, H, bx, by;
   float c0;
 
   __device__ __forceinline__ const float* taps(float xs, float ys, float* wx, float* wy,
@@ -154,28 +182,32 @@ struct ImageSampler {
     const float fx = floorf(xs), fy = floorf(ys);
     tx = xs - fx;
     ty = ys - fy;
-    keys_weights32(tx, wx);
-    keys_weights32(ty, wy);
-    const int c = min(max(bx + (int)fx - 1, 0), maxc), r = min(max(by + (int)fy - 1, 0), maxr);
+    interp_weights<NT>(tx, wx);
+    interp_weights<NT>(ty, wy);
+    constexpr int lo = NT == 4 ? 1 : 0;
+    const int c = min(max(bx + (int)fx - lo, 0), W - NT);
+    const int r = min(max(by + (int)fy - lo, 0), H - NT);
     return img + (int64_t)r * W + c;
   }
   __device__ __forceinline__ int pitch() const { return W; }
+  static constexpr int ntaps() { return NT; }
   __device__ __forceinline__ float tap(const float* q) const { return *q - c0; }
 };
 
 // g - c0 at local offset (xs, ys).
 template <class Smp>
 __device__ __forceinline__ float sample_value(const Smp& smp, float xs, float ys) {
-  float wx[4], wy[4], tx, ty;
+  constexpr int NT = Smp::ntaps();
+  float wx[NT], wy[NT], tx, ty;
   const float* q = smp.taps(xs, ys, wx, wy, tx, ty);
   const int P = smp.pitch();
   float acc = 0.f;
 #pragma unroll
-  for (int l = 0; l < 4; ++l) {
+  for (int l = 0; l < NT; ++l) {
     const float* row = q + l * P;
-    const float r =
-        fmaf(wx[3], smp.tap(row + 3),
-             fmaf(wx[2], smp.tap(row + 2), fmaf(wx[1], smp.tap(row + 1), wx[0] * smp.tap(row))));
+    float r = wx[0] * smp.tap(row);
+#pragma unroll
+    for (int k = 1; k < NT; ++k) r = fmaf(wx[k], smp.tap(row + k), r);
     acc = l == 0 ? wy[0] * r : fmaf(wy[l], r, acc);
   }
   return acc;
@@ -185,19 +217,24 @@ __device__ __forceinline__ float sample_value(const Smp& smp, float xs, float ys
 template <class Smp>
 __device__ __forceinline__ void sample_value_grad(const Smp& smp, float xs, float ys, float& v,
                                                   float& gx, float& gy) {
-  float wx[4], wy[4], tx, ty, dwx[4], dwy[4];
+  constexpr int NT = Smp::ntaps();
+  float wx[NT], wy[NT], tx, ty, dwx[NT], dwy[NT];
   const float* q = smp.taps(xs, ys, wx, wy, tx, ty);
-  keys_dweights32(tx, dwx);
-  keys_dweights32(ty, dwy);
+  interp_dweights<NT>(tx, dwx);
+  interp_dweights<NT>(ty, dwy);
   const int P = smp.pitch();
 #pragma unroll
-  for (int l = 0; l < 4; ++l) {
+  for (int l = 0; l < NT; ++l) {
     const float* row = q + l * P;
-    float t[4];
+    float t[NT];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) t[c] = smp.tap(row + c);
-    const float r = fmaf(wx[3], t[3], fmaf(wx[2], t[2], fmaf(wx[1], t[1], wx[0] * t[0])));
-    const float rd = fmaf(dwx[3], t[3], fmaf(dwx[2], t[2], fmaf(dwx[1], t[1], dwx[0] * t[0])));
+    for (int c = 0; c < NT; ++c) t[c] = smp.tap(row + c);
+    float r = wx[0] * t[0], rd = dwx[0] * t[0];
+#pragma unroll
+    for (int c = 1; c < NT; ++c) {
+      r = fmaf(wx[c], t[c], r);
+      rd = fmaf(dwx[c], t[c], rd);
+    }
     v = l == 0 ? wy[0] * r : fmaf(wy[l], r, v);
     gx = l == 0 ? wy[0] * rd : fmaf(wy[l], rd, gx);
     gy = l == 0 ? dwy[0] * r : fmaf(dwy[l], r, gy);
@@ -312,8 +349,9 @@ struct LdsPatch {
   }
 
   // Sampler for a warp whose integer base is (bx, by).
-  __device__ __forceinline__ PatchSampler<P> sampler(int bx, int by) const {
-    return PatchSampler<P>{buf + (by - y0 - 1) * P + (bx - x0 - 1)};
+  template <int NT>
+  __device__ __forceinline__ PatchSampler<P, NT> sampler(int bx, int by) const {
+    return PatchSampler<P, NT>{buf + (by - y0 - 1) * P + (bx - x0 - 1)};
   }
 };
 
