@@ -284,6 +284,29 @@ def main() -> int:
                      "bicubic_mean_abs_error_px": float(ec.mean()) if okc.any() else None,
                      "p99_abs_error_px": float(np.percentile(eb.max(axis=1), 99)) if okb.any() else None,
                      "bicubic_p99_abs_error_px": float(np.percentile(ec.max(axis=1), 99)) if okc.any() else None}
+    # the bicubic coefficient table (look-up table of the interpolant): the
+    # refinements without (cached table) and with the table build
+    lut = {}
+    for name, nrf in (("icgn", False), ("nr", True)):
+        lo = tuple(torch.empty_like(x) for x in (so["p"], so["zncc"], so["iters"], so["status"]))
+        t_l = {}
+        for cached in (True, False):
+            lp = dic.single_pair_plan(W, H, pair.M, pair.S, N, dic.FP32_BATCHED,
+                                      flags=dic.FLAG_BICUBIC_LUT
+                                      | (dic.FLAG_CACHE_REF_PREP if cached else 0))
+            lp.tuning = plan.tuning
+            fn = lp.nr_refine if nrf else lp.icgn_refine
+            t_l[cached] = time_launches(
+                torch, lambda: fn(F, G, Q, so["uv"], so["status_int"], out=lo), reps)
+        lpn, lst = lo[0].cpu().numpy(), lo[3].cpu().numpy()
+        cp, cst = ref_err[name][0].cpu().numpy(), ref_err[name][1].cpu().numpy()
+        okl = (lst == 0) & (cst == 0)
+        lut[name] = {"refine_ms": round(t_l[True], 4),
+                     "refine_with_table_build_ms": round(t_l[False], 4),
+                     "taps_refine_ms": round(t_icgn if name == "icgn" else t_nr, 4),
+                     "max_vs_taps_px": float(np.abs(lpn[okl][:, [0, 3]] - cp[okl][:, [0, 3]]
+                                                    ).max(initial=0)),
+                     "status_equal_to_taps": float((lst == cst).mean())}
     # particle swarm searches (Sec. 2.1, Eqs. 2-4) on the same pair, and the
     # modified swarm + Newton-Raphson pipeline (the paper's fastest combination)
     Rs = torch.from_numpy(dicgen.swarm_random(N, 7)).to(dev)
@@ -409,6 +432,7 @@ def main() -> int:
         },
         "particle_swarm": swarm,
         "bilinear": bil,
+        "bicubic_lut": lut,
     }
     if args.copy_probe_mb > 0:
         n = args.copy_probe_mb * (1 << 20) // 4

@@ -92,13 +92,25 @@ enum {
   DIC_FLAG_REFINE_NR = 1u << 3,       /* dic_correlate (and the autotuner)
                                          refine with Newton-Raphson instead
                                          of IC-GN                            */
-  DIC_FLAG_INTERP_BILINEAR = 1u << 4  /* IC-GN and Newton-Raphson interpolate
+  DIC_FLAG_INTERP_BILINEAR = 1u << 4, /* IC-GN and Newton-Raphson interpolate
                                          g bilinearly (Eq. (5), 2x2 taps,
                                          out of bounds when a 2x2
                                          neighbourhood leaves the image)
                                          instead of bicubically; FP32
                                          batched plans only; the ZNSSD
                                          adjoint rejects such plans         */
+  DIC_FLAG_BICUBIC_LUT = 1u << 5      /* IC-GN and Newton-Raphson evaluate
+                                         the bicubic interpolant from a
+                                         table of its 16 polynomial
+                                         coefficients per pixel cell (the
+                                         look-up tables of Sec. 2.2), built
+                                         from each deformed image before the
+                                         refinement (64 bytes per pixel of
+                                         workspace), instead of from 4x4
+                                         taps; same interpolant and bounds
+                                         up to FP32 rounding.  FP32 batched
+                                         plans only; exclusive with
+                                         DIC_FLAG_INTERP_BILINEAR           */
 };
 
 typedef struct {
@@ -185,11 +197,12 @@ dic_status_t dic_prepare_reference(dic_plan_t plan, const float* ref_images,
 
 /* Deformed-side precomputation for the FP32 search: for every subset centre
  * of every deformed image, the exact (FP64) sums of g and g^2 over the
- * subset, so each candidate's normalisation is a lookup.  Called implicitly
- * by dic_integer_search / dic_correlate unless DIC_FLAG_CACHE_REF_PREP holds
- * a valid cache for this `def_images` pointer (then call it again, or
- * dic_plan_invalidate_reference, after changing the images in place).  A
- * no-op for the FP64 plain form. */
+ * subset, so each candidate's normalisation is a lookup; with
+ * DIC_FLAG_BICUBIC_LUT also the bicubic coefficient table.  Called
+ * implicitly by dic_integer_search / dic_correlate (the table by the
+ * refinements) unless DIC_FLAG_CACHE_REF_PREP holds a valid cache for this
+ * `def_images` pointer (then call it again, or dic_plan_invalidate_reference,
+ * after changing the images in place).  A no-op for the FP64 plain form. */
 dic_status_t dic_prepare_deformed(dic_plan_t plan, const float* def_images,
                                   dic_stream_t stream);
 

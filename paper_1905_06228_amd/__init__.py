@@ -2,7 +2,8 @@
 ZNCC integer searches, IC-GN and Newton-Raphson sub-pixel refinement and the
 ZNSSD adjoint, as HIP kernels behind the C ABI in include/dic.h (libdic.so),
 with a thin ctypes binding."""
-from .dic import (FLAG_CACHE_REF_PREP, FLAG_DETERMINISTIC_BWD, FLAG_INTERP_BILINEAR,  # noqa: F401
+from .dic import (FLAG_BICUBIC_LUT, FLAG_CACHE_REF_PREP, FLAG_DETERMINISTIC_BWD,  # noqa: F401
+                  FLAG_INTERP_BILINEAR,
                   FLAG_REFINE_NR, FLAG_USE_GRAPH,
                   FP32_BATCHED, FP64_PLAIN, POI_NAN_INPUT, POI_NO_VALID_CANDIDATE,
                   PSO_GENERATIONS, PSO_PARTICLES,

@@ -38,7 +38,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t pairs = 0, poi_pair = 0, work = 0, counters = 0, grads = 0, recs = 0, tmpl = 0,
-         box = 0, fix_off = 0, fix = 0, s_status = 0, s_zncc = 0, total = 0;
+         box = 0, lut = 0, fix_off = 0, fix = 0, s_status = 0, s_zncc = 0, total = 0;
   int64_t fix_count = 0;
 };
 
@@ -82,6 +82,8 @@ struct dic_plan_s {
   const void* ref_poi = nullptr;
   bool def_valid = false;
   const void* def_img = nullptr;
+  bool lut_valid = false;
+  const void* lut_img = nullptr;
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
   std::vector<hipGraph_t> graph_objs;
   hipStream_t cap_stream = nullptr;
@@ -90,6 +92,10 @@ struct dic_plan_s {
   bool det() const { return (desc.flags & DIC_FLAG_DETERMINISTIC_BWD) != 0; }
   bool nr() const { return (desc.flags & DIC_FLAG_REFINE_NR) != 0; }
   bool bilinear() const { return (desc.flags & DIC_FLAG_INTERP_BILINEAR) != 0; }
+  bool lut() const { return (desc.flags & DIC_FLAG_BICUBIC_LUT) != 0; }
+  int interp() const {
+    return bilinear() ? kInterpBilinear : lut() ? kInterpBicubicLut : kInterpBicubic;
+  }
 };
 
 namespace {
@@ -199,6 +205,18 @@ dic_status_t prepare_deformed(dic_plan_t p, const float* def, hipStream_t s, boo
   return DIC_SUCCESS;
 }
 
+// The bicubic coefficient table of the deformed images (plans with
+// DIC_FLAG_BICUBIC_LUT), cached like the box sums.
+dic_status_t prepare_lut(dic_plan_t p, const float* def, hipStream_t s, bool force) {
+  if (!p->lut()) return DIC_SUCCESS;
+  if (!force && (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->lut_valid && p->lut_img == def)
+    return DIC_SUCCESS;
+  DIC_HIP(launch_bicubic_lut(p->st, def, s));
+  p->lut_valid = true;
+  p->lut_img = def;
+  return DIC_SUCCESS;
+}
+
 dic_status_t enqueue_search(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
                             const int32_t* seed, int32_t* uv, float* zn, int32_t* status,
                             hipStream_t s) {
@@ -225,13 +243,15 @@ dic_status_t enqueue_refine(dic_plan_t p, const float* ref, const float* def, co
                             double* p_out, float* zn, int32_t* iters, int32_t* status,
                             hipStream_t s, bool nr) {
   if (p->fp32()) {
+    dic_status_t r = prepare_lut(p, def, s, false);
+    if (r) return r;
     DIC_HIP(launch_reset_counters(p->st, s));
     if (nr)
       DIC_HIP(launch_nr_f32(p->st, p->tuning, def, poi, uv, status_in, p_init, p_out, zn, iters,
-                            status, p->num_cu, s, p->bilinear()));
+                            status, p->num_cu, s, p->interp()));
     else
       DIC_HIP(launch_icgn_f32(p->st, p->tuning, ref, def, poi, uv, status_in, p_init, p_out, zn,
-                              iters, status, p->num_cu, s, p->bilinear()));
+                              iters, status, p->num_cu, s, p->interp()));
   } else if (nr) {
     DIC_HIP(launch_nr_f64(p->st, p->dpairs.data(), ref, def, poi, uv, status_in, p_init, p_out,
                           zn, iters, status, s));
@@ -295,10 +315,15 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
     return fail(DIC_ERR_INVALID_ARGUMENT, "conv_tol must be positive and finite");
   const uint32_t known = DIC_FLAG_USE_GRAPH | DIC_FLAG_CACHE_REF_PREP |
                          DIC_FLAG_DETERMINISTIC_BWD | DIC_FLAG_REFINE_NR |
-                         DIC_FLAG_INTERP_BILINEAR;
+                         DIC_FLAG_INTERP_BILINEAR | DIC_FLAG_BICUBIC_LUT;
   if (d->flags & ~known) return fail(DIC_ERR_INVALID_ARGUMENT, "unknown flag bits");
   if ((d->flags & DIC_FLAG_INTERP_BILINEAR) && d->precision != DIC_FP32_BATCHED)
     return fail(DIC_ERR_UNSUPPORTED, "bilinear interpolation needs the FP32 batched form");
+  if ((d->flags & DIC_FLAG_BICUBIC_LUT) && d->precision != DIC_FP32_BATCHED)
+    return fail(DIC_ERR_UNSUPPORTED, "the bicubic coefficient table needs the FP32 batched form");
+  if ((d->flags & DIC_FLAG_BICUBIC_LUT) && (d->flags & DIC_FLAG_INTERP_BILINEAR))
+    return fail(DIC_ERR_INVALID_ARGUMENT,
+                "DIC_FLAG_BICUBIC_LUT and DIC_FLAG_INTERP_BILINEAR are exclusive");
   auto p = new dic_plan_s();
   p->desc = *d;
   p->pairs.assign(d->pairs, d->pairs + d->num_pairs);
@@ -340,7 +365,8 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
   L.poi_pair = take(sizeof(int32_t) * p->N);
   L.work = take(sizeof(int32_t) * p->N);
   L.counters = take(sizeof(int32_t) * kNumCounters);
-  int64_t gfl = 0, tfl = 0, bxd = 0, fix = 0;
+  int64_t gfl = 0, tfl = 0, bxd = 0, lut4 = 0, fix = 0;
+  const bool use_lut = (d->flags & DIC_FLAG_BICUBIC_LUT) != 0;
   p->dpairs.resize(d->num_pairs);
   p->fix_off.resize(d->num_pairs);
   for (int k = 0; k < d->num_pairs; ++k) {
@@ -359,11 +385,13 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
     P.tmpl_pitch = template_pitch(q.subset_radius);
     P.pad_ = 0;
     P.box_off = bxd;
+    P.lut_off = lut4;
     const int64_t tn = (int64_t)(2 * q.subset_radius + 1) * P.tmpl_pitch;
     if (f32) {
       gfl += 2 * (int64_t)q.width * q.height;
       tfl += q.poi_count * tn;
       bxd += 5 * (int64_t)q.width * q.height;
+      if (use_lut) lut4 += 4 * (int64_t)q.width * q.height;
     }
     p->fix_off[k] = fix;
     if (p->det()) fix += (int64_t)q.width * q.height;
@@ -376,6 +404,7 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
   L.recs = take(sizeof(RefRec) * p->N);
   L.tmpl = take(sizeof(float) * tfl);
   L.box = take(sizeof(double) * bxd);
+  L.lut = take(sizeof(float) * 4 * lut4);
   L.fix_off = take(sizeof(int64_t) * d->num_pairs);
   L.fix = take(sizeof(unsigned long long) * fix);
   L.fix_count = fix;
@@ -473,6 +502,7 @@ dic_status_t dic_plan_bind(dic_plan_t p, void* ws, size_t bytes, dic_stream_t st
   st.recs = reinterpret_cast<RefRec*>(base + p->lay.recs);
   st.tmpl = reinterpret_cast<float*>(base + p->lay.tmpl);
   st.box = reinterpret_cast<double*>(base + p->lay.box);
+  st.lut = reinterpret_cast<float*>(base + p->lay.lut);
   st.N = p->N;
   st.num_pairs = p->desc.num_pairs;
   st.maxM = p->maxM;
@@ -485,6 +515,7 @@ dic_status_t dic_plan_bind(dic_plan_t p, void* ws, size_t bytes, dic_stream_t st
   p->bound = true;
   p->ref_valid = false;
   p->def_valid = false;
+  p->lut_valid = false;
   drop_graphs(p);
   if (const char* path = std::getenv("DIC_AUTOTUNE_CACHE")) {
     auto m = read_tune_cache(path);
@@ -503,6 +534,7 @@ dic_status_t dic_plan_invalidate_reference(dic_plan_t p) {
   if (r) return r;
   p->ref_valid = false;
   p->def_valid = false;
+  p->lut_valid = false;
   drop_graphs(p);
   return DIC_SUCCESS;
 }
@@ -519,7 +551,10 @@ dic_status_t dic_prepare_deformed(dic_plan_t p, const float* def, dic_stream_t s
   dic_status_t r = check_plan(p, true);
   if (r) return r;
   if (!def) return fail(DIC_ERR_INVALID_ARGUMENT, "null image pointer");
-  return prepare_deformed(p, def, reinterpret_cast<hipStream_t>(stream), true);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  r = prepare_deformed(p, def, s, true);
+  if (r) return r;
+  return prepare_lut(p, def, s, true);
 }
 
 dic_status_t dic_integer_search(dic_plan_t p, const float* ref, const float* def,
@@ -610,7 +645,8 @@ dic_status_t dic_correlate(dic_plan_t p, const float* ref, const float* def, con
   if (!(p->desc.flags & DIC_FLAG_USE_GRAPH)) return enqueue_correlate(p, a, s);
   const bool cached_ref = (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->ref_valid &&
                           p->ref_img == ref && p->ref_poi == poi && p->def_valid &&
-                          p->def_img == def;
+                          p->def_img == def &&
+                          (!p->lut() || (p->lut_valid && p->lut_img == def));
   std::vector<uintptr_t> key = {
       (uintptr_t)ref, (uintptr_t)def, (uintptr_t)poi, (uintptr_t)seed, (uintptr_t)p_init,
       (uintptr_t)uv, (uintptr_t)a.zn_int, (uintptr_t)a.st_int, (uintptr_t)p_out, (uintptr_t)zn,

@@ -19,6 +19,14 @@ constexpr int kPsoStar = 5;            // positions per particle and generation,
 constexpr double kPsoC1 = 2.0, kPsoC2 = 2.0;
 constexpr double kPsoStopCC = 0.995;
 
+// Interpolation of the deformed image in the FP32 refinements.
+enum Interp : int {
+  kInterpBicubic = 0,     // Keys taps from the LDS patch (or the image)
+  kInterpBilinear = 1,    // Eq. (5), 2x2 taps from the LDS patch (or the image)
+  kInterpBicubicLut = 2,  // Keys interpolant from the per-cell coefficient table
+};
+__host__ __device__ constexpr int interp_taps(int im) { return im == kInterpBilinear ? 2 : 4; }
+
 // Device copy of a pair description plus derived offsets.
 struct DevPair {
   int32_t width, height, M, S;
@@ -32,6 +40,8 @@ struct DevPair {
   int64_t box_off;   // double offset of this pair's five [H, W] box-sum planes:
                      // column sums of g and g^2, subset sums of g and g^2, and
                      // float pairs (subset mean, 1/sqrt(sum (g - mean)^2))
+  int64_t lut_off;   // float4 offset of this pair's [H, W, 4] bicubic coefficient
+                     // table (plans with DIC_FLAG_BICUBIC_LUT only)
 };
 
 __host__ __device__ __forceinline__ int template_pitch(int M) { return (2 * M + 1 + 7) / 8 * 8; }
@@ -59,6 +69,7 @@ struct DevState {
   RefRec* recs;             // [N]
   float* tmpl;              // template arena
   double* box;              // box-sum arena (deformed images)
+  float* lut;               // bicubic coefficient tables (deformed images), 16 floats per pixel
   int64_t N;
   int32_t num_pairs;
   int32_t maxM, maxS;
@@ -81,6 +92,7 @@ struct SearchGroup {
 hipError_t launch_reset_counters(const DevState& st, hipStream_t s);
 hipError_t launch_gradients(const DevState& st, const float* ref, hipStream_t s);
 hipError_t launch_box_sums(const DevState& st, const float* def, hipStream_t s);
+hipError_t launch_bicubic_lut(const DevState& st, const float* def, hipStream_t s);
 hipError_t launch_pso(const DevState& st, bool modified, const float* ref, const float* def,
                       const int32_t* poi, const int32_t* seed, const float* rand, int32_t* uv,
                       float* zn, int32_t* status, int32_t* gens, int32_t* evals, int num_cu,
@@ -118,11 +130,11 @@ hipError_t launch_icgn_f32(const DevState& st, const dic_tuning_t& tu, const flo
                            const float* def, const int32_t* poi, const int32_t* uv_init,
                            const int32_t* status_in, const double* p_init, double* p_out,
                            float* zncc, int32_t* iters, int32_t* status, int num_cu,
-                           hipStream_t s, bool bilinear);
+                           hipStream_t s, int interp);
 hipError_t launch_nr_f32(const DevState& st, const dic_tuning_t& tu, const float* def,
                          const int32_t* poi, const int32_t* uv_init, const int32_t* status_in,
                          const double* p_init, double* p_out, float* zncc, int32_t* iters,
-                         int32_t* status, int num_cu, hipStream_t s, bool bilinear);
+                         int32_t* status, int num_cu, hipStream_t s, int interp);
 hipError_t launch_nr_f64(const DevState& st, const DevPair* host_pairs, const float* ref,
                          const float* def, const int32_t* poi, const int32_t* uv_init,
                          const int32_t* status_in, const double* p_init, double* p_out,

@@ -48,7 +48,7 @@ __device__ __forceinline__ void iter_pass(const Smp& smp, int n, const Warp32& w
 
 }  // namespace
 
-template <int MAXS, int NT>
+template <int MAXS, int IM>
 __global__ void __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
     DevState st, int slack, const float* __restrict__ def, const int32_t* __restrict__ poi,
@@ -56,6 +56,7 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
     const double* __restrict__ p_init, double* __restrict__ p_out, float* __restrict__ zncc_out,
     int32_t* __restrict__ iters_out, int32_t* __restrict__ status_out) {
   constexpr int PP = refine_patch_pitch(MAXS);
+  constexpr int NT = interp_taps(IM);
   extern __shared__ float lds[];
   const int lane = lane_id(), wid = threadIdx.x / kWave;
   const int pside = icgn_patch_side(st.maxM, slack);
@@ -84,6 +85,7 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
     if (status == DIC_POI_OK) {
       const int M = P.M, n1 = 2 * M + 1, n = n1 * n1, W = P.width, H = P.height;
       const float* gimg = def + P.def_off;
+      const float4* glut = reinterpret_cast<const float4*>(st.lut) + P.lut_off;
       const int64_t corner = (int64_t)(y0 - M) * W + (x0 - M);
       const float* gx = st.grads + P.grad_off + corner;
       const float* gy = gx + (int64_t)W * H;
@@ -105,7 +107,9 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
           break;
         }
         float K[8];
-        if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
+        if constexpr (IM == kInterpBicubicLut)
+          iter_pass<MAXS>(LutSampler{glut, W, H, w.bx, w.by, c0}, n, w, fxs, fys, dxy, K);
+        else if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
           iter_pass<MAXS>(patch.template sampler<NT>(w.bx, w.by), n, w, fxs, fys, dxy, K);
         else
           iter_pass<MAXS>(ImageSampler<NT>{gimg, W, H, w.bx, w.by, c0}, n, w, fxs, fys,
@@ -148,7 +152,9 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
             return tm[__mul24((int)dy, tp) + (int)dx];
           };
           float K[3];
-          if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
+          if constexpr (IM == kInterpBicubicLut)
+            final_pass<MAXS>(LutSampler{glut, W, H, w.bx, w.by, c0}, n, w, dxy, tval, K);
+          else if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
             final_pass<MAXS>(patch.template sampler<NT>(w.bx, w.by), n, w, dxy, tval, K);
           else
             final_pass<MAXS>(ImageSampler<NT>{gimg, W, H, w.bx, w.by, c0}, n, w, dxy,
@@ -179,29 +185,32 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
   }
 }
 
-template <int MAXS, int NT>
+template <int MAXS, int IM>
 static hipError_t launch_icgn_f32_t(const DevState& st, const dic_tuning_t& tu, const float* def,
                                     const int32_t* poi, const int32_t* uv_init,
                                     const int32_t* status_in, const double* p_init, double* p_out,
                                     float* zncc, int32_t* iters, int32_t* status, int num_cu,
                                     hipStream_t s) {
   const int threads = tu.icgn_waves * kWave;
-  const size_t lds = refine_lds_bytes(refine_patch_pitch(MAXS),
-                                      icgn_patch_side(st.maxM, tu.icgn_slack), tu.icgn_waves);
+  // the table form reads no LDS patch
+  const size_t lds = IM == kInterpBicubicLut
+                         ? 0
+                         : refine_lds_bytes(refine_patch_pitch(MAXS),
+                                            icgn_patch_side(st.maxM, tu.icgn_slack), tu.icgn_waves);
   if (lds > 65536) {
-    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&icgn_f32_kernel<MAXS, NT>),
+    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&icgn_f32_kernel<MAXS, IM>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ea != hipSuccess) return ea;
   }
   int occ = 0;
   hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, icgn_f32_kernel<MAXS, NT>, threads, lds);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, icgn_f32_kernel<MAXS, IM>, threads, lds);
   if (e != hipSuccess) return e;
   if (occ < 1) return hipErrorInvalidConfiguration;
   int64_t blocks = (int64_t)occ * num_cu;
   const int64_t need = (st.N + tu.icgn_waves - 1) / tu.icgn_waves;
   if (blocks > need) blocks = need;
-  hipLaunchKernelGGL((icgn_f32_kernel<MAXS, NT>), dim3((unsigned)blocks), dim3(threads), lds, s, st,
+  hipLaunchKernelGGL((icgn_f32_kernel<MAXS, IM>), dim3((unsigned)blocks), dim3(threads), lds, s, st,
                      tu.icgn_slack, def, poi, uv_init, status_in, p_init, p_out, zncc, iters,
                      status);
   return hipGetLastError();
@@ -211,16 +220,22 @@ hipError_t launch_icgn_f32(const DevState& st, const dic_tuning_t& tu, const flo
                            const float* def, const int32_t* poi, const int32_t* uv_init,
                            const int32_t* status_in, const double* p_init, double* p_out,
                            float* zncc, int32_t* iters, int32_t* status, int num_cu,
-                           hipStream_t s, bool bilinear) {
+                           hipStream_t s, int interp) {
   if (st.N == 0) return hipSuccess;
   const int n = (2 * st.maxM + 1) * (2 * st.maxM + 1);
   const int need = (n + kWave - 1) / kWave;
 #define DIC_ICGN_CASE(S_)                                                                       \
-  if (need <= S_)                                                                               \
-    return bilinear ? launch_icgn_f32_t<S_, 2>(st, tu, def, poi, uv_init, status_in, p_init, p_out, \
-                                               zncc, iters, status, num_cu, s)                     \
-                    : launch_icgn_f32_t<S_, 4>(st, tu, def, poi, uv_init, status_in, p_init, p_out, \
-                                               zncc, iters, status, num_cu, s);
+  if (need <= S_) {                                                                             \
+    if (interp == kInterpBilinear)                                                              \
+      return launch_icgn_f32_t<S_, kInterpBilinear>(st, tu, def, poi, uv_init, status_in, p_init,  \
+                                                    p_out, zncc, iters, status, num_cu, s);      \
+    if (interp == kInterpBicubicLut)                                                            \
+      return launch_icgn_f32_t<S_, kInterpBicubicLut>(st, tu, def, poi, uv_init, status_in,     \
+                                                      p_init, p_out, zncc, iters, status, num_cu, \
+                                                      s);                                       \
+    return launch_icgn_f32_t<S_, kInterpBicubic>(st, tu, def, poi, uv_init, status_in, p_init,   \
+                                                 p_out, zncc, iters, status, num_cu, s);         \
+  }
   DIC_ICGN_CASE(4)
   DIC_ICGN_CASE(8)
   DIC_ICGN_CASE(12)

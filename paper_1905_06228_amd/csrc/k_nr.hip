@@ -68,13 +68,14 @@ __device__ __forceinline__ void nr_pass(const Smp& smp, int n, const Warp32& w, 
 
 }  // namespace
 
-template <int MAXS, int NT>
+template <int MAXS, int IM>
 __global__ void __launch_bounds__(512) nr_f32_kernel(
     DevState st, int slack, const float* __restrict__ def, const int32_t* __restrict__ poi,
     const int32_t* __restrict__ uv_init, const int32_t* __restrict__ status_in,
     const double* __restrict__ p_init, double* __restrict__ p_out, float* __restrict__ zncc_out,
     int32_t* __restrict__ iters_out, int32_t* __restrict__ status_out) {
   constexpr int PP = refine_patch_pitch(MAXS);
+  constexpr int NT = interp_taps(IM);
   extern __shared__ float lds[];
   const int lane = lane_id(), wid = threadIdx.x / kWave;
   const int pside = icgn_patch_side(st.maxM, slack);
@@ -105,6 +106,7 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
     if (status == DIC_POI_OK) {
       const int M = P.M, n1 = 2 * M + 1, n = n1 * n1, W = P.width, H = P.height;
       const float* gimg = def + P.def_off;
+      const float4* glut = reinterpret_cast<const float4*>(st.lut) + P.lut_off;
       const int tp = P.tmpl_pitch;
       const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * tp;
       float tv[MAXS];
@@ -125,7 +127,9 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
           break;
         }
         NrSums A;
-        if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
+        if constexpr (IM == kInterpBicubicLut)
+          nr_pass<MAXS>(LutSampler{glut, W, H, w.bx, w.by, c0}, n, w, tv, dxy, A);
+        else if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
           nr_pass<MAXS>(patch.template sampler<NT>(w.bx, w.by), n, w, tv, dxy, A);
         else
           nr_pass<MAXS>(ImageSampler<NT>{gimg, W, H, w.bx, w.by, c0}, n, w, tv, dxy, A);
@@ -186,7 +190,9 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
         } else {
           const auto tval = [&](int k, float, float) { return tv[k]; };
           float K[3];
-          if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
+          if constexpr (IM == kInterpBicubicLut)
+            final_pass<MAXS>(LutSampler{glut, W, H, w.bx, w.by, c0}, n, w, dxy, tval, K);
+          else if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
             final_pass<MAXS>(patch.template sampler<NT>(w.bx, w.by), n, w, dxy, tval, K);
           else
             final_pass<MAXS>(ImageSampler<NT>{gimg, W, H, w.bx, w.by, c0}, n, w, dxy,
@@ -217,29 +223,32 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
   }
 }
 
-template <int MAXS, int NT>
+template <int MAXS, int IM>
 static hipError_t launch_nr_f32_t(const DevState& st, const dic_tuning_t& tu, const float* def,
                                   const int32_t* poi, const int32_t* uv_init,
                                   const int32_t* status_in, const double* p_init, double* p_out,
                                   float* zncc, int32_t* iters, int32_t* status, int num_cu,
                                   hipStream_t s) {
   const int threads = tu.icgn_waves * kWave;
-  const size_t lds = refine_lds_bytes(refine_patch_pitch(MAXS),
-                                      icgn_patch_side(st.maxM, tu.icgn_slack), tu.icgn_waves);
+  // the table form reads no LDS patch
+  const size_t lds = IM == kInterpBicubicLut
+                         ? 0
+                         : refine_lds_bytes(refine_patch_pitch(MAXS),
+                                            icgn_patch_side(st.maxM, tu.icgn_slack), tu.icgn_waves);
   if (lds > 65536) {
-    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&nr_f32_kernel<MAXS, NT>),
+    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&nr_f32_kernel<MAXS, IM>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ea != hipSuccess) return ea;
   }
   int occ = 0;
   hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, nr_f32_kernel<MAXS, NT>, threads, lds);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, nr_f32_kernel<MAXS, IM>, threads, lds);
   if (e != hipSuccess) return e;
   if (occ < 1) return hipErrorInvalidConfiguration;
   int64_t blocks = (int64_t)occ * num_cu;
   const int64_t need = (st.N + tu.icgn_waves - 1) / tu.icgn_waves;
   if (blocks > need) blocks = need;
-  hipLaunchKernelGGL((nr_f32_kernel<MAXS, NT>), dim3((unsigned)blocks), dim3(threads), lds, s, st,
+  hipLaunchKernelGGL((nr_f32_kernel<MAXS, IM>), dim3((unsigned)blocks), dim3(threads), lds, s, st,
                      tu.icgn_slack, def, poi, uv_init, status_in, p_init, p_out, zncc, iters,
                      status);
   return hipGetLastError();
@@ -248,16 +257,22 @@ static hipError_t launch_nr_f32_t(const DevState& st, const dic_tuning_t& tu, co
 hipError_t launch_nr_f32(const DevState& st, const dic_tuning_t& tu, const float* def,
                          const int32_t* poi, const int32_t* uv_init, const int32_t* status_in,
                          const double* p_init, double* p_out, float* zncc, int32_t* iters,
-                         int32_t* status, int num_cu, hipStream_t s, bool bilinear) {
+                         int32_t* status, int num_cu, hipStream_t s, int interp) {
   if (st.N == 0) return hipSuccess;
   const int n = (2 * st.maxM + 1) * (2 * st.maxM + 1);
   const int need = (n + kWave - 1) / kWave;
 #define DIC_NR_CASE(S_)                                                                       \
-  if (need <= S_)                                                                             \
-    return bilinear ? launch_nr_f32_t<S_, 2>(st, tu, def, poi, uv_init, status_in, p_init, p_out, \
-                                             zncc, iters, status, num_cu, s)                      \
-                    : launch_nr_f32_t<S_, 4>(st, tu, def, poi, uv_init, status_in, p_init, p_out, \
-                                             zncc, iters, status, num_cu, s);
+  if (need <= S_) {                                                                           \
+    if (interp == kInterpBilinear)                                                            \
+      return launch_nr_f32_t<S_, kInterpBilinear>(st, tu, def, poi, uv_init, status_in, p_init,  \
+                                                  p_out, zncc, iters, status, num_cu, s);      \
+    if (interp == kInterpBicubicLut)                                                          \
+      return launch_nr_f32_t<S_, kInterpBicubicLut>(st, tu, def, poi, uv_init, status_in,     \
+                                                    p_init, p_out, zncc, iters, status, num_cu, \
+                                                    s);                                       \
+    return launch_nr_f32_t<S_, kInterpBicubic>(st, tu, def, poi, uv_init, status_in, p_init,   \
+                                               p_out, zncc, iters, status, num_cu, s);         \
+  }
   DIC_NR_CASE(4)
   DIC_NR_CASE(8)
   DIC_NR_CASE(12)

@@ -151,6 +151,68 @@ hipError_t launch_box_sums(const DevState& st, const float* def, hipStream_t s) 
   return hipGetLastError();
 }
 
+// Bicubic coefficient table of every deformed image (the look-up table of
+// interpolation coefficients): per cell (x, y) with 1 <= x <= W - 3 and
+// 1 <= y <= H - 3, the 16 coefficients C[b][a] of the Keys interpolant on
+// [x, x+1) x [y, y+1) written as sum C[b][a] t^a s^b.  With Keys' weights
+// expanded in powers of t, the taps g-1..g2 of a row give
+//   t^0: g0,  t^1: (g1 - g-1)/2,  t^2: g-1 - 5/2 g0 + 2 g1 - 1/2 g2,
+//   t^3: -1/2 g-1 + 3/2 g0 - 3/2 g1 + 1/2 g2,
+// applied along x to the four rows, then along y to those row coefficients.
+// Formed in FP64 and rounded once; cells outside that range hold zeros (the
+// refinements' bounds test never reads them).  Grid: (column blocks, rows,
+// pairs); each thread writes its cell's four float4 rows (64 contiguous bytes).
+__device__ __forceinline__ void keys_powers(double gm, double g0, double g1, double g2,
+                                            double* c) {
+  c[0] = g0;
+  c[1] = 0.5 * (g1 - gm);
+  c[2] = gm - 2.5 * g0 + 2.0 * g1 - 0.5 * g2;
+  c[3] = -0.5 * gm + 1.5 * g0 - 1.5 * g1 + 0.5 * g2;
+}
+
+__global__ void __launch_bounds__(256) bicubic_lut_kernel(const DevPair* __restrict__ pairs,
+                                                          const float* __restrict__ def,
+                                                          float4* __restrict__ lut) {
+  const DevPair P = pairs[blockIdx.z];
+  const int y = blockIdx.y;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= P.height || x >= P.width) return;
+  const int W = P.width, H = P.height;
+  float4* out = lut + P.lut_off + ((int64_t)y * W + x) * 4;
+  if (x < 1 || x > W - 3 || y < 1 || y > H - 3) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) out[b] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  const float* g = def + P.def_off + (int64_t)(y - 1) * W + (x - 1);
+  double rc[4][4];  // [row][power of t]
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const float* row = g + (int64_t)l * W;
+    keys_powers(row[0], row[1], row[2], row[3], rc[l]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double cb[4];
+    keys_powers(rc[0][a], rc[1][a], rc[2][a], rc[3][a], cb);
+    // cb[b] = C[b][a]; row b of the output holds powers a = 0..3
+    rc[0][a] = cb[0];
+    rc[1][a] = cb[1];
+    rc[2][a] = cb[2];
+    rc[3][a] = cb[3];
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+    out[b] = make_float4((float)rc[b][0], (float)rc[b][1], (float)rc[b][2], (float)rc[b][3]);
+}
+
+hipError_t launch_bicubic_lut(const DevState& st, const float* def, hipStream_t s) {
+  dim3 grid((st.max_width + 255) / 256, st.max_height, st.num_pairs);
+  hipLaunchKernelGGL(bicubic_lut_kernel, grid, dim3(256), 0, s, st.pairs, def,
+                     reinterpret_cast<float4*>(st.lut));
+  return hipGetLastError();
+}
+
 // Writes the record of a POI that cannot be processed.
 __device__ __forceinline__ void write_bad_record(RefRec* R, int status, int lane) {
   if (lane == 0) {

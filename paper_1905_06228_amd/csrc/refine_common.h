@@ -2,8 +2,9 @@
 // Newton-Raphson, FP32 batched forms): the first-order warp in FP32 local
 // form, the bounding box of the taps it touches, the per-wave LDS patch of
 // the deformed image, interpolation from that patch or from the image (Keys
-// bicubic, NT = 4 taps per direction, or Eq. (5)'s bilinear, NT = 2), and the
-// final pass that evaluates Eq. (1) at the converged warp.
+// bicubic, NT = 4 taps per direction, or Eq. (5)'s bilinear, NT = 2), or
+// bicubic from a per-cell table of polynomial coefficients, and the final
+// pass that evaluates Eq. (1) at the converged warp.
 //
 // Sample layout: lane l holds samples s = l + 64 k (slot k) of the subset in
 // row-major order; slots below n / 64 are full, the next one is partial and
@@ -163,6 +164,7 @@ struct PatchSampler {
   }
   static constexpr int pitch() { return P; }
   static constexpr int ntaps() { return NT; }
+  static constexpr bool kLut = false;
   __device__ __forceinline__ float tap(const float* q) const { return *q; }
 };
 
@@ -191,53 +193,119 @@ struct ImageSampler {
   }
   __device__ __forceinline__ int pitch() const { return W; }
   static constexpr int ntaps() { return NT; }
+  static constexpr bool kLut = false;
   __device__ __forceinline__ float tap(const float* q) const { return *q - c0; }
+};
+
+// Keys bicubic from the coefficient table: cell (c, r) holds the interpolant
+// on [c, c+1) x [r, r+1) as sum_{a,b} C[b][a] t^a s^b (t, s the fractional
+// offsets), four float4 rows b = 0..3 of powers a = 0..3.  The value is
+// Horner in t per row, then in s, with c0 taken off C[0][0] first so the
+// sums run on g - c0 like the tap samplers'.  The cell is clamped to
+// [1, W - 3] x [1, H - 3]: the tap box test keeps it there, the clamp only
+// guards the reads of a degenerate warp.
+struct LutSampler {
+  const float4* lut;
+  int W, H, bx, by;
+  float c0;
+  static constexpr int ntaps() { return 4; }
+  static constexpr bool kLut = true;
+
+  __device__ __forceinline__ const float4* cell(float xs, float ys, float& t, float& s) const {
+    const float fx = floorf(xs), fy = floorf(ys);
+    t = xs - fx;
+    s = ys - fy;
+    const int c = min(max(bx + (int)fx, 1), W - 3);
+    const int r = min(max(by + (int)fy, 1), H - 3);
+    return lut + ((int64_t)r * W + c) * 4;
+  }
+  static __device__ __forceinline__ float horner(const float4& c, float t) {
+    return fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x);
+  }
+  __device__ __forceinline__ float value(float xs, float ys) const {
+    float t, s;
+    const float4* q = cell(xs, ys, t, s);
+    float4 c[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) c[b] = q[b];
+    c[0].x -= c0;
+    float r[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) r[b] = horner(c[b], t);
+    return fmaf(fmaf(fmaf(r[3], s, r[2]), s, r[1]), s, r[0]);
+  }
+  __device__ __forceinline__ void value_grad(float xs, float ys, float& v, float& gx,
+                                             float& gy) const {
+    float t, s;
+    const float4* q = cell(xs, ys, t, s);
+    float4 c[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) c[b] = q[b];
+    c[0].x -= c0;
+    float r[4], d[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      r[b] = horner(c[b], t);
+      d[b] = fmaf(fmaf(3.f * c[b].w, t, 2.f * c[b].z), t, c[b].y);
+    }
+    v = fmaf(fmaf(fmaf(r[3], s, r[2]), s, r[1]), s, r[0]);
+    gx = fmaf(fmaf(fmaf(d[3], s, d[2]), s, d[1]), s, d[0]);
+    gy = fmaf(fmaf(3.f * r[3], s, 2.f * r[2]), s, r[1]);
+  }
 };
 
 // g - c0 at local offset (xs, ys).
 template <class Smp>
 __device__ __forceinline__ float sample_value(const Smp& smp, float xs, float ys) {
-  constexpr int NT = Smp::ntaps();
-  float wx[NT], wy[NT], tx, ty;
-  const float* q = smp.taps(xs, ys, wx, wy, tx, ty);
-  const int P = smp.pitch();
-  float acc = 0.f;
+  if constexpr (Smp::kLut) {
+    return smp.value(xs, ys);
+  } else {
+    constexpr int NT = Smp::ntaps();
+    float wx[NT], wy[NT], tx, ty;
+    const float* q = smp.taps(xs, ys, wx, wy, tx, ty);
+    const int P = smp.pitch();
+    float acc = 0.f;
 #pragma unroll
-  for (int l = 0; l < NT; ++l) {
-    const float* row = q + l * P;
-    float r = wx[0] * smp.tap(row);
+    for (int l = 0; l < NT; ++l) {
+      const float* row = q + l * P;
+      float r = wx[0] * smp.tap(row);
 #pragma unroll
-    for (int k = 1; k < NT; ++k) r = fmaf(wx[k], smp.tap(row + k), r);
-    acc = l == 0 ? wy[0] * r : fmaf(wy[l], r, acc);
+      for (int k = 1; k < NT; ++k) r = fmaf(wx[k], smp.tap(row + k), r);
+      acc = l == 0 ? wy[0] * r : fmaf(wy[l], r, acc);
+    }
+    return acc;
   }
-  return acc;
 }
 
 // g - c0 and the interpolant's gradient (d/dx, d/dy) at local offset (xs, ys).
 template <class Smp>
 __device__ __forceinline__ void sample_value_grad(const Smp& smp, float xs, float ys, float& v,
                                                   float& gx, float& gy) {
-  constexpr int NT = Smp::ntaps();
-  float wx[NT], wy[NT], tx, ty, dwx[NT], dwy[NT];
-  const float* q = smp.taps(xs, ys, wx, wy, tx, ty);
-  interp_dweights<NT>(tx, dwx);
-  interp_dweights<NT>(ty, dwy);
-  const int P = smp.pitch();
+  if constexpr (Smp::kLut) {
+    smp.value_grad(xs, ys, v, gx, gy);
+  } else {
+    constexpr int NT = Smp::ntaps();
+    float wx[NT], wy[NT], tx, ty, dwx[NT], dwy[NT];
+    const float* q = smp.taps(xs, ys, wx, wy, tx, ty);
+    interp_dweights<NT>(tx, dwx);
+    interp_dweights<NT>(ty, dwy);
+    const int P = smp.pitch();
 #pragma unroll
-  for (int l = 0; l < NT; ++l) {
-    const float* row = q + l * P;
-    float t[NT];
+    for (int l = 0; l < NT; ++l) {
+      const float* row = q + l * P;
+      float t[NT];
 #pragma unroll
-    for (int c = 0; c < NT; ++c) t[c] = smp.tap(row + c);
-    float r = wx[0] * t[0], rd = dwx[0] * t[0];
+      for (int c = 0; c < NT; ++c) t[c] = smp.tap(row + c);
+      float r = wx[0] * t[0], rd = dwx[0] * t[0];
 #pragma unroll
-    for (int c = 1; c < NT; ++c) {
-      r = fmaf(wx[c], t[c], r);
-      rd = fmaf(dwx[c], t[c], rd);
+      for (int c = 1; c < NT; ++c) {
+        r = fmaf(wx[c], t[c], r);
+        rd = fmaf(dwx[c], t[c], rd);
+      }
+      v = l == 0 ? wy[0] * r : fmaf(wy[l], r, v);
+      gx = l == 0 ? wy[0] * rd : fmaf(wy[l], rd, gx);
+      gy = l == 0 ? dwy[0] * r : fmaf(dwy[l], r, gy);
     }
-    v = l == 0 ? wy[0] * r : fmaf(wy[l], r, v);
-    gx = l == 0 ? wy[0] * rd : fmaf(wy[l], rd, gx);
-    gy = l == 0 ? dwy[0] * r : fmaf(dwy[l], r, gy);
   }
 }
 

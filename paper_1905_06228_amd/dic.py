@@ -24,6 +24,7 @@ FLAG_CACHE_REF_PREP = 2
 FLAG_DETERMINISTIC_BWD = 4
 FLAG_REFINE_NR = 8
 FLAG_INTERP_BILINEAR = 16   # IC-GN / Newton-Raphson with Eq. (5) bilinear interpolation
+FLAG_BICUBIC_LUT = 32       # IC-GN / Newton-Raphson from the per-cell bicubic coefficient table
 
 POI_OK = 0
 POI_NOT_CONVERGED = 1

@@ -107,6 +107,27 @@ def test_plan_create_rejects(L, pairs, kw, why):
     assert why in L.dic_last_error().decode()
 
 
+def test_interpolation_flags(L):
+    """Bilinear (16) and the bicubic coefficient table (32) are FP32-only and
+    exclusive; the table adds 64 bytes of workspace per deformed pixel."""
+    pair = [(256, 128, 10, 8, 0, 0, 0, 50)]
+    sizes = {}
+    for flags in (0, 16, 32):
+        rc, h = make(L, pair, flags=flags)
+        assert rc == 0
+        nb = ctypes.c_size_t(0)
+        assert L.dic_plan_workspace_size(h, ctypes.byref(nb)) == 0
+        sizes[flags] = nb.value
+        L.dic_plan_destroy(h)
+    assert sizes[16] == sizes[0]
+    assert 256 * 128 * 64 <= sizes[32] - sizes[0] <= 256 * 128 * 64 + 256
+    rc, h = make(L, pair, flags=48)
+    assert rc == -1 and not h.value and "exclusive" in L.dic_last_error().decode()
+    for flags in (16, 32):
+        rc, h = make(L, pair, precision=1, flags=flags)
+        assert rc == -4 and not h.value and "FP32" in L.dic_last_error().decode()
+
+
 def test_null_arguments_and_unbound(L):
     assert L.dic_plan_create(None, None) == -1
     rc, h = make(L, [(64, 64, 5, 4, 0, 0, 0, 10)])
