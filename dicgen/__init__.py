@@ -171,6 +171,26 @@ def true_displacement(fld: Field, pts_xy: np.ndarray) -> np.ndarray:
     return np.stack([u, v], axis=1)
 
 
+def true_increment(fld_prev: Optional[Field], fld_next: Field, pts_xy: np.ndarray,
+                   tol: float = 1e-12, max_iter: int = 500) -> np.ndarray:
+    """Displacement between two frames at points ``pts_xy`` of the first one:
+    the material point X under x = X + u_prev(X) (fixed-point iteration; X = x
+    when ``fld_prev`` is None) moves to X + u_next(X)."""
+    x = pts_xy[:, 0].astype(np.float64)
+    y = pts_xy[:, 1].astype(np.float64)
+    X, Y = x.copy(), y.copy()
+    if fld_prev is not None:
+        for _ in range(max_iter):
+            u, v = fld_prev(X, Y)
+            Xn, Yn = x - u, y - v
+            err = max(float(np.abs(Xn - X).max(initial=0)), float(np.abs(Yn - Y).max(initial=0)))
+            X, Y = Xn, Yn
+            if err < tol:
+                break
+    u, v = fld_next(X, Y)
+    return np.stack([X + u - x, Y + v - y], axis=1)
+
+
 def render_image(blobs: Blobs, fld: Optional[Field], height: int, width: int,
                  noise_sigma: float = 0.0,
                  noise_rng: Optional[np.random.Generator] = None) -> np.ndarray:

@@ -806,17 +806,31 @@ def correlate(f: np.ndarray, g: np.ndarray, pois: np.ndarray, M: int, S: int,
 
 
 def correlate_sequence(frames: Sequence[np.ndarray], pois: np.ndarray, M: int, S: int,
-                       max_iters: int = 20, tol: float = 1e-3):
-    """Every frame k >= 1 against frame 0.  Reading of 'seeded by the previous
-    frame's result': the search window is centred on round(u, v) of the last
-    frame whose status was OK (frame 1: (0, 0)), and IC-GN starts from that
-    frame's gradient terms."""
+                       max_iters: int = 20, tol: float = 1e-3,
+                       reference: str = "first") -> list:
+    """A frame sequence, seeded frame to frame.
+
+    reference="first": every frame k >= 1 against frame 0 (a constant
+    reference; the paper examines accuracy this way).  reference="previous":
+    frame k against frame k - 1, the policy the paper times (the reference is
+    updated after every evaluation, so every pair is two consecutive images;
+    Sec. 3) and the live policy of Sec. 6 (the previously used target becomes
+    the next reference) when ``frames`` lists the frames actually used.
+    Readings: the POIs are the same pixel positions of every reference, so
+    each result of the "previous" policy is the increment between the two
+    frames at those positions, not a displacement accumulated from frame 0;
+    'seeded by the previous result' centres the search window on round(u, v)
+    of the last result whose status was OK (first pair: (0, 0)) and starts
+    IC-GN from that result's gradient terms, under either policy."""
+    if reference not in ("first", "previous"):
+        raise ValueError("reference must be 'first' or 'previous'")
     N = pois.shape[0]
     last_p = np.zeros((N, 6))
     results = []
     for k in range(1, len(frames)):
         centers = np.stack([np.rint(last_p[:, 0]), np.rint(last_p[:, 3])], axis=1).astype(np.int64)
-        r = correlate(frames[0], frames[k], pois, M, S, centers, last_p, max_iters, tol)
+        ref = frames[0] if reference == "first" else frames[k - 1]
+        r = correlate(ref, frames[k], pois, M, S, centers, last_p, max_iters, tol)
         ok = r["status"] == OK
         last_p[ok] = r["p"][ok]
         results.append(r)
