@@ -131,9 +131,12 @@ def cpu_baseline(pair, got, n_sample: int, seed: int = 11):
     return base, acc
 
 
-def sequence_bench(torch, dic, dicgen, dev, n_frames: int) -> dict:
-    """Frames/s of the camera-scale sequence: frame k against frame 0, seeded
-    by the last OK frame, 4096 x 3000 frames of ~600k blobs under the
+def sequence_bench(torch, dic, dicgen, dev, n_frames: int, reference: str = "first",
+                   live_fps: float = 0.0) -> dict:
+    """Frames/s of the camera-scale sequence: frame k against frame 0
+    (reference "first") or against frame k - 1 (reference "previous", the
+    reference updated after every pair), seeded by the last OK result,
+    4096 x 3000 frames of ~600k blobs under the
     heterogeneous strain field (noise 3), subset 29 x 29, step 7, search +-24
     around the seed.  Frames rendered on the device (same recipe as the NumPy
     generator); timed once with every frame resident in HBM and once from
@@ -147,13 +150,13 @@ def sequence_bench(torch, dic, dicgen, dev, n_frames: int) -> dict:
     pois = dicgen.poi_grid(W, H, M, S, step)
     Q = torch.from_numpy(pois).to(dev)
     host = [f.cpu() for f in frames]
-    dic.correlate_sequence(frames[:2], Q, M, S)          # load kernels, warm caches
+    dic.correlate_sequence(frames[:2], Q, M, S, reference=reference)   # load kernels
     torch.cuda.synchronize()
 
     def run(src):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        res = dic.correlate_sequence(src, Q, M, S)
+        res = dic.correlate_sequence(src, Q, M, S, reference=reference)
         torch.cuda.synchronize()
         return res, time.perf_counter() - t
 
@@ -162,8 +165,12 @@ def sequence_bench(torch, dic, dicgen, dev, n_frames: int) -> dict:
     last = res[-1]
     st = last["status"].cpu().numpy()
     ok = st == 0
-    truth = dicgen.true_displacement(dicgen.heterogeneous_strain(n_frames - 1),
-                                     pois[ok].astype(np.float64))
+    if reference == "first":
+        truth = dicgen.true_displacement(dicgen.heterogeneous_strain(n_frames - 1),
+                                         pois[ok].astype(np.float64))
+    else:
+        truth = dicgen.true_increment(dicgen.heterogeneous_strain(n_frames - 2),
+                                      dicgen.heterogeneous_strain(n_frames - 1), pois[ok])
     p = last["p"].cpu().numpy()[ok]
     err = np.abs(p[:, [0, 3]] - truth)
     iters = [float(r["iters"].float()[r["status"] == 0].mean()) for r in res]
@@ -172,7 +179,10 @@ def sequence_bench(torch, dic, dicgen, dev, n_frames: int) -> dict:
             "ms_per_frame": round(t_dev * 1e3 / (n_frames - 1), 3),
             "ms_per_frame_with_h2d": round(t_host * 1e3 / (n_frames - 1), 3),
             "frames": n_frames, "pois_per_frame": int(len(pois)),
-            "config": {"workload": "sequence_4096x3000: frames 1..K against frame 0, ~600k blobs, "
+            "reference": reference,
+            "config": {"workload": "sequence_4096x3000: frames 1..K against "
+                                   + ("frame 0" if reference == "first" else "frame k-1")
+                                   + ", ~600k blobs, "
                                    "u = 0.002 k x (1 + 0.5 sin(2 pi y / 1500)), v = -0.0006 k y, "
                                    "noise sigma 3, subset 29x29, step 7, search +-24 around "
                                    "the seed", "form": "FP32 batched"},
@@ -181,7 +191,68 @@ def sequence_bench(torch, dic, dicgen, dev, n_frames: int) -> dict:
             "last_frame": {"ok_fraction": float(ok.mean()),
                            "mean_abs_err_vs_field_px": float(err.mean()),
                            "p99_abs_err_vs_field_px": float(np.percentile(err, 99))},
+            "live": live_bench(torch, dic, dicgen, host, Q, pois, M, S, live_fps)
+            if live_fps > 0 else None,
             "data": "synthetic"}
+
+
+def live_bench(torch, dic, dicgen, host_frames, Q, pois, M, S, fps: float) -> dict:
+    """The live policy: a camera thread offers the host frames at ``fps``;
+    the correlator takes the newest frame, correlates it against the
+    previously used one and waits for the result (as a display would); frames
+    that arrive meanwhile are skipped.  Latency = frame offered -> its
+    result on the host."""
+    import threading
+    H, W = host_frames[0].shape
+    live = dic.LiveCorrelator(H, W, Q, M, S)
+    offered = {}
+    done = threading.Event()
+
+    def camera():
+        t0 = time.perf_counter()
+        for k, f in enumerate(host_frames):
+            wait = t0 + k / fps - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            offered[k] = time.perf_counter()
+            live.put(f)
+        done.set()
+
+    cam = threading.Thread(target=camera)
+    lat, used, results = [], [], []
+    t_start = time.perf_counter()
+    cam.start()
+    while True:
+        finished = done.is_set()
+        ref_before = live.ref_seq
+        o = live.step()
+        if o is None:
+            if live.ref_seq != ref_before:          # the first frame became the reference
+                used.append(live.ref_seq)
+                continue
+            if finished:                            # nothing new and nothing more to come
+                break
+            time.sleep(0.0005)
+            continue
+        st = o["status"].cpu()                      # the display waits for the result
+        lat.append(time.perf_counter() - offered[o["frame"]])
+        used.append(o["frame"])
+        results.append((o["reference"], o["frame"], o["p"].cpu().numpy(), st.numpy()))
+    cam.join()
+    elapsed = time.perf_counter() - t_start
+    a, b, p, st = results[-1]
+    ok = st == 0
+    truth = dicgen.true_increment(None if a == 0 else dicgen.heterogeneous_strain(a),
+                                  dicgen.heterogeneous_strain(b), pois[ok])
+    err = np.abs(p[ok][:, [0, 3]] - truth)
+    return {"camera_fps": fps, "frames_offered": len(host_frames),
+            "pairs_correlated": len(results), "frames_skipped": live.mailbox.skipped,
+            "processed_pairs_per_s": round(len(results) / elapsed, 2),
+            "latency_ms_mean": round(1e3 * float(np.mean(lat)), 2),
+            "latency_ms_max": round(1e3 * float(np.max(lat)), 2),
+            "frames_used": used,
+            "last_pair": {"reference": int(a), "frame": int(b), "ok_fraction": float(ok.mean()),
+                          "mean_abs_err_vs_field_px": float(err.mean())}}
 
 
 def main() -> int:
@@ -197,6 +268,11 @@ def main() -> int:
                     help="search_block,search_occupancy,icgn_waves,icgn_slack (skips autotuning)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--reference", choices=("first", "previous"), default="first",
+                    help="sequence benchmark: frame k against frame 0 or against frame k-1")
+    ap.add_argument("--live-fps", type=float, default=0.0,
+                    help="sequence benchmark: also run the live policy with a camera "
+                         "offering the frames at this rate")
     ap.add_argument("--sequence-frames", type=int, default=0,
                     help="instead of the pair benchmark, time the camera-scale frame sequence "
                          "(4096x3000 frames, 239,932 POIs each) over this many frames")
@@ -213,7 +289,8 @@ def main() -> int:
 
     dev = torch.device("cuda", 0)
     if args.sequence_frames > 0:
-        print(json.dumps(sequence_bench(torch, dic, dicgen, dev, args.sequence_frames)))
+        print(json.dumps(sequence_bench(torch, dic, dicgen, dev, args.sequence_frames,
+                                        args.reference, args.live_fps)))
         return 0
     pair = dicgen.affine_pair_1024()
     N = len(pair.pois)

@@ -9,5 +9,6 @@ from .dic import (FLAG_BICUBIC_LUT, FLAG_CACHE_REF_PREP, FLAG_DETERMINISTIC_BWD,
                   PSO_GENERATIONS, PSO_PARTICLES,
                   POI_NOT_CONVERGED, POI_OK, POI_OUT_OF_BOUNDS, POI_SINGULAR_HESSIAN,
                   POI_ZERO_VARIANCE, ZNSSD, DicError, PairSpec, Plan, batch_layout,
-                  correlate, correlate_batch, correlate_sequence, load_library, poi_grid,
+                  LatestFrame, LiveCorrelator, correlate, correlate_batch, correlate_sequence,
+                  load_library, poi_grid,
                   single_pair_plan)

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import threading
 from dataclasses import dataclass
 from typing import List, Optional, Sequence, Tuple
 
@@ -391,55 +392,204 @@ def correlate_batch(pairs, precision: int = FP32_BATCHED, **kw) -> dict:
     return out
 
 
+class _FrameRing:
+    """A ring of device frame buffers for the sequence drivers.  Host frames go
+    through two pinned staging buffers and are copied on a side stream, so the
+    copy of the next frame overlaps the current pair's kernels; a slot is
+    overwritten only after the work that last read it (``release``).  Frames
+    already on the device as contiguous float32 are used in place unless
+    ``copy_device`` (a caller that may reuse its buffer)."""
+
+    def __init__(self, shape, slots: int, device: torch.device, copy_device: bool = False):
+        self.shape = tuple(shape)
+        self.device = device
+        self.copy_device = copy_device
+        self.bufs = [torch.empty(self.shape, dtype=torch.float32, device=device)
+                     for _ in range(slots)]
+        self.pinned = [torch.empty(self.shape, dtype=torch.float32).pin_memory()
+                       for _ in range(2)]
+        self.copy = torch.cuda.Stream(device=device)
+        self.ready = [torch.cuda.Event() for _ in range(slots)]
+        self.released = [torch.cuda.Event() for _ in range(slots)]
+        self.copied = [torch.cuda.Event() for _ in range(2)]
+        for e in self.released + self.copied:
+            e.record()
+        self.views: List[Optional[torch.Tensor]] = [None] * slots
+        self.staged = 0
+
+    def stage(self, slot: int, frame) -> None:
+        if (not self.copy_device and isinstance(frame, torch.Tensor)
+                and frame.device == self.device and frame.dtype == torch.float32
+                and frame.is_contiguous()):
+            if tuple(frame.shape) != self.shape:
+                raise DicError(f"frame shape {tuple(frame.shape)} != {self.shape}")
+            self.views[slot] = frame
+            self.ready[slot].record()
+            return
+        src = torch.as_tensor(frame, dtype=torch.float32)
+        if tuple(src.shape) != self.shape:
+            raise DicError(f"frame shape {tuple(src.shape)} != {self.shape}")
+        if src.device.type == "cuda":
+            self.bufs[slot].copy_(src)
+            self.ready[slot].record()
+        else:
+            k = self.staged % 2
+            self.copied[k].synchronize()          # the pinned buffer's last copy is done
+            self.pinned[k].copy_(src)
+            with torch.cuda.stream(self.copy):
+                self.copy.wait_event(self.released[slot])
+                self.bufs[slot].copy_(self.pinned[k], non_blocking=True)
+                self.ready[slot].record(self.copy)
+                self.copied[k].record(self.copy)
+            self.staged += 1
+        self.views[slot] = self.bufs[slot]
+
+    def acquire(self, slot: int) -> torch.Tensor:
+        torch.cuda.current_stream().wait_event(self.ready[slot])
+        return self.views[slot]
+
+    def release(self, slot: int) -> None:
+        self.released[slot].record()
+
+
 def correlate_sequence(frames: Sequence, pois: torch.Tensor, M: int, S: int,
-                       precision: int = FP32_BATCHED, device=None, **kw) -> List[dict]:
-    """Every frame k >= 1 against frame 0; frame k is seeded by the last frame
-    whose status was OK (search centred on its rounded displacement, IC-GN
-    starting from its gradient terms).  Host frames are copied through pinned
-    memory on a side stream, one frame ahead of the compute."""
+                       precision: int = FP32_BATCHED, device=None, reference: str = "first",
+                       **kw) -> List[dict]:
+    """A frame sequence, each pair seeded by the last OK result of its POI
+    (search centred on its rounded displacement, refinement starting from its
+    gradient terms).
+
+    reference="first": every frame k >= 1 against frame 0, whose reference
+    record is computed once.  reference="previous": frame k against frame
+    k - 1 (the reference updated after every evaluation, Sec. 3): the POIs
+    are the same pixel positions of every reference and each result is the
+    increment between the two frames.  Host frames are copied through pinned
+    memory on a side stream, one frame ahead of the kernels."""
+    if reference not in ("first", "previous"):
+        raise DicError("reference must be 'first' or 'previous'")
     device = torch.device(device if device is not None else "cuda")
-    f0 = torch.as_tensor(frames[0]).to(device=device, dtype=torch.float32).contiguous()
-    H, W = f0.shape
+    if device.index is None:
+        device = torch.device("cuda", torch.cuda.current_device())
+    shape = tuple(torch.as_tensor(frames[0]).shape) if not isinstance(frames[0], torch.Tensor) \
+        else tuple(frames[0].shape)
+    H, W = shape
     N = pois.shape[0]
-    flags = kw.pop("flags", 0) | FLAG_CACHE_REF_PREP
-    plan = single_pair_plan(W, H, M, S, N, precision, flags=flags, **kw)
+    flags = kw.pop("flags", 0)
+    # "first": the reference never changes, so its record is cached; "previous":
+    # buffers are reused for other frames, so nothing may be cached by pointer
+    flags = flags | FLAG_CACHE_REF_PREP if reference == "first" else flags & ~FLAG_CACHE_REF_PREP
+    plan = single_pair_plan(W, H, M, S, N, precision, flags=flags, device=device, **kw)
     seed = torch.zeros((N, 2), dtype=torch.int32, device=device)
     p_seed = torch.zeros((N, 6), dtype=torch.float64, device=device)
-    copy = torch.cuda.Stream(device=device)
-    bufs = [torch.empty_like(f0), torch.empty_like(f0)]
-    pinned = [torch.empty((H, W), dtype=torch.float32).pin_memory() for _ in range(2)]
-    ready = [torch.cuda.Event(), torch.cuda.Event()]
-    free = [torch.cuda.Event(), torch.cuda.Event()]
-
-    def stage(k: int) -> None:
-        slot = k % 2
-        src = frames[k]
-        if isinstance(src, torch.Tensor) and src.device.type == "cuda":
-            bufs[slot].copy_(src)
-            ready[slot].record()
-            return
-        pinned[slot].copy_(torch.as_tensor(src, dtype=torch.float32))
-        with torch.cuda.stream(copy):
-            copy.wait_event(free[slot])
-            bufs[slot].copy_(pinned[slot], non_blocking=True)
-            ready[slot].record(copy)
-
-    for e in free:
-        e.record()
+    ring = _FrameRing(shape, 3, device)
+    if reference == "first":
+        def slot(k: int) -> int:
+            return 0 if k == 0 else 1 + (k - 1) % 2
+    else:
+        def slot(k: int) -> int:
+            return k % 3
     results = []
+    out = plan.new_outputs()          # fixed buffers: graph replays keep their key
+    ring.stage(slot(0), frames[0])
     if len(frames) > 1:
-        stage(1)
+        ring.stage(slot(1), frames[1])
     for k in range(1, len(frames)):
-        slot = k % 2
-        torch.cuda.current_stream().wait_event(ready[slot])
-        o = plan.correlate(f0, bufs[slot], pois, seed, p_seed)
+        ref = ring.acquire(slot(0) if reference == "first" else slot(k - 1))
+        cur = ring.acquire(slot(k))
+        o = plan.correlate(ref, cur, pois, seed, p_seed, out=out)
         plan.seed_update(o["p"], o["status"], seed, p_seed)
-        free[slot].record()
+        ring.release(slot(k) if reference == "first" else slot(k - 1))
         if k + 1 < len(frames):
-            free[(k + 1) % 2].synchronize()
-            stage(k + 1)
+            ring.stage(slot(k + 1), frames[k + 1])
         results.append({key: v.clone() for key, v in o.items()})
     return results
+
+
+class LatestFrame:
+    """One-frame mailbox between a camera (producer) and the correlator
+    (consumer): ``put`` replaces a frame that was not taken yet (counted in
+    ``skipped``), ``take`` returns the newest frame and its sequence number
+    and empties the box.  Thread-safe.  The box holds the caller's object, not
+    a copy: a frame must stay unchanged until it is taken or replaced."""
+
+    def __init__(self):
+        self._lock = threading.Lock()
+        self._frame = None
+        self._seq = -1
+        self._pending = False
+        self.received = 0
+        self.skipped = 0
+
+    def put(self, frame) -> int:
+        with self._lock:
+            if self._pending:
+                self.skipped += 1
+            self._frame = frame
+            self._seq += 1
+            self._pending = True
+            self.received += 1
+            return self._seq
+
+    def take(self):
+        with self._lock:
+            if not self._pending:
+                return None, -1
+            frame, seq = self._frame, self._seq
+            self._frame = None
+            self._pending = False
+            return frame, seq
+
+
+class LiveCorrelator:
+    """Live pipelining (Sec. 6): each ``step`` correlates the most recent
+    frame against the previously used target, which it replaces as the
+    reference, so frames that arrive faster than they are processed are
+    skipped instead of queued.  The copy of a step's frame to the device runs
+    on a side stream and overlaps the previous step's kernels.  A step returns
+    None until a reference exists or when no new frame arrived; otherwise the
+    pair's outputs (device tensors, not synchronised) with the sequence
+    numbers of the frame and its reference.  Seeding as in
+    ``correlate_sequence(reference="previous")``."""
+
+    def __init__(self, height: int, width: int, pois: torch.Tensor, M: int, S: int,
+                 precision: int = FP32_BATCHED, device=None, **kw):
+        device = torch.device(device if device is not None else "cuda")
+        if device.index is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        flags = kw.pop("flags", 0) & ~(FLAG_CACHE_REF_PREP | FLAG_USE_GRAPH)
+        self.pois = pois
+        self.plan = single_pair_plan(width, height, M, S, pois.shape[0], precision, flags=flags,
+                                     device=device, **kw)
+        N = pois.shape[0]
+        self.seed = torch.zeros((N, 2), dtype=torch.int32, device=device)
+        self.p_seed = torch.zeros((N, 6), dtype=torch.float64, device=device)
+        self.ring = _FrameRing((height, width), 3, device, copy_device=True)
+        self.mailbox = LatestFrame()
+        self.ref_slot: Optional[int] = None
+        self.ref_seq = -1
+        self.pairs = 0
+
+    def put(self, frame) -> int:
+        return self.mailbox.put(frame)
+
+    def step(self) -> Optional[dict]:
+        frame, seq = self.mailbox.take()
+        if frame is None:
+            return None
+        slot = 0 if self.ref_slot is None else (self.ref_slot + 1) % 3
+        self.ring.stage(slot, frame)
+        if self.ref_slot is None:
+            self.ref_slot, self.ref_seq = slot, seq
+            return None
+        ref = self.ring.acquire(self.ref_slot)
+        cur = self.ring.acquire(slot)
+        o = self.plan.correlate(ref, cur, self.pois, self.seed, self.p_seed)
+        self.plan.seed_update(o["p"], o["status"], self.seed, self.p_seed)
+        self.ring.release(self.ref_slot)
+        o.update(frame=seq, reference=self.ref_seq)
+        self.ref_slot, self.ref_seq = slot, seq
+        self.pairs += 1
+        return o
 
 
 class ZNSSD(torch.autograd.Function):
