@@ -87,6 +87,10 @@ struct dic_plan_s {
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
   std::vector<hipGraph_t> graph_objs;
   hipStream_t cap_stream = nullptr;
+  // second stream for the deformed-side preparation, which runs beside the
+  // reference-side one (forked from and joined back to the caller's stream)
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   bool fp32() const { return desc.precision == DIC_FP32_BATCHED; }
   bool det() const { return (desc.flags & DIC_FLAG_DETERMINISTIC_BWD) != 0; }
@@ -219,11 +223,13 @@ dic_status_t prepare_lut(dic_plan_t p, const float* def, hipStream_t s, bool for
 
 dic_status_t enqueue_search(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
                             const int32_t* seed, int32_t* uv, float* zn, int32_t* status,
-                            hipStream_t s) {
+                            hipStream_t s, bool def_ready = false) {
   if (p->fp32()) {
     const std::vector<SearchGroup> groups = search_groups(p, p->tuning.search_block);
-    dic_status_t r = prepare_deformed(p, def, s, false);
-    if (r) return r;
+    if (!def_ready) {
+      dic_status_t r = prepare_deformed(p, def, s, false);
+      if (r) return r;
+    }
     DIC_HIP(launch_reset_counters(p->st, s));
     if (p->tuning.search_block == kMfmaBlock)
       DIC_HIP(launch_search_mfma(p->st, p->tuning, groups.data(), (int)groups.size(), ref, def,
@@ -276,10 +282,26 @@ struct CorrArgs {
   int32_t* status;
 };
 
+// Search then refine.  In the FP32 form the deformed-side box sums (when not
+// cached) run on the plan's side stream beside the reference-side
+// preparation: the two read different images and write different sections.
 dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s) {
+  const bool fork = p->fp32() && !((p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->def_valid &&
+                                   p->def_img == a.def);
+  if (fork) {
+    if (!p->side_stream) DIC_HIP(hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking));
+    if (!p->ev_fork) DIC_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    if (!p->ev_join) DIC_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+    DIC_HIP(hipEventRecord(p->ev_fork, s));
+    DIC_HIP(hipStreamWaitEvent(p->side_stream, p->ev_fork, 0));
+    dic_status_t r = prepare_deformed(p, a.def, p->side_stream, false);
+    if (r != DIC_SUCCESS) return r;
+    DIC_HIP(hipEventRecord(p->ev_join, p->side_stream));
+  }
   dic_status_t r = prepare(p, a.ref, a.poi, s, false);
+  if (fork) DIC_HIP(hipStreamWaitEvent(s, p->ev_join, 0));
   if (r != DIC_SUCCESS) return r;
-  r = enqueue_search(p, a.ref, a.def, a.poi, a.seed, a.uv, a.zn_int, a.st_int, s);
+  r = enqueue_search(p, a.ref, a.def, a.poi, a.seed, a.uv, a.zn_int, a.st_int, s, fork);
   if (r != DIC_SUCCESS) return r;
   return enqueue_refine(p, a.ref, a.def, a.poi, a.uv, a.st_int, a.p_init, a.p_out, a.zn, a.iters,
                         a.status, s, p->nr());
@@ -440,6 +462,9 @@ void dic_plan_destroy(dic_plan_t p) {
   if (!p) return;
   drop_graphs(p);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   delete p;
 }
 
