@@ -37,6 +37,8 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// four floats at any 4-byte aligned global address (one dwordx4 load)
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
 
 constexpr float kBoundRel = 8.5e-3f;
 constexpr int kXcds = 8;   // accelerator complex dies of the MI355X
@@ -316,7 +318,11 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     if (lane < kMaskWords) mask[lane] = 0u;
     // 2. window g - fbar in bf16, CB chunks of 8 columns per lane at a time;
     //    outside the window or the image, and non-finite pixels, are 0 (their
-    //    candidates are invalid by the box sums)
+    //    candidates are invalid by the box sums).  A window whose staged
+    //    rows and columns all lie in the image (the usual case) is read as
+    //    two 16-byte loads per chunk; otherwise every element's address is
+    //    clamped into the image.
+    const bool interior = wx0 >= 0 && wx0 + WC <= W && wy0 >= 0 && wy0 + wrows <= H;
     constexpr int CB = 4;
 #pragma unroll
     for (int k0 = 0; k0 < CH; k0 += CB) {
@@ -325,11 +331,20 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
       for (int kk = 0; kk < CB; ++kk) {
         const int idx = lane + (k0 + kk) * kWave;
         const int rr = idx / CPR, ch = idx - rr * CPR;
-        const int Yc = min(max(wy0 + rr, 0), H - 1);
+        if (interior) {
+          // rows past the staged ones (not stored) read the last staged row
+          const f32x4u* src = reinterpret_cast<const f32x4u*>(
+              gimg + (int64_t)(wy0 + min(rr, wrows - 1)) * W + wx0 + ch * 8);
+          const f32x4u a = src[0], b = src[1];
+          v[kk][0] = a.x; v[kk][1] = a.y; v[kk][2] = a.z; v[kk][3] = a.w;
+          v[kk][4] = b.x; v[kk][5] = b.y; v[kk][6] = b.z; v[kk][7] = b.w;
+        } else {
+          const int Yc = min(max(wy0 + rr, 0), H - 1);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int Xc = min(max(wx0 + ch * 8 + e, 0), W - 1);
-          v[kk][e] = gimg[(int64_t)Yc * W + Xc];
+          for (int e = 0; e < 8; ++e) {
+            const int Xc = min(max(wx0 + ch * 8 + e, 0), W - 1);
+            v[kk][e] = gimg[(int64_t)Yc * W + Xc];
+          }
         }
       }
 #pragma unroll
@@ -338,13 +353,14 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
         const int rr = idx / CPR, ch = idx - rr * CPR;
         if (k0 + kk < CH && rr < wrows) {
           const int Y = wy0 + rr;
-          const bool rowok = rr < wn && Y >= 0 && Y < H;
+          const bool rowok = rr < wn && (interior || (Y >= 0 && Y < H));
           float w[8];
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
             const int col = ch * 8 + e, X = wx0 + col;
             const float x = v[kk][e];
-            w[e] = (rowok && col < wn && X >= 0 && X < W && isfinite(x)) ? x - c0 : 0.f;
+            w[e] = (rowok && col < wn && (interior || (X >= 0 && X < W)) && isfinite(x)) ? x - c0
+                                                                                       : 0.f;
           }
           const u32x4 pk = {pack_bf16(w[0], w[1]), pack_bf16(w[2], w[3]), pack_bf16(w[4], w[5]),
                             pack_bf16(w[6], w[7])};
