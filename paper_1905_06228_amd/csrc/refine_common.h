@@ -386,9 +386,10 @@ struct LdsPatch {
 
   // Makes [x_lo, x_hi] x [y_lo, y_hi] resident, centred in the patch; false
   // when it cannot fit.  One column per lane (two passes when the side
-  // exceeds 64), eight rows per batch of loads; the loads read clamped, always
-  // valid addresses so a batch is issued back to back, and the pixels outside
-  // the image are replaced by zero afterwards.
+  // exceeds 64).  A patch inside the image is read in batches of 16 rows; one
+  // that is not reads clamped, always valid addresses in batches of eight, so
+  // a batch is issued back to back, and replaces the pixels outside the image
+  // by zero afterwards.
   __device__ __forceinline__ bool ensure(const float* __restrict__ img, int W, int H, int x_lo,
                                          int x_hi, int y_lo, int y_hi, float c0) {
     if (x_lo >= x0 && x_hi < x0 + side && y_lo >= y0 && y_hi < y0 + side) return true;
@@ -397,18 +398,34 @@ struct LdsPatch {
     x0 = x_lo - (side - bw) / 2;
     y0 = y_lo - (side - bh) / 2;
     wave_lds_sync();
-    for (int c = lane_id(); c < side; c += kWave) {
-      const int X = x0 + c;
-      const bool col_in = X >= 0 && X < W;
-      const float* col = img + min(max(X, 0), W - 1);
-      for (int r0 = 0; r0 < side; r0 += 8) {
-        float v[8];
+    if (x0 >= 0 && x0 + side <= W && y0 >= 0 && y0 + side <= H) {
+      // the whole patch lies in the image: no clamping, 16 rows per batch
+      for (int c = lane_id(); c < side; c += kWave) {
+        const float* col = img + (int64_t)y0 * W + x0 + c;
+        for (int r0 = 0; r0 < side; r0 += 16) {
+          float v[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = col[(int64_t)min(max(y0 + r0 + u, 0), H - 1) * W];
+          for (int u = 0; u < 16; ++u) v[u] = col[(int64_t)min(r0 + u, side - 1) * W];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int Y = y0 + r0 + u;
-          if (r0 + u < side) buf[(r0 + u) * P + c] = (col_in && Y >= 0 && Y < H) ? v[u] - c0 : 0.f;
+          for (int u = 0; u < 16; ++u)
+            if (r0 + u < side) buf[(r0 + u) * P + c] = v[u] - c0;
+        }
+      }
+    } else {
+      for (int c = lane_id(); c < side; c += kWave) {
+        const int X = x0 + c;
+        const bool col_in = X >= 0 && X < W;
+        const float* col = img + min(max(X, 0), W - 1);
+        for (int r0 = 0; r0 < side; r0 += 8) {
+          float v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = col[(int64_t)min(max(y0 + r0 + u, 0), H - 1) * W];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int Y = y0 + r0 + u;
+            if (r0 + u < side)
+              buf[(r0 + u) * P + c] = (col_in && Y >= 0 && Y < H) ? v[u] - c0 : 0.f;
+          }
         }
       }
     }
