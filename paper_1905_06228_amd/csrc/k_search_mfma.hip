@@ -323,22 +323,55 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     //    two 16-byte loads per chunk; otherwise every element's address is
     //    clamped into the image.
     const bool interior = wx0 >= 0 && wx0 + WC <= W && wy0 >= 0 && wy0 + wrows <= H;
-    constexpr int CB = 4;
+    auto store_chunk = [&](int k, const float* v) {
+      const int idx = lane + k * kWave;
+      const int rr = idx / CPR, ch = idx - rr * CPR;
+      if (k < CH && rr < wrows) {
+        const int Y = wy0 + rr;
+        const bool rowok = rr < wn && (interior || (Y >= 0 && Y < H));
+        float w[8];
 #pragma unroll
-    for (int k0 = 0; k0 < CH; k0 += CB) {
-      float v[CB][8];
+        for (int e = 0; e < 8; ++e) {
+          const int col = ch * 8 + e, X = wx0 + col;
+          const float x = v[e];
+          w[e] = (rowok && col < wn && (interior || (X >= 0 && X < W)) && isfinite(x)) ? x - c0
+                                                                                     : 0.f;
+        }
+        const u32x4 pk = {pack_bf16(w[0], w[1]), pack_bf16(w[2], w[3]), pack_bf16(w[4], w[5]),
+                          pack_bf16(w[6], w[7])};
+        *reinterpret_cast<u32x4*>(win + rr * wpb + ch * 8) = pk;
+      }
+    };
+    // an interior window's chunks are all requested at once when they fit in
+    // registers (one memory round trip)
+    constexpr int CBI = CH <= 8 ? CH : 4;
+    if (interior) {
 #pragma unroll
-      for (int kk = 0; kk < CB; ++kk) {
-        const int idx = lane + (k0 + kk) * kWave;
-        const int rr = idx / CPR, ch = idx - rr * CPR;
-        if (interior) {
+      for (int k0 = 0; k0 < CH; k0 += CBI) {
+        float v[CBI][8];
+#pragma unroll
+        for (int kk = 0; kk < CBI; ++kk) {
+          const int idx = lane + (k0 + kk) * kWave;
+          const int rr = idx / CPR, ch = idx - rr * CPR;
           // rows past the staged ones (not stored) read the last staged row
           const f32x4u* src = reinterpret_cast<const f32x4u*>(
               gimg + (int64_t)(wy0 + min(rr, wrows - 1)) * W + wx0 + ch * 8);
           const f32x4u a = src[0], b = src[1];
           v[kk][0] = a.x; v[kk][1] = a.y; v[kk][2] = a.z; v[kk][3] = a.w;
           v[kk][4] = b.x; v[kk][5] = b.y; v[kk][6] = b.z; v[kk][7] = b.w;
-        } else {
+        }
+#pragma unroll
+        for (int kk = 0; kk < CBI; ++kk) store_chunk(k0 + kk, v[kk]);
+      }
+    } else {
+      constexpr int CB = 4;
+#pragma unroll
+      for (int k0 = 0; k0 < CH; k0 += CB) {
+        float v[CB][8];
+#pragma unroll
+        for (int kk = 0; kk < CB; ++kk) {
+          const int idx = lane + (k0 + kk) * kWave;
+          const int rr = idx / CPR, ch = idx - rr * CPR;
           const int Yc = min(max(wy0 + rr, 0), H - 1);
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
@@ -346,26 +379,8 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
             v[kk][e] = gimg[(int64_t)Yc * W + Xc];
           }
         }
-      }
 #pragma unroll
-      for (int kk = 0; kk < CB; ++kk) {
-        const int idx = lane + (k0 + kk) * kWave;
-        const int rr = idx / CPR, ch = idx - rr * CPR;
-        if (k0 + kk < CH && rr < wrows) {
-          const int Y = wy0 + rr;
-          const bool rowok = rr < wn && (interior || (Y >= 0 && Y < H));
-          float w[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int col = ch * 8 + e, X = wx0 + col;
-            const float x = v[kk][e];
-            w[e] = (rowok && col < wn && (interior || (X >= 0 && X < W)) && isfinite(x)) ? x - c0
-                                                                                       : 0.f;
-          }
-          const u32x4 pk = {pack_bf16(w[0], w[1]), pack_bf16(w[2], w[3]), pack_bf16(w[4], w[5]),
-                            pack_bf16(w[6], w[7])};
-          *reinterpret_cast<u32x4*>(win + rr * wpb + ch * 8) = pk;
-        }
+        for (int kk = 0; kk < CB; ++kk) store_chunk(k0 + kk, v[kk]);
       }
     }
     wave_lds_sync();
