@@ -213,13 +213,15 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
   constexpr int CH = (16 * KB * CPR + kWave - 1) / kWave;       // window chunks per lane
   constexpr int TPD = 8 * KB + 16;
   constexpr int TG = (TPD - 16) / 2;   // 4-column groups of a template row past the left pad
-  constexpr int TGL = (NMAX * TG + kWave - 1) / kWave;   // groups per lane
+  constexpr int TQ = NMAX / 4;         // the groups a template of this K-block count can fill
+  constexpr int TQL = (NMAX * TQ + kWave - 1) / kWave;   // such groups per lane
+  static_assert(TQ <= TG, "template groups exceed the row");
   const int wpb = Ly.wpb;
-  // the 32 zero elements left of every template row, in both copies, once
-  for (int idx = lane; idx < nmax * 16; idx += kWave) {
-    const int r = idx >> 4, i = idx & 15;
-    te[r * TPD + i] = 0u;
-    to[r * TPD + i] = 0u;
+  // both template copies zero, once: the 32 elements left of every row and
+  // the groups past TQ stay zero; a POI rewrites groups 0..TQ-1 of its rows
+  for (int idx = lane; idx < nmax * TPD; idx += kWave) {
+    te[idx] = 0u;
+    to[idx] = 0u;
   }
 
   // Static assignment: every POI costs about the same, and a device-wide
@@ -280,11 +282,11 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     // 0. the FP32 template as 4-column groups (rows of pitch tp, 16-byte
     //    aligned; groups past tp are zero), requested at once
     const int tq = tp / 4;
-    float4 tv[TGL];
+    float4 tv[TQL];
 #pragma unroll
-    for (int k = 0; k < TGL; ++k) {
-      const int idx = lane + k * kWave, r = idx / TG, qq = idx - r * TG;
-      const bool in = idx < n1 * TG && qq < tq;
+    for (int k = 0; k < TQL; ++k) {
+      const int idx = lane + k * kWave, r = idx / TQ, qq = idx - r * TQ;
+      const bool in = idx < n1 * TQ && qq < tq;
       tv[k] = reinterpret_cast<const float4*>(tm)[in ? r * tq + qq : 0];
     }
 
@@ -294,21 +296,21 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     //    (2i+1, 2i+2).  A group's odd pair (3, 4) takes element 4 from the
     //    next group, which the next lane holds.
 #pragma unroll
-    for (int k = 0; k < TGL; ++k) {
-      const int idx = lane + k * kWave, r = idx / TG, qq = idx - r * TG;
-      const bool in = idx < n1 * TG && qq < tq;
+    for (int k = 0; k < TQL; ++k) {
+      const int idx = lane + k * kWave, r = idx / TQ, qq = idx - r * TQ;
+      const bool in = idx < n1 * TQ && qq < tq;
       const float4 v = in ? tv[k] : make_float4(0.f, 0.f, 0.f, 0.f);
       float nxt = __builtin_bit_cast(
           float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v.x), 0x130, 0xF, 0xF, true));
-      if (k + 1 < TGL) {
-        const int idx1 = (k + 1) * kWave, r1 = idx1 / TG, q1 = idx1 - r1 * TG;
-        const float x1 = (idx1 < n1 * TG && q1 < tq) ? tv[k + 1 < TGL ? k + 1 : k].x : 0.f;
+      if (k + 1 < TQL) {
+        const int idx1 = (k + 1) * kWave, r1 = idx1 / TQ, q1 = idx1 - r1 * TQ;
+        const float x1 = (idx1 < n1 * TQ && q1 < tq) ? tv[k + 1 < TQL ? k + 1 : k].x : 0.f;
         const float lane0 = __builtin_bit_cast(
             float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x1), 0));
         if (lane == kWave - 1) nxt = lane0;
       }
-      if (qq == TG - 1) nxt = 0.f;
-      if (idx < n1 * TG) {
+      if (qq == TQ - 1) nxt = 0.f;
+      if (idx < n1 * TQ) {
         const int base = r * TPD + 16 + 2 * qq;
         *reinterpret_cast<uint2*>(te + base) = make_uint2(pack_bf16(v.x, v.y), pack_bf16(v.z, v.w));
         *reinterpret_cast<uint2*>(to + base) = make_uint2(pack_bf16(v.y, v.z), pack_bf16(v.w, nxt));

@@ -19,8 +19,9 @@ constexpr int kNearCap = 64;   // re-scored candidates kept per POI (a second sw
 // n, and each lane accumulates sum (f - fbar)(g - gbar), sum (g - gbar)^2 and
 // sum g^2 over pixels k = lane, lane + 64, ...; one DPP reduction per sum adds
 // the lanes in a fixed order.  The arithmetic of a candidate does not depend
-// on B or on the other candidates.  Loads are issued eight rounds at a time
-// from clamped, always valid addresses so their latencies overlap.  All 64
+// on B or on the other candidates.  Loads are issued sixteen rounds at a time
+// (a subset of up to 1024 pixels in one batch) from clamped, always valid
+// addresses so their latencies overlap.  All 64
 // lanes of the wave must call it together; z[b] is the same on every lane,
 // -inf for a flat window.
 template <int B>
@@ -43,10 +44,11 @@ __device__ __forceinline__ void rescore_wave(const float* __restrict__ f,
   // pixel k = (r, c) of this lane, advanced by 64 pixels per round
   const int dr = kWave / n1, dc = kWave - dr * n1;
   int r = lane / n1, c = lane - r * n1;
-  for (int k0 = 0; k0 < n; k0 += 8 * kWave) {
-    float fv[8], gv[B][8];
+  constexpr int U = 16;
+  for (int k0 = 0; k0 < n; k0 += U * kWave) {
+    float fv[U], gv[B][U];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
       const bool in = k0 + u * kWave + lane < n;
       const int o = in ? r * W + c : (n1 - 1) * (W + 1);
       fv[u] = fb[o];
@@ -63,7 +65,7 @@ __device__ __forceinline__ void rescore_wave(const float* __restrict__ f,
     for (int b = 0; b < B; ++b) {
       const double gbar = sum_g[b] / (double)n;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < U; ++u) {
         const bool in = k0 + u * kWave + lane < n;
         const double d = in ? (double)gv[b][u] - gbar : 0.0;
         const double e = in ? (double)fv[u] - fbar : 0.0;
