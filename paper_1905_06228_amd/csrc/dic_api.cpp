@@ -230,13 +230,15 @@ dic_status_t enqueue_search(dic_plan_t p, const float* ref, const float* def, co
       dic_status_t r = prepare_deformed(p, def, s, false);
       if (r) return r;
     }
-    DIC_HIP(launch_reset_counters(p->st, s));
-    if (p->tuning.search_block == kMfmaBlock)
+    // the matrix-core form assigns POIs statically and uses no work counter
+    if (p->tuning.search_block == kMfmaBlock) {
       DIC_HIP(launch_search_mfma(p->st, p->tuning, groups.data(), (int)groups.size(), ref, def,
                                  poi, seed, uv, zn, status, p->num_cu, s));
-    else
+    } else {
+      DIC_HIP(launch_reset_counters(p->st, s));
       DIC_HIP(launch_search_f32(p->st, p->tuning, groups.data(), (int)groups.size(), ref, def,
                                 poi, seed, uv, zn, status, p->num_cu, s));
+    }
   } else {
     DIC_HIP(launch_search_f64(p->st, p->dpairs.data(), ref, def, poi, seed, uv, zn, status, s));
   }
