@@ -108,7 +108,7 @@ def test_identical_images_and_integer_shift():
     g = np.ascontiguousarray(big[20 + 2:140 + 2, 20 - 3:140 - 3])   # (du, dv) = (3, -2)
     pois = dicgen.poi_grid(120, 120, 10, 6, 11)
     # The FP64 form reproduces the exact answer; the FP32 form's right-hand side
-    # is a difference of compensated FP32 sums, so it lands within ~1e-7 px.
+    # is a difference of blocked FP32 sums, so it lands within ~1e-7 px.
     for name, prec in PRECISIONS:
         atol = 0.0 if prec == dic.FP64_PLAIN else 1e-6
         _, same = run_pair(f, f, pois, 10, 6, prec)
