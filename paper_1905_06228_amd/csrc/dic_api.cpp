@@ -48,7 +48,8 @@ const dic_tuning_t kDefaultTuning = {8, 0, 4, 4};  // block, occupancy, waves, s
 // to radius maxM.
 bool search_fits(int maxM, int maxS, int block) {
   if (block == kMfmaBlock)
-    return maxS <= kMfmaMaxS && search_mfma_wave_lds(mfma_kb(maxM), maxM) <= 160 * 1024;
+    return maxS <= kMfmaWideMaxS &&
+           search_mfma_wave_lds(mfma_kb(maxM), maxM, maxS > kMfmaMaxS) <= 160 * 1024;
   return search_lds_bytes(maxM, maxS, block) <= 160 * 1024 &&
          search_threads(maxS, block) <= search_max_threads();
 }

@@ -110,15 +110,17 @@ hipError_t launch_search_f32(const DevState& st, const dic_tuning_t& tu,
 // +-kMfmaMaxS, grouped by the number of 16-wide K blocks a template row of
 // 2M+1 plus the 32 Toeplitz shifts spans.
 constexpr int kMfmaBlock = 32;
-constexpr int kMfmaMaxS = 16;
+constexpr int kMfmaMaxS = 16;       // one tile, or two for a 33 x 33 window
+constexpr int kMfmaWideMaxS = 31;   // 2 x 2 tiles of 32 x 32 candidates
 __host__ __device__ __forceinline__ int mfma_kb(int M) { return (2 * M + 48) / 16; }
 hipError_t launch_search_mfma(const DevState& st, const dic_tuning_t& tu,
                               const SearchGroup* groups, int ngroups, const float* ref,
                               const float* def, const int32_t* poi, const int32_t* seed,
                               int32_t* uv, float* zncc, int32_t* status, int num_cu,
                               hipStream_t s);
-// LDS bytes of one matrix-core search wave (one wave per workgroup).
-size_t search_mfma_wave_lds(int kb, int maxM);
+// LDS bytes of one matrix-core search wave (one wave per workgroup); `wide`
+// for windows beyond +-kMfmaMaxS.
+size_t search_mfma_wave_lds(int kb, int maxM, bool wide);
 // Template row length the search kernel with tile width `block` uses.
 __host__ __device__ __forceinline__ int search_np(int M, int block) {
   return (2 * M + 1 + block - 1) / block * block;

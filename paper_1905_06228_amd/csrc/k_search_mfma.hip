@@ -42,27 +42,30 @@ typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
 
 constexpr float kBoundRel = 8.5e-3f;
 constexpr int kXcds = 8;   // accelerator complex dies of the MI355X
-constexpr int kMaskWords = 36;   // >= ceil(33 * 33 / 32)
+constexpr int kMaskWords = 36;        // >= ceil(33 * 33 / 32)
+constexpr int kMaskWordsWide = 128;   // >= ceil(64 * 64 / 32)
 
-// Per-wave LDS layout for K-block count KB and subsets up to nmax wide.
+// Per-wave LDS layout for K-block count KB and subsets up to nmax wide; TT
+// tiles of 32 candidates per direction (TT = 2: the window is 32 rows and
+// columns wider).
 struct MfmaLayout {
   int wpb;     // window row pitch (bf16 elements)
   int tpd;     // template row pitch (dwords)
   int win, te, to, mask, edge, total;   // byte offsets / size
 };
 
-__host__ __device__ __forceinline__ MfmaLayout mfma_layout(int KB, int nmax) {
+__host__ __device__ __forceinline__ MfmaLayout mfma_layout(int KB, int nmax, int TT = 1) {
   MfmaLayout L;
-  L.wpb = 16 * KB + 8;
+  L.wpb = 16 * KB + 32 * (TT - 1) + 8;
   L.tpd = 8 * KB + 16;
   L.win = 0;
-  const int wrows = nmax + 32;
+  const int wrows = nmax + 32 * TT;
   L.te = (wrows * L.wpb * 2 + 127) / 128 * 128;
   const int tbytes = nmax * L.tpd * 4;
   // odd copy 16 banks (64 bytes) past a 128-byte boundary after the even one
   L.to = (L.te + tbytes + 127) / 128 * 128 + 64;
   L.mask = L.to + tbytes;
-  L.edge = L.mask + kMaskWords * 4;
+  L.edge = L.mask + (TT == 2 ? kMaskWordsWide : kMaskWords) * 4;
   L.total = (L.edge + 64 * 4 + 15) / 16 * 16;
   return L;
 }
@@ -187,12 +190,16 @@ __device__ __forceinline__ int64_t box_index(const ScoreCtx& q, int dv, int du) 
 
 }  // namespace
 
-size_t search_mfma_wave_lds(int kb, int maxM) {
+size_t search_mfma_wave_lds(int kb, int maxM, bool wide) {
   const int nmax = min(16 * kb - 32, 2 * maxM + 1);
-  return (size_t)mfma_layout(kb, nmax).total;
+  return (size_t)mfma_layout(kb, nmax, wide ? 2 : 1).total;
 }
 
-template <int KB>
+// TT = 1: windows up to 33 x 33 candidates (one tile, or two sharing their
+// window fragments for 33 x 33).  TT = 2: windows of 34..64 per side, covered
+// by 2 x 2 tiles of 32 x 32 candidates at (dv, du) offsets (32a, 32b), each
+// the TT = 1 product on the window shifted by 32a rows and 32b columns.
+template <int KB, int TT>
 __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     DevState st, const int32_t* __restrict__ work, int64_t count, int nmax,
     const float* __restrict__ tmpl_arena, const double* __restrict__ box,
@@ -200,17 +207,17 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     const int32_t* __restrict__ seed, int32_t* __restrict__ uv_out, float* __restrict__ zncc_out,
     int32_t* __restrict__ status_out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  const MfmaLayout Ly = mfma_layout(KB, nmax);
+  const MfmaLayout Ly = mfma_layout(KB, nmax, TT);
   uint16_t* win = reinterpret_cast<uint16_t*>(lds_raw + Ly.win);
   uint32_t* te = reinterpret_cast<uint32_t*>(lds_raw + Ly.te);
   uint32_t* to = reinterpret_cast<uint32_t*>(lds_raw + Ly.to);
   uint32_t* mask = reinterpret_cast<uint32_t*>(lds_raw + Ly.mask);
   float* edge = reinterpret_cast<float*>(lds_raw + Ly.edge);
   const int lane = lane_id(), n = lane & 31, kg = lane >> 5;
-  constexpr int WC = 16 * KB;        // staged window columns
-  constexpr int CPR = WC / 8;        // 8-element chunks per window row
-  constexpr int NMAX = 16 * KB - 32; // widest subset of this K-block count
-  constexpr int CH = (16 * KB * CPR + kWave - 1) / kWave;       // window chunks per lane
+  constexpr int WC = 16 * KB + 32 * (TT - 1);   // staged window columns
+  constexpr int CPR = WC / 8;                   // 8-element chunks per window row
+  constexpr int NMAX = 16 * KB - 32;            // widest subset of this K-block count
+  constexpr int CH = ((NMAX + 32 * TT) * CPR + kWave - 1) / kWave;   // window chunks per lane
   constexpr int TPD = 8 * KB + 16;
   constexpr int TG = (TPD - 16) / 2;   // 4-column groups of a template row past the left pad
   constexpr int TQ = NMAX / 4;         // the groups a template of this K-block count can fill
@@ -264,7 +271,7 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     const float c0 = (float)R->fbar;
     const int wx0 = x0 + cu - S - M, wy0 = y0 + cv - S - M;
     const int wn = n1 + side - 1;   // real window side
-    const int wrows = n1 + 32;      // staged rows (the second tile reads up to n1 + 31)
+    const int wrows = n1 + 32 * TT;   // staged rows (a tile reads up to 32 (TT - 1) + n1 + 31)
     const int tp = P.tmpl_pitch;
     const float* tm = tmpl_arena + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * tp;
     const bool two = side == 33;
@@ -317,7 +324,12 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
         if (qq == 0) to[base - 1] = pack_bf16(0.f, v.x);
       }
     }
-    if (lane < kMaskWords) mask[lane] = 0u;
+    if constexpr (TT == 2) {
+      mask[lane] = 0u;
+      mask[lane + kWave] = 0u;
+    } else {
+      if (lane < kMaskWords) mask[lane] = 0u;
+    }
     // 2. window g - fbar in bf16, CB chunks of 8 columns per lane at a time;
     //    outside the window or the image, and non-finite pixels, are 0 (their
     //    candidates are invalid by the box sums).  A window whose staged
@@ -387,106 +399,158 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     }
     wave_lds_sync();
 
-    // 3. cross terms on the matrix cores
-    f32x16 acc_a = {}, acc_b = {};
-    if (two)
-      correlate_tiles<KB, true>(win, te, to, n1, wpb, TPD, acc_a, acc_b);
-    else
-      correlate_tiles<KB, false>(win, te, to, n1, wpb, TPD, acc_a, acc_b);
-    // box sums of every candidate this lane scores, requested at once: 16 of
-    // tile A, then one edge candidate of tile B (lanes 0..62) or the two
-    // corners (lane 63); their latency overlaps the corner sums below
-    float2 sta[16];
+    // 3.-5. cross terms on the matrix cores, approximate coefficients and
+    //    their bounds, and the bit set of the candidates that may hold the
+    //    FP64 maximum
+    float tau = -INFINITY;
+    if constexpr (TT == 1) {
+      // 3. cross terms on the matrix cores
+      f32x16 acc_a = {}, acc_b = {};
+      if (two)
+        correlate_tiles<KB, true>(win, te, to, n1, wpb, TPD, acc_a, acc_b);
+      else
+        correlate_tiles<KB, false>(win, te, to, n1, wpb, TPD, acc_a, acc_b);
+      // box sums of every candidate this lane scores, requested at once: 16 of
+      // tile A, then one edge candidate of tile B (lanes 0..62) or the two
+      // corners (lane 63); their latency overlaps the corner sums below
+      float2 sta[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) sta[j] = stimg[box_index(q, (j & 3) + 8 * (j >> 2) + 4 * kg, n)];
-    // edge candidates: lane b < 32 -> (32, b + 1); 32 <= b < 63 -> (b - 31, 32);
-    // lane 63 -> corners (32, 0) and (0, 32)
-    const int e0v = lane < 32 ? 32 : lane < 63 ? lane - 31 : 32;
-    const int e0u = lane < 32 ? lane + 1 : lane < 63 ? 32 : 0;
-    const int e1v = 0, e1u = 32;
-    const float2 ste0 = stimg[box_index(q, e0v, e0u)];
-    const float2 ste1 = stimg[box_index(q, e1v, e1u)];
+      for (int j = 0; j < 16; ++j) sta[j] = stimg[box_index(q, (j & 3) + 8 * (j >> 2) + 4 * kg, n)];
+      // edge candidates: lane b < 32 -> (32, b + 1); 32 <= b < 63 -> (b - 31, 32);
+      // lane 63 -> corners (32, 0) and (0, 32)
+      const int e0v = lane < 32 ? 32 : lane < 63 ? lane - 31 : 32;
+      const int e0u = lane < 32 ? lane + 1 : lane < 63 ? 32 : 0;
+      const int e1v = 0, e1u = 32;
+      const float2 ste0 = stimg[box_index(q, e0v, e0u)];
+      const float2 ste1 = stimg[box_index(q, e1v, e1u)];
 
-    // the two corners on the vector ALUs
-    float cr1 = 0.f, cr2 = 0.f;   // corners (dv, du) = (32, 0) and (0, 32)
-    if (two) {
-      double s_a = 0.0, s_b = 0.0;
-      const int dr = kWave / n1, dc = kWave - dr * n1;
-      int r = lane / n1, c = lane - r * n1;
+      // the two corners on the vector ALUs
+      float cr1 = 0.f, cr2 = 0.f;   // corners (dv, du) = (32, 0) and (0, 32)
+      if (two) {
+        double s_a = 0.0, s_b = 0.0;
+        const int dr = kWave / n1, dc = kWave - dr * n1;
+        int r = lane / n1, c = lane - r * n1;
 #pragma unroll 4
-      for (int k = lane; k < nn; k += kWave) {
-        const double t = (double)tmpl_elem(te + r * TPD, c + 32);
-        s_a += t * (double)__builtin_bit_cast(float, (uint32_t)win[(r + 32) * wpb + c] << 16);
-        s_b += t * (double)__builtin_bit_cast(float, (uint32_t)win[r * wpb + c + 32] << 16);
-        c += dc;
-        r += dr;
-        if (c >= n1) {
-          c -= n1;
-          ++r;
+        for (int k = lane; k < nn; k += kWave) {
+          const double t = (double)tmpl_elem(te + r * TPD, c + 32);
+          s_a += t * (double)__builtin_bit_cast(float, (uint32_t)win[(r + 32) * wpb + c] << 16);
+          s_b += t * (double)__builtin_bit_cast(float, (uint32_t)win[r * wpb + c + 32] << 16);
+          c += dc;
+          r += dr;
+          if (c >= n1) {
+            c -= n1;
+            ++r;
+          }
         }
+        cr1 = (float)wave_sum_dpp(s_a);
+        cr2 = (float)wave_sum_dpp(s_b);
+        // tile B's edge row dv = 32 and column du = 32, one value per lane
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int i = (j & 3) + 8 * (j >> 2) + 4 * kg;
+          if (i == 31) edge[n] = acc_b[j];               // (32, n + 1)
+          else if (n == 31) edge[32 + i] = acc_b[j];     // (i + 1, 32), i < 31
+        }
+        wave_lds_sync();
       }
-      cr1 = (float)wave_sum_dpp(s_a);
-      cr2 = (float)wave_sum_dpp(s_b);
-      // tile B's edge row dv = 32 and column du = 32, one value per lane
+
+      // 4. approximate coefficients, their bounds, and the threshold
+      float sa[16], ea[16];
+      float lo = -INFINITY;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int i = (j & 3) + 8 * (j >> 2) + 4 * kg;
-        if (i == 31) edge[n] = acc_b[j];               // (32, n + 1)
-        else if (n == 31) edge[32 + i] = acc_b[j];     // (i + 1, 32), i < 31
+        sa[j] = score_of(q, acc_a[j], i, n, sta[j], ea[j]);
+        lo = fmaxf(lo, sa[j] - ea[j]);
       }
-      wave_lds_sync();
-    }
-
-    // 4. approximate coefficients, their bounds, and the threshold
-    float sa[16], ea[16];
-    float lo = -INFINITY;
+      float s0 = -INFINITY, e0 = 0.f, s1 = -INFINITY, e1 = 0.f;
+      if (two) {
+        const float c_e0 = lane < 63 ? edge[lane] : cr1;
+        s0 = score_of(q, c_e0, e0v, e0u, ste0, e0);
+        if (lane == 63) s1 = score_of(q, cr2, e1v, e1u, ste1, e1);
+        lo = fmaxf(lo, fmaxf(s0 - e0, s1 - e1));
+      }
+      tau = wave_max_dpp(lo);
+      if (tau > -INFINITY) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int i = (j & 3) + 8 * (j >> 2) + 4 * kg;
-      sa[j] = score_of(q, acc_a[j], i, n, sta[j], ea[j]);
-      lo = fmaxf(lo, sa[j] - ea[j]);
+        for (int j = 0; j < 16; ++j)
+          if (sa[j] + ea[j] >= tau) {
+            const int cand = ((j & 3) + 8 * (j >> 2) + 4 * kg) * side + n;
+            atomicOr(&mask[cand >> 5], 1u << (cand & 31));
+          }
+        if (s0 + e0 >= tau) {
+          const int cand = e0v * side + e0u;
+          atomicOr(&mask[cand >> 5], 1u << (cand & 31));
+        }
+        if (s1 + e1 >= tau) {
+          const int cand = e1v * side + e1u;
+          atomicOr(&mask[cand >> 5], 1u << (cand & 31));
+        }
+      }
+    } else {
+      // 2 x 2 tiles, the one holding the window centre first.  The running
+      // threshold only grows, so a tile's bits (set against the threshold
+      // after it) are a superset of those the final threshold selects; the
+      // FP64 re-score decides among them.
+      float lo = -INFINITY;
+#pragma unroll 1
+      for (int t = 0; t < 4; ++t) {
+        const int a = t >> 1, b = t & 1;
+        if (32 * a >= side || 32 * b >= side) continue;
+        f32x16 acc = {}, acc_unused = {};
+        correlate_tiles<KB, false>(win + 32 * a * wpb + 32 * b, te, to, n1, wpb, TPD, acc,
+                                   acc_unused);
+        float2 stt[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          stt[j] = stimg[box_index(q, 32 * a + (j & 3) + 8 * (j >> 2) + 4 * kg, 32 * b + n)];
+        float st_s[16], st_e[16];
+        float l = lo;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int i = 32 * a + (j & 3) + 8 * (j >> 2) + 4 * kg;
+          st_s[j] = score_of(q, acc[j], i, 32 * b + n, stt[j], st_e[j]);
+          l = fmaxf(l, st_s[j] - st_e[j]);
+        }
+        lo = wave_max_dpp(l);
+        if (lo > -INFINITY) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (st_s[j] + st_e[j] >= lo) {
+              const int cand = (32 * a + (j & 3) + 8 * (j >> 2) + 4 * kg) * side + 32 * b + n;
+              atomicOr(&mask[cand >> 5], 1u << (cand & 31));
+            }
+        }
+      }
+      tau = lo;
     }
-    float s0 = -INFINITY, e0 = 0.f, s1 = -INFINITY, e1 = 0.f;
-    if (two) {
-      const float c_e0 = lane < 63 ? edge[lane] : cr1;
-      s0 = score_of(q, c_e0, e0v, e0u, ste0, e0);
-      if (lane == 63) s1 = score_of(q, cr2, e1v, e1u, ste1, e1);
-      lo = fmaxf(lo, fmaxf(s0 - e0, s1 - e1));
-    }
-    const float tau = wave_max_dpp(lo);
 
-    // 5. the candidates that may hold the FP64 maximum: a bit set, then the
-    //    list of its members in index order (lane e holds the e-th)
+    // the list of the bit set's members in index order (lane e holds the e-th)
     int pick = -1;
     double best = -INFINITY;
     if (tau > -INFINITY) {
-#pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (sa[j] + ea[j] >= tau) {
-          const int cand = ((j & 3) + 8 * (j >> 2) + 4 * kg) * side + n;
-          atomicOr(&mask[cand >> 5], 1u << (cand & 31));
-        }
-      if (s0 + e0 >= tau) {
-        const int cand = e0v * side + e0u;
-        atomicOr(&mask[cand >> 5], 1u << (cand & 31));
-      }
-      if (s1 + e1 >= tau) {
-        const int cand = e1v * side + e1u;
-        atomicOr(&mask[cand >> 5], 1u << (cand & 31));
-      }
       wave_lds_sync();
+      constexpr int kHalves = TT == 2 ? 2 : 1;   // mask words per lane
       const int words = (K + 31) / 32;
-      const uint32_t myword = lane < words ? mask[lane] : 0u;
-      const uint64_t nonempty = __ballot(myword != 0u);
-      int count = 0, mycand = 0;
-      for (uint64_t ws = nonempty; ws; ws &= ws - 1) {
-        const int w = __builtin_ctzll(ws);
-        for (uint32_t bits = (uint32_t)__builtin_amdgcn_readlane((int)myword, w); bits;
-             bits &= bits - 1) {
-          if (lane == count) mycand = 32 * w + __builtin_ctz(bits);
-          ++count;
-        }
+      uint32_t myword[kHalves];
+      uint64_t nonempty[kHalves];
+#pragma unroll
+      for (int h = 0; h < kHalves; ++h) {
+        const int wi = kWave * h + lane;
+        myword[h] = wi < words ? mask[wi] : 0u;
+        nonempty[h] = __ballot(myword[h] != 0u);
       }
+      int count = 0, mycand = 0;
+#pragma unroll
+      for (int h = 0; h < kHalves; ++h)
+        for (uint64_t ws = nonempty[h]; ws; ws &= ws - 1) {
+          const int w = __builtin_ctzll(ws);
+          for (uint32_t bits = (uint32_t)__builtin_amdgcn_readlane((int)myword[h], w); bits;
+               bits &= bits - 1) {
+            if (lane == count) mycand = 32 * (kWave * h + w) + __builtin_ctz(bits);
+            ++count;
+          }
+        }
 
       // 6. FP64 re-score, two candidates per pass over the subset; the
       //    first candidate in index order within 1e-12 of the maximum wins.
@@ -507,12 +571,14 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
       // calls fn(cand) for the members past the 64th, in index order, while it returns true
       auto walk_rest = [&](auto&& fn) {
         int e = 0;
-        for (uint64_t ws = nonempty; ws; ws &= ws - 1) {
-          const int w = __builtin_ctzll(ws);
-          for (uint32_t bits = (uint32_t)__builtin_amdgcn_readlane((int)myword, w); bits;
-               bits &= bits - 1, ++e)
-            if (e >= kWave && !fn(32 * w + __builtin_ctz(bits))) return;
-        }
+#pragma unroll
+        for (int h = 0; h < kHalves; ++h)
+          for (uint64_t ws = nonempty[h]; ws; ws &= ws - 1) {
+            const int w = __builtin_ctzll(ws);
+            for (uint32_t bits = (uint32_t)__builtin_amdgcn_readlane((int)myword[h], w); bits;
+                 bits &= bits - 1, ++e)
+              if (e >= kWave && !fn(32 * (kWave * h + w) + __builtin_ctz(bits))) return;
+          }
       };
       const int listed = min(count, kWave);
       double keep = -INFINITY, cmax = -INFINITY;
@@ -573,29 +639,55 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
   }
 }
 
-template <int KB>
-static hipError_t launch_search_mfma_kb(const DevState& st, const SearchGroup& gr, int occ_cap, const float* ref, const float* def,
-                                        const int32_t* poi, const int32_t* seed, int32_t* uv,
-                                        float* zncc, int32_t* status, int num_cu, hipStream_t s) {
+template <int KB, int TT>
+static hipError_t launch_search_mfma_kb(const DevState& st, const SearchGroup& gr, int occ_cap,
+                                        const float* ref, const float* def, const int32_t* poi,
+                                        const int32_t* seed, int32_t* uv, float* zncc,
+                                        int32_t* status, int num_cu, hipStream_t s) {
   const int nmax = min(16 * KB - 32, 2 * st.maxM + 1);
-  const size_t lds = search_mfma_wave_lds(KB, st.maxM);
-  const void* fn = reinterpret_cast<const void*>(&search_mfma_kernel<KB>);
+  const size_t lds = search_mfma_wave_lds(KB, st.maxM, TT == 2);
+  const void* fn = reinterpret_cast<const void*>(&search_mfma_kernel<KB, TT>);
   if (lds > 65536) {
     hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ea != hipSuccess) return ea;
   }
   int occ = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, search_mfma_kernel<KB>, kWave, lds);
+  hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, search_mfma_kernel<KB, TT>, kWave, lds);
   if (e != hipSuccess) return e;
   if (occ < 1) return hipErrorInvalidConfiguration;
   if (occ_cap > 0 && occ > occ_cap) occ = occ_cap;
   int64_t blocks = (int64_t)occ * num_cu;
   if (blocks > gr.count) blocks = gr.count;
   if (blocks >= kXcds) blocks -= blocks % kXcds;
-  hipLaunchKernelGGL(search_mfma_kernel<KB>, dim3((unsigned)blocks), dim3(kWave), lds, s, st,
-                     st.work + gr.begin, gr.count, nmax, st.tmpl, st.box, ref, def, poi, seed,
+  hipLaunchKernelGGL((search_mfma_kernel<KB, TT>), dim3((unsigned)blocks), dim3(kWave), lds, s,
+                     st, st.work + gr.begin, gr.count, nmax, st.tmpl, st.box, ref, def, poi, seed,
                      uv, zncc, status);
   return hipGetLastError();
+}
+
+template <int TT>
+static hipError_t launch_search_mfma_tt(const DevState& st, const dic_tuning_t& tu,
+                                        const SearchGroup* groups, int ngroups, const float* ref,
+                                        const float* def, const int32_t* poi,
+                                        const int32_t* seed, int32_t* uv, float* zncc,
+                                        int32_t* status, int num_cu, hipStream_t s) {
+  for (int k = 0; k < ngroups; ++k) {
+    const SearchGroup& gr = groups[k];
+    if (gr.count == 0) continue;
+    hipError_t e = hipErrorInvalidValue;
+    if (gr.np == 3)
+      e = launch_search_mfma_kb<3, TT>(st, gr, tu.search_occupancy, ref, def, poi, seed, uv,
+                                       zncc, status, num_cu, s);
+    else if (gr.np == 4)
+      e = launch_search_mfma_kb<4, TT>(st, gr, tu.search_occupancy, ref, def, poi, seed, uv,
+                                       zncc, status, num_cu, s);
+    else if (gr.np == 5)
+      e = launch_search_mfma_kb<5, TT>(st, gr, tu.search_occupancy, ref, def, poi, seed, uv,
+                                       zncc, status, num_cu, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_search_mfma(const DevState& st, const dic_tuning_t& tu,
@@ -603,23 +695,13 @@ hipError_t launch_search_mfma(const DevState& st, const dic_tuning_t& tu,
                               const float* def, const int32_t* poi, const int32_t* seed,
                               int32_t* uv, float* zncc, int32_t* status, int num_cu,
                               hipStream_t s) {
-  if (ngroups > kMaxSearchGroups || st.maxS > kMfmaMaxS) return hipErrorInvalidValue;
-  for (int k = 0; k < ngroups; ++k) {
-    const SearchGroup& gr = groups[k];
-    if (gr.count == 0) continue;
-    hipError_t e = hipErrorInvalidValue;
-    if (gr.np == 3)
-      e = launch_search_mfma_kb<3>(st, gr, tu.search_occupancy, ref, def, poi,
-                                   seed, uv, zncc, status, num_cu, s);
-    else if (gr.np == 4)
-      e = launch_search_mfma_kb<4>(st, gr, tu.search_occupancy, ref, def, poi,
-                                   seed, uv, zncc, status, num_cu, s);
-    else if (gr.np == 5)
-      e = launch_search_mfma_kb<5>(st, gr, tu.search_occupancy, ref, def, poi,
-                                   seed, uv, zncc, status, num_cu, s);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  if (ngroups > kMaxSearchGroups || st.maxS > kMfmaWideMaxS) return hipErrorInvalidValue;
+  // windows beyond +-kMfmaMaxS in the plan: every POI takes the 2 x 2 tile form
+  if (st.maxS > kMfmaMaxS)
+    return launch_search_mfma_tt<2>(st, tu, groups, ngroups, ref, def, poi, seed, uv, zncc,
+                                    status, num_cu, s);
+  return launch_search_mfma_tt<1>(st, tu, groups, ngroups, ref, def, poi, seed, uv, zncc, status,
+                                  num_cu, s);
 }
 
 }  // namespace dic

@@ -72,11 +72,18 @@ def test_plan_create_and_workspace(L):
 
 
 def test_search_form_follows_radius(L):
-    """Windows beyond +-16 use the vector-ALU search form; the matrix-core
-    form is refused for them."""
-    rc, h = make(L, [(512, 512, 12, 20, 0, 0, 0, 100)])
-    assert rc == 0
+    """Windows up to +-31 default to the matrix-core search form (2 x 2 tiles
+    beyond +-16); beyond that the vector-ALU form runs and the matrix-core
+    form is refused."""
     t = Tuning()
+    for S in (16, 20, 31):
+        rc, h = make(L, [(512, 512, 12, S, 0, 0, 0, 100)])
+        assert rc == 0
+        L.dic_plan_get_tuning(h, ctypes.byref(t))
+        assert t.search_block == 32, S
+        L.dic_plan_destroy(h)
+    rc, h = make(L, [(512, 512, 12, 32, 0, 0, 0, 100)])
+    assert rc == 0
     L.dic_plan_get_tuning(h, ctypes.byref(t))
     assert t.search_block == 8
     assert L.dic_plan_set_tuning(h, ctypes.byref(Tuning(32, 0, 4, 4))) == -4

@@ -2,9 +2,9 @@
 with FP64 decision, and the vector-ALU form) against the FP64 oracle's
 brute-force search (Sec. 2.1, Eq. (1)): integer displacements and statuses
 bit-exact, coefficients within 1e-5, and the two forms bit-identical to each
-other.  Cases cover every K-block count of the matrix-core kernel, one and two
-candidate tiles, seeded windows, windows leaving the image, NaN pixels, and
-more exact ties than the re-score list holds."""
+other.  Cases cover every K-block count of the matrix-core kernel, one, two
+and 2 x 2 candidate tiles (radius up to 31), seeded windows, windows leaving
+the image, NaN pixels, and more exact ties than the re-score list holds."""
 import numpy as np
 import pytest
 import torch
@@ -107,13 +107,40 @@ def test_forms_exact_ties_beyond_list():
     both_forms(f, f, pois, M, S, ref, "ties")
 
 
-def test_valu_form_wide_seeded_window():
-    """Radius 24 (beyond the matrix-core form): the vector-ALU form alone, on
-    seeded windows as the frame sequence uses them."""
-    pr = dicgen.affine_pair_1024(size=200, M=14, S=24, step=9, tag=73)
-    pois = pr.pois[::2]
-    rng = np.random.default_rng(74)
+@pytest.mark.parametrize("M,S,size", [(14, 24, 200), (10, 17, 160), (5, 31, 176), (20, 20, 220)])
+def test_wide_windows_match_oracle(M, S, size):
+    """Radius 17..31: the matrix-core form's 2 x 2 tiles (34 to 63 candidates
+    a side, K blocks 3, 4 and 5) and the vector-ALU form, on seeded windows
+    as the frame sequence uses them."""
+    pr = dicgen.affine_pair_1024(size=size, M=M, S=S, step=9, tag=73 + S)
+    pois = pr.pois[:: max(1, len(pr.pois) // 40)]
+    rng = np.random.default_rng(74 + S)
     seeds = rng.integers(-4, 5, size=(len(pois), 2)).astype(np.int32)
-    print(f"case valu wide window M=14 S=24 N={len(pois)}", flush=True)
-    ref = oracle_search(pr.ref, pr.defm, pois, 14, 24, seeds)
-    check(gpu_search(pr.ref, pr.defm, pois, 14, 24, VALU, seeds), ref, "M14S24/valu")
+    print(f"case wide window M={M} S={S} N={len(pois)}", flush=True)
+    ref = oracle_search(pr.ref, pr.defm, pois, M, S, seeds)
+    both_forms(pr.ref, pr.defm, pois, M, S, ref, f"wide M{M}S{S}", seeds)
+
+
+def test_wide_windows_border_nan_and_ties():
+    """Radius 24: windows leaving the image (clamped staging), NaN pixels,
+    and exact ties across the four tiles (stripes: every du ties)."""
+    pr = dicgen.affine_pair_1024(size=160, M=8, S=24, step=9, tag=79)
+    g = pr.defm.copy()
+    g[60:63, 90:92] = np.nan
+    xs = [9, 20, 40, 80, 120, 150]
+    pois = np.array([(x, y) for x in xs for y in xs], dtype=np.int32)
+    rng = np.random.default_rng(80)
+    seeds = rng.integers(-8, 9, size=(len(pois), 2)).astype(np.int32)
+    print(f"case wide border/nan N={len(pois)}", flush=True)
+    ref = oracle_search(pr.ref, g, pois, 8, 24, seeds)
+    assert np.any(ref["status"] == O.OK)
+    both_forms(pr.ref, g, pois, 8, 24, ref, "wide border", seeds)
+    H, W = 160, 160
+    y = np.arange(H, dtype=np.float64)[:, None]
+    f = (120 + 40 * np.sin(0.05 * y) + 15 * np.sin(0.13 * y + 1.0)).repeat(W, axis=1)
+    f = f.astype(np.float32)
+    tp = np.array([(80, 50), (80, 80), (76, 100)], dtype=np.int32)
+    print(f"case wide ties N={len(tp)}", flush=True)
+    ref = oracle_search(f, f, tp, 8, 24)
+    assert np.all(ref["uv"][:, 0] == -24)
+    both_forms(f, f, tp, 8, 24, ref, "wide ties")
