@@ -142,7 +142,8 @@ typedef struct {
                                with that many candidates per lane along du (a
                                workgroup has one lane per tile of the widest
                                window, at most 1024); 32 = matrix-core form
-                               (bf16 filter, FP64 decision; radii up to 16)  */
+                               (bf16 filter, FP64 decision; radii up to 31,
+                               2 x 2 candidate tiles beyond 16)             */
   int32_t search_occupancy; /* resident search workgroups per CU, 0 = as many
                                as registers and LDS allow, else 1..16        */
   int32_t icgn_waves;      /* waves (POIs in flight) per refinement workgroup
@@ -213,7 +214,7 @@ dic_status_t dic_prepare_deformed(dic_plan_t plan, const float* def_images,
  * The winner is the smallest (dv, du), row-major, among candidates within
  * 1e-12 of the maximum coefficient.  The FP32 batched form first scores
  * every candidate approximately (bf16 matrix-core products with a rigorous
- * error bound for radii up to 16 and subsets up to 41 x 41, FP32 vector
+ * error bound for radii up to 31 and subsets up to 41 x 41, FP32 vector
  * sums otherwise), keeps every candidate whose bound still reaches the
  * maximum, and evaluates Eq. (1) for those in FP64 before the tie rule; the
  * winner and its FP64 coefficient (rounded to float) do not depend on the
