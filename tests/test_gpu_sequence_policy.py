@@ -94,3 +94,31 @@ def test_live_policy_skips_and_matches_oracle(frames):
     for a, b in zip(outs, seq):
         for key in b:
             np.testing.assert_array_equal(a[key].cpu().numpy(), b[key].cpu().numpy(), err_msg=key)
+
+
+def test_camera_scale_pair_sampled():
+    """One pair of the 4096 x 3000 camera sequence (frames 1 and 2, ~600k
+    blobs, noise 3; 239,932 POIs, subset 29 x 29, search +-24, so the
+    matrix-core form with 2 x 2 tiles) in the launch configuration of the
+    sequence benchmark; 24 seeded POIs checked against the oracle one by one,
+    the increment against the generating field at every POI."""
+    H, W, M, S, step = 3000, 4096, 14, 24, 7
+    fr = dicgen.sequence_frames_torch(3, H, W, 600_000, noise=3.0, tag=5, pad=96.0,
+                                      device=torch.device("cuda", 0))
+    pois = dicgen.poi_grid(W, H, M, S, step)
+    Q = to_dev(pois)
+    print(f"case camera pair N={len(pois)}", flush=True)
+    got = dic.correlate_sequence([fr[1], fr[2]], Q, M, S, reference="previous")[0]
+    torch.cuda.synchronize()
+    h = host(got)
+    f1, f2 = fr[1].cpu().numpy(), fr[2].cpu().numpy()
+    idx = np.sort(np.random.default_rng(19).choice(len(pois), 24, replace=False))
+    ref = O.correlate(f1, f2, pois[idx], M, S)
+    compare(h, ref, idx=idx, label="camera pair sampled")
+    ok = h["status"] == O.OK
+    assert ok.mean() > 0.99
+    truth = dicgen.true_increment(dicgen.heterogeneous_strain(1), dicgen.heterogeneous_strain(2),
+                                  pois[ok])
+    err = np.abs(h["p"][ok][:, [0, 3]] - truth)
+    print(f"[camera pair] ok={ok.mean():.4f} mean err={err.mean():.4f} px", flush=True)
+    assert err.mean() < 0.02
