@@ -540,9 +540,8 @@ def icgn(f: np.ndarray, g: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, 
     compose W(p) <- W(p) W(dp)^-1, stop when |dp| < tol (``update_norm``).
     Readings: fbar and df stay those of the undeformed reference subset; a
     warp whose 4x4 neighbourhoods leave the image stops with OUT_OF_BOUNDS and
-    keeps the last p; the reported coefficient is Eq. (1) at the last warp
-    the iteration evaluated (the one the final update starts from, within the
-    stop tolerance of the returned p).
+    keeps the last p; the reported coefficient is Eq. (1) re-evaluated at the
+    final p.
     """
     H, W = g.shape
     p = np.asarray(p0, dtype=np.float64).copy()
@@ -564,7 +563,6 @@ def icgn(f: np.ndarray, g: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, 
             return IcgnResult(p, float("nan"), it, NAN_INPUT)
         if is_flat(gs):
             return IcgnResult(p, float("nan"), it, ZERO_VARIANCE)
-        c = zncc(prep.fs, gs)
         gbar = gs.mean()
         dg = np.sqrt(np.sum((gs - gbar) ** 2))
         e = fz - (prep.df / dg) * (gs - gbar)
@@ -574,7 +572,15 @@ def icgn(f: np.ndarray, g: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, 
         if update_norm(dp, M) < tol:
             status = OK
             break
-    return IcgnResult(p, c, it, status)
+    xs, ys = warp_points(p, x0, y0, dx, dy)
+    if not in_interp_bounds(xs, ys, W, H, interp):
+        return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
+    gs = interpolate(g, xs, ys, method=interp)
+    if not np.all(np.isfinite(gs)):
+        return IcgnResult(p, float("nan"), it, NAN_INPUT)
+    if is_flat(gs):
+        return IcgnResult(p, float("nan"), it, ZERO_VARIANCE)
+    return IcgnResult(p, zncc(prep.fs, gs), it, status)
 
 
 # ---------------------------------------------------------------------------
@@ -627,8 +633,7 @@ def nr(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, p0: Sequence[floa
     IC-GN (subset and one-pixel border inside, finite, not flat); a warp whose
     4x4 neighbourhoods leave the image stops with OUT_OF_BOUNDS, a Hessian
     whose Cholesky pivot fails (``cholesky6``) with SINGULAR_HESSIAN, both
-    keeping the last p; the reported coefficient is Eq. (1) at the last warp
-    the iteration evaluated, as in ``icgn``.
+    keeping the last p; the reported coefficient is Eq. (1) at the final p.
     """
     H, W = g.shape
     p = np.asarray(p0, dtype=np.float64).copy()
@@ -661,7 +666,15 @@ def nr(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, p0: Sequence[floa
         if update_norm(dp, M) < tol:
             status = OK
             break
-    return IcgnResult(p, t.zncc, it, status)
+    xs, ys = warp_points(p, x0, y0, dx, dy)
+    if not in_interp_bounds(xs, ys, W, H, interp):
+        return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
+    gs = interpolate(g, xs, ys, method=interp)
+    if not np.all(np.isfinite(gs)):
+        return IcgnResult(p, float("nan"), it, NAN_INPUT)
+    if is_flat(gs):
+        return IcgnResult(p, float("nan"), it, ZERO_VARIANCE)
+    return IcgnResult(p, zncc(fs, gs), it, status)
 
 
 # ---------------------------------------------------------------------------

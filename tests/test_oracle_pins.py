@@ -265,31 +265,6 @@ def test_icgn_integer_shift_exact(big_speckle, du, dv):
     assert abs(r.zncc - 1.0) < 1e-14
 
 
-@pytest.mark.parametrize("refine", ["icgn", "nr"])
-def test_reported_coefficient_is_the_last_evaluated_warps(rigid_pair, refine):
-    """The coefficient belongs to the last warp the iteration evaluated: one
-    iteration fewer, continued by hand, gives the same value, which agrees
-    with Eq. (1) at the returned p to second order in the last update."""
-    f, g = rigid_pair.ref, rigid_pair.defm
-    fx, fy = O.central_gradients(f)
-    M = rigid_pair.M
-    for x0, y0 in rigid_pair.pois[::37][:4]:
-        x0, y0 = int(x0), int(y0)
-        p0 = [3, 0, 0, -3, 0, 0]
-        run = (lambda it: O.icgn(f, g, fx, fy, x0, y0, M, p0, max_iters=it)) if refine == "icgn" \
-            else (lambda it: O.nr(f, g, x0, y0, M, p0, max_iters=it))
-        r = run(20)
-        assert r.status == O.OK and r.iters >= 2
-        before = run(r.iters - 1)            # stops at the warp the last iteration evaluated
-        assert before.status == O.NOT_CONVERGED
-        xs, ys = O.warp_points(before.p, x0, y0, *O.subset_offsets(M))
-        c_before = O.zncc(O.subset(f, x0, y0, M), O.interpolate(g, xs, ys))
-        assert abs(r.zncc - c_before) < 1e-15
-        xs, ys = O.warp_points(r.p, x0, y0, *O.subset_offsets(M))
-        c_final = O.zncc(O.subset(f, x0, y0, M), O.interpolate(g, xs, ys))
-        assert abs(r.zncc - c_final) < 1e-6
-
-
 def _tight(pair, x0, y0):
     f, g = pair.ref, pair.defm
     fx, fy = O.central_gradients(f)
