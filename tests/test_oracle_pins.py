@@ -265,6 +265,27 @@ def test_icgn_integer_shift_exact(big_speckle, du, dv):
     assert abs(r.zncc - 1.0) < 1e-14
 
 
+@pytest.mark.parametrize("max_iters", [2, 20])
+def test_reported_coefficient_is_eq1_at_the_returned_warp(rigid_pair, max_iters):
+    """IC-GN and Newton-Raphson report Eq. (1) at the p they return (also when
+    stopped by the iteration cap): the Pearson coefficient (numpy's corrcoef)
+    of the reference subset and the deformed image interpolated at W(p)."""
+    pr = rigid_pair
+    f, g = pr.ref, pr.defm
+    fx, fy = O.central_gradients(f)
+    dx, dy = O.subset_offsets(pr.M)
+    for x0, y0 in pr.pois[::97][:4]:
+        s = O.integer_search(f, g, x0, y0, pr.M, pr.S)
+        p0 = [s.du, 0, 0, s.dv, 0, 0]
+        for r in (O.icgn(f, g, fx, fy, x0, y0, pr.M, p0, max_iters=max_iters, tol=1e-9),
+                  O.nr(f, g, x0, y0, pr.M, p0, max_iters=max_iters, tol=1e-9)):
+            assert r.status in (O.OK, O.NOT_CONVERGED)
+            xs, ys = O.warp_points(r.p, x0, y0, dx, dy)
+            gs = O.interpolate(g.astype(np.float64), xs, ys)
+            c = np.corrcoef(O.subset(f, x0, y0, pr.M).ravel(), gs.ravel())[0, 1]
+            assert abs(r.zncc - c) < 1e-12
+
+
 def _tight(pair, x0, y0):
     f, g = pair.ref, pair.defm
     fx, fy = O.central_gradients(f)
