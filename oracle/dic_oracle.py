@@ -19,7 +19,9 @@ MATLAB"):
   (Eqs. 2-4) and its modified form with a star step evaluate at most
   250 / 1250 positions (Sec. 5.2).
 * Sec. 2.2: a pixel's grey level is the value at its centre; bicubic
-  interpolation; IC-GN with an affine (first-order) warp whose reference-side
+  interpolation (Eq. (5) bilinear and cubic B-spline interpolation as the
+  cheaper and the higher-order alternatives the section names); IC-GN with
+  an affine (first-order) warp whose reference-side
   quantities (gradients, steepest-descent images, Hessian) are precomputed;
   Newton-Raphson, whose quantities are recomputed at every iteration.
 
@@ -345,8 +347,8 @@ def cubic_dweights(t: np.ndarray) -> np.ndarray:
 
 def in_interp_bounds(xs: np.ndarray, ys: np.ndarray, width: int, height: int,
                      method: str = "bicubic") -> bool:
-    """All interpolation neighbourhoods inside the image: 4x4 for bicubic
-    (1 <= floor <= size - 3), 2x2 for bilinear (0 <= floor <= size - 2)."""
+    """All interpolation neighbourhoods inside the image: 4x4 for bicubic and
+    B-spline (1 <= floor <= size - 3), 2x2 for bilinear (0 <= floor <= size - 2)."""
     ix = np.floor(xs)
     iy = np.floor(ys)
     lo, hi = (0, 1) if method == "bilinear" else (1, 2)
@@ -378,17 +380,73 @@ def bilinear(g: np.ndarray, xs: np.ndarray, ys: np.ndarray, with_grad: bool = Fa
     return val, a10 + a11 * y1, a01 + a11 * x1
 
 
+# ---------------------------------------------------------------------------
+# Sec. 2.2: spline interpolation (cubic B-spline, the higher-order method
+# named beside bicubic)
+# ---------------------------------------------------------------------------
+
+def bspline_weights(t: np.ndarray) -> np.ndarray:
+    """Cubic B-spline basis at taps -1, 0, 1, 2 relative to floor(x), given
+    t = x - floor(x): (1-t)^3/6, (3t^3 - 6t^2 + 4)/6, (-3t^3 + 3t^2 + 3t + 1)/6,
+    t^3/6.  Shape [..., 4]."""
+    t = np.asarray(t, dtype=np.float64)
+    s = 1.0 - t
+    return np.stack([s ** 3 / 6, (3 * t ** 3 - 6 * t ** 2 + 4) / 6,
+                     (-3 * t ** 3 + 3 * t ** 2 + 3 * t + 1) / 6, t ** 3 / 6], axis=-1)
+
+
+def bspline_dweights(t: np.ndarray) -> np.ndarray:
+    """d/dt of ``bspline_weights``."""
+    t = np.asarray(t, dtype=np.float64)
+    s = 1.0 - t
+    return np.stack([-s ** 2 / 2, (9 * t ** 2 - 12 * t) / 6,
+                     (-9 * t ** 2 + 6 * t + 3) / 6, t ** 2 / 2], axis=-1)
+
+
+def _bspline_system(n: int) -> np.ndarray:
+    """The interpolation condition along one axis of n samples: the spline's
+    value at node k is (c[k-1] + 4 c[k] + c[k+1]) / 6, with the coefficients
+    extended symmetrically about the end samples (c[-1] = c[1],
+    c[n] = c[n-2]), as the image is."""
+    A = np.zeros((n, n))
+    for k in range(n):
+        A[k, k] += 4.0 / 6.0
+        for j in (k - 1, k + 1):
+            jj = -j if j < 0 else (2 * (n - 1) - j if j > n - 1 else j)
+            A[k, jj] += 1.0 / 6.0
+    return A
+
+
+def bspline_coefficients(g: np.ndarray) -> np.ndarray:
+    """Coefficients c of the cubic B-spline that passes through every pixel
+    of g (the interpolant is sum_{l,k} b_l(ty) b_k(tx) c[floor(y)+l,
+    floor(x)+k] and equals g at the pixel centres): the interpolation
+    condition solved exactly along the rows, then along the columns
+    (``_bspline_system``).  Reading: an image with a non-finite pixel has no
+    such spline, and all its coefficients are NaN."""
+    g = np.asarray(g, dtype=np.float64)
+    H, W = g.shape
+    if not np.all(np.isfinite(g)):
+        return np.full((H, W), np.nan)
+    c = np.linalg.solve(_bspline_system(W), g.T).T
+    return np.linalg.solve(_bspline_system(H), c)
+
+
 def interpolate(g: np.ndarray, xs: np.ndarray, ys: np.ndarray,
                 with_grad: bool = False, method: str = "bicubic"):
     """g at sub-pixel points: sum_{l,k} w_l(ty) w_k(tx) g[floor(y)+l, floor(x)+k],
     k, l in {-1, 0, 1, 2} (Keys bicubic), or Eq. (5) with method="bilinear".
+    With method="bspline" ``g`` holds B-spline coefficients
+    (``bspline_coefficients``) and the weights are the cubic B-spline basis.
     Optionally the analytic gradient of the interpolant."""
     if method == "bilinear":
         return bilinear(g, xs, ys, with_grad)
+    wf, dwf = (bspline_weights, bspline_dweights) if method == "bspline" else \
+        (cubic_weights, cubic_dweights)
     ix = np.floor(xs).astype(np.int64)
     iy = np.floor(ys).astype(np.int64)
-    wx = cubic_weights(xs - ix)
-    wy = cubic_weights(ys - iy)
+    wx = wf(xs - ix)
+    wy = wf(ys - iy)
     taps = np.empty(xs.shape + (4, 4))
     for l in range(4):
         for k in range(4):
@@ -396,8 +454,8 @@ def interpolate(g: np.ndarray, xs: np.ndarray, ys: np.ndarray,
     val = np.einsum("...l,...lk,...k->...", wy, taps, wx)
     if not with_grad:
         return val
-    dwx = cubic_dweights(xs - ix)
-    dwy = cubic_dweights(ys - iy)
+    dwx = dwf(xs - ix)
+    dwy = dwf(ys - iy)
     gx = np.einsum("...l,...lk,...k->...", wy, taps, dwx)
     gy = np.einsum("...l,...lk,...k->...", dwy, taps, wx)
     return val, gx, gy
@@ -530,9 +588,20 @@ class IcgnResult:
     status: int
 
 
+def _interp_source(g: np.ndarray, interp: str, gcoef: Optional[np.ndarray]) -> np.ndarray:
+    """The array the interpolation weights apply to: the image itself, or its
+    B-spline coefficients."""
+    if interp not in ("bicubic", "bilinear", "bspline"):
+        raise ValueError(f"unknown interpolation {interp!r}")
+    if interp != "bspline":
+        return g
+    return bspline_coefficients(g) if gcoef is None else gcoef
+
+
 def icgn(f: np.ndarray, g: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, y0: int,
          M: int, p0: Sequence[float], max_iters: int = 20, tol: float = 1e-3,
-         prep: Optional[RefPrep] = None, interp: str = "bicubic") -> IcgnResult:
+         prep: Optional[RefPrep] = None, interp: str = "bicubic",
+         gcoef: Optional[np.ndarray] = None) -> IcgnResult:
     """IC-GN on the ZNSSD criterion with a first-order warp.
 
     Per iteration: warp the subset with W(p), interpolate g, form
@@ -541,10 +610,12 @@ def icgn(f: np.ndarray, g: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, 
     Readings: fbar and df stay those of the undeformed reference subset; a
     warp whose 4x4 neighbourhoods leave the image stops with OUT_OF_BOUNDS and
     keeps the last p; the reported coefficient is Eq. (1) re-evaluated at the
-    final p.
+    final p.  ``interp`` is "bicubic", "bilinear" or "bspline" (then
+    ``gcoef``, when given, is ``bspline_coefficients(g)``, computed otherwise).
     """
     H, W = g.shape
     p = np.asarray(p0, dtype=np.float64).copy()
+    src = _interp_source(g, interp, gcoef)
     if prep is None:
         prep = reference_prep(f, fx, fy, x0, y0, M)
     if prep.status != OK:
@@ -558,7 +629,7 @@ def icgn(f: np.ndarray, g: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, 
         xs, ys = warp_points(p, x0, y0, dx, dy)
         if not in_interp_bounds(xs, ys, W, H, interp):
             return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
-        gs = interpolate(g, xs, ys, method=interp)
+        gs = interpolate(src, xs, ys, method=interp)
         if not np.all(np.isfinite(gs)):
             return IcgnResult(p, float("nan"), it, NAN_INPUT)
         if is_flat(gs):
@@ -575,7 +646,7 @@ def icgn(f: np.ndarray, g: np.ndarray, fx: np.ndarray, fy: np.ndarray, x0: int, 
     xs, ys = warp_points(p, x0, y0, dx, dy)
     if not in_interp_bounds(xs, ys, W, H, interp):
         return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
-    gs = interpolate(g, xs, ys, method=interp)
+    gs = interpolate(src, xs, ys, method=interp)
     if not np.all(np.isfinite(gs)):
         return IcgnResult(p, float("nan"), it, NAN_INPUT)
     if is_flat(gs):
@@ -620,7 +691,8 @@ def nr_terms(fs: np.ndarray, gs: np.ndarray, gx: np.ndarray, gy: np.ndarray,
 
 
 def nr(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, p0: Sequence[float],
-       max_iters: int = 20, tol: float = 1e-3, interp: str = "bicubic") -> IcgnResult:
+       max_iters: int = 20, tol: float = 1e-3, interp: str = "bicubic",
+       gcoef: Optional[np.ndarray] = None) -> IcgnResult:
     """Newton-Raphson refinement (Sec. 2.2: the method whose parameters are
     recomputed at every iteration, in contrast to IC-GN) on the ZNSSD
     criterion with the first-order warp applied forward, x_i = x0 + W(p) xi_i,
@@ -637,6 +709,7 @@ def nr(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, p0: Sequence[floa
     """
     H, W = g.shape
     p = np.asarray(p0, dtype=np.float64).copy()
+    src = _interp_source(g, interp, gcoef)
     if not poi_inside(x0, y0, M, f.shape[1], f.shape[0]):
         return IcgnResult(p, float("nan"), 0, OUT_OF_BOUNDS)
     fs = subset(f, x0, y0, M)
@@ -652,7 +725,7 @@ def nr(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, p0: Sequence[floa
         xs, ys = warp_points(p, x0, y0, dx, dy)
         if not in_interp_bounds(xs, ys, W, H, interp):
             return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
-        gs, gx, gy = interpolate(g, xs, ys, with_grad=True, method=interp)
+        gs, gx, gy = interpolate(src, xs, ys, with_grad=True, method=interp)
         if not (np.all(np.isfinite(gs)) and np.all(np.isfinite(gx)) and np.all(np.isfinite(gy))):
             return IcgnResult(p, float("nan"), it, NAN_INPUT)
         if is_flat(gs):
@@ -669,7 +742,7 @@ def nr(f: np.ndarray, g: np.ndarray, x0: int, y0: int, M: int, p0: Sequence[floa
     xs, ys = warp_points(p, x0, y0, dx, dy)
     if not in_interp_bounds(xs, ys, W, H, interp):
         return IcgnResult(p, float("nan"), it, OUT_OF_BOUNDS)
-    gs = interpolate(g, xs, ys, method=interp)
+    gs = interpolate(src, xs, ys, method=interp)
     if not np.all(np.isfinite(gs)):
         return IcgnResult(p, float("nan"), it, NAN_INPUT)
     if is_flat(gs):
@@ -773,6 +846,7 @@ def correlate(f: np.ndarray, g: np.ndarray, pois: np.ndarray, M: int, S: int,
     gradient terms of ``p_init`` when given)."""
     N = pois.shape[0]
     fx, fy = central_gradients(f)
+    gcoef = bspline_coefficients(g) if interp == "bspline" else None
     out = dict(uv=np.zeros((N, 2), np.int32), zncc_int=np.full(N, np.nan),
                status_int=np.zeros(N, np.int32), p=np.zeros((N, 6)),
                zncc=np.full(N, np.nan), iters=np.zeros(N, np.int32),
@@ -795,9 +869,9 @@ def correlate(f: np.ndarray, g: np.ndarray, pois: np.ndarray, M: int, S: int,
         if p_init is not None:
             p0[[1, 2, 4, 5]] = p_init[i, [1, 2, 4, 5]]
         if refine == "nr":
-            r = nr(f, g, x0, y0, M, p0, max_iters, tol, interp=interp)
+            r = nr(f, g, x0, y0, M, p0, max_iters, tol, interp=interp, gcoef=gcoef)
         else:
-            r = icgn(f, g, fx, fy, x0, y0, M, p0, max_iters, tol, interp=interp)
+            r = icgn(f, g, fx, fy, x0, y0, M, p0, max_iters, tol, interp=interp, gcoef=gcoef)
         out["p"][i] = r.p
         out["zncc"][i] = r.zncc
         out["iters"][i] = r.iters
