@@ -384,6 +384,33 @@ def main() -> int:
                      "max_vs_taps_px": float(np.abs(lpn[okl][:, [0, 3]] - cp[okl][:, [0, 3]]
                                                     ).max(initial=0)),
                      "status_equal_to_taps": float((lst == cst).mean())}
+    # cubic B-spline interpolation (the spline option of Sec. 2.2): the
+    # refinements with the coefficient image cached and with it recomputed,
+    # and the accuracy against the true field beside bicubic's
+    bsp = {}
+    for name, nrf in (("icgn", False), ("nr", True)):
+        bo = tuple(torch.empty_like(x) for x in (so["p"], so["zncc"], so["iters"], so["status"]))
+        t_s = {}
+        for cached in (True, False):
+            sp = dic.single_pair_plan(W, H, pair.M, pair.S, N, dic.FP32_BATCHED,
+                                      flags=dic.FLAG_INTERP_BSPLINE
+                                      | (dic.FLAG_CACHE_REF_PREP if cached else 0))
+            sp.tuning = plan.tuning
+            fn = sp.nr_refine if nrf else sp.icgn_refine
+            t_s[cached] = time_launches(
+                torch, lambda: fn(F, G, Q, so["uv"], so["status_int"], out=bo), reps)
+        spn, sit, sst = bo[0].cpu().numpy(), bo[2].cpu().numpy(), bo[3].cpu().numpy()
+        cp, cst = ref_err[name][0].cpu().numpy(), ref_err[name][1].cpu().numpy()
+        oks, okc = sst == 0, cst == 0
+        es = np.abs(spn[oks][:, [0, 3]] - truth[oks])
+        ec = np.abs(cp[okc][:, [0, 3]] - truth[okc])
+        bsp[name] = {"refine_ms": round(t_s[True], 4),
+                     "refine_with_coefficients_ms": round(t_s[False], 4),
+                     "bicubic_refine_ms": round(t_icgn if name == "icgn" else t_nr, 4),
+                     "mean_iterations": float(sit[oks].mean()) if oks.any() else 0.0,
+                     "ok_fraction": float(oks.mean()),
+                     "mean_abs_error_px": float(es.mean()) if oks.any() else None,
+                     "bicubic_mean_abs_error_px": float(ec.mean()) if okc.any() else None}
     # particle swarm searches (Sec. 2.1, Eqs. 2-4) on the same pair, and the
     # modified swarm + Newton-Raphson pipeline (the paper's fastest combination)
     Rs = torch.from_numpy(dicgen.swarm_random(N, 7)).to(dev)
@@ -510,6 +537,7 @@ def main() -> int:
         "particle_swarm": swarm,
         "bilinear": bil,
         "bicubic_lut": lut,
+        "bspline": bsp,
     }
     if args.copy_probe_mb > 0:
         n = args.copy_probe_mb * (1 << 20) // 4

@@ -99,7 +99,7 @@ enum {
                                          instead of bicubically; FP32
                                          batched plans only; the ZNSSD
                                          adjoint rejects such plans         */
-  DIC_FLAG_BICUBIC_LUT = 1u << 5      /* IC-GN and Newton-Raphson evaluate
+  DIC_FLAG_BICUBIC_LUT = 1u << 5,     /* IC-GN and Newton-Raphson evaluate
                                          the bicubic interpolant from a
                                          table of its 16 polynomial
                                          coefficients per pixel cell (the
@@ -111,6 +111,23 @@ enum {
                                          up to FP32 rounding.  FP32 batched
                                          plans only; exclusive with
                                          DIC_FLAG_INTERP_BILINEAR           */
+  DIC_FLAG_INTERP_BSPLINE = 1u << 6   /* IC-GN and Newton-Raphson interpolate
+                                         g with the cubic B-spline through
+                                         its pixels (the spline
+                                         interpolation of Sec. 2.2): the
+                                         spline's coefficient image is
+                                         computed from each deformed image
+                                         before the refinement (mirror
+                                         boundary, 8 bytes per pixel of
+                                         workspace) and sampled with 4x4
+                                         taps; same bounds as bicubic; an
+                                         image with a non-finite pixel gives
+                                         DIC_POI_NAN_INPUT at every POI the
+                                         refinement reaches.  FP32 batched
+                                         plans only; exclusive with
+                                         DIC_FLAG_INTERP_BILINEAR and
+                                         DIC_FLAG_BICUBIC_LUT; the ZNSSD
+                                         adjoint rejects such plans         */
 };
 
 typedef struct {
@@ -199,7 +216,8 @@ dic_status_t dic_prepare_reference(dic_plan_t plan, const float* ref_images,
 /* Deformed-side precomputation for the FP32 search: for every subset centre
  * of every deformed image, the exact (FP64) sums of g and g^2 over the
  * subset, so each candidate's normalisation is a lookup; with
- * DIC_FLAG_BICUBIC_LUT also the bicubic coefficient table.  Called
+ * DIC_FLAG_BICUBIC_LUT also the bicubic coefficient table, with
+ * DIC_FLAG_INTERP_BSPLINE the B-spline coefficient image.  Called
  * implicitly by dic_integer_search / dic_correlate (the table by the
  * refinements) unless DIC_FLAG_CACHE_REF_PREP holds a valid cache for this
  * `def_images` pointer (then call it again, or dic_plan_invalidate_reference,

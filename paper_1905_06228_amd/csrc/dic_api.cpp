@@ -38,7 +38,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t pairs = 0, poi_pair = 0, work = 0, counters = 0, grads = 0, recs = 0, tmpl = 0,
-         box = 0, lut = 0, fix_off = 0, fix = 0, s_status = 0, s_zncc = 0, total = 0;
+         box = 0, lut = 0, bsp_flags = 0, fix_off = 0, fix = 0, s_status = 0, s_zncc = 0,
+         total = 0;
   int64_t fix_count = 0;
 };
 
@@ -98,8 +99,15 @@ struct dic_plan_s {
   bool nr() const { return (desc.flags & DIC_FLAG_REFINE_NR) != 0; }
   bool bilinear() const { return (desc.flags & DIC_FLAG_INTERP_BILINEAR) != 0; }
   bool lut() const { return (desc.flags & DIC_FLAG_BICUBIC_LUT) != 0; }
+  bool bspline() const { return (desc.flags & DIC_FLAG_INTERP_BSPLINE) != 0; }
+  // a per-image table the refinements read: bicubic coefficients or the
+  // B-spline coefficient image
+  bool table() const { return lut() || bspline(); }
   int interp() const {
-    return bilinear() ? kInterpBilinear : lut() ? kInterpBicubicLut : kInterpBicubic;
+    return bilinear()  ? kInterpBilinear
+           : lut()     ? kInterpBicubicLut
+           : bspline() ? kInterpBSpline
+                       : kInterpBicubic;
   }
 };
 
@@ -210,13 +218,17 @@ dic_status_t prepare_deformed(dic_plan_t p, const float* def, hipStream_t s, boo
   return DIC_SUCCESS;
 }
 
-// The bicubic coefficient table of the deformed images (plans with
-// DIC_FLAG_BICUBIC_LUT), cached like the box sums.
+// The bicubic coefficient table (DIC_FLAG_BICUBIC_LUT) or the B-spline
+// coefficient image (DIC_FLAG_INTERP_BSPLINE) of the deformed images,
+// cached like the box sums.
 dic_status_t prepare_lut(dic_plan_t p, const float* def, hipStream_t s, bool force) {
-  if (!p->lut()) return DIC_SUCCESS;
+  if (!p->table()) return DIC_SUCCESS;
   if (!force && (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->lut_valid && p->lut_img == def)
     return DIC_SUCCESS;
-  DIC_HIP(launch_bicubic_lut(p->st, def, s));
+  if (p->lut())
+    DIC_HIP(launch_bicubic_lut(p->st, def, s));
+  else
+    DIC_HIP(launch_bspline_coeffs(p->st, def, s));
   p->lut_valid = true;
   p->lut_img = def;
   return DIC_SUCCESS;
@@ -340,15 +352,23 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
     return fail(DIC_ERR_INVALID_ARGUMENT, "conv_tol must be positive and finite");
   const uint32_t known = DIC_FLAG_USE_GRAPH | DIC_FLAG_CACHE_REF_PREP |
                          DIC_FLAG_DETERMINISTIC_BWD | DIC_FLAG_REFINE_NR |
-                         DIC_FLAG_INTERP_BILINEAR | DIC_FLAG_BICUBIC_LUT;
+                         DIC_FLAG_INTERP_BILINEAR | DIC_FLAG_BICUBIC_LUT |
+                         DIC_FLAG_INTERP_BSPLINE;
   if (d->flags & ~known) return fail(DIC_ERR_INVALID_ARGUMENT, "unknown flag bits");
   if ((d->flags & DIC_FLAG_INTERP_BILINEAR) && d->precision != DIC_FP32_BATCHED)
     return fail(DIC_ERR_UNSUPPORTED, "bilinear interpolation needs the FP32 batched form");
   if ((d->flags & DIC_FLAG_BICUBIC_LUT) && d->precision != DIC_FP32_BATCHED)
     return fail(DIC_ERR_UNSUPPORTED, "the bicubic coefficient table needs the FP32 batched form");
-  if ((d->flags & DIC_FLAG_BICUBIC_LUT) && (d->flags & DIC_FLAG_INTERP_BILINEAR))
-    return fail(DIC_ERR_INVALID_ARGUMENT,
-                "DIC_FLAG_BICUBIC_LUT and DIC_FLAG_INTERP_BILINEAR are exclusive");
+  if ((d->flags & DIC_FLAG_INTERP_BSPLINE) && d->precision != DIC_FP32_BATCHED)
+    return fail(DIC_ERR_UNSUPPORTED, "B-spline interpolation needs the FP32 batched form");
+  {
+    const uint32_t im = d->flags & (DIC_FLAG_INTERP_BILINEAR | DIC_FLAG_BICUBIC_LUT |
+                                    DIC_FLAG_INTERP_BSPLINE);
+    if (im & (im - 1))
+      return fail(DIC_ERR_INVALID_ARGUMENT,
+                  "DIC_FLAG_INTERP_BILINEAR, DIC_FLAG_BICUBIC_LUT and DIC_FLAG_INTERP_BSPLINE "
+                  "are exclusive");
+  }
   auto p = new dic_plan_s();
   p->desc = *d;
   p->pairs.assign(d->pairs, d->pairs + d->num_pairs);
@@ -392,6 +412,7 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
   L.counters = take(sizeof(int32_t) * kNumCounters);
   int64_t gfl = 0, tfl = 0, bxd = 0, lut4 = 0, fix = 0;
   const bool use_lut = (d->flags & DIC_FLAG_BICUBIC_LUT) != 0;
+  const bool use_bsp = (d->flags & DIC_FLAG_INTERP_BSPLINE) != 0;
   p->dpairs.resize(d->num_pairs);
   p->fix_off.resize(d->num_pairs);
   for (int k = 0; k < d->num_pairs; ++k) {
@@ -417,6 +438,7 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
       tfl += q.poi_count * tn;
       bxd += 5 * (int64_t)q.width * q.height;
       if (use_lut) lut4 += 4 * (int64_t)q.width * q.height;
+      if (use_bsp) lut4 += (2 * (int64_t)q.width * q.height + 3) / 4;
     }
     p->fix_off[k] = fix;
     if (p->det()) fix += (int64_t)q.width * q.height;
@@ -430,6 +452,7 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
   L.tmpl = take(sizeof(float) * tfl);
   L.box = take(sizeof(double) * bxd);
   L.lut = take(sizeof(float) * 4 * lut4);
+  L.bsp_flags = take(use_bsp ? sizeof(int32_t) * d->num_pairs : 0);
   L.fix_off = take(sizeof(int64_t) * d->num_pairs);
   L.fix = take(sizeof(unsigned long long) * fix);
   L.fix_count = fix;
@@ -531,6 +554,7 @@ dic_status_t dic_plan_bind(dic_plan_t p, void* ws, size_t bytes, dic_stream_t st
   st.tmpl = reinterpret_cast<float*>(base + p->lay.tmpl);
   st.box = reinterpret_cast<double*>(base + p->lay.box);
   st.lut = reinterpret_cast<float*>(base + p->lay.lut);
+  st.bsp_flags = reinterpret_cast<int32_t*>(base + p->lay.bsp_flags);
   st.N = p->N;
   st.num_pairs = p->desc.num_pairs;
   st.maxM = p->maxM;
@@ -674,7 +698,7 @@ dic_status_t dic_correlate(dic_plan_t p, const float* ref, const float* def, con
   const bool cached_ref = (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->ref_valid &&
                           p->ref_img == ref && p->ref_poi == poi && p->def_valid &&
                           p->def_img == def &&
-                          (!p->lut() || (p->lut_valid && p->lut_img == def));
+                          (!p->table() || (p->lut_valid && p->lut_img == def));
   std::vector<uintptr_t> key = {
       (uintptr_t)ref, (uintptr_t)def, (uintptr_t)poi, (uintptr_t)seed, (uintptr_t)p_init,
       (uintptr_t)uv, (uintptr_t)a.zn_int, (uintptr_t)a.st_int, (uintptr_t)p_out, (uintptr_t)zn,
@@ -712,7 +736,7 @@ dic_status_t dic_znssd_backward(dic_plan_t p, const float* ref, const float* def
   if (r) return r;
   if (p->N == 0) return DIC_SUCCESS;
   if (!ref || !def || !poi || !pw) return fail(DIC_ERR_INVALID_ARGUMENT, "null required pointer");
-  if (p->bilinear())
+  if (p->bilinear() || p->bspline())
     return fail(DIC_ERR_UNSUPPORTED, "the ZNSSD adjoint interpolates bicubically only");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   r = prepare(p, ref, poi, s, false);

@@ -24,6 +24,7 @@ enum Interp : int {
   kInterpBicubic = 0,     // Keys taps from the LDS patch (or the image)
   kInterpBilinear = 1,    // Eq. (5), 2x2 taps from the LDS patch (or the image)
   kInterpBicubicLut = 2,  // Keys interpolant from the per-cell coefficient table
+  kInterpBSpline = 3,     // cubic B-spline, 4x4 taps of the spline coefficient image
 };
 __host__ __device__ constexpr int interp_taps(int im) { return im == kInterpBilinear ? 2 : 4; }
 
@@ -41,7 +42,9 @@ struct DevPair {
                      // column sums of g and g^2, subset sums of g and g^2, and
                      // float pairs (subset mean, 1/sqrt(sum (g - mean)^2))
   int64_t lut_off;   // float4 offset of this pair's [H, W, 4] bicubic coefficient
-                     // table (plans with DIC_FLAG_BICUBIC_LUT only)
+                     // table (DIC_FLAG_BICUBIC_LUT) or of its [H, W] B-spline
+                     // coefficient image followed by an [H, W] scratch image
+                     // (DIC_FLAG_INTERP_BSPLINE)
 };
 
 __host__ __device__ __forceinline__ int template_pitch(int M) { return (2 * M + 1 + 7) / 8 * 8; }
@@ -69,7 +72,10 @@ struct DevState {
   RefRec* recs;             // [N]
   float* tmpl;              // template arena
   double* box;              // box-sum arena (deformed images)
-  float* lut;               // bicubic coefficient tables (deformed images), 16 floats per pixel
+  float* lut;               // bicubic coefficient tables (16 floats per pixel) or B-spline
+                            // coefficient images (1 float per pixel, then 1 of scratch) of
+                            // the deformed images
+  int32_t* bsp_flags;       // per pair: the deformed image has a non-finite pixel (B-spline)
   int64_t N;
   int32_t num_pairs;
   int32_t maxM, maxS;
@@ -93,6 +99,7 @@ hipError_t launch_reset_counters(const DevState& st, hipStream_t s);
 hipError_t launch_gradients(const DevState& st, const float* ref, hipStream_t s);
 hipError_t launch_box_sums(const DevState& st, const float* def, hipStream_t s);
 hipError_t launch_bicubic_lut(const DevState& st, const float* def, hipStream_t s);
+hipError_t launch_bspline_coeffs(const DevState& st, const float* def, hipStream_t s);
 hipError_t launch_pso(const DevState& st, bool modified, const float* ref, const float* def,
                       const int32_t* poi, const int32_t* seed, const float* rand, int32_t* uv,
                       float* zn, int32_t* status, int32_t* gens, int32_t* evals, int num_cu,

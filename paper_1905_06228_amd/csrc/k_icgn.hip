@@ -84,7 +84,9 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
     float zn = nanf("");
     if (status == DIC_POI_OK) {
       const int M = P.M, n1 = 2 * M + 1, n = n1 * n1, W = P.width, H = P.height;
-      const float* gimg = def + P.def_off;
+      // the taps: the image's pixels, or its cubic B-spline coefficients
+      const float* gimg =
+          IM == kInterpBSpline ? st.lut + 4 * P.lut_off : def + P.def_off;
       const float4* glut = reinterpret_cast<const float4*>(st.lut) + P.lut_off;
       const int64_t corner = (int64_t)(y0 - M) * W + (x0 - M);
       const float* gx = st.grads + P.grad_off + corner;
@@ -110,9 +112,9 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
         if constexpr (IM == kInterpBicubicLut)
           iter_pass<MAXS>(LutSampler{glut, W, H, w.bx, w.by, c0}, n, w, fxs, fys, dxy, K);
         else if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
-          iter_pass<MAXS>(patch.template sampler<NT>(w.bx, w.by), n, w, fxs, fys, dxy, K);
+          iter_pass<MAXS>(patch.template sampler<IM>(w.bx, w.by), n, w, fxs, fys, dxy, K);
         else
-          iter_pass<MAXS>(ImageSampler<NT>{gimg, W, H, w.bx, w.by, c0}, n, w, fxs, fys,
+          iter_pass<MAXS>(ImageSampler<IM>{gimg, W, H, w.bx, w.by, c0}, n, w, fxs, fys,
                           dxy, K);
         double S[8];
         wave_sums_f32<8>(K, S);
@@ -155,9 +157,9 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
           if constexpr (IM == kInterpBicubicLut)
             final_pass<MAXS>(LutSampler{glut, W, H, w.bx, w.by, c0}, n, w, dxy, tval, K);
           else if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
-            final_pass<MAXS>(patch.template sampler<NT>(w.bx, w.by), n, w, dxy, tval, K);
+            final_pass<MAXS>(patch.template sampler<IM>(w.bx, w.by), n, w, dxy, tval, K);
           else
-            final_pass<MAXS>(ImageSampler<NT>{gimg, W, H, w.bx, w.by, c0}, n, w, dxy,
+            final_pass<MAXS>(ImageSampler<IM>{gimg, W, H, w.bx, w.by, c0}, n, w, dxy,
                              tval, K);
           double S[3];
           wave_sums_f32<3>(K, S);
@@ -229,6 +231,9 @@ hipError_t launch_icgn_f32(const DevState& st, const dic_tuning_t& tu, const flo
     if (interp == kInterpBilinear)                                                              \
       return launch_icgn_f32_t<S_, kInterpBilinear>(st, tu, def, poi, uv_init, status_in, p_init,  \
                                                     p_out, zncc, iters, status, num_cu, s);      \
+    if (interp == kInterpBSpline)                                                               \
+      return launch_icgn_f32_t<S_, kInterpBSpline>(st, tu, def, poi, uv_init, status_in,        \
+                                                    p_init, p_out, zncc, iters, status, num_cu, s);\
     if (interp == kInterpBicubicLut)                                                            \
       return launch_icgn_f32_t<S_, kInterpBicubicLut>(st, tu, def, poi, uv_init, status_in,     \
                                                       p_init, p_out, zncc, iters, status, num_cu, \

@@ -105,7 +105,9 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
     float zn = nanf("");
     if (status == DIC_POI_OK) {
       const int M = P.M, n1 = 2 * M + 1, n = n1 * n1, W = P.width, H = P.height;
-      const float* gimg = def + P.def_off;
+      // the taps: the image's pixels, or its cubic B-spline coefficients
+      const float* gimg =
+          IM == kInterpBSpline ? st.lut + 4 * P.lut_off : def + P.def_off;
       const float4* glut = reinterpret_cast<const float4*>(st.lut) + P.lut_off;
       const int tp = P.tmpl_pitch;
       const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * tp;
@@ -130,9 +132,9 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
         if constexpr (IM == kInterpBicubicLut)
           nr_pass<MAXS>(LutSampler{glut, W, H, w.bx, w.by, c0}, n, w, tv, dxy, A);
         else if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
-          nr_pass<MAXS>(patch.template sampler<NT>(w.bx, w.by), n, w, tv, dxy, A);
+          nr_pass<MAXS>(patch.template sampler<IM>(w.bx, w.by), n, w, tv, dxy, A);
         else
-          nr_pass<MAXS>(ImageSampler<NT>{gimg, W, H, w.bx, w.by, c0}, n, w, tv, dxy, A);
+          nr_pass<MAXS>(ImageSampler<IM>{gimg, W, H, w.bx, w.by, c0}, n, w, tv, dxy, A);
         // all 42 sums in one reduction, in struct order
         static_assert(sizeof(NrSums) == 42 * sizeof(float), "NrSums layout");
         double S[42];
@@ -193,9 +195,9 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
           if constexpr (IM == kInterpBicubicLut)
             final_pass<MAXS>(LutSampler{glut, W, H, w.bx, w.by, c0}, n, w, dxy, tval, K);
           else if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
-            final_pass<MAXS>(patch.template sampler<NT>(w.bx, w.by), n, w, dxy, tval, K);
+            final_pass<MAXS>(patch.template sampler<IM>(w.bx, w.by), n, w, dxy, tval, K);
           else
-            final_pass<MAXS>(ImageSampler<NT>{gimg, W, H, w.bx, w.by, c0}, n, w, dxy,
+            final_pass<MAXS>(ImageSampler<IM>{gimg, W, H, w.bx, w.by, c0}, n, w, dxy,
                              tval, K);
           double S[3];
           wave_sums_f32<3>(K, S);
@@ -266,6 +268,9 @@ hipError_t launch_nr_f32(const DevState& st, const dic_tuning_t& tu, const float
     if (interp == kInterpBilinear)                                                            \
       return launch_nr_f32_t<S_, kInterpBilinear>(st, tu, def, poi, uv_init, status_in, p_init,  \
                                                   p_out, zncc, iters, status, num_cu, s);      \
+    if (interp == kInterpBSpline)                                                             \
+      return launch_nr_f32_t<S_, kInterpBSpline>(st, tu, def, poi, uv_init, status_in,        \
+                                                  p_init, p_out, zncc, iters, status, num_cu, s);\
     if (interp == kInterpBicubicLut)                                                          \
       return launch_nr_f32_t<S_, kInterpBicubicLut>(st, tu, def, poi, uv_init, status_in,     \
                                                     p_init, p_out, zncc, iters, status, num_cu, \

@@ -206,6 +206,101 @@ __global__ void __launch_bounds__(256) bicubic_lut_kernel(const DevPair* __restr
     out[b] = make_float4((float)rc[b][0], (float)rc[b][1], (float)rc[b][2], (float)rc[b][3]);
 }
 
+// Cubic B-spline coefficients of every deformed image (the spline
+// interpolation of Sec. 2.2): c with (c[k-1] + 4 c[k] + c[k+1]) / 6 = g[k]
+// along each axis, the image extended symmetrically about its end samples.
+// The inverse of that three-tap filter has the impulse response
+// sqrt(3) z^|j| with z = sqrt(3) - 2, so along one axis
+//   c[k] = sqrt(3) sum_j z^|j| g[k + j]
+// over the symmetric extension (index reflected into one period of 2n - 2
+// samples), truncated at |j| <= 16: the terms dropped sum to below 1e-9 of
+// the largest pixel, under FP32 rounding.  Every output is independent: one
+// thread per pixel, the rows pass into a scratch image, the columns pass
+// from it into the coefficient image, FP64 sums rounded once per pass, the
+// 33 loads of a thread coalesced across the wave (L1/L2 hits after the
+// first).  A non-finite pixel has no spline through it: the rows pass sets
+// its pair's flag and the columns pass then writes NaN over the whole image
+// (the recursive form's result, whose recursions carry such a value along
+// every row and column).  Grid: (column blocks, rows, pairs).
+constexpr int kBsplineHalf = 16;
+
+__device__ __forceinline__ int bspline_mirror(int i, int n) {
+  const int per = 2 * n - 2;
+  i %= per;
+  if (i < 0) i += per;
+  return i < n ? i : per - i;
+}
+
+// sqrt(3) sum_{|j| <= 16} z^|j| v(k + j), v read at the reflected index
+template <class V>
+__device__ __forceinline__ double bspline_fir(int k, int n, const V& v) {
+  constexpr double z = -0.2679491924311227;  // sqrt(3) - 2
+  double acc = v(k), w = 1.0;
+  if (k >= kBsplineHalf && k < n - kBsplineHalf) {
+#pragma unroll
+    for (int j = 1; j <= kBsplineHalf; ++j) {
+      w *= z;
+      acc = fma(w, (double)v(k - j) + (double)v(k + j), acc);
+    }
+  } else {
+    for (int j = 1; j <= kBsplineHalf; ++j) {
+      w *= z;
+      acc = fma(w, (double)v(bspline_mirror(k - j, n)) + (double)v(bspline_mirror(k + j, n)),
+                acc);
+    }
+  }
+  return 1.7320508075688772 * acc;  // sqrt(3)
+}
+
+__global__ void __launch_bounds__(256) bspline_flags_kernel(int32_t* __restrict__ flags, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = 0;
+}
+
+__global__ void __launch_bounds__(256) bspline_rows_kernel(const DevPair* __restrict__ pairs,
+                                                           const float* __restrict__ def,
+                                                           float* __restrict__ coef,
+                                                           int32_t* __restrict__ flags) {
+  const DevPair P = pairs[blockIdx.z];
+  const int W = P.width, H = P.height, y = blockIdx.y;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= H || blockIdx.x * blockDim.x >= W) return;  // whole block
+  bool bad = false;
+  if (x < W) {
+    const float* row = def + P.def_off + (int64_t)y * W;
+    const double c = bspline_fir(x, W, [&](int i) { return row[i]; });
+    // scratch image: the second half of the pair's region
+    coef[4 * P.lut_off + (int64_t)W * H + (int64_t)y * W + x] = (float)c;
+    bad = !isfinite(c);
+  }
+  const unsigned long long m = __ballot(bad);
+  if (m && lane_id() == __ffsll((long long)m) - 1) atomicOr(&flags[blockIdx.z], 1);
+}
+
+__global__ void __launch_bounds__(256) bspline_cols_kernel(const DevPair* __restrict__ pairs,
+                                                           float* __restrict__ coef,
+                                                           const int32_t* __restrict__ flags) {
+  const DevPair P = pairs[blockIdx.z];
+  const int W = P.width, H = P.height, y = blockIdx.y;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= H || x >= W) return;
+  float* out = coef + 4 * P.lut_off;
+  const float* col = out + (int64_t)W * H + x;
+  const double c = bspline_fir(y, H, [&](int i) { return col[(int64_t)i * W]; });
+  out[(int64_t)y * W + x] = flags[blockIdx.z] ? nanf("") : (float)c;
+}
+
+hipError_t launch_bspline_coeffs(const DevState& st, const float* def, hipStream_t s) {
+  hipLaunchKernelGGL(bspline_flags_kernel, dim3((st.num_pairs + 255) / 256), dim3(256), 0, s,
+                     st.bsp_flags, st.num_pairs);
+  const dim3 grid((st.max_width + 255) / 256, st.max_height, st.num_pairs);
+  hipLaunchKernelGGL(bspline_rows_kernel, grid, dim3(256), 0, s, st.pairs, def, st.lut,
+                     st.bsp_flags);
+  hipLaunchKernelGGL(bspline_cols_kernel, grid, dim3(256), 0, s, st.pairs, st.lut,
+                     st.bsp_flags);
+  return hipGetLastError();
+}
+
 hipError_t launch_bicubic_lut(const DevState& st, const float* def, hipStream_t s) {
   dim3 grid((st.max_width + 255) / 256, st.max_height, st.num_pairs);
   hipLaunchKernelGGL(bicubic_lut_kernel, grid, dim3(256), 0, s, st.pairs, def,

@@ -2,7 +2,8 @@
 // Newton-Raphson, FP32 batched forms): the first-order warp in FP32 local
 // form, the bounding box of the taps it touches, the per-wave LDS patch of
 // the deformed image, interpolation from that patch or from the image (Keys
-// bicubic, NT = 4 taps per direction, or Eq. (5)'s bilinear, NT = 2), or
+// bicubic, NT = 4 taps per direction; Eq. (5)'s bilinear, NT = 2; or the
+// cubic B-spline, NT = 4 taps of the image's spline coefficients), or
 // bicubic from a per-cell table of polynomial coefficients, and the final
 // pass that evaluates Eq. (1) at the converged warp.
 //
@@ -123,33 +124,62 @@ __device__ __forceinline__ void keys_dweights32(float t, float* w) {
   w[2] = -((w[0] + w[1]) + w[3]);
 }
 
-// Interpolation weights of NT taps at fractional offset t: Keys (taps -1..2)
-// or Eq. (5)'s bilinear (taps 0, 1: G = a00 + a10 x' + ... is the weighted
-// sum (1 - x') g0 + x' g1 along each direction).
-template <int NT>
+// Cubic B-spline basis at taps -1, 0, 1, 2 for fractional offset t; with
+// s = 1 - t: w-1 = s^3 / 6, w2 = t^3 / 6, w0 = 2/3 + t^2 (t / 2 - 1) and
+// w1 = 1 - w-1 - w0 - w2.
+__device__ __forceinline__ void bspline_weights32(float t, float* w) {
+  const float s = 1.f - t;
+  w[0] = (s * s) * (s * (1.f / 6.f));
+  w[3] = (t * t) * (t * (1.f / 6.f));
+  w[1] = fmaf(t * t, fmaf(0.5f, t, -1.f), 2.f / 3.f);
+  w[2] = ((1.f - w[0]) - w[1]) - w[3];
+}
+
+// d/dt of the basis: w-1' = -s^2 / 2, w2' = t^2 / 2, w0' = t (3t / 2 - 2)
+// and w1' = -(w-1' + w0' + w2').
+__device__ __forceinline__ void bspline_dweights32(float t, float* w) {
+  const float s = 1.f - t;
+  w[0] = -0.5f * (s * s);
+  w[3] = 0.5f * (t * t);
+  w[1] = t * fmaf(1.5f, t, -2.f);
+  w[2] = -((w[0] + w[1]) + w[3]);
+}
+
+// Interpolation weights of the taps at fractional offset t: Keys (taps
+// -1..2), Eq. (5)'s bilinear (taps 0, 1: G = a00 + a10 x' + ... is the
+// weighted sum (1 - x') g0 + x' g1 along each direction) or the cubic
+// B-spline basis (taps -1..2, applied to spline coefficients).
+template <int IM>
 __device__ __forceinline__ void interp_weights(float t, float* w) {
-  if constexpr (NT == 4) {
-    keys_weights32(t, w);
-  } else {
+  if constexpr (IM == kInterpBilinear) {
     w[0] = 1.f - t;
     w[1] = t;
+  } else if constexpr (IM == kInterpBSpline) {
+    bspline_weights32(t, w);
+  } else {
+    keys_weights32(t, w);
   }
 }
-template <int NT>
+template <int IM>
 __device__ __forceinline__ void interp_dweights(float t, float* w) {
-  if constexpr (NT == 4) {
-    keys_dweights32(t, w);
-  } else {
+  if constexpr (IM == kInterpBilinear) {
     w[0] = -1.f;
     w[1] = 1.f;
+  } else if constexpr (IM == kInterpBSpline) {
+    bspline_dweights32(t, w);
+  } else {
+    keys_dweights32(t, w);
   }
 }
 
 // Interpolation of one sample at local offset (xs, ys) from the integer
-// base.  PatchSampler reads a wave's LDS patch, which holds g - c0; q0
-// addresses its element at offset (-1, -1) from the base.
-template <int P, int NT = 4>
+// base.  PatchSampler reads a wave's LDS patch, which holds g - c0 (or the
+// spline coefficients minus c0: the basis sums to one, so that is the
+// interpolant minus c0 too); q0 addresses its element at offset (-1, -1)
+// from the base.
+template <int P, int IM>
 struct PatchSampler {
+  static constexpr int NT = interp_taps(IM);
   const float* q0;
 
   __device__ __forceinline__ const float* taps(float xs, float ys, float* wx, float* wy,
@@ -157,13 +187,14 @@ struct PatchSampler {
     const float fx = floorf(xs), fy = floorf(ys);
     tx = xs - fx;
     ty = ys - fy;
-    interp_weights<NT>(tx, wx);
-    interp_weights<NT>(ty, wy);
+    interp_weights<IM>(tx, wx);
+    interp_weights<IM>(ty, wy);
     constexpr int first = NT == 4 ? 0 : P + 1;   // the 2x2 neighbourhood starts at (0, 0)
     return q0 + (first + __mul24((int)fy, P) + (int)fx);
   }
   static constexpr int pitch() { return P; }
   static constexpr int ntaps() { return NT; }
+  static constexpr int kIm = IM;
   static constexpr bool kLut = false;
   __device__ __forceinline__ float tap(const float* q) const { return *q; }
 };
@@ -173,8 +204,9 @@ struct PatchSampler {
 // NT x NT neighbourhood origin is clamped to [0, W - NT] x [0, H - NT]: the
 // tap box test already keeps it there, the clamp only guards the reads of a
 // degenerate warp.
-template <int NT = 4>
+template <int IM>
 struct ImageSampler {
+  static constexpr int NT = interp_taps(IM);
   const float* img;
   int W, H, bx, by;
   float c0;
@@ -184,8 +216,8 @@ struct ImageSampler {
     const float fx = floorf(xs), fy = floorf(ys);
     tx = xs - fx;
     ty = ys - fy;
-    interp_weights<NT>(tx, wx);
-    interp_weights<NT>(ty, wy);
+    interp_weights<IM>(tx, wx);
+    interp_weights<IM>(ty, wy);
     constexpr int lo = NT == 4 ? 1 : 0;
     const int c = min(max(bx + (int)fx - lo, 0), W - NT);
     const int r = min(max(by + (int)fy - lo, 0), H - NT);
@@ -193,6 +225,7 @@ struct ImageSampler {
   }
   __device__ __forceinline__ int pitch() const { return W; }
   static constexpr int ntaps() { return NT; }
+  static constexpr int kIm = IM;
   static constexpr bool kLut = false;
   __device__ __forceinline__ float tap(const float* q) const { return *q - c0; }
 };
@@ -287,8 +320,8 @@ __device__ __forceinline__ void sample_value_grad(const Smp& smp, float xs, floa
     constexpr int NT = Smp::ntaps();
     float wx[NT], wy[NT], tx, ty, dwx[NT], dwy[NT];
     const float* q = smp.taps(xs, ys, wx, wy, tx, ty);
-    interp_dweights<NT>(tx, dwx);
-    interp_dweights<NT>(ty, dwy);
+    interp_dweights<Smp::kIm>(tx, dwx);
+    interp_dweights<Smp::kIm>(ty, dwy);
     const int P = smp.pitch();
 #pragma unroll
     for (int l = 0; l < NT; ++l) {
@@ -434,9 +467,9 @@ struct LdsPatch {
   }
 
   // Sampler for a warp whose integer base is (bx, by).
-  template <int NT>
-  __device__ __forceinline__ PatchSampler<P, NT> sampler(int bx, int by) const {
-    return PatchSampler<P, NT>{buf + (by - y0 - 1) * P + (bx - x0 - 1)};
+  template <int IM>
+  __device__ __forceinline__ PatchSampler<P, IM> sampler(int bx, int by) const {
+    return PatchSampler<P, IM>{buf + (by - y0 - 1) * P + (bx - x0 - 1)};
   }
 };
 

@@ -26,6 +26,7 @@ FLAG_DETERMINISTIC_BWD = 4
 FLAG_REFINE_NR = 8
 FLAG_INTERP_BILINEAR = 16   # IC-GN / Newton-Raphson with Eq. (5) bilinear interpolation
 FLAG_BICUBIC_LUT = 32       # IC-GN / Newton-Raphson from the per-cell bicubic coefficient table
+FLAG_INTERP_BSPLINE = 64    # IC-GN / Newton-Raphson with cubic B-spline interpolation
 
 POI_OK = 0
 POI_NOT_CONVERGED = 1

@@ -105,7 +105,7 @@ def test_search_form_follows_radius(L):
     ([(256, 256, 10, 8, 0, 0, 0, 1)], {"max_iters": 0}, "max_iters"),
     ([(256, 256, 10, 8, 0, 0, 0, 1)], {"tol": 0.0}, "conv_tol"),
     ([(256, 256, 10, 8, 0, 0, 0, 1)], {"precision": 7}, "precision"),
-    ([(256, 256, 10, 8, 0, 0, 0, 1)], {"flags": 64}, "flag"),
+    ([(256, 256, 10, 8, 0, 0, 0, 1)], {"flags": 128}, "flag"),
     ([(20, 20, 9, 0, 0, 0, 0, 1)], {}, "fit"),
 ])
 def test_plan_create_rejects(L, pairs, kw, why):
@@ -115,11 +115,12 @@ def test_plan_create_rejects(L, pairs, kw, why):
 
 
 def test_interpolation_flags(L):
-    """Bilinear (16) and the bicubic coefficient table (32) are FP32-only and
-    exclusive; the table adds 64 bytes of workspace per deformed pixel."""
+    """Bilinear (16), the bicubic coefficient table (32) and the B-spline (64)
+    are FP32-only and exclusive; the table adds 64 bytes of workspace per
+    deformed pixel, the spline's coefficient and scratch images 8."""
     pair = [(256, 128, 10, 8, 0, 0, 0, 50)]
     sizes = {}
-    for flags in (0, 16, 32):
+    for flags in (0, 16, 32, 64):
         rc, h = make(L, pair, flags=flags)
         assert rc == 0
         nb = ctypes.c_size_t(0)
@@ -128,9 +129,11 @@ def test_interpolation_flags(L):
         L.dic_plan_destroy(h)
     assert sizes[16] == sizes[0]
     assert 256 * 128 * 64 <= sizes[32] - sizes[0] <= 256 * 128 * 64 + 256
-    rc, h = make(L, pair, flags=48)
-    assert rc == -1 and not h.value and "exclusive" in L.dic_last_error().decode()
-    for flags in (16, 32):
+    assert 256 * 128 * 8 <= sizes[64] - sizes[0] <= 256 * 128 * 8 + 1024
+    for flags in (48, 80, 96, 112):
+        rc, h = make(L, pair, flags=flags)
+        assert rc == -1 and not h.value and "exclusive" in L.dic_last_error().decode()
+    for flags in (16, 32, 64):
         rc, h = make(L, pair, precision=1, flags=flags)
         assert rc == -4 and not h.value and "FP32" in L.dic_last_error().decode()
 
