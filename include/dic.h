@@ -7,7 +7,8 @@
  *      search, Sec. 2.1), and
  *   2. its sub-pixel refinement by inverse-compositional Gauss-Newton with a
  *      first-order (affine) shape function and bicubic interpolation of the
- *      deformed image (Sec. 2.2),
+ *      deformed image (Sec. 2.2; Newton-Raphson, bilinear or cubic B-spline
+ *      interpolation and a bicubic coefficient table by plan flags),
  * plus the adjoint of the ZNSSD criterion with respect to the warp parameters
  * and the deformed-image grey levels.
  *
@@ -250,7 +251,8 @@ dic_status_t dic_integer_search(dic_plan_t plan, const float* ref_images,
  * with (du, dv) = uv_init[i]; the gradient terms come from p_init (float64
  * [N,6], nullable) when given.  POIs whose status_in (nullable) is not OK are
  * skipped and keep that status.  Each iteration warps the subset, interpolates
- * the deformed image with Keys' cubic kernel (a = -1/2), solves
+ * the deformed image with Keys' cubic kernel (a = -1/2; bilinear, the
+ * coefficient table or the cubic B-spline when a plan flag selects it), solves
  * H dp = -sum SD^T e with e = (f - fbar) - (df/dg)(g - gbar) and composes
  * W(p) <- W(p) W(dp)^-1; it stops when |dp| < conv_tol (OK) or after
  * max_iters (NOT_CONVERGED).  Outputs: p_out float64 [N,6], zncc_out float [N]
@@ -267,7 +269,8 @@ dic_status_t dic_icgn_refine(dic_plan_t plan, const float* ref_images,
  * whose quantities are recomputed at every iteration), on the ZNSSD
  * criterion with the first-order warp applied forward,
  * x_i = x0 + W(p) xi_i, and updated additively.  Each iteration interpolates
- * g and its gradient (Keys, a = -1/2) at the warped samples, forms
+ * g and its gradient (Keys, a = -1/2, unless a plan flag selects bilinear,
+ * the coefficient table or the B-spline) at the warped samples, forms
  * J_i = [gx, gx dx, gx dy, gy, gy dx, gy dy], Jc = J - mean(J), and takes
  *   dp = Hc^-1 sum Jc_i [(dg/df)(f_i - fbar) - ZNCC (g_i - gbar)],
  *   Hc = sum Jc_i^T Jc_i,
