@@ -1,0 +1,70 @@
+"""Host-side logic of the benchmark (CPU only): the single-GPU contract, and
+the rule that a committed counter summary is used only while the kernel
+sources it was taken on are unchanged."""
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("n", ["2", "8", "0"])
+def test_more_than_one_gpu_is_refused(n):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", n],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_committed_summaries_name_their_sources(bench):
+    """Every kernel summary names its sources and their hash, and gives the
+    command that produced it."""
+    for path in (bench.TRAFFIC_FILE, bench.COUNTERS_FILE):
+        with open(path) as fh:
+            doc = json.load(fh)
+        assert doc["kernels"]
+        assert "rocprofv3" in json.dumps(doc.get("commands", doc.get("command")))
+        for name, k in doc["kernels"].items():
+            assert k["sources"] and len(k["source_hash"]) == 16, name
+
+
+def test_current_summary_is_used(bench, tmp_path, monkeypatch):
+    """A summary whose hash is that of the current sources is read."""
+    for attr in ("TRAFFIC_FILE", "COUNTERS_FILE"):
+        with open(getattr(bench, attr)) as fh:
+            doc = json.load(fh)
+        k = doc["kernels"]["icgn_f32"]
+        k["sources"] = list(bench.KERNEL_SOURCES["icgn_f32"])
+        k["source_hash"] = bench.kernel_source_hash(k["sources"])
+        p = tmp_path / os.path.basename(getattr(bench, attr))
+        p.write_text(json.dumps(doc))
+        monkeypatch.setattr(bench, attr, str(p))
+    assert bench.measured_traffic("icgn_f32") > 0
+    assert 0 < bench.measured_issue("icgn_f32", 0.5)["valu_issue_frac"]
+
+
+def test_stale_summary_is_not_used(bench, tmp_path, monkeypatch):
+    """A summary whose source hash differs from the current sources gives
+    null traffic and issue fractions."""
+    for attr in ("TRAFFIC_FILE", "COUNTERS_FILE"):
+        with open(getattr(bench, attr)) as fh:
+            doc = json.load(fh)
+        doc["kernels"]["icgn_f32"]["source_hash"] = "0" * 16
+        p = tmp_path / os.path.basename(getattr(bench, attr))
+        p.write_text(json.dumps(doc))
+        monkeypatch.setattr(bench, attr, str(p))
+    assert bench.measured_traffic("icgn_f32") is None
+    assert bench.measured_issue("icgn_f32", 0.5) is None
