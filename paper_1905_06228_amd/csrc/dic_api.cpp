@@ -262,10 +262,12 @@ dic_status_t enqueue_search(dic_plan_t p, const float* ref, const float* def, co
 dic_status_t enqueue_refine(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
                             const int32_t* uv, const int32_t* status_in, const double* p_init,
                             double* p_out, float* zn, int32_t* iters, int32_t* status,
-                            hipStream_t s, bool nr) {
+                            hipStream_t s, bool nr, bool table_ready = false) {
   if (p->fp32()) {
-    dic_status_t r = prepare_lut(p, def, s, false);
-    if (r) return r;
+    if (!table_ready) {
+      dic_status_t r = prepare_lut(p, def, s, false);
+      if (r) return r;
+    }
     DIC_HIP(launch_reset_counters(p->st, s));
     if (nr)
       DIC_HIP(launch_nr_f32(p->st, p->tuning, def, poi, uv, status_in, p_init, p_out, zn, iters,
@@ -297,9 +299,10 @@ struct CorrArgs {
   int32_t* status;
 };
 
-// Search then refine.  In the FP32 form the deformed-side box sums (when not
-// cached) run on the plan's side stream beside the reference-side
-// preparation: the two read different images and write different sections.
+// Search then refine.  In the FP32 form the deformed-side box sums and the
+// interpolation table or B-spline coefficients (when not cached) run on the
+// plan's side stream beside the reference-side preparation: the two read
+// different images and write different sections.
 dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s) {
   const bool fork = p->fp32() && !((p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->def_valid &&
                                    p->def_img == a.def);
@@ -309,7 +312,10 @@ dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s) {
     if (!p->ev_join) DIC_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
     DIC_HIP(hipEventRecord(p->ev_fork, s));
     DIC_HIP(hipStreamWaitEvent(p->side_stream, p->ev_fork, 0));
+    // the deformed side: box sums, then the refinement's coefficient table
+    // or B-spline coefficients (if the plan has one), beside the reference side
     dic_status_t r = prepare_deformed(p, a.def, p->side_stream, false);
+    if (r == DIC_SUCCESS) r = prepare_lut(p, a.def, p->side_stream, false);
     if (r != DIC_SUCCESS) return r;
     DIC_HIP(hipEventRecord(p->ev_join, p->side_stream));
   }
@@ -319,7 +325,7 @@ dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s) {
   r = enqueue_search(p, a.ref, a.def, a.poi, a.seed, a.uv, a.zn_int, a.st_int, s, fork);
   if (r != DIC_SUCCESS) return r;
   return enqueue_refine(p, a.ref, a.def, a.poi, a.uv, a.st_int, a.p_init, a.p_out, a.zn, a.iters,
-                        a.status, s, p->nr());
+                        a.status, s, p->nr(), fork);
 }
 
 }  // namespace

@@ -5,7 +5,8 @@ against the FP64 oracle, which solves the interpolation condition exactly.
 Integer results and statuses bit-exact, sub-pixel displacements within
 1e-3 px, coefficients within 1e-5; one pair, a batch (one coefficient image
 per pair), the 1024 x 1024 workload sampled, edge and failure cases, a
-non-finite pixel far from every POI, graph replay and the cache."""
+non-finite pixel far from every POI, graph replay, the cache, and the
+coefficients built on the side stream inside dic_correlate."""
 import numpy as np
 import pytest
 import torch
@@ -220,3 +221,28 @@ def test_bspline_restrictions():
     p = torch.zeros(1, 6, dtype=torch.float64, device="cuda")
     with pytest.raises(dic.DicError, match="UNSUPPORTED|unsupported|bicubic"):
         plan.znssd(img, img, pois, p)
+
+
+@pytest.mark.parametrize("flag", [BSP, dic.FLAG_BICUBIC_LUT])
+def test_correlate_builds_the_table_beside_the_reference_side(affine_bsp, flag):
+    """dic_correlate builds the coefficient image (or table) on the plan's
+    side stream beside the reference preparation; the results are the bits
+    of the separate search and refinement calls, which build it in order on
+    the caller's stream, eager and graph-replayed."""
+    pr, pois, _ = affine_bsp
+    F, G, Q = to_dev(pr.ref), to_dev(pr.defm), to_dev(pois)
+    print(f"case side-stream table flag={flag} N={len(pois)}", flush=True)
+    sep = dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois), flags=flag)
+    so = sep.new_outputs()
+    sep.integer_search(F, G, Q, out=(so["uv"], so["zncc_int"], so["status_int"]))
+    sep.icgn_refine(F, G, Q, so["uv"], so["status_int"],
+                    out=(so["p"], so["zncc"], so["iters"], so["status"]))
+    torch.cuda.synchronize()
+    ref = host(so)
+    for extra in (0, dic.FLAG_USE_GRAPH):
+        plan = dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois), flags=flag | extra)
+        for rep in range(2):
+            got = host(plan.correlate(F, G, Q))
+            torch.cuda.synchronize()
+            for k in ref:
+                np.testing.assert_array_equal(ref[k], got[k], err_msg=f"{k} {extra} {rep}")
