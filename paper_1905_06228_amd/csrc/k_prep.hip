@@ -211,45 +211,46 @@ __global__ void __launch_bounds__(256) bicubic_lut_kernel(const DevPair* __restr
 // along each axis, the image extended symmetrically about its end samples.
 // The inverse of that three-tap filter has the impulse response
 // sqrt(3) z^|j| with z = sqrt(3) - 2, so along one axis
-//   c[k] = sqrt(3) sum_j z^|j| g[k + j]
+//   c[k] = sqrt(3) (g[k] + sum_{j=1..16} z^j (g[k - j] + g[k + j]))
 // over the symmetric extension (index reflected into one period of 2n - 2
 // samples), truncated at |j| <= 16: the terms dropped sum to below 1e-9 of
-// the largest pixel, under FP32 rounding.  Every output is independent: one
-// thread per pixel, the rows pass into a scratch image, the columns pass
-// from it into the coefficient image, FP64 sums rounded once per pass, the
-// 33 loads of a thread coalesced across the wave (L1/L2 hits after the
-// first).  A non-finite pixel has no spline through it: the rows pass sets
+// the largest pixel, under FP32 rounding.  Every output is independent.  A
+// rows pass writes a scratch image, a columns pass reads it and writes the
+// coefficient image, FP64 sums rounded once per pass.  The rows pass stages
+// a row tile in LDS (reflected indices resolved while staging) and each
+// thread forms four outputs from one run of staged values held in
+// registers; the columns pass does the same down a column from direct
+// loads.  A non-finite pixel has no spline through it: the rows pass sets
 // its pair's flag and the columns pass then writes NaN over the whole image
 // (the recursive form's result, whose recursions carry such a value along
-// every row and column).  Grid: (column blocks, rows, pairs).
+// every row and column).
 constexpr int kBsplineHalf = 16;
+constexpr int kBsplineRowTile = 1024;   // rows pass: outputs per block, 4 per thread
+static_assert(256 * 4 == kBsplineRowTile, "rows pass: 4 outputs per thread");
 
 __device__ __forceinline__ int bspline_mirror(int i, int n) {
+  if (i >= 0 && i < n) return i;
   const int per = 2 * n - 2;
   i %= per;
   if (i < 0) i += per;
   return i < n ? i : per - i;
 }
 
-// sqrt(3) sum_{|j| <= 16} z^|j| v(k + j), v read at the reflected index
-template <class V>
-__device__ __forceinline__ double bspline_fir(int k, int n, const V& v) {
+// sqrt(3) (v[16 + u] + sum_j z^j (v[16 + u - j] + v[16 + u + j])) for the
+// outputs u = 0..NOUT-1 of a run v of NOUT + 32 staged values
+template <int NOUT>
+__device__ __forceinline__ void bspline_run(const double* v, double* c) {
   constexpr double z = -0.2679491924311227;  // sqrt(3) - 2
-  double acc = v(k), w = 1.0;
-  if (k >= kBsplineHalf && k < n - kBsplineHalf) {
+#pragma unroll
+  for (int u = 0; u < NOUT; ++u) {
+    double acc = v[kBsplineHalf + u], w = 1.0;
 #pragma unroll
     for (int j = 1; j <= kBsplineHalf; ++j) {
       w *= z;
-      acc = fma(w, (double)v(k - j) + (double)v(k + j), acc);
+      acc = fma(w, v[kBsplineHalf + u - j] + v[kBsplineHalf + u + j], acc);
     }
-  } else {
-    for (int j = 1; j <= kBsplineHalf; ++j) {
-      w *= z;
-      acc = fma(w, (double)v(bspline_mirror(k - j, n)) + (double)v(bspline_mirror(k + j, n)),
-                acc);
-    }
+    c[u] = 1.7320508075688772 * acc;  // sqrt(3)
   }
-  return 1.7320508075688772 * acc;  // sqrt(3)
 }
 
 __global__ void __launch_bounds__(256) bspline_flags_kernel(int32_t* __restrict__ flags, int n) {
@@ -257,47 +258,91 @@ __global__ void __launch_bounds__(256) bspline_flags_kernel(int32_t* __restrict_
   if (i < n) flags[i] = 0;
 }
 
+// Grid (row tiles of 1024, rows, pairs).  Thread t forms outputs
+// x0 + 4t .. x0 + 4t + 3 from staged values 4t .. 4t + 35 (nine 16-byte
+// LDS reads).
 __global__ void __launch_bounds__(256) bspline_rows_kernel(const DevPair* __restrict__ pairs,
                                                            const float* __restrict__ def,
                                                            float* __restrict__ coef,
                                                            int32_t* __restrict__ flags) {
+  __shared__ __attribute__((aligned(16))) float s[kBsplineRowTile + 2 * kBsplineHalf];
   const DevPair P = pairs[blockIdx.z];
   const int W = P.width, H = P.height, y = blockIdx.y;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (y >= H || blockIdx.x * blockDim.x >= W) return;  // whole block
+  const int x0 = blockIdx.x * kBsplineRowTile;
+  if (y >= H || x0 >= W) return;  // whole block
+  const float* row = def + P.def_off + (int64_t)y * W;
+  for (int t = threadIdx.x; t < kBsplineRowTile + 2 * kBsplineHalf; t += blockDim.x) {
+    const int x = x0 - kBsplineHalf + t;
+    s[t] = x < W + kBsplineHalf ? row[bspline_mirror(x, W)] : 0.f;
+  }
+  __syncthreads();
+  const int xo = x0 + 4 * (int)threadIdx.x;
   bool bad = false;
-  if (x < W) {
-    const float* row = def + P.def_off + (int64_t)y * W;
-    const double c = bspline_fir(x, W, [&](int i) { return row[i]; });
+  if (xo < W) {
+    double v[4 + 2 * kBsplineHalf], c[4];
+    const float4* q = reinterpret_cast<const float4*>(s) + threadIdx.x;
+#pragma unroll
+    for (int a = 0; a < (4 + 2 * kBsplineHalf) / 4; ++a) {
+      const float4 f4 = q[a];
+      v[4 * a] = f4.x;
+      v[4 * a + 1] = f4.y;
+      v[4 * a + 2] = f4.z;
+      v[4 * a + 3] = f4.w;
+    }
+    bspline_run<4>(v, c);
     // scratch image: the second half of the pair's region
-    coef[4 * P.lut_off + (int64_t)W * H + (int64_t)y * W + x] = (float)c;
-    bad = !isfinite(c);
+    float* o = coef + 4 * P.lut_off + (int64_t)W * H + (int64_t)y * W + xo;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (xo + u < W) {
+        o[u] = (float)c[u];
+        bad |= !isfinite(c[u]);
+      }
   }
   const unsigned long long m = __ballot(bad);
   if (m && lane_id() == __ffsll((long long)m) - 1) atomicOr(&flags[blockIdx.z], 1);
 }
 
+// Grid (column blocks of 256, row groups of 4, pairs): a thread forms the
+// outputs of 4 consecutive rows of one column from the 36 values around
+// them, read straight from the scratch image (coalesced across the wave;
+// the reflected indices only for the groups within 16 rows of an edge).
 __global__ void __launch_bounds__(256) bspline_cols_kernel(const DevPair* __restrict__ pairs,
                                                            float* __restrict__ coef,
                                                            const int32_t* __restrict__ flags) {
   const DevPair P = pairs[blockIdx.z];
-  const int W = P.width, H = P.height, y = blockIdx.y;
+  const int W = P.width, H = P.height, y0 = 4 * blockIdx.y;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (y >= H || x >= W) return;
+  if (y0 >= H || x >= W) return;
   float* out = coef + 4 * P.lut_off;
   const float* col = out + (int64_t)W * H + x;
-  const double c = bspline_fir(y, H, [&](int i) { return col[(int64_t)i * W]; });
-  out[(int64_t)y * W + x] = flags[blockIdx.z] ? nanf("") : (float)c;
+  double v[4 + 2 * kBsplineHalf], c[4];
+  if (y0 >= kBsplineHalf && y0 + 3 + kBsplineHalf < H) {
+#pragma unroll
+    for (int i = 0; i < 4 + 2 * kBsplineHalf; ++i)
+      v[i] = col[(int64_t)(y0 - kBsplineHalf + i) * W];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4 + 2 * kBsplineHalf; ++i)
+      v[i] = col[(int64_t)bspline_mirror(y0 - kBsplineHalf + i, H) * W];
+  }
+  bspline_run<4>(v, c);
+  const bool poisoned = flags[blockIdx.z] != 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (y0 + u < H) out[(int64_t)(y0 + u) * W + x] = poisoned ? nanf("") : (float)c[u];
 }
 
 hipError_t launch_bspline_coeffs(const DevState& st, const float* def, hipStream_t s) {
   hipLaunchKernelGGL(bspline_flags_kernel, dim3((st.num_pairs + 255) / 256), dim3(256), 0, s,
                      st.bsp_flags, st.num_pairs);
-  const dim3 grid((st.max_width + 255) / 256, st.max_height, st.num_pairs);
-  hipLaunchKernelGGL(bspline_rows_kernel, grid, dim3(256), 0, s, st.pairs, def, st.lut,
-                     st.bsp_flags);
-  hipLaunchKernelGGL(bspline_cols_kernel, grid, dim3(256), 0, s, st.pairs, st.lut,
-                     st.bsp_flags);
+  hipLaunchKernelGGL(bspline_rows_kernel,
+                     dim3((st.max_width + kBsplineRowTile - 1) / kBsplineRowTile, st.max_height,
+                          st.num_pairs),
+                     dim3(256), 0, s, st.pairs, def, st.lut, st.bsp_flags);
+  hipLaunchKernelGGL(bspline_cols_kernel, dim3((st.max_width + 255) / 256,
+                                                 (st.max_height + 3) / 4, st.num_pairs),
+                     dim3(256), 0, s, st.pairs, st.lut, st.bsp_flags);
   return hipGetLastError();
 }
 
