@@ -134,3 +134,30 @@ def test_higher_order_is_more_accurate(du, dv):
         err[interp] = np.abs(r["p"][:, [0, 3]] - [du, dv]).mean()
     assert err["bspline"] < 0.2 * err["bicubic"] and err["bicubic"] < err["bilinear"], err
     assert err["bspline"] < 1e-3
+
+
+@pytest.mark.parametrize("n", [8, 9, 13, 17, 33, 64])
+def test_truncated_inverse_filter_is_within_1e_9(n):
+    """The inverse of the (1, 4, 1) / 6 filter has impulse response
+    sqrt(3) z^|j|, z = sqrt(3) - 2 (closed form); applied over the
+    symmetric extension and cut at |j| <= 16 it stays within 1e-9 of the
+    largest sample of the exact solution of the interpolation condition,
+    also for lines shorter than the cut (several reflections)."""
+    z = np.sqrt(3.0) - 2.0
+    per = 2 * n - 2
+
+    def refl(i):
+        i %= per
+        return i if i < n else per - i
+
+    rng = np.random.default_rng(n)
+    f = rng.uniform(0, 255, n)
+    exact = np.linalg.solve(O._bspline_system(n), f)
+    fir = np.array([np.sqrt(3.0) * sum(z ** abs(j) * f[refl(k + j)] for j in range(-16, 17))
+                    for k in range(n)])
+    assert np.abs(fir - exact).max() < 1e-9 * np.abs(f).max()
+    # and the impulse response inverts the three-tap filter away from edges
+    h = np.sqrt(3.0) * z ** np.abs(np.arange(-40, 41))
+    conv = np.convolve(h, np.array([1.0, 4.0, 1.0]) / 6.0)
+    centre = len(conv) // 2
+    np.testing.assert_allclose(conv[centre - 20:centre + 21], np.eye(41)[20], atol=1e-12)
