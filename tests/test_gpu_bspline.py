@@ -246,3 +246,24 @@ def test_correlate_builds_the_table_beside_the_reference_side(affine_bsp, flag):
             torch.cuda.synchronize()
             for k in ref:
                 np.testing.assert_array_equal(ref[k], got[k], err_msg=f"{k} {extra} {rep}")
+
+
+@pytest.mark.parametrize("name,flag", REFINES)
+def test_bspline_wide_image_row_tiles(name, flag):
+    """A 2600-pixel-wide image: the coefficient rows pass works in tiles of
+    1,024 outputs whose halos come from the neighbouring tile; POIs on both
+    sides of the tile boundaries at x = 1024 and 2048 (and away from them)
+    against the oracle, whose coefficients solve the whole row at once."""
+    H, W = 160, 2600
+    b = dicgen.make_blobs(dicgen.rng_for(61, 0, 0), H * W // 50, H, W)
+    f = dicgen.render_image(b, None, H, W)
+    g = dicgen.render_image(b, dicgen.affine(0.0008, 1.3, -0.002, -0.6), H, W)
+    xs = [1000, 1010, 1018, 1024, 1030, 1040, 2040, 2048, 2056, 500, 2500]
+    pois = np.array([(x, y) for x in xs for y in (60, 90)], np.int32)
+    print(f"case bspline wide {name} N={len(pois)}", flush=True)
+    ref = O.correlate(f, g, pois, 10, 6, refine=name, interp="bspline")
+    plan = dic.single_pair_plan(W, H, 10, 6, len(pois), flags=BSP | flag)
+    got = host(plan.correlate(to_dev(f), to_dev(g), to_dev(pois)))
+    torch.cuda.synchronize()
+    s = compare(got, ref, label=f"bspline wide {name}")
+    assert s["n_ok"] == len(pois)
