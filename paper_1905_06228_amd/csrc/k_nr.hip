@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
   constexpr int PP = refine_patch_pitch(MAXS);
   constexpr int NT = interp_taps(IM);
   extern __shared__ float lds[];
-  const int lane = lane_id(), wid = threadIdx.x / kWave;
+  const int wid = threadIdx.x / kWave;
   const int pside = icgn_patch_side(st.maxM, slack);
   LdsPatch<PP> patch;
   patch.buf = lds + (size_t)wid * pside * PP;

@@ -126,7 +126,8 @@ __global__ void __launch_bounds__(kBoxRowTile) box_rows_kernel(const DevPair* __
   float2* o3 = reinterpret_cast<float2*>(o2 + plane);
   double s1 = 0.0, s2 = 0.0;
   bool bad = x - M < 0 || x + M > W - 1;
-  for (int i = threadIdx.x; i <= threadIdx.x + 2 * M; ++i) {
+  const int t0 = threadIdx.x;
+  for (int i = t0; i <= t0 + 2 * M; ++i) {
     const double q = l2[i];
     bad |= q < 0.0;
     s1 += l1[i];
