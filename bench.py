@@ -132,7 +132,7 @@ def cpu_baseline(pair, got, n_sample: int, seed: int = 11):
 
 
 def sequence_bench(torch, dic, dicgen, dev, n_frames: int, reference: str = "first",
-                   live_fps: float = 0.0) -> dict:
+                   live_fps: float = 0.0, interp: str = "bicubic") -> dict:
     """Frames/s of the camera-scale sequence: frame k against frame 0
     (reference "first") or against frame k - 1 (reference "previous", the
     reference updated after every pair), seeded by the last OK result,
@@ -140,7 +140,8 @@ def sequence_bench(torch, dic, dicgen, dev, n_frames: int, reference: str = "fir
     heterogeneous strain field (noise 3), subset 29 x 29, step 7, search +-24
     around the seed.  Frames rendered on the device (same recipe as the NumPy
     generator); timed once with every frame resident in HBM and once from
-    host memory through the driver's pinned double buffer."""
+    host memory through the driver's pinned double buffer.  ``interp``
+    selects the refinement's interpolation (bicubic taps by default)."""
     H, W, M, S, step = 3000, 4096, 14, 24, 7
     t0 = time.perf_counter()
     frames = dicgen.sequence_frames_torch(n_frames, H, W, 600_000, noise=3.0, tag=5, pad=96.0,
@@ -150,13 +151,14 @@ def sequence_bench(torch, dic, dicgen, dev, n_frames: int, reference: str = "fir
     pois = dicgen.poi_grid(W, H, M, S, step)
     Q = torch.from_numpy(pois).to(dev)
     host = [f.cpu() for f in frames]
-    dic.correlate_sequence(frames[:2], Q, M, S, reference=reference)   # load kernels
+    flags = INTERP_FLAGS[interp](dic)
+    dic.correlate_sequence(frames[:2], Q, M, S, reference=reference, flags=flags)   # load kernels
     torch.cuda.synchronize()
 
     def run(src):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        res = dic.correlate_sequence(src, Q, M, S, reference=reference)
+        res = dic.correlate_sequence(src, Q, M, S, reference=reference, flags=flags)
         torch.cuda.synchronize()
         return res, time.perf_counter() - t
 
@@ -185,7 +187,7 @@ def sequence_bench(torch, dic, dicgen, dev, n_frames: int, reference: str = "fir
                                    + ", ~600k blobs, "
                                    "u = 0.002 k x (1 + 0.5 sin(2 pi y / 1500)), v = -0.0006 k y, "
                                    "noise sigma 3, subset 29x29, step 7, search +-24 around "
-                                   "the seed", "form": "FP32 batched"},
+                                   "the seed", "form": "FP32 batched", "interp": interp},
             "render_s": round(render_s, 1),
             "mean_iterations_per_frame": [round(v, 3) for v in iters],
             "last_frame": {"ok_fraction": float(ok.mean()),
@@ -194,6 +196,15 @@ def sequence_bench(torch, dic, dicgen, dev, n_frames: int, reference: str = "fir
             "live": live_bench(torch, dic, dicgen, host, Q, pois, M, S, live_fps)
             if live_fps > 0 else None,
             "data": "synthetic"}
+
+
+# plan flags of the refinement's interpolation options
+INTERP_FLAGS = {
+    "bicubic": lambda dic: 0,
+    "bilinear": lambda dic: dic.FLAG_INTERP_BILINEAR,
+    "bicubic_lut": lambda dic: dic.FLAG_BICUBIC_LUT,
+    "bspline": lambda dic: dic.FLAG_INTERP_BSPLINE,
+}
 
 
 def live_bench(torch, dic, dicgen, host_frames, Q, pois, M, S, fps: float) -> dict:
@@ -273,6 +284,8 @@ def main() -> int:
     ap.add_argument("--live-fps", type=float, default=0.0,
                     help="sequence benchmark: also run the live policy with a camera "
                          "offering the frames at this rate")
+    ap.add_argument("--interp", choices=tuple(INTERP_FLAGS), default="bicubic",
+                    help="sequence benchmark: the refinement's interpolation")
     ap.add_argument("--sequence-frames", type=int, default=0,
                     help="instead of the pair benchmark, time the camera-scale frame sequence "
                          "(4096x3000 frames, 239,932 POIs each) over this many frames")
@@ -290,7 +303,7 @@ def main() -> int:
     dev = torch.device("cuda", 0)
     if args.sequence_frames > 0:
         print(json.dumps(sequence_bench(torch, dic, dicgen, dev, args.sequence_frames,
-                                        args.reference, args.live_fps)))
+                                        args.reference, args.live_fps, args.interp)))
         return 0
     pair = dicgen.affine_pair_1024()
     N = len(pair.pois)

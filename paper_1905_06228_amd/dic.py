@@ -497,6 +497,11 @@ def correlate_sequence(frames: Sequence, pois: torch.Tensor, M: int, S: int,
     for k in range(1, len(frames)):
         ref = ring.acquire(slot(0) if reference == "first" else slot(k - 1))
         cur = ring.acquire(slot(k))
+        if reference == "first":
+            # the deformed frames reuse ring slots, so a pointer comes back with
+            # new pixels: its preparation (box sums, interpolation table) is
+            # redone here, and only the reference side stays cached
+            plan.prepare_deformed(cur)
         o = plan.correlate(ref, cur, pois, seed, p_seed, out=out)
         plan.seed_update(o["p"], o["status"], seed, p_seed)
         ring.release(slot(k) if reference == "first" else slot(k - 1))

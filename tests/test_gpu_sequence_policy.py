@@ -122,3 +122,30 @@ def test_camera_scale_pair_sampled():
     err = np.abs(h["p"][ok][:, [0, 3]] - truth)
     print(f"[camera pair] ok={ok.mean():.4f} mean err={err.mean():.4f} px", flush=True)
     assert err.mean() < 0.02
+
+
+@pytest.mark.parametrize("flag", [0, dic.FLAG_INTERP_BSPLINE, dic.FLAG_BICUBIC_LUT])
+def test_first_reference_with_reused_slots_matches_fresh_plans(frames, flag):
+    """Host frames against frame 0: the deformed frames take turns in two
+    device slots, so a pointer comes back with new pixels (frames 1, 3 and
+    2, 4).  Every pair must equal a fresh, uncached plan's result for the
+    same frames and seeds, bit for bit: nothing of an earlier frame (box
+    sums, interpolation table) may be reused."""
+    fr = frames[:5]
+    pois = dicgen.poi_grid(260, 200, M, S, 13)
+    Q = to_dev(pois)
+    N = len(pois)
+    print(f"case sequence first reused slots flag={flag} N={N}", flush=True)
+    got = dic.correlate_sequence([torch.from_numpy(f) for f in fr], Q, M, S, flags=flag)
+    plan = dic.single_pair_plan(260, 200, M, S, N, flags=flag)
+    seed = torch.zeros((N, 2), dtype=torch.int32, device="cuda")
+    p_seed = torch.zeros((N, 6), dtype=torch.float64, device="cuda")
+    F0 = to_dev(fr[0])
+    for k in range(1, len(fr)):
+        o = plan.correlate(F0, to_dev(fr[k]), Q, seed, p_seed)
+        plan.seed_update(o["p"], o["status"], seed, p_seed)
+        torch.cuda.synchronize()
+        ref = host(o)
+        g = host(got[k - 1])
+        for key in ref:
+            np.testing.assert_array_equal(ref[key], g[key], err_msg=f"frame {k} {key}")
