@@ -82,6 +82,38 @@ def test_znssd_deterministic_mode(adjoint_case):
     assert np.abs(a[2] - gg).max() / np.abs(gg).max() <= TOL_GRAD_REL
 
 
+def test_znssd_deterministic_pairs_on_one_image(adjoint_case):
+    """Two pairs of one plan on the same deformed image (the image run at
+    subset radii 12 and 9): in deterministic mode both pairs add into one
+    fixed-point accumulator that is flushed once, so grad_def is the sum of
+    the oracle's two image gradients, and repeated runs are bit-identical."""
+    pr, pois, M, P, up, C, gp, gg = adjoint_case
+    M2 = 9
+    q2 = pois[::2]
+    P2 = P[::2].copy()
+    up2 = up[::2]
+    _, _, gg2 = O.znssd_batch(pr.ref, pr.defm, q2, M2, P2, upstream=up2)
+    expect = gg + gg2
+    n1, n2 = len(pois), len(q2)
+    specs = [dic.PairSpec(256, 256, M, 8, 0, 0, 0, n1), dic.PairSpec(256, 256, M2, 8, 0, 0, n1, n2)]
+    print(f"case znssd deterministic two pairs one image N={n1}+{n2}", flush=True)
+    runs = []
+    for flags in (dic.FLAG_DETERMINISTIC_BWD, dic.FLAG_DETERMINISTIC_BWD, 0):
+        plan = dic.Plan(specs, flags=flags)
+        F, G = to_dev(pr.ref), to_dev(pr.defm)
+        Q = to_dev(np.concatenate([pois, q2]))
+        gpp = torch.empty((n1 + n2, 6), dtype=torch.float64, device="cuda")
+        gg_d = torch.zeros((256, 256), dtype=torch.float32, device="cuda")
+        plan.znssd(F, G, Q, to_dev(np.concatenate([P, P2])),
+                   grad_c=to_dev(np.concatenate([up, up2]).astype(np.float32)),
+                   grad_p=gpp, grad_def=gg_d)
+        torch.cuda.synchronize()
+        runs.append(gg_d.cpu().numpy())
+    np.testing.assert_array_equal(runs[0], runs[1])
+    for r in runs:
+        assert np.abs(r - expect).max() / np.abs(expect).max() <= TOL_GRAD_REL
+
+
 def test_znssd_autograd(adjoint_case):
     pr, pois, M, P, up, C, gp, gg = adjoint_case
     plan = dic.single_pair_plan(256, 256, M, 8, len(pois))
@@ -135,7 +167,7 @@ def test_sequence_matches_oracle():
         assert len(got) == len(ref)
         for k, (g, r) in enumerate(zip(got, ref), start=1):
             h = {key: v.cpu().numpy() for key, v in g.items()}
-            compare(h, r, label=f"sequence frame {k}/{name}")
+            compare(h, r, M, label=f"sequence frame {k}/{name}")
         # the late frames move up to ~1.5 px: seeds were used
         assert np.abs(ref[-1]["p"][:, 0]).max() > 1.0
 

@@ -43,7 +43,7 @@ def run(pr, pois, flags, tuning=None, graph=False):
 def test_bilinear_affine_256(affine_bil, name, flag):
     pr, pois, refs = affine_bil
     print(f"case bilinear {name} affine_256 N={len(pois)}", flush=True)
-    s = compare(run(pr, pois, BIL | flag), refs[name], label=f"bilinear {name} affine_256")
+    s = compare(run(pr, pois, BIL | flag), refs[name], pr.M, label=f"bilinear {name} affine_256")
     assert s["n_ok"] > 0.95 * s["n"]
 
 
@@ -72,7 +72,7 @@ def test_bilinear_1024_sampled():
     got = run(pr, pr.pois, BIL)
     idx = np.sort(np.random.default_rng(11).choice(len(pr.pois), 64, replace=False))
     ref = O.correlate(pr.ref, pr.defm, pr.pois[idx], pr.M, pr.S, interp="bilinear")
-    compare(got, ref, idx=idx, label="bilinear icgn affine_1024 sampled")
+    compare(got, ref, pr.M, idx=idx, label="bilinear icgn affine_1024 sampled")
     ok = got["status"] == O.OK
     assert ok.mean() > 0.99
     truth = dicgen.true_displacement(pr.field, pr.pois[ok].astype(np.float64))

@@ -46,7 +46,7 @@ def run(pr, pois, flags, tuning=None):
 def test_bspline_affine_256(affine_bsp, name, flag):
     pr, pois, refs = affine_bsp
     print(f"case bspline {name} affine_256 N={len(pois)}", flush=True)
-    s = compare(run(pr, pois, BSP | flag), refs[name], label=f"bspline {name} affine_256")
+    s = compare(run(pr, pois, BSP | flag), refs[name], pr.M, label=f"bspline {name} affine_256")
     assert s["n_ok"] > 0.95 * s["n"]
 
 
@@ -89,7 +89,7 @@ def test_bspline_batch_mixed_subsets():
     for p in pairs:
         ref = O.correlate(p.ref, p.defm, p.pois, p.M, p.S, interp="bspline")
         sl = slice(off, off + len(p.pois))
-        compare({k: v[sl] for k, v in got.items()}, ref, label=f"bspline batch M={p.M}")
+        compare({k: v[sl] for k, v in got.items()}, ref, p.M, label=f"bspline batch M={p.M}")
         off += len(p.pois)
 
 
@@ -101,7 +101,7 @@ def test_bspline_1024_sampled():
     got = run(pr, pr.pois, BSP)
     idx = np.sort(np.random.default_rng(17).choice(len(pr.pois), 64, replace=False))
     ref = O.correlate(pr.ref, pr.defm, pr.pois[idx], pr.M, pr.S, interp="bspline")
-    compare(got, ref, idx=idx, label="bspline icgn affine_1024 sampled")
+    compare(got, ref, pr.M, idx=idx, label="bspline icgn affine_1024 sampled")
     ok = got["status"] == O.OK
     assert ok.mean() > 0.99
     truth = dicgen.true_displacement(pr.field, pr.pois[ok].astype(np.float64))
@@ -179,7 +179,7 @@ def test_bspline_nonfinite_pixel_reaches_every_poi(affine_bsp, name, flag):
     plan = dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois), flags=BSP | flag)
     got = host(plan.correlate(to_dev(pr.ref), to_dev(g), to_dev(pois)))
     torch.cuda.synchronize()
-    compare(got, ref, label=f"bspline nan corner {name}")
+    compare(got, ref, pr.M, label=f"bspline nan corner {name}")
     reached = got["status_int"] == O.OK
     assert reached.sum() > 0.9 * len(pois)
     assert np.all(got["status"][reached] == O.NAN_INPUT)
@@ -194,7 +194,7 @@ def test_bspline_cache_follows_the_image(affine_bsp):
     plan = dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois),
                                 flags=BSP | dic.FLAG_CACHE_REF_PREP)
     a = host(plan.correlate(F, G, Q))
-    compare(a, refs["icgn"], label="bspline cached first")
+    compare(a, refs["icgn"], pr.M, label="bspline cached first")
     other = dicgen.affine_pair_1024(size=256, tag=5)
     G2 = to_dev(other.defm)
     b = host(plan.correlate(F, G2, Q))
@@ -265,5 +265,5 @@ def test_bspline_wide_image_row_tiles(name, flag):
     plan = dic.single_pair_plan(W, H, 10, 6, len(pois), flags=BSP | flag)
     got = host(plan.correlate(to_dev(f), to_dev(g), to_dev(pois)))
     torch.cuda.synchronize()
-    s = compare(got, ref, label=f"bspline wide {name}")
+    s = compare(got, ref, 10, label=f"bspline wide {name}")
     assert s["n_ok"] == len(pois)

@@ -46,7 +46,7 @@ def test_lut_affine_256(affine_lut, name, flag):
     pr, pois, refs = affine_lut
     print(f"case lut {name} affine_256 N={len(pois)}", flush=True)
     got = run(pr, pois, LUT | flag)
-    s = compare(got, refs[name], label=f"lut {name} affine_256")
+    s = compare(got, refs[name], pr.M, label=f"lut {name} affine_256")
     assert s["n_ok"] > 0.95 * s["n"]
     taps = run(pr, pois, flag)
     np.testing.assert_array_equal(got["status"], taps["status"])
@@ -93,7 +93,7 @@ def test_lut_batch_mixed_subsets():
     for p in pairs:
         ref = O.correlate(p.ref, p.defm, p.pois, p.M, p.S)
         sl = slice(off, off + len(p.pois))
-        compare({k: v[sl] for k, v in got.items()}, ref, label=f"lut batch M={p.M}")
+        compare({k: v[sl] for k, v in got.items()}, ref, p.M, label=f"lut batch M={p.M}")
         off += len(p.pois)
 
 
@@ -103,7 +103,7 @@ def test_lut_1024_sampled():
     got = run(pr, pr.pois, LUT)
     idx = np.sort(np.random.default_rng(13).choice(len(pr.pois), 64, replace=False))
     ref = O.correlate(pr.ref, pr.defm, pr.pois[idx], pr.M, pr.S)
-    compare(got, ref, idx=idx, label="lut icgn affine_1024 sampled")
+    compare(got, ref, pr.M, idx=idx, label="lut icgn affine_1024 sampled")
     ok = got["status"] == O.OK
     assert ok.mean() > 0.99
     truth = dicgen.true_displacement(pr.field, pr.pois[ok].astype(np.float64))
@@ -163,7 +163,7 @@ def test_lut_cache_follows_the_image(affine_lut):
     plan = dic.single_pair_plan(256, 256, pr.M, pr.S, len(pois),
                                 flags=LUT | dic.FLAG_CACHE_REF_PREP)
     a = host(plan.correlate(F, G, Q))
-    compare(a, refs["icgn"], label="lut cached first")
+    compare(a, refs["icgn"], pr.M, label="lut cached first")
     other = dicgen.affine_pair_1024(size=256, tag=5)
     G2 = to_dev(other.defm)
     b = host(plan.correlate(F, G2, Q))

@@ -41,14 +41,14 @@ def run_nr(f, g, pois, M, S, precision, **kw):
 def test_nr_rigid_256(rigid_nr, name, prec):
     pr, ref = rigid_nr
     print(f"case nr rigid_256 {name} N={len(pr.pois)}", flush=True)
-    compare(run_nr(pr.ref, pr.defm, pr.pois, pr.M, pr.S, prec), ref, label=f"nr rigid_256/{name}")
+    compare(run_nr(pr.ref, pr.defm, pr.pois, pr.M, pr.S, prec), ref, pr.M, label=f"nr rigid_256/{name}")
 
 
 @pytest.mark.parametrize("name,prec", PRECISIONS)
 def test_nr_affine_256(affine_nr, name, prec):
     pr, pois, ref = affine_nr
     print(f"case nr affine_256 {name} N={len(pois)}", flush=True)
-    s = compare(run_nr(pr.ref, pr.defm, pois, pr.M, pr.S, prec), ref, label=f"nr affine_256/{name}")
+    s = compare(run_nr(pr.ref, pr.defm, pois, pr.M, pr.S, prec), ref, pr.M, label=f"nr affine_256/{name}")
     assert s["n_ok"] > 0.95 * s["n"]
 
 

@@ -50,7 +50,7 @@ def test_rigid_256_full(rigid, name, prec):
     pr, ref = rigid
     print(f"case rigid_256 {name} N={len(pr.pois)}", flush=True)
     _, got = run_pair(pr.ref, pr.defm, pr.pois, pr.M, pr.S, prec)
-    compare(got, ref, label=f"rigid_256/{name}")
+    compare(got, ref, pr.M, label=f"rigid_256/{name}")
 
 
 @pytest.mark.parametrize("name,prec", PRECISIONS)
@@ -58,7 +58,7 @@ def test_affine_256_full(affine_small, name, prec):
     pr, pois, ref = affine_small
     print(f"case affine_256 {name} N={len(pois)}", flush=True)
     _, got = run_pair(pr.ref, pr.defm, pois, pr.M, pr.S, prec)
-    compare(got, ref, label=f"affine_256/{name}")
+    compare(got, ref, pr.M, label=f"affine_256/{name}")
 
 
 def test_affine_1024_sampled():
@@ -69,7 +69,7 @@ def test_affine_1024_sampled():
     _, got = run_pair(pr.ref, pr.defm, pr.pois, pr.M, pr.S, dic.FP32_BATCHED)
     idx = np.sort(np.random.default_rng(7).choice(len(pr.pois), 96, replace=False))
     ref = O.correlate(pr.ref, pr.defm, pr.pois[idx], pr.M, pr.S)
-    compare(got, ref, idx=idx, label="affine_1024/fp32 sampled")
+    compare(got, ref, pr.M, idx=idx, label="affine_1024/fp32 sampled")
     # properties that hold at every POI: statuses, coefficient range, truth
     ok = got["status"] == O.OK
     assert ok.mean() > 0.99
@@ -93,7 +93,7 @@ def test_batch_mixed_subsets():
         for p in pairs:
             ref = O.correlate(p.ref, p.defm, p.pois, p.M, p.S)
             sl = slice(off, off + len(p.pois))
-            compare({k: v[sl] for k, v in got.items()}, ref, label=f"batch M={p.M}/{name}")
+            compare({k: v[sl] for k, v in got.items()}, ref, p.M, label=f"batch M={p.M}/{name}")
             off += len(p.pois)
 
 
@@ -140,7 +140,7 @@ def test_status_codes_match_oracle():
             plan = dic.single_pair_plan(128, 128, 7, 6, len(pois), prec, max_iters=max_iters)
             out = host(plan.correlate(to_dev(f), to_dev(g), to_dev(pois)))
             ref = O.correlate(f, g, pois, 7, 6, max_iters=max_iters)
-            compare(out, ref, label=f"status/{name}/it{max_iters}")
+            compare(out, ref, 7, label=f"status/{name}/it{max_iters}")
     # stripes along x only: singular Hessian, search still works
     stripes = np.tile(60 + 30 * np.sin(x / 3.0) + 10 * np.cos(x / 1.7), (128, 1)).astype(np.float32)
     for name, prec in PRECISIONS:
@@ -149,7 +149,7 @@ def test_status_codes_match_oracle():
         out = host(plan.correlate(to_dev(stripes), to_dev(stripes), to_dev(q)))
         ref = O.correlate(stripes, stripes, q, 7, 4)
         assert np.all(ref["status"] == O.SINGULAR_HESSIAN)
-        compare(out, ref, label=f"stripes/{name}")
+        compare(out, ref, 7, label=f"stripes/{name}")
 
 
 def test_seeded_window_leaving_image():

@@ -38,7 +38,7 @@ def test_previous_reference_matches_oracle(frames, name, prec):
                                  precision=prec, reference="previous")
     assert len(got) == len(ref)
     for k, (g, r) in enumerate(zip(got, ref), start=1):
-        compare(host(g), r, label=f"sequence previous {k}/{name}")
+        compare(host(g), r, M, label=f"sequence previous {k}/{name}")
     # from device frames, in place: the same bits
     dev = dic.correlate_sequence([to_dev(f) for f in fr], to_dev(pois), M, S, precision=prec,
                                  reference="previous")
@@ -87,7 +87,7 @@ def test_live_policy_skips_and_matches_oracle(frames):
     used = [frames[k] for k in (0, 2, 3, 6)]
     ref = O.correlate_sequence(used, pois, M, S, reference="previous")
     for k, (o, r) in enumerate(zip(outs, ref)):
-        compare(host(o), r, label=f"live pair {k}")
+        compare(host(o), r, M, label=f"live pair {k}")
     # the same pairs through the sequence driver: the same bits
     seq = dic.correlate_sequence([torch.from_numpy(f) for f in used], Q, M, S,
                                  reference="previous")
@@ -114,7 +114,7 @@ def test_camera_scale_pair_sampled():
     f1, f2 = fr[1].cpu().numpy(), fr[2].cpu().numpy()
     idx = np.sort(np.random.default_rng(19).choice(len(pois), 24, replace=False))
     ref = O.correlate(f1, f2, pois[idx], M, S)
-    compare(h, ref, idx=idx, label="camera pair sampled")
+    compare(h, ref, M, idx=idx, label="camera pair sampled")
     ok = h["status"] == O.OK
     assert ok.mean() > 0.99
     truth = dicgen.true_increment(dicgen.heterogeneous_strain(1), dicgen.heterogeneous_strain(2),
