@@ -89,7 +89,15 @@ enum {
                                          the same image pointers until
                                          dic_plan_invalidate_reference()     */
   DIC_FLAG_DETERMINISTIC_BWD = 1u << 2, /* grad_def accumulated in a fixed
-                                         order (no float atomics)            */
+                                         order (no float atomics): 2^-40
+                                         fixed-point integer sums per
+                                         distinct deformed image, added to
+                                         grad_def once.  Pairs must name
+                                         the same deformed image (equal
+                                         def_offset, width and height) or
+                                         disjoint ones; dic_plan_create
+                                         rejects partial overlaps with
+                                         INVALID_ARGUMENT                    */
   DIC_FLAG_REFINE_NR = 1u << 3,       /* dic_correlate (and the autotuner)
                                          refine with Newton-Raphson instead
                                          of IC-GN                            */

@@ -38,8 +38,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t pairs = 0, poi_pair = 0, work = 0, counters = 0, grads = 0, recs = 0, tmpl = 0,
-         box = 0, lut = 0, bsp_flags = 0, fix_off = 0, fix = 0, s_status = 0, s_zncc = 0,
-         total = 0;
+         box = 0, lut = 0, bsp_flags = 0, fix_off = 0, fix_owner = 0, fix = 0, s_status = 0,
+         s_zncc = 0, total = 0;
   int64_t fix_count = 0;
 };
 
@@ -71,6 +71,9 @@ struct dic_plan_s {
   std::vector<int32_t> poi_pair, work;
   std::vector<std::pair<int, int64_t>> m_runs;  // (M, length) runs of the work list
   std::vector<int64_t> fix_off;
+  // deterministic adjoint: the pair that owns each distinct deformed image
+  // (pairs on the same image share its fixed-point accumulator, flushed once)
+  std::vector<int32_t> fix_owner;
   int64_t N = 0;
   int maxM = 0, maxS = 0, maxW = 0, maxH = 0;
   Layout lay;
@@ -447,7 +450,34 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
       if (use_bsp) lut4 += (2 * (int64_t)q.width * q.height + 3) / 4;
     }
     p->fix_off[k] = fix;
-    if (p->det()) fix += (int64_t)q.width * q.height;
+    if (p->det()) {
+      // Pairs that name the same deformed image (offset and size) share one
+      // accumulator; partly overlapping images would be flushed twice over
+      // the same pixels, so they are rejected.
+      int shared = -1;
+      const int64_t a0 = q.def_offset, a1 = a0 + (int64_t)q.width * q.height;
+      for (int j : p->fix_owner) {
+        const dic_pair_desc_t& o = p->pairs[j];
+        const int64_t b0 = o.def_offset, b1 = b0 + (int64_t)o.width * o.height;
+        if (o.def_offset == q.def_offset && o.width == q.width && o.height == q.height) {
+          shared = j;
+          break;
+        }
+        if (a0 < b1 && b0 < a1) {
+          std::ostringstream why;
+          why << "pair " << k << ": with DIC_FLAG_DETERMINISTIC_BWD the deformed image must be "
+              << "the same image as, or disjoint from, that of pair " << j;
+          delete p;
+          return fail(DIC_ERR_INVALID_ARGUMENT, why.str());
+        }
+      }
+      if (shared >= 0) {
+        p->fix_off[k] = p->fix_off[shared];
+      } else {
+        p->fix_owner.push_back(k);
+        fix += (int64_t)q.width * q.height;
+      }
+    }
     p->maxM = std::max(p->maxM, (int)q.subset_radius);
     p->maxS = std::max(p->maxS, (int)q.search_radius);
     p->maxW = std::max(p->maxW, (int)q.width);
@@ -460,6 +490,7 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
   L.lut = take(sizeof(float) * 4 * lut4);
   L.bsp_flags = take(use_bsp ? sizeof(int32_t) * d->num_pairs : 0);
   L.fix_off = take(sizeof(int64_t) * d->num_pairs);
+  L.fix_owner = take(sizeof(int32_t) * p->fix_owner.size());
   L.fix = take(sizeof(unsigned long long) * fix);
   L.fix_count = fix;
   L.s_status = take(sizeof(int32_t) * p->N);
@@ -550,6 +581,9 @@ dic_status_t dic_plan_bind(dic_plan_t p, void* ws, size_t bytes, dic_stream_t st
   }
   DIC_HIP(hipMemcpyAsync(base + p->lay.fix_off, p->fix_off.data(), sizeof(int64_t) * p->fix_off.size(),
                          hipMemcpyHostToDevice, s));
+  if (!p->fix_owner.empty())
+    DIC_HIP(hipMemcpyAsync(base + p->lay.fix_owner, p->fix_owner.data(),
+                           sizeof(int32_t) * p->fix_owner.size(), hipMemcpyHostToDevice, s));
   DevState& st = p->st;
   st.pairs = reinterpret_cast<const DevPair*>(base + p->lay.pairs);
   st.poi_pair = reinterpret_cast<const int32_t*>(base + p->lay.poi_pair);
@@ -750,8 +784,9 @@ dic_status_t dic_znssd_backward(dic_plan_t p, const float* ref, const float* def
   char* base = static_cast<char*>(p->ws);
   unsigned long long* fix = p->det() ? reinterpret_cast<unsigned long long*>(base + p->lay.fix) : nullptr;
   const int64_t* fix_off = reinterpret_cast<const int64_t*>(base + p->lay.fix_off);
+  const int32_t* fix_owner = reinterpret_cast<const int32_t*>(base + p->lay.fix_owner);
   DIC_HIP(launch_znssd(p->st, ref, def, poi, pw, grad_c, c_out, grad_p, grad_def, fix, fix_off,
-                       p->lay.fix_count, p->num_cu, s));
+                       fix_owner, (int)p->fix_owner.size(), p->lay.fix_count, p->num_cu, s));
   return DIC_SUCCESS;
 }
 

@@ -155,7 +155,8 @@ hipError_t launch_icgn_f64(const DevState& st, const DevPair* host_pairs, const 
 hipError_t launch_znssd(const DevState& st, const float* ref, const float* def,
                         const int32_t* poi, const double* p, const float* grad_c,
                         float* c_out, double* grad_p, float* grad_def,
-                        unsigned long long* fix_acc, const int64_t* fix_off, int64_t fix_count,
+                        unsigned long long* fix_acc, const int64_t* fix_off,
+                        const int32_t* fix_owner, int num_regions, int64_t fix_count,
                         int num_cu, hipStream_t s);
 hipError_t launch_seed_update(int64_t N, const double* p, const int32_t* status,
                               int32_t* seed_uv, double* p_seed, hipStream_t s);

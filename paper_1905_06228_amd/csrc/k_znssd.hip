@@ -181,16 +181,20 @@ __global__ void fix_clear_kernel(unsigned long long* acc, int64_t count) {
     acc[i] = 0ull;
 }
 
-// grad_def[pair image] += fixed-point accumulator, per pair.
+// grad_def[image] += fixed-point accumulator, once per distinct deformed
+// image (grid row y: the pair owner[y] that owns it; pairs on the same image
+// accumulated into the same block, and no two owners overlap).
 __global__ void fix_flush_kernel(const DevPair* __restrict__ pairs,
                                  const int64_t* __restrict__ fix_off,
+                                 const int32_t* __restrict__ owner,
                                  const unsigned long long* __restrict__ acc,
                                  float* __restrict__ grad_def) {
-  const DevPair P = pairs[blockIdx.y];
+  const int k = owner[blockIdx.y];
+  const DevPair P = pairs[k];
   const int64_t count = (int64_t)P.width * P.height;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const long long v = (long long)acc[fix_off[blockIdx.y] + i];
+    const long long v = (long long)acc[fix_off[k] + i];
     if (v != 0) grad_def[P.def_off + i] += (float)((double)v / kFixScale);
   }
 }
@@ -198,8 +202,8 @@ __global__ void fix_flush_kernel(const DevPair* __restrict__ pairs,
 hipError_t launch_znssd(const DevState& st, const float* ref, const float* def,
                         const int32_t* poi, const double* p, const float* grad_c, float* c_out,
                         double* grad_p, float* grad_def, unsigned long long* fix_acc,
-                        const int64_t* fix_off, int64_t fix_count, int /*num_cu*/,
-                        hipStream_t s) {
+                        const int64_t* fix_off, const int32_t* fix_owner, int num_regions,
+                        int64_t fix_count, int /*num_cu*/, hipStream_t s) {
   if (st.N == 0) return hipSuccess;
   const bool det = fix_acc != nullptr && grad_def != nullptr;
   if (det) {
@@ -225,9 +229,9 @@ hipError_t launch_znssd(const DevState& st, const float* ref, const float* def,
 #undef DIC_ZN_CASE
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (det) {
-    hipLaunchKernelGGL(fix_flush_kernel, dim3(256, st.num_pairs), dim3(256), 0, s, st.pairs,
-                       fix_off, fix_acc, grad_def);
+  if (det && num_regions > 0) {
+    hipLaunchKernelGGL(fix_flush_kernel, dim3(256, num_regions), dim3(256), 0, s, st.pairs,
+                       fix_off, fix_owner, fix_acc, grad_def);
     e = hipGetLastError();
   }
   return e;

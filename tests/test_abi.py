@@ -107,11 +107,36 @@ def test_search_form_follows_radius(L):
     ([(256, 256, 10, 8, 0, 0, 0, 1)], {"precision": 7}, "precision"),
     ([(256, 256, 10, 8, 0, 0, 0, 1)], {"flags": 128}, "flag"),
     ([(20, 20, 9, 0, 0, 0, 0, 1)], {}, "fit"),
+    # deterministic adjoint: a deformed image partly overlapping another pair's
+    ([(64, 64, 5, 4, 0, 0, 0, 1), (64, 64, 5, 4, 0, 100, 1, 1)], {"flags": 4}, "disjoint"),
+    ([(64, 64, 5, 4, 0, 0, 0, 1), (32, 64, 5, 4, 0, 0, 1, 1)], {"flags": 4}, "disjoint"),
 ])
 def test_plan_create_rejects(L, pairs, kw, why):
     rc, h = make(L, pairs, **kw)
     assert rc == -1 and not h.value
     assert why in L.dic_last_error().decode()
+
+
+def test_deterministic_adjoint_shared_or_disjoint_images(L):
+    """With the deterministic adjoint, pairs on the same deformed image share
+    one fixed-point accumulator (no extra workspace); disjoint images each
+    get one; without the flag overlaps are allowed (float atomics)."""
+    one = (64, 64, 5, 4, 0, 0, 0, 1)
+    same = (64, 64, 7, 4, 0, 0, 1, 1)             # same def_offset, width, height
+    apart = (64, 64, 7, 4, 0, 64 * 64, 1, 1)      # the next image of the arena
+    sizes = {}
+    for name, pairs in (("single", [one]), ("same", [one, same]), ("apart", [one, apart])):
+        rc, h = make(L, pairs, flags=4)
+        assert rc == 0, L.dic_last_error()
+        nb = ctypes.c_size_t(0)
+        L.dic_plan_workspace_size(h, ctypes.byref(nb))
+        sizes[name] = nb.value
+        L.dic_plan_destroy(h)
+    # a second accumulator (8 bytes per pixel) only for a distinct image
+    assert sizes["apart"] - sizes["same"] >= 8 * 64 * 64 - 512
+    rc, h = make(L, [one, (64, 64, 5, 4, 0, 100, 1, 1)])
+    assert rc == 0
+    L.dic_plan_destroy(h)
 
 
 def test_interpolation_flags(L):
