@@ -31,7 +31,7 @@ paper defers IC-GN details to Pan et al. and Baker & Matthews).
 Parity status: every function here is pinned by the CPU test-suite against
 closed forms, invariants, brute force or independent library routines, except
 the conventions that have no external value (POI grid margin, tie-break rule,
-convergence norm, seed policy of the sequence), which are "parity unpinned"
+seed policy of the sequence), which are "parity unpinned"
 beyond both sides implementing the same stated rule.
 """
 from __future__ import annotations
