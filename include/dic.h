@@ -74,9 +74,13 @@ enum {
 };
 
 typedef enum {
-  DIC_FP32_BATCHED = 0, /* FP32 sums with compensation, LDS staging,
-                           persistent batched launches; FP64 only for the
-                           6x6 factorisation/solve and warp composition     */
+  DIC_FP32_BATCHED = 0, /* FP32 interpolation and correlation sums in short
+                           per-lane blocks with a fixed reduction tree (no
+                           Kahan compensation), FP64 for the sums that decide
+                           means and statuses, bf16 matrix-core search
+                           filter with an FP64 decision, LDS staging,
+                           persistent batched launches; FP64 for the 6x6
+                           factorisation/solve and warp composition         */
   DIC_FP64_PLAIN = 1    /* FP64 throughout, no staging, no compensation,
                            one launch per pair                               */
 } dic_precision_t;

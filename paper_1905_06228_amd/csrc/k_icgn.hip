@@ -5,12 +5,13 @@
 // (several waves per workgroup, each independent).  Per lane: the reference
 // gradients of its samples stay in registers for the whole solve, so an
 // iteration reads only the deformed image, from a per-wave LDS patch (holding
-// g - fbar, compile-time row pitch) that is restaged only when the warped
-// subset leaves it.  Sample positions are an integer base (POI + rounded
-// translation) plus an FP32 local offset below ~M+slack pixels.  Eight sums
-// per iteration (sum g, sum g^2 and the six steepest-descent products, g
-// taken relative to fbar) are blocked: each lane sums its at most MAXS
-// samples in FP32 (fused multiply-adds) and the 64 lane partials are added in
+// g - c0, c0 a deformed grey level at the subset's centre, compile-time row
+// pitch) that is restaged only when the warped subset leaves it.  Sample
+// positions are an integer base (POI + rounded translation) plus an FP32
+// local offset below ~M+slack pixels.  Eight sums per iteration (sum g,
+// sum g^2 and the six steepest-descent products, g taken relative to c0)
+// are blocked: each lane sums its at most MAXS samples in FP32 (fused
+// multiply-adds) and the 64 lane partials are added in
 // FP32 in a fixed tree of six levels, so the relative error stays near
 // (MAXS + 6) * 2^-24 of the sum of magnitudes; with the precomputed
 // sum SD_i (f_i - fbar) and sum SD_i the right-hand side needs no second pass:
@@ -94,7 +95,7 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
       float fxs[MAXS], fys[MAXS];
       half2v dxy[MAXS];
       load_slots<MAXS>(M, n, gx, gy, W, dxy, fxs, fys);
-      const float c0 = (float)R->fbar;
+      const float c0 = deformed_centre(gimg, W, H, p, x0, y0);
       const double df = R->df;
       const double nn = (double)n;
       patch.x0 = patch.y0 = INT_MIN;

@@ -14,7 +14,8 @@
 // f_i - fbar and sample offsets stay in registers; the deformed patch is
 // staged per wave in LDS as for IC-GN.  One pass per iteration accumulates
 // sum g, sum g^2, sum (f - fbar) g, sum J, sum J J^T, sum J (f - fbar) and
-// sum J g (42 sums, g taken relative to fbar) in FP32 per lane and in a fixed
+// sum J g (42 sums, g taken relative to c0, a deformed grey level at the
+// subset's centre) in FP32 per lane and in a fixed
 // FP32 tree across lanes; the centring by the means is applied to the sums in
 // FP64.  Hessian, solve and update in FP64.
 #include "refine_common.h"
@@ -114,7 +115,7 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
       float tv[MAXS];
       half2v dxy[MAXS];
       load_slots<MAXS>(M, n, tm, nullptr, tp, dxy, tv, nullptr);
-      const float c0 = (float)R->fbar;
+      const float c0 = deformed_centre(gimg, W, H, p, x0, y0);
       const double df = R->df, tsum = (double)R->tsum;
       const double nn = (double)n;
       patch.x0 = patch.y0 = INT_MIN;

@@ -3,16 +3,18 @@
 //
 // FP32 batched form on the vector ALUs.  One workgroup per POI at a time,
 // persistent over a shared work counter.  The deformed window (2S+2M+1
-// square, shifted by the subset mean so sums stay small) is staged in LDS
-// once.  Per candidate the window sums sum(g) and sum(g^2) come from the
+// square, shifted by the mean of its centre subset so sums stay small) is
+// staged in LDS once.  Per candidate the window sums sum(g) and sum(g^2) come from the
 // FP64 box-sum images, and the cross term sum(t_i g_i) with the mean-free
 // template t from a register-blocked loop: a lane owns L horizontally
 // adjacent candidates, keeps a sliding window of grey levels in registers and
 // reads each template value once from scalar memory, so one LDS read feeds L
-// FMAs.  Row partial sums accumulate in FP64.  The FP32 maximum selects the
-// candidates within 2e-5 of it; one wave re-scores them in FP64 (always at
-// least the winner) and the tie rule picks the smallest row-major index
-// within 1e-12 of the FP64 maximum.
+// FMAs.  Row partial sums accumulate in FP64.  Each FP32 score s_c comes
+// with a bound E_c on its distance from Eq. (1) (search_f32_error); the
+// candidates whose s_c + E_c reaches max_k (s_k - E_k) may hold the maximum,
+// and one wave re-scores them in FP64 (always at least the winner); the tie
+// rule then picks the smallest row-major index within 1e-12 of the FP64
+// maximum.
 #include "search_common.h"
 
 namespace dic {
@@ -125,6 +127,22 @@ __device__ __forceinline__ void cross_terms(const float* __restrict__ tm, int tp
   }
 }
 
+// Bound on |s_c - Eq. (1)| for the FP32 score of a candidate whose
+// template rows run over NP terms.  The cross term sum t_i (g_i - c0) is
+// formed from FP32 inputs rounded once (t and g - c0) by FP32 multiply-adds
+// over at most NP terms per row, the rows added in FP64, so its error is at
+// most (NP + 2) 2^-24 sum |t_i| |g_i - c0|, and by Cauchy-Schwarz at most
+// (NP + 2) 2^-24 df sqrt(sum (g_i - c0)^2); divided by df sqrt(var), the
+// score's scale, that is (NP + 2) 2^-24 R with R = sqrt(sum (g - c0)^2 /
+// var), which grows with the window's offset from c0.  The final FP32
+// division, square root and conversions add at most 6 2^-24 to a score of
+// magnitude at most 1.  Margins: NP + 4 and 8 in place of NP + 2 and 6, and
+// 1 %.
+__device__ __forceinline__ float search_f32_error(int np, double sgc2, double var) {
+  const float R = sqrtf(fmaxf((float)(sgc2 / var), 1.f));
+  return 1.01f * fmaf((float)(np + 4), R, 8.f) * 5.9604645e-8f;
+}
+
 }  // namespace
 
 size_t search_lds_bytes(int maxM, int maxS, int block) {
@@ -181,7 +199,19 @@ __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
     const SearchGeom G = search_geom(P.M, P.S, L);
     const int W = P.width, H = P.height;
     const float* gimg = def + P.def_off;
-    const float c0 = (float)R->fbar;
+    const int64_t plane = (int64_t)W * H;
+    const double* s1img = box + P.box_off + 2 * plane;
+    const double* s2img = s1img + plane;
+    const double rnd = 1.0 / (double)G.n;
+    // The window is staged as g - c0: c0 is the exact mean of the subset at
+    // the window centre (clamped into the image) when that subset is
+    // admissible, so the staged values stay within the grey levels the window
+    // holds whatever its offset against the reference; else the reference mean.
+    float c0 = (float)R->fbar;
+    {
+      const int64_t oc = (int64_t)min(max(y0 + cv, 0), H - 1) * W + min(max(x0 + cu, 0), W - 1);
+      if (s2img[oc] >= 0.0) c0 = (float)(s1img[oc] * rnd);
+    }
     const int wx0 = x0 + cu - G.S - G.M, wy0 = y0 + cv - G.S - G.M;
 
     float* win = lds;
@@ -223,15 +253,12 @@ __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
     const float* tm = tmpl_arena + P.tmpl_off + (int64_t)(g - P.poi_off) * G.n1 * tp;
     const double dfd = R->df;
     const float df = (float)dfd;
-    const double rnd = 1.0 / (double)G.n;
     const double tsum = R->tsum;
+    float lmax = kNegInf;   // this lane's largest s_c - E_c
     if (mine) {
       double tot[L];
       const float* wrow = win + r * G.P + b * L;
       cross_terms<L, NP>(tm, tp, G.n1, wrow, G.P, tot);   // G.NP == NP for this group
-      const int64_t plane = (int64_t)W * H;
-      const double* s1img = box + P.box_off + 2 * plane;
-      const double* s2img = s1img + plane;
 #pragma unroll
       for (int k = 0; k < L; ++k) {
         const int c = b * L + k;
@@ -248,32 +275,38 @@ __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
             // sum t (g - gbar) = sum t (g - c0) - (gbar - c0) sum t
             const double num = tot[k] - (sg * rnd - (double)c0) * tsum;
             sc = (float)num / (df * sqrtf((float)var));
-            if (!isfinite(sc)) sc = kNegInf;
+            if (isfinite(sc)) {
+              // sum (g - c0)^2 from the exact sums
+              const double sgc2 = sq - 2.0 * (double)c0 * sg + (double)G.n * (double)c0 * c0;
+              const float e = search_f32_error(NP, sgc2, var);
+              lmax = fmaxf(lmax, sc - e);
+              sc += e;
+            } else {
+              sc = kNegInf;
+            }
           }
         }
-        scores[r * G.side + c] = sc;
+        scores[r * G.side + c] = sc;   // the upper bound s_c + E_c
       }
     }
     if (tid == 0) s_cnt = 0;
     __syncthreads();
 
-    // 4. block maximum of the FP32 scores.
+    // 4. block maximum of the lower bounds s_c - E_c.
     const int K = G.side * G.side;
-    float m = kNegInf;
-    for (int c = tid; c < K; c += nthr) m = fmaxf(m, scores[c]);
-    m = wave_max(m);
+    float m = wave_max(lmax);
     if (lane == 0) s_wmax[wid] = m;
     __syncthreads();
     float mm = kNegInf;
     for (int k = 0; k < nthr / kWave; ++k) mm = fmaxf(mm, s_wmax[k]);
 
-    // 5. Candidates within 2e-5 of the FP32 maximum (the FP32 scores are
-    //    within ~1e-6 of Eq. (1)) go to a list; wave 0 re-scores them in FP64
-    //    and applies the tie rule: the smallest row-major index within 1e-12
-    //    of the FP64 maximum.  A list that overflows is swept twice in index
-    //    order instead.
+    // 5. Candidates whose upper bound reaches the largest lower bound go to
+    //    a list (the FP64 maximum is among them); wave 0 re-scores them in
+    //    FP64 and applies the tie rule: the smallest row-major index within
+    //    1e-12 of the FP64 maximum.  A list that overflows is swept twice in
+    //    index order instead.
     if (mm > kNegInf) {
-      const float thr = mm - 2e-5f;
+      const float thr = mm;
       for (int c = tid; c < K; c += nthr)
         if (scores[c] >= thr) {
           const int slot = atomicAdd(&s_cnt, 1);
@@ -283,7 +316,6 @@ __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
     __syncthreads();
     if (wid == 0) {
       const float* fimg = ref + P.ref_off;
-      const double* s1img = box + P.box_off + 2 * (int64_t)W * H;
       auto rescore = [&](int cand) -> double {
         const int rr = cand / G.side, cc = cand - rr * G.side;
         const int xg = x0 + cu - G.S + cc, yg = y0 + cv - G.S + rr;
@@ -311,7 +343,7 @@ __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
             }
           }
       } else {
-        const float thr = mm - 2e-5f;
+        const float thr = mm;
         double cmax = -INFINITY;
         for (int cand = 0; cand < K; ++cand)
           if (scores[cand] >= thr) cmax = fmax(cmax, rescore(cand));

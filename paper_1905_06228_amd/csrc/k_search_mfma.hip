@@ -10,9 +10,10 @@
 // second tile for dv, du in [1, 33) (its A operand is the next row's, loaded
 // once for both tiles) and two corner candidates on the vector ALUs.
 //
-// Operands are rounded to bf16 (t and g' = g - fbar each to 8 significant
-// bits), so each product carries a relative error below 2^-7 + 3 * 2^-16 and
-// the FP32 accumulation adds at most (terms) * 2^-24.  With Cauchy-Schwarz,
+// Operands are rounded to bf16 (t and g' = g - c0 each to 8 significant
+// bits, c0 the mean of the window's centre subset), so each product carries
+// a relative error below 2^-7 + 3 * 2^-16 and the FP32 accumulation adds at
+// most (terms) * 2^-24.  With Cauchy-Schwarz,
 // sum |t| |g'| <= df * sqrt(sum g'^2), the approximate coefficient of every
 // candidate is within
 //   E = kappa * sqrt(sum g'^2 / sum (g - gbar)^2)
@@ -159,7 +160,7 @@ __device__ __forceinline__ void correlate_tiles(const uint16_t* win, const uint3
 // Approximate coefficient of candidate (dv, du) of the window (row-major in
 // [0, side)^2) from its cross term C and the window statistics st = (mean,
 // 1/sqrt(sum (g - mean)^2)) of the box-sum pass, and its error bound E (the
-// ratio sum g'^2 / sum (g - mean)^2 is 1 + n ((mean - fbar) / sd)^2); -inf for
+// ratio sum g'^2 / sum (g - mean)^2 is 1 + n ((mean - c0) / sd)^2); -inf for
 // an inadmissible or flat candidate.
 struct ScoreCtx {
   int x0, y0, cu, cv, S, M, W, H, side;
@@ -171,7 +172,7 @@ __device__ __forceinline__ float score_of(const ScoreCtx& q, float C, int dv, in
   const int dua = q.cu - q.S + du, dva = q.cv - q.S + dv;
   bool ok = dv < q.side && du < q.side && q.x0 + dua - q.M >= 0 && q.x0 + dua + q.M <= q.W - 1 &&
             q.y0 + dva - q.M >= 0 && q.y0 + dva + q.M <= q.H - 1 && st.y > 0.f;
-  // sum t (g - mean) = sum t (g - fbar) - (mean - fbar) sum t
+  // sum t (g - mean) = sum t (g - c0) - (mean - c0) sum t
   const float dm = st.x - q.c0;
   const float sc = fmaf(-dm, q.tsum, C) * st.y * q.rdf;
   const float z = dm * st.y;
@@ -268,7 +269,20 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     const int W = P.width, H = P.height, K = side * side;
     const float* gimg = def + P.def_off;
     const float* fimg = ref + P.ref_off;
-    const float c0 = (float)R->fbar;
+    const int64_t plane = (int64_t)W * H;
+    const double* s1img = box + P.box_off + 2 * plane;
+    const float2* stimg = reinterpret_cast<const float2*>(box + P.box_off + 4 * plane);
+    // The window is staged as g - c0 in bf16: c0 is the mean of the subset at
+    // the window centre (clamped into the image) when that subset is
+    // admissible and not flat, so the staged values, and the bound E, stay
+    // small whatever the window's offset against the reference; else the
+    // reference mean.
+    float c0 = (float)R->fbar;
+    {
+      const float2 sc = stimg[(int64_t)min(max(y0 + cv, 0), H - 1) * W +
+                              min(max(x0 + cu, 0), W - 1)];
+      if (sc.y > 0.f && isfinite(sc.x)) c0 = sc.x;
+    }
     const int wx0 = x0 + cu - S - M, wy0 = y0 + cv - S - M;
     const int wn = n1 + side - 1;   // real window side
     const int wrows = n1 + 32 * TT;   // staged rows (a tile reads up to 32 (TT - 1) + n1 + 31)
@@ -282,9 +296,6 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     q.tsum = R->tsum;
     q.rdf = (float)(1.0 / R->df);
     q.nn = (float)nn;
-    const int64_t plane = (int64_t)W * H;
-    const double* s1img = box + P.box_off + 2 * plane;
-    const float2* stimg = reinterpret_cast<const float2*>(box + P.box_off + 4 * plane);
 
     // 0. the FP32 template as 4-column groups (rows of pitch tp, 16-byte
     //    aligned; groups past tp are zero), requested at once
@@ -330,7 +341,7 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     } else {
       if (lane < kMaskWords) mask[lane] = 0u;
     }
-    // 2. window g - fbar in bf16, CB chunks of 8 columns per lane at a time;
+    // 2. window g - c0 in bf16, CB chunks of 8 columns per lane at a time;
     //    outside the window or the image, and non-finite pixels, are 0 (their
     //    candidates are invalid by the box sums).  A window whose staged
     //    rows and columns all lie in the image (the usual case) is read as

@@ -1,9 +1,10 @@
 // Pieces shared by the sub-pixel refinements of Sec. 2.2 (IC-GN and
 // Newton-Raphson, FP32 batched forms): the first-order warp in FP32 local
-// form, the bounding box of the taps it touches, the per-wave LDS patch of
-// the deformed image, interpolation from that patch or from the image (Keys
-// bicubic, NT = 4 taps per direction; Eq. (5)'s bilinear, NT = 2; or the
-// cubic B-spline, NT = 4 taps of the image's spline coefficients), or
+// form, the bounding box of the taps it touches, the centring constant of
+// the deformed samples, the per-wave LDS patch of the deformed image,
+// interpolation from that patch or from the image (Keys bicubic, NT = 4
+// taps per direction; Eq. (5)'s bilinear, NT = 2; or the cubic B-spline,
+// NT = 4 taps of the image's spline coefficients), or
 // bicubic from a per-cell table of polynomial coefficients, and the final
 // pass that evaluates Eq. (1) at the converged warp.
 //
@@ -68,6 +69,23 @@ __device__ __forceinline__ Warp32 make_warp32(const double* p, int x0, int y0) {
   w.vx = (float)p[4];
   w.ay = (float)(1.0 + p[5]);
   return w;
+}
+
+// Centring constant of a refinement's deformed samples: the deformed image
+// (or its spline coefficients) at the integer base of the starting warp, one
+// of the first iteration's taps.  Samples are handled as g - c0 in FP32, so
+// c0 has to lie among the grey levels the subset meets whatever offset the
+// deformed image has against the reference (ZNCC ignores a change g = a f +
+// b): the reference mean would leave that offset in every FP32 sum and lose
+// the variance sum g^2 - n gbar^2 to cancellation.  0 when the base is
+// outside the image (the first iteration then stops with OUT_OF_BOUNDS); a
+// non-finite value makes the first iteration's sums non-finite, as the tap
+// it is would (NAN_INPUT).
+__device__ __forceinline__ float deformed_centre(const float* __restrict__ gimg, int W, int H,
+                                                 const double* p, int x0, int y0) {
+  const int bx = x0 + (int)rint(p[0]), by = y0 + (int)rint(p[3]);
+  if (bx < 0 || bx >= W || by < 0 || by >= H) return 0.f;
+  return gimg[(int64_t)by * W + bx];
 }
 
 __device__ __forceinline__ float warp_x(const Warp32& w, float dx, float dy) {
