@@ -410,3 +410,33 @@ def sequence_frames_torch(n_frames: int, height: int, width: int, n_blobs: int,
         frames.append(render_image_torch(blobs, fld, height, width, lip, noise,
                                          rng_for(tag, k, 1), device=device))
     return frames
+
+
+def sinusoidal_torch(A: float, lam: float):
+    """``sinusoidal(A, lam)`` on torch tensors."""
+    import torch
+    k = 2.0 * math.pi / lam
+    return lambda X, Y: (A * torch.sin(k * Y), A * torch.cos(k * X))
+
+
+def sinusoidal_batch_torch(n_pairs: int = 64, size: int = 512, S: int = 8, step: int = 6,
+                           first: int = 0, device="cuda") -> List[Pair]:
+    """``sinusoidal_batch`` rendered with ``render_image_torch`` (same blobs,
+    parameters and fields): ``ref`` and ``defm`` are float32 tensors on
+    ``device``, ``pois`` NumPy as there.  The field's displacement gradient is
+    bounded by A 2 pi / lam."""
+    out = []
+    n = int(round(2000 * (size / 256.0) ** 2))
+    for k in range(first, first + n_pairs):
+        prm = rng_for(3, k, 3)
+        A = prm.uniform(0.5, 2.0)
+        lam = prm.uniform(64.0, 256.0)
+        sub = int(BATCH_SUBSETS[prm.integers(0, len(BATCH_SUBSETS))])
+        M = sub // 2
+        blobs = make_blobs(rng_for(3, k, 0), n, size, size)
+        f = render_image_torch(blobs, None, size, size, device=device)
+        g = render_image_torch(blobs, sinusoidal_torch(A, lam), size, size,
+                               A * 2.0 * math.pi / lam, device=device)
+        out.append(Pair(f, g, poi_grid(size, size, M, S, step), M, S, sinusoidal(A, lam),
+                        dict(name=f"sinusoidal_{k}", A=A, lam=lam)))
+    return out

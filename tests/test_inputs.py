@@ -22,3 +22,12 @@ def test_torch_render_under_late_frame_shear():
                                   dicgen.heterogeneous_strain_lipschitz(k, W + 96.0),
                                   device="cpu").numpy()
     np.testing.assert_allclose(b, a, rtol=0, atol=1e-4)
+
+
+def test_torch_sinusoidal_batch_matches_numpy():
+    a = dicgen.sinusoidal_batch(n_pairs=2, size=96, first=5)
+    b = dicgen.sinusoidal_batch_torch(n_pairs=2, size=96, first=5, device="cpu")
+    for pa, pb in zip(a, b):
+        assert (pa.M, pa.S) == (pb.M, pb.S) and np.array_equal(pa.pois, pb.pois)
+        np.testing.assert_allclose(pb.ref.numpy(), pa.ref, rtol=0, atol=1e-4)
+        np.testing.assert_allclose(pb.defm.numpy(), pa.defm, rtol=0, atol=1e-4)
