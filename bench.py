@@ -99,9 +99,70 @@ def time_launches(torch, fn, reps: int) -> float:
     return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline(pair, got, n_sample: int, seed: int = 11):
-    """The FP64 oracle, as it stands, on a seeded sample of POIs (one process);
-    also checks the GPU result on that sample."""
+def host_cpu() -> dict:
+    """The host's CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "usable_cores": usable, "os_cpu_count": os.cpu_count()}
+
+
+def pool_size() -> int:
+    """Oracle worker processes: the usable cores, at most 16 (a one-GPU machine's
+    CPU share)."""
+    return max(1, min(16, host_cpu()["usable_cores"]))
+
+
+_POOL_DATA = {}
+
+
+def _pool_init(data):
+    """Worker set-up: one BLAS thread per process; the images once per worker."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(limits=1)
+    except ImportError:
+        pass
+    _POOL_DATA.update(data)
+
+
+def _pool_correlate(args):
+    from oracle import dic_oracle as O
+    key, pois, M, S = args
+    f, g = _POOL_DATA[key]
+    return O.correlate(f, g, pois, M, S)
+
+
+def _pool_znssd(args):
+    from oracle import dic_oracle as O
+    key, pois, M, P, up = args
+    f, g = _POOL_DATA[key]
+    return O.znssd_batch(f, g, pois, M, P, upstream=up)
+
+
+def make_oracle_pool(procs: int, data: dict):
+    """A spawn-started pool of oracle workers (made before any GPU call; the
+    workers never touch the GPU)."""
+    import multiprocessing as mp
+    return mp.get_context("spawn").Pool(procs, initializer=_pool_init, initargs=(data,))
+
+
+def cpu_baseline(pair, got, n_sample: int, seed: int = 11, pool=None, procs: int = 1,
+                 extra=None):
+    """The FP64 oracle, as it stands, on seeded samples of the benchmark's POIs:
+    one process (one BLAS thread), and, with ``pool``, ``procs`` processes
+    over chunks of a larger sample (the all-cores figure, reported as the
+    value).  The single-process sample also checks the GPU result."""
     from oracle import dic_oracle as O
 
     idx = np.sort(np.random.default_rng(seed).choice(len(pair.pois), n_sample, replace=False))
@@ -124,11 +185,62 @@ def cpu_baseline(pair, got, n_sample: int, seed: int = 11):
                p99_err_px=float(np.percentile(duv.max(axis=1), 99)) if ok.any() else 0.0,
                mean_err_px=float(duv.mean()) if ok.any() else 0.0,
                max_dzncc=float(np.abs(got["zncc"][idx][ok] - ref["zncc"][ok]).max(initial=0.0)))
-    base = dict(value=n_sample / dt, unit="POIs/s", cores=1, kind="oracle",
-                sample=f"{n_sample} seeded POIs of the 36,864-POI grid, FP64 NumPy oracle, "
-                       f"one process, {dt:.1f} s",
-                seconds=dt)
+    cpu = host_cpu()
+    single = dict(value=n_sample / dt, unit="POIs/s", cores=1, kind="oracle",
+                  sample=f"{n_sample} seeded POIs of the 36,864-POI grid, FP64 NumPy oracle, "
+                         f"one process, one BLAS thread, {dt:.1f} s",
+                  seconds=dt)
+    if pool is None:
+        base = dict(single, cpu=cpu)
+        return base, acc
+    n_pool = min(len(pair.pois), 600 * procs)
+    pidx = np.sort(np.random.default_rng(seed + 1).choice(len(pair.pois), n_pool, replace=False))
+    chunks = [("pair", pair.pois[c], pair.M, pair.S) for c in np.array_split(pidx, 4 * procs)]
+    t0 = time.perf_counter()
+    pool.map(_pool_correlate, chunks)
+    dtp = time.perf_counter() - t0
+    base = dict(value=n_pool / dtp, unit="POIs/s", cores=procs, kind="oracle",
+                sample=f"{n_pool} seeded POIs of the 36,864-POI grid, FP64 NumPy oracle, "
+                       f"{procs} spawn-started processes (one BLAS thread each) over "
+                       f"{len(chunks)} chunks, {dtp:.1f} s",
+                seconds=dtp, cpu=cpu, single_process=single)
+    if extra:
+        base["other_workloads"] = extra(pool, procs)
     return base, acc
+
+
+def oracle_other_workloads(pool, procs: int) -> dict:
+    """The oracle on the whole rigid 256 x 256 pair (484 POIs, search and
+    IC-GN) and on the whole differentiation workload (16,384 POIs, criterion
+    and adjoint), over the pool."""
+    import dicgen
+    out = {}
+    pr = dicgen.rigid_pair_256()
+    chunks = [("rigid", q, pr.M, pr.S) for q in np.array_split(pr.pois, 4 * procs)]
+    t0 = time.perf_counter()
+    pool.map(_pool_correlate, chunks)
+    dt = time.perf_counter() - t0
+    out["rigid_256"] = dict(pois=len(pr.pois), seconds=round(dt, 2),
+                            pois_per_s=round(len(pr.pois) / dt, 1), cores=procs)
+    pr4 = dicgen.affine_pair_1024(size=1024, tag=4)
+    pois = dicgen.gradient_grid_1024()
+    N = len(pois)
+    rng = np.random.default_rng(41)
+    ctr = dicgen.true_displacement(pr4.field, pois.astype(np.float64))
+    P = np.zeros((N, 6))
+    P[:, 0], P[:, 3] = ctr[:, 0], ctr[:, 1]
+    P[:, 1], P[:, 5] = 0.005, -0.0015
+    P[:, [0, 3]] += rng.uniform(-0.3, 0.3, (N, 2))
+    P[:, [1, 2, 4, 5]] += rng.uniform(-0.01, 0.01, (N, 4))
+    up = rng.uniform(0.5, 2.0, N)
+    parts = np.array_split(np.arange(N), 4 * procs)
+    chunks = [("diff", pois[c], 12, P[c], up[c]) for c in parts]
+    t0 = time.perf_counter()
+    pool.map(_pool_znssd, chunks)
+    dt = time.perf_counter() - t0
+    out["differentiation"] = dict(pois=N, seconds=round(dt, 2), pois_per_s=round(N / dt, 1),
+                                  cores=procs, what="criterion, dC/dp and dC/dG")
+    return out
 
 
 def sequence_bench(torch, dic, dicgen, dev, n_frames: int, reference: str = "first",
@@ -196,6 +308,128 @@ def sequence_bench(torch, dic, dicgen, dev, n_frames: int, reference: str = "fir
             "live": live_bench(torch, dic, dicgen, host, Q, pois, M, S, live_fps)
             if live_fps > 0 else None,
             "data": "synthetic"}
+
+
+def batched_bench(torch, dic, dicgen, dev, reps: int) -> dict:
+    """The batched workload: 64 independent 512 x 512 speckle pairs with
+    sinusoidal fields, one subset size per pair from {15, 21, 31, 41}, step 6,
+    search +-8, in one plan: every stage is one persistent launch over all
+    pairs' POIs, the whole step replayed as a HIP graph.  POIs/s end to end,
+    per-stage kernel times and the IC-GN roofline (the largest subsets, 41 x 41,
+    run in the 28-slot refinement kernel)."""
+    t0 = time.perf_counter()
+    pairs = dicgen.sinusoidal_batch_torch(n_pairs=64, size=512, S=8, step=6, device=dev)
+    torch.cuda.synchronize()
+    render_s = time.perf_counter() - t0
+    tens = [(p.ref, p.defm, torch.from_numpy(p.pois).to(dev), p.M, p.S) for p in pairs]
+    specs, F, G, Q = dic.batch_layout(tens, dev)
+    N = int(Q.shape[0])
+    plan = dic.Plan(specs, dic.FP32_BATCHED, flags=dic.FLAG_USE_GRAPH)
+    out = plan.new_outputs()
+    ms = time_launches(torch, lambda: plan.correlate(F, G, Q, out=out), reps)
+    st = dic.Plan(specs, dic.FP32_BATCHED, flags=dic.FLAG_CACHE_REF_PREP)
+    st.tuning = plan.tuning
+    so = st.new_outputs()
+    t_prep = time_launches(torch, lambda: st.prepare_reference(F, Q), reps)
+    t_box = time_launches(torch, lambda: st.prepare_deformed(G), reps)
+    t_search = time_launches(torch, lambda: st.integer_search(
+        F, G, Q, out=(so["uv"], so["zncc_int"], so["status_int"])), reps)
+    t_icgn = time_launches(torch, lambda: st.icgn_refine(
+        F, G, Q, so["uv"], so["status_int"],
+        out=(so["p"], so["zncc"], so["iters"], so["status"])), reps)
+    stat = out["status"].cpu().numpy()
+    iters = out["iters"].cpu().numpy()[stat == 0]
+    # algorithmic bytes and flops summed over the pairs' subset sizes
+    icgn_bytes, flops, per_m = 0, 0.0, {}
+    for p in pairs:
+        n = (2 * p.M + 1) ** 2
+        A = (2 * p.M + 4) ** 2
+        icgn_bytes += (12 * n + 4 * A + 70) * len(p.pois)
+        flops += 2.0 * (2 * p.S + 1) ** 2 * n * len(p.pois)
+        per_m[2 * p.M + 1] = per_m.get(2 * p.M + 1, 0) + len(p.pois)
+    gbs = icgn_bytes / (t_icgn * 1e-3) / 1e9
+    tfl = flops / (t_search * 1e-3) / 1e12
+    return {"pois": N, "pairs": len(pairs), "pois_per_subset": dict(sorted(per_m.items())),
+            "ms_per_step": round(ms, 4), "pois_per_s": round(N / (ms * 1e-3), 1),
+            "stages_ms": {"reference_prep": round(t_prep, 4),
+                          "deformed_box_sums": round(t_box, 4),
+                          "search": round(t_search, 4), "icgn": round(t_icgn, 4)},
+            "icgn_pois_per_s": round(N / (t_icgn * 1e-3), 1),
+            "mean_iterations": float(iters.mean()) if iters.size else 0.0,
+            "ok_fraction": float((stat == 0).mean()),
+            "tuning": list(plan.tuning),
+            "roofline_icgn": dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
+                                  unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
+                                  kernel="icgn_f32_kernel (28-, 16- and 8-slot instances)",
+                                  kernel_ms=round(t_icgn, 4),
+                                  algorithmic_bytes_per_launch=int(icgn_bytes)),
+            "roofline_search": dict(bound="mfma", achieved=round(tfl, 2),
+                                    peak=BF16_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                                    frac=round(tfl / BF16_MFMA_PEAK_TFLOPS, 4),
+                                    kernel="search_mfma_kernel", kernel_ms=round(t_search, 4),
+                                    algorithmic_flops_per_launch=flops),
+            "render_s": round(render_s, 1),
+            "config": {"workload": "batched: 64 independent 512x512 speckle pairs (8,000 blobs "
+                                   "each), u = A sin(2 pi y / lam), v = A cos(2 pi x / lam), "
+                                   "A ~ U(0.5, 2), lam ~ U(64, 256), subset per pair from "
+                                   "{15, 21, 31, 41}, step 6, search +-8, one plan, HIP graph"}}
+
+
+# algorithmic bytes of the ZNSSD adjoint per POI: the reference subset (4 n),
+# the deformed patch read (4 A) and its gradient read and written (8 A), the
+# warp, upstream scale, criterion and warp gradient (104 B) and the reference
+# record's mean, norm and status (24 B)
+def znssd_bytes_per_poi(M: int) -> int:
+    n, A = (2 * M + 1) ** 2, (2 * M + 4) ** 2
+    return 4 * n + 12 * A + 128
+
+
+def adjoint_bench(torch, dic, dicgen, dev, reps: int) -> dict:
+    """The differentiation workload: a 1024 x 1024 pair (the affine field with
+    noise), 16,384 POIs on the 68 + 7k grid, subset 25 x 25, the warp off the
+    optimum by a seeded offset; the forward criterion alone, and forward plus
+    backward (dC/dp and dC/dG) in the float-atomic and the deterministic
+    fixed-point modes."""
+    pr = dicgen.affine_pair_1024(size=1024, tag=4)
+    pois = dicgen.gradient_grid_1024()
+    N, M = len(pois), 12
+    rng = np.random.default_rng(41)
+    ctr = dicgen.true_displacement(pr.field, pois.astype(np.float64))
+    P = np.zeros((N, 6))
+    P[:, 0], P[:, 3] = ctr[:, 0], ctr[:, 1]
+    P[:, 1], P[:, 5] = 0.005, -0.0015            # the affine field's gradient terms
+    P[:, [0, 3]] += rng.uniform(-0.3, 0.3, (N, 2))
+    P[:, [1, 2, 4, 5]] += rng.uniform(-0.01, 0.01, (N, 4))
+    up = rng.uniform(0.5, 2.0, N).astype(np.float32)
+    F = torch.from_numpy(pr.ref).to(dev)
+    G = torch.from_numpy(pr.defm).to(dev)
+    Q = torch.from_numpy(pois).to(dev)
+    Pd = torch.from_numpy(P).to(dev)
+    U = torch.from_numpy(up).to(dev)
+    c = torch.empty(N, dtype=torch.float32, device=dev)
+    gp = torch.empty((N, 6), dtype=torch.float64, device=dev)
+    gg = torch.zeros((1024, 1024), dtype=torch.float32, device=dev)
+    res = {}
+    B = znssd_bytes_per_poi(M) * N
+    for mode, flags in (("atomic", 0), ("deterministic", dic.FLAG_DETERMINISTIC_BWD)):
+        plan = dic.single_pair_plan(1024, 1024, M, 16, N, dic.FP32_BATCHED,
+                                    flags=flags | dic.FLAG_CACHE_REF_PREP)
+        plan.prepare_reference(F, Q)
+        t_fwd = time_launches(torch, lambda: plan.znssd(F, G, Q, Pd, grad_c=U, c_out=c), reps)
+        t_bwd = time_launches(torch, lambda: plan.znssd(F, G, Q, Pd, grad_c=U, c_out=c,
+                                                        grad_p=gp, grad_def=gg), reps)
+        gbs = B / (t_bwd * 1e-3) / 1e9
+        res[mode] = {"forward_ms": round(t_fwd, 4), "forward_backward_ms": round(t_bwd, 4),
+                     "pois_per_s": round(N / (t_bwd * 1e-3), 1),
+                     "roofline": dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
+                                      unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+                                      traffic=None, kernel="znssd_kernel",
+                                      algorithmic_bytes_per_launch=int(B))}
+    res["config"] = {"workload": "differentiation: 1024x1024 pair (16,000 blobs, u = 0.005x + "
+                                 "1.3, v = -0.0015y - 0.6, noise sigma 2), 16,384 POIs at "
+                                 "68 + 7k, subset 25x25, warp = the field's plus a seeded offset "
+                                 "(u, v within 0.3 px, gradient terms within 0.01)"}
+    return res
 
 
 # plan flags of the refinement's interpolation options
@@ -273,7 +507,14 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pool", type=int, default=1,
+                    help="1: also time the oracle over a pool of worker processes (all "
+                         "usable cores, at most 16); 0: one process only")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--minimal", action="store_true",
+                    help="time only the FP32 step and its stages (profiler runs)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the batched and differentiation workloads")
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--tuning", type=str, default=None,
                     help="search_block,search_occupancy,icgn_waves,icgn_slack (skips autotuning)")
@@ -295,6 +536,20 @@ def main() -> int:
                           "single-device build; --gpus must be 1"}))
         return 2
 
+    pool, procs, pair = None, 1, None
+    if args.sequence_frames <= 0:
+        import dicgen
+        pair = dicgen.affine_pair_1024()
+        if not args.no_cpu_baseline and args.cpu_pool and not args.minimal:
+            # the oracle's worker pool starts before anything touches the GPU
+            procs = pool_size()
+            data = {"pair": (pair.ref, pair.defm)}
+            if not args.no_configs:
+                pr1 = dicgen.rigid_pair_256()
+                pr4 = dicgen.affine_pair_1024(size=1024, tag=4)
+                data.update(rigid=(pr1.ref, pr1.defm), diff=(pr4.ref, pr4.defm))
+            pool = make_oracle_pool(procs, data)
+
     import torch
 
     import dicgen
@@ -305,7 +560,6 @@ def main() -> int:
         print(json.dumps(sequence_bench(torch, dic, dicgen, dev, args.sequence_frames,
                                         args.reference, args.live_fps, args.interp)))
         return 0
-    pair = dicgen.affine_pair_1024()
     N = len(pair.pois)
     F = torch.from_numpy(pair.ref).to(dev)
     G = torch.from_numpy(pair.defm).to(dev)
@@ -344,6 +598,15 @@ def main() -> int:
         F, G, Q, so["uv"], so["status_int"],
         out=(so["p"], so["zncc"], so["iters"], so["status"])), reps)
     iters = got["iters"][got["status"] == 0]
+    if args.minimal:
+        # the FP32 step and its stages only (for profiler runs)
+        print(json.dumps({"metric": METRIC, "value": round(N / (ms * 1e-3), 1), "unit": "POIs/s",
+                          "ms_per_step": round(ms, 4), "minimal": True,
+                          "stages_ms": {"reference_prep": round(t_prep, 4),
+                                        "deformed_box_sums": round(t_box, 4),
+                                        "search": round(t_search, 4), "icgn": round(t_icgn, 4)},
+                          "tuning": list(plan.tuning)}), flush=True)
+        return 0
     # Newton-Raphson refinement of the same search result (Sec. 2.2's other
     # sub-pixel method), both precisions
     nro = (so["p"].clone(), so["zncc"].clone(), so["iters"].clone(), so["status"].clone())
@@ -562,6 +825,9 @@ def main() -> int:
         "bicubic_lut": lut,
         "bspline": bsp,
     }
+    if not args.no_configs:
+        rec["batched"] = batched_bench(torch, dic, dicgen, dev, reps)
+        rec["differentiation"] = adjoint_bench(torch, dic, dicgen, dev, reps)
     if args.copy_probe_mb > 0:
         n = args.copy_probe_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -571,7 +837,11 @@ def main() -> int:
         torch.cuda.synchronize()
         rec["copy_probe_bytes_each_way"] = n * 4
     if not args.no_cpu_baseline:
-        base, acc = cpu_baseline(pair, got, args.cpu_sample)
+        base, acc = cpu_baseline(pair, got, args.cpu_sample, pool=pool, procs=procs,
+                                 extra=None if args.no_configs else oracle_other_workloads)
+        if pool is not None:
+            pool.close()
+            pool.join()
         rec["cpu_baseline"] = base
         rec["accuracy_vs_oracle"] = acc
     print(json.dumps(rec), flush=True)
