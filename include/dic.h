@@ -341,6 +341,29 @@ dic_status_t dic_correlate(dic_plan_t plan, const float* ref_images,
                            float* zncc_out, int32_t* iters_out,
                            int32_t* status_out, dic_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search and refinement as dic_correlate, with the same arguments, outputs
+ * and results, but the plan's workspace is a static device array of 64 MiB
+ * inside the library (one per device, held until the process ends) instead of
+ * a caller-bound one, so the plan need not be bound.  The call allocates
+ * nothing: it uploads the plan's tables into the array, prepares both images
+ * again (no cache), and runs every kernel in order on `stream` (no side
+ * stream, no graph).  The plan's own binding, caches and graphs are left as
+ * they were.  Errors: WORKSPACE_TOO_SMALL when dic_plan_workspace_size
+ * exceeds 64 MiB (use dic_plan_bind and dic_correlate), INVALID_ARGUMENT for
+ * a null required pointer, HIP when the array's address cannot be found.
+ * Every call on one device shares its array and leaves its contents behind:
+ * calls that overlap in time on one device (two streams, two threads) race
+ * and must be ordered by the caller. */
+dic_status_t dic_correlate_noalloc(dic_plan_t plan, const float* ref_images,
+                                   const float* def_images, const int32_t* poi_xy,
+                                   const int32_t* seed_uv, const double* p_init,
+                                   int32_t* uv_out, float* zncc_int_out,
+                                   int32_t* status_int_out, double* p_out,
+                                   float* zncc_out, int32_t* iters_out,
+                                   int32_t* status_out, dic_stream_t stream);
+
 /* ZNSSD criterion and its adjoint.  For each POI with warp p (float64 [N,6],
  * forward-additive), C = sum_i (fhat_i - ghat_i)^2 with fhat = (f - fbar)/df
  * and ghat = (g - gbar)/dg, g interpolated at x0 + W(p) xi_i (= 2 - 2 ZNCC).

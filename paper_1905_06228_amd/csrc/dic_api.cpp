@@ -8,6 +8,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -16,6 +17,15 @@
 #include "dic_internal.h"
 
 using namespace dic;
+
+// Device scratch of dic_correlate_noalloc: the plan's workspace for callers
+// that cannot allocate device memory.  Each device the library runs on holds
+// its own copy for the life of the process.  Host code never passes the
+// array's name to a kernel or a copy (on the host it is a stand-in symbol, not
+// a device address): it uses the per-device address that hipGetSymbolAddress
+// returns (noalloc_scratch below).
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 
 namespace {
 
@@ -180,6 +190,78 @@ dic_status_t check_plan(dic_plan_t p, bool need_bound) {
   return DIC_SUCCESS;
 }
 
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device: the address of `scratch`, null until looked up
+
+// Device address of the current device's copy of `scratch`, looked up once per
+// device with that device current.
+dic_status_t noalloc_scratch(void** out) {
+  int dev = 0, ndev = 0;
+  DIC_HIP(hipGetDevice(&dev));
+  DIC_HIP(hipGetDeviceCount(&ndev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() < ndev) g_scratch_ptr.resize(ndev, nullptr);
+  if (dev < 0 || dev >= ndev) return fail(DIC_ERR_HIP, "current device outside the device count");
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    DIC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || reinterpret_cast<uintptr_t>(ptr) % kAlign)
+      return fail(DIC_ERR_INTERNAL, "static scratch address missing or misaligned");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return DIC_SUCCESS;
+}
+
+// Points the plan's device state at the workspace `base` and uploads the pair
+// table, the POI -> pair map, the work list and the adjoint's accumulator
+// table there (asynchronous on `s`); every cached preparation is marked
+// stale.  Copies only: no allocation.
+dic_status_t attach_workspace(dic_plan_t p, void* ws, hipStream_t s) {
+  int dev = 0;
+  DIC_HIP(hipGetDevice(&dev));
+  DIC_HIP(hipDeviceGetAttribute(&p->num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  char* base = static_cast<char*>(ws);
+  DIC_HIP(hipMemcpyAsync(base + p->lay.pairs, p->dpairs.data(), sizeof(DevPair) * p->dpairs.size(),
+                         hipMemcpyHostToDevice, s));
+  if (p->N) {
+    DIC_HIP(hipMemcpyAsync(base + p->lay.poi_pair, p->poi_pair.data(), sizeof(int32_t) * p->N,
+                           hipMemcpyHostToDevice, s));
+    DIC_HIP(hipMemcpyAsync(base + p->lay.work, p->work.data(), sizeof(int32_t) * p->N,
+                           hipMemcpyHostToDevice, s));
+  }
+  DIC_HIP(hipMemcpyAsync(base + p->lay.fix_off, p->fix_off.data(), sizeof(int64_t) * p->fix_off.size(),
+                         hipMemcpyHostToDevice, s));
+  if (!p->fix_owner.empty())
+    DIC_HIP(hipMemcpyAsync(base + p->lay.fix_owner, p->fix_owner.data(),
+                           sizeof(int32_t) * p->fix_owner.size(), hipMemcpyHostToDevice, s));
+  DevState& st = p->st;
+  st.pairs = reinterpret_cast<const DevPair*>(base + p->lay.pairs);
+  st.poi_pair = reinterpret_cast<const int32_t*>(base + p->lay.poi_pair);
+  st.work = reinterpret_cast<const int32_t*>(base + p->lay.work);
+  st.counters = reinterpret_cast<int32_t*>(base + p->lay.counters);
+  st.grads = reinterpret_cast<float*>(base + p->lay.grads);
+  st.recs = reinterpret_cast<RefRec*>(base + p->lay.recs);
+  st.tmpl = reinterpret_cast<float*>(base + p->lay.tmpl);
+  st.box = reinterpret_cast<double*>(base + p->lay.box);
+  st.lut = reinterpret_cast<float*>(base + p->lay.lut);
+  st.bsp_flags = reinterpret_cast<int32_t*>(base + p->lay.bsp_flags);
+  st.N = p->N;
+  st.num_pairs = p->desc.num_pairs;
+  st.maxM = p->maxM;
+  st.maxS = p->maxS;
+  st.max_width = p->maxW;
+  st.max_height = p->maxH;
+  st.max_iters = p->desc.max_iters;
+  st.conv_tol = p->desc.conv_tol;
+  p->ws = ws;
+  p->bound = true;
+  p->ref_valid = false;
+  p->def_valid = false;
+  p->lut_valid = false;
+  return DIC_SUCCESS;
+}
+
 dic_status_t prepare(dic_plan_t p, const float* ref, const int32_t* poi, hipStream_t s,
                      bool force) {
   if (!force && (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->ref_valid && p->ref_img == ref &&
@@ -306,9 +388,13 @@ struct CorrArgs {
 // interpolation table or B-spline coefficients (when not cached) run on the
 // plan's side stream beside the reference-side preparation: the two read
 // different images and write different sections.
-dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s) {
-  const bool fork = p->fp32() && !((p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->def_valid &&
-                                   p->def_img == a.def);
+// With `allow_fork` false everything runs in order on `s` (no side stream is
+// created or used).
+dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s,
+                               bool allow_fork = true) {
+  const bool fork = allow_fork && p->fp32() &&
+                    !((p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->def_valid &&
+                      p->def_img == a.def);
   if (fork) {
     if (!p->side_stream) DIC_HIP(hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking));
     if (!p->ev_fork) DIC_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
@@ -566,48 +652,8 @@ dic_status_t dic_plan_bind(dic_plan_t p, void* ws, size_t bytes, dic_stream_t st
   if (!ws) return fail(DIC_ERR_INVALID_ARGUMENT, "null workspace");
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(DIC_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
   if (bytes < p->lay.total) return fail(DIC_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than dic_plan_workspace_size");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  int dev = 0;
-  DIC_HIP(hipGetDevice(&dev));
-  DIC_HIP(hipDeviceGetAttribute(&p->num_cu, hipDeviceAttributeMultiprocessorCount, dev));
-  char* base = static_cast<char*>(ws);
-  DIC_HIP(hipMemcpyAsync(base + p->lay.pairs, p->dpairs.data(), sizeof(DevPair) * p->dpairs.size(),
-                         hipMemcpyHostToDevice, s));
-  if (p->N) {
-    DIC_HIP(hipMemcpyAsync(base + p->lay.poi_pair, p->poi_pair.data(), sizeof(int32_t) * p->N,
-                           hipMemcpyHostToDevice, s));
-    DIC_HIP(hipMemcpyAsync(base + p->lay.work, p->work.data(), sizeof(int32_t) * p->N,
-                           hipMemcpyHostToDevice, s));
-  }
-  DIC_HIP(hipMemcpyAsync(base + p->lay.fix_off, p->fix_off.data(), sizeof(int64_t) * p->fix_off.size(),
-                         hipMemcpyHostToDevice, s));
-  if (!p->fix_owner.empty())
-    DIC_HIP(hipMemcpyAsync(base + p->lay.fix_owner, p->fix_owner.data(),
-                           sizeof(int32_t) * p->fix_owner.size(), hipMemcpyHostToDevice, s));
-  DevState& st = p->st;
-  st.pairs = reinterpret_cast<const DevPair*>(base + p->lay.pairs);
-  st.poi_pair = reinterpret_cast<const int32_t*>(base + p->lay.poi_pair);
-  st.work = reinterpret_cast<const int32_t*>(base + p->lay.work);
-  st.counters = reinterpret_cast<int32_t*>(base + p->lay.counters);
-  st.grads = reinterpret_cast<float*>(base + p->lay.grads);
-  st.recs = reinterpret_cast<RefRec*>(base + p->lay.recs);
-  st.tmpl = reinterpret_cast<float*>(base + p->lay.tmpl);
-  st.box = reinterpret_cast<double*>(base + p->lay.box);
-  st.lut = reinterpret_cast<float*>(base + p->lay.lut);
-  st.bsp_flags = reinterpret_cast<int32_t*>(base + p->lay.bsp_flags);
-  st.N = p->N;
-  st.num_pairs = p->desc.num_pairs;
-  st.maxM = p->maxM;
-  st.maxS = p->maxS;
-  st.max_width = p->maxW;
-  st.max_height = p->maxH;
-  st.max_iters = p->desc.max_iters;
-  st.conv_tol = p->desc.conv_tol;
-  p->ws = ws;
-  p->bound = true;
-  p->ref_valid = false;
-  p->def_valid = false;
-  p->lut_valid = false;
+  r = attach_workspace(p, ws, reinterpret_cast<hipStream_t>(stream));
+  if (r) return r;
   drop_graphs(p);
   if (const char* path = std::getenv("DIC_AUTOTUNE_CACHE")) {
     auto m = read_tune_cache(path);
@@ -766,6 +812,60 @@ dic_status_t dic_correlate(dic_plan_t p, const float* ref, const float* def, con
   }
   DIC_HIP(hipGraphLaunch(it->second, s));
   return DIC_SUCCESS;
+}
+
+dic_status_t dic_correlate_noalloc(dic_plan_t p, const float* ref, const float* def,
+                                   const int32_t* poi, const int32_t* seed, const double* p_init,
+                                   int32_t* uv, float* zn_int, int32_t* st_int, double* p_out,
+                                   float* zn, int32_t* iters, int32_t* status,
+                                   dic_stream_t stream) {
+  dic_status_t r = check_plan(p, false);
+  if (r) return r;
+  if (p->N == 0) return DIC_SUCCESS;
+  if (!ref || !def || !poi || !uv || !p_out || !zn || !iters || !status)
+    return fail(DIC_ERR_INVALID_ARGUMENT, "null required pointer");
+  if (p->lay.total > kNoallocScratchBytes) {
+    std::ostringstream why;
+    why << "plan needs " << p->lay.total << " bytes of device workspace; the static scratch of "
+        << "dic_correlate_noalloc holds " << kNoallocScratchBytes
+        << ": bind a caller workspace (dic_plan_bind) and use dic_correlate";
+    return fail(DIC_ERR_WORKSPACE_TOO_SMALL, why.str());
+  }
+  void* base = nullptr;
+  r = noalloc_scratch(&base);
+  if (r) return r;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // The plan runs attached to the scratch for this call only: its own binding
+  // (workspace, caches, graphs) is put back afterwards, untouched.
+  struct Saved {
+    void* ws;
+    bool bound, ref_valid, def_valid, lut_valid;
+    const void *ref_img, *ref_poi, *def_img, *lut_img;
+    DevState st;
+    int num_cu;
+  } sv{p->ws, p->bound, p->ref_valid, p->def_valid, p->lut_valid, p->ref_img, p->ref_poi,
+       p->def_img, p->lut_img, p->st, p->num_cu};
+  r = attach_workspace(p, base, s);
+  if (r == DIC_SUCCESS) {
+    char* b = static_cast<char*>(base);
+    CorrArgs a{ref, def, poi, seed, p_init, uv,
+               zn_int ? zn_int : reinterpret_cast<float*>(b + p->lay.s_zncc),
+               st_int ? st_int : reinterpret_cast<int32_t*>(b + p->lay.s_status),
+               p_out, zn, iters, status};
+    r = enqueue_correlate(p, a, s, false);
+  }
+  p->ws = sv.ws;
+  p->bound = sv.bound;
+  p->ref_valid = sv.ref_valid;
+  p->def_valid = sv.def_valid;
+  p->lut_valid = sv.lut_valid;
+  p->ref_img = sv.ref_img;
+  p->ref_poi = sv.ref_poi;
+  p->def_img = sv.def_img;
+  p->lut_img = sv.lut_img;
+  p->st = sv.st;
+  p->num_cu = sv.num_cu;
+  return r;
 }
 
 dic_status_t dic_znssd_backward(dic_plan_t p, const float* ref, const float* def,

@@ -62,7 +62,7 @@ EXPORTS = [
     "dic_plan_create", "dic_plan_workspace_size", "dic_plan_bind", "dic_plan_get_tuning",
     "dic_plan_set_tuning", "dic_plan_autotune", "dic_plan_invalidate_reference",
     "dic_prepare_reference", "dic_prepare_deformed", "dic_integer_search", "dic_pso_search",
-    "dic_icgn_refine", "dic_nr_refine", "dic_correlate",
+    "dic_icgn_refine", "dic_nr_refine", "dic_correlate", "dic_correlate_noalloc",
     "dic_znssd_backward", "dic_seed_update", "dic_poi_grid", "dic_plan_destroy",
     "dic_status_string", "dic_last_error",
 ]
@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.dic_icgn_refine.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V]
     L.dic_nr_refine.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V]
     L.dic_correlate.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V, V, V]
+    L.dic_correlate_noalloc.argtypes = [P, V, V, V, V, V, V, V, V, V, V, V, V, V]
     L.dic_znssd_backward.argtypes = [P, V, V, V, V, V, V, V, V, V]
     L.dic_seed_update.argtypes = [P, V, V, V, V, V]
     L.dic_poi_grid.argtypes = [I32, I32, I32, I32, I32, V, I64, ctypes.POINTER(I64)]
@@ -169,7 +170,9 @@ class Plan:
 
     def __init__(self, pairs: Sequence[PairSpec], precision: int = FP32_BATCHED,
                  max_iters: int = 20, conv_tol: float = 1e-3, flags: int = 0,
-                 device: Optional[torch.device] = None):
+                 device: Optional[torch.device] = None, bind: bool = True):
+        """``bind=False`` leaves the plan without a workspace (no device
+        allocation): only ``correlate_noalloc`` can run it then."""
         self.L = load_library()
         dev = torch.device(device) if device is not None else torch.device("cuda")
         if dev.type != "cuda":
@@ -189,6 +192,9 @@ class Plan:
         nbytes = ctypes.c_size_t(0)
         _check(self.L.dic_plan_workspace_size(self._h, ctypes.byref(nbytes)))
         self.workspace_bytes = int(nbytes.value)
+        self.workspace = None
+        if not bind:
+            return
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8,
                                          device=self.device)
@@ -314,9 +320,18 @@ class Plan:
 
     def correlate(self, ref, defm, pois, seed=None, p_init=None, out: Optional[dict] = None) -> dict:
         """Search then refine (graph-replayed when the plan has FLAG_USE_GRAPH)."""
+        return self._correlate(self.L.dic_correlate, ref, defm, pois, seed, p_init, out)
+
+    def correlate_noalloc(self, ref, defm, pois, seed=None, p_init=None,
+                          out: Optional[dict] = None) -> dict:
+        """dic_correlate_noalloc: the same call run in the library's static
+        device scratch (plans up to 64 MiB of workspace; no binding needed)."""
+        return self._correlate(self.L.dic_correlate_noalloc, ref, defm, pois, seed, p_init, out)
+
+    def _correlate(self, fn, ref, defm, pois, seed, p_init, out) -> dict:
         d = self.device
         o = out if out is not None else self.new_outputs()
-        _check(self.L.dic_correlate(
+        _check(fn(
             self._h, _ptr(ref, torch.float32, d, "ref"), _ptr(defm, torch.float32, d, "def"),
             _ptr(pois, torch.int32, d, "pois"), _ptr(seed, torch.int32, d, "seed"),
             _ptr(p_init, torch.float64, d, "p_init"), _ptr(o["uv"], torch.int32, d, "uv"),

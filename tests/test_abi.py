@@ -188,3 +188,21 @@ def test_empty_plan_is_valid(L):
 def test_library_grid_matches_generator(W, H, M, S, step):
     lib = dic.poi_grid(W, H, M, S, step).numpy()
     np.testing.assert_array_equal(lib, dicgen.poi_grid(W, H, M, S, step))
+
+
+def test_noalloc_rejects_plans_beyond_its_scratch(L):
+    """dic_correlate_noalloc checks the plan's workspace against its 64 MiB
+    static scratch before touching the device."""
+    rc, h = make(L, [(4096, 3000, 14, 24, 0, 0, 0, 16)])
+    assert rc == 0
+    nb = ctypes.c_size_t(0)
+    L.dic_plan_workspace_size(h, ctypes.byref(nb))
+    assert nb.value > 64 << 20
+    fake = ctypes.c_void_p(256)
+    args = [h, fake, fake, fake, None, None, fake, None, None, fake, fake, fake, fake, None]
+    assert L.dic_correlate_noalloc(*args) == -2
+    assert b"64" in L.dic_last_error() or b"67108864" in L.dic_last_error()
+    # null required pointers are rejected first
+    args[1] = None
+    assert L.dic_correlate_noalloc(*args) == -1
+    L.dic_plan_destroy(h)
