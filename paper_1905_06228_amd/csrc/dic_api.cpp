@@ -80,6 +80,7 @@ struct dic_plan_s {
   std::vector<DevPair> dpairs;
   std::vector<int32_t> poi_pair, work;
   std::vector<std::pair<int, int64_t>> m_runs;  // (M, length) runs of the work list
+  std::vector<RefineGroup> rgroups;  // runs of the work list that share a refinement kernel
   std::vector<int64_t> fix_off;
   // deterministic adjoint: the pair that owns each distinct deformed image
   // (pairs on the same image share its fixed-point accumulator, flushed once)
@@ -354,12 +355,13 @@ dic_status_t enqueue_refine(dic_plan_t p, const float* ref, const float* def, co
       if (r) return r;
     }
     DIC_HIP(launch_reset_counters(p->st, s));
+    const int ng = (int)p->rgroups.size();
     if (nr)
-      DIC_HIP(launch_nr_f32(p->st, p->tuning, def, poi, uv, status_in, p_init, p_out, zn, iters,
-                            status, p->num_cu, s, p->interp()));
+      DIC_HIP(launch_nr_f32(p->st, p->tuning, p->rgroups.data(), ng, def, poi, uv, status_in,
+                            p_init, p_out, zn, iters, status, p->num_cu, s, p->interp()));
     else
-      DIC_HIP(launch_icgn_f32(p->st, p->tuning, ref, def, poi, uv, status_in, p_init, p_out, zn,
-                              iters, status, p->num_cu, s, p->interp()));
+      DIC_HIP(launch_icgn_f32(p->st, p->tuning, p->rgroups.data(), ng, def, poi, uv, status_in,
+                              p_init, p_out, zn, iters, status, p->num_cu, s, p->interp()));
   } else if (nr) {
     DIC_HIP(launch_nr_f64(p->st, p->dpairs.data(), ref, def, poi, uv, status_in, p_init, p_out,
                           zn, iters, status, s));
@@ -596,6 +598,15 @@ dic_status_t dic_plan_create(const dic_plan_desc_t* d, dic_plan_t* out) {
     const int m = p->pairs[p->poi_pair[p->work[i]]].subset_radius;
     if (p->m_runs.empty() || p->m_runs.back().first != m) p->m_runs.emplace_back(m, 0);
     ++p->m_runs.back().second;
+  }
+  {
+    int64_t at = 0;
+    for (auto& run : p->m_runs) {
+      if (p->rgroups.empty() || refine_class(p->rgroups.back().maxM) != refine_class(run.first))
+        p->rgroups.push_back({at, 0, run.first});
+      p->rgroups.back().count += run.second;
+      at += run.second;
+    }
   }
   // the matrix-core search where the window allows it, else the vector-ALU form
   if (f32 && search_fits(p->maxM, p->maxS, kMfmaBlock)) p->tuning.search_block = kMfmaBlock;

@@ -84,7 +84,8 @@ struct DevState {
   double conv_tol;
 };
 
-// Persistent-launch work counters: one per search group, then IC-GN.
+// Persistent-launch work counters: one per search group, then one per
+// refinement group.
 enum Counter { kCtrSearch = 0, kMaxSearchGroups = 16, kCtrIcgn = 16, kNumCounters = 32 };
 
 // A run of the work list whose subsets share the search kernel's template
@@ -93,6 +94,31 @@ struct SearchGroup {
   int np;
   int64_t begin, count;
 };
+
+// Refinement kernels (IC-GN, Newton-Raphson) come in sizes of 4, 8, 12, 16,
+// 20 and 28 sample slots per lane (64 samples per slot); subsets of 29 and 31
+// columns (M = 14, 15) use the 16-slot kernel with two subset rows per slot.
+// A plan refines its work list (ordered by decreasing M) in runs of POIs that
+// share a kernel, one persistent launch each, so a small subset never runs in
+// a kernel sized (registers, LDS patch) for the plan's largest one.
+__host__ __device__ constexpr int refine_slots(int M) {
+  return ((2 * M + 1) * (2 * M + 1) + 63) / 64 <= 4    ? 4
+         : ((2 * M + 1) * (2 * M + 1) + 63) / 64 <= 8  ? 8
+         : ((2 * M + 1) * (2 * M + 1) + 63) / 64 <= 12 ? 12
+         : ((2 * M + 1) * (2 * M + 1) + 63) / 64 <= 16 ? 16
+         : ((2 * M + 1) * (2 * M + 1) + 63) / 64 <= 20 ? 20
+                                                       : 28;
+}
+__host__ __device__ constexpr bool refine_two_rows(int M) { return M == 14 || M == 15; }
+// the refinement kernel a radius runs in (slots and layout)
+__host__ __device__ constexpr int refine_class(int M) {
+  return 2 * refine_slots(M) + (refine_two_rows(M) ? 1 : 0);
+}
+struct RefineGroup {
+  int64_t begin, count;  // a run of the work list
+  int maxM;              // its largest subset radius (the first in the run)
+};
+constexpr int kMaxRefineGroups = 16;
 
 // Kernel launchers (defined in the .hip files).  All asynchronous on `s`.
 hipError_t launch_reset_counters(const DevState& st, hipStream_t s);
@@ -135,13 +161,15 @@ __host__ __device__ __forceinline__ int search_np(int M, int block) {
 hipError_t launch_search_f64(const DevState& st, const DevPair* host_pairs, const float* ref,
                              const float* def, const int32_t* poi, const int32_t* seed,
                              int32_t* uv, float* zncc, int32_t* status, hipStream_t s);
-hipError_t launch_icgn_f32(const DevState& st, const dic_tuning_t& tu, const float* ref,
-                           const float* def, const int32_t* poi, const int32_t* uv_init,
+hipError_t launch_icgn_f32(const DevState& st, const dic_tuning_t& tu,
+                           const RefineGroup* groups, int ngroups, const float* def,
+                           const int32_t* poi, const int32_t* uv_init,
                            const int32_t* status_in, const double* p_init, double* p_out,
                            float* zncc, int32_t* iters, int32_t* status, int num_cu,
                            hipStream_t s, int interp);
-hipError_t launch_nr_f32(const DevState& st, const dic_tuning_t& tu, const float* def,
-                         const int32_t* poi, const int32_t* uv_init, const int32_t* status_in,
+hipError_t launch_nr_f32(const DevState& st, const dic_tuning_t& tu, const RefineGroup* groups,
+                         int ngroups, const float* def, const int32_t* poi,
+                         const int32_t* uv_init, const int32_t* status_in,
                          const double* p_init, double* p_out, float* zncc, int32_t* iters,
                          int32_t* status, int num_cu, hipStream_t s, int interp);
 hipError_t launch_nr_f64(const DevState& st, const DevPair* host_pairs, const float* ref,

@@ -47,28 +47,81 @@ __device__ __forceinline__ void iter_pass(const Smp& smp, int n, const Warp32& w
   }
 }
 
+// The pass of iter_pass in the two-rows layout (same eight sums).
+template <int MAXS, class Smp>
+__device__ __forceinline__ void iter_pass_r2(const Smp& smp, int M, const R2Lane& L,
+                                             const Warp32& w, const float* fxs, const float* fys,
+                                             float fxp, float fyp, float* K) {
+  const int Mu = __builtin_amdgcn_readfirstlane(M);
+  const float bx = fmaf(w.ax, L.dx, fmaf(w.uy, L.hm, w.uf));
+  const float by = fmaf(w.vx, L.dx, fmaf(w.ay, L.hm, w.vf));
+  float k0 = 0.f, k1 = 0.f, k2 = 0.f, k4 = 0.f, k5 = 0.f, k7 = 0.f;
+#pragma unroll
+  for (int k = 0; k < MAXS - 1; ++k) {
+    if (k >= Mu) continue;
+    const float dk = (float)(2 * k);
+    const float gs = sample_value(smp, fmaf(w.uy, dk, bx), fmaf(w.ay, dk, by));
+    const float fg = fxs[k] * gs, hg = fys[k] * gs;
+    k0 += gs;
+    k1 = fmaf(gs, gs, k1);
+    k2 += fg;
+    k4 = fmaf(fg, dk, k4);
+    k5 += hg;
+    k7 = fmaf(hg, dk, k7);
+  }
+  {
+    // the last row (offset M), read by both half-waves at the lower one's
+    // positions, counted once
+    const float dm = (float)Mu;
+    const float x = fmaf(w.ax, L.dx, fmaf(w.uy, dm, w.uf));
+    const float y = fmaf(w.vx, L.dx, fmaf(w.ay, dm, w.vf));
+    const float v = sample_value(smp, x, y);
+    const float gs = L.upper ? 0.f : v;
+    const float fg = fxp * gs, hg = fyp * gs;
+    const float d2 = 2.f * dm;
+    k0 += gs;
+    k1 = fmaf(gs, gs, k1);
+    k2 += fg;
+    k4 = fmaf(fg, d2, k4);
+    k5 += hg;
+    k7 = fmaf(hg, d2, k7);
+  }
+  K[0] = L.colok ? k0 : 0.f;
+  K[1] = L.colok ? k1 : 0.f;
+  K[2] = k2;
+  K[3] = L.dx * k2;
+  K[4] = fmaf(L.hm, k2, k4);
+  K[5] = k5;
+  K[6] = L.dx * k5;
+  K[7] = fmaf(L.hm, k5, k7);
+}
+
 }  // namespace
 
-template <int MAXS, int IM>
+// Three waves per SIMD (two for the largest subsets); the two-rows kernels
+// fit four, which measured slower (0.54 against 0.52 ms on the 1024^2
+// benchmark pair).
+template <int MAXS, int IM, bool R2>
 __global__ void __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
-    DevState st, int slack, const float* __restrict__ def, const int32_t* __restrict__ poi,
+    DevState st, const int32_t* __restrict__ work, int64_t count, int ctr, int gmaxM, int slack,
+    const float* __restrict__ def, const int32_t* __restrict__ poi,
     const int32_t* __restrict__ uv_init, const int32_t* __restrict__ status_in,
     const double* __restrict__ p_init, double* __restrict__ p_out, float* __restrict__ zncc_out,
     int32_t* __restrict__ iters_out, int32_t* __restrict__ status_out) {
-  constexpr int PP = refine_patch_pitch(MAXS);
+  constexpr int PP = R2 ? kR2Pitch : refine_patch_pitch(MAXS);
   constexpr int NT = interp_taps(IM);
   extern __shared__ float lds[];
   const int wid = threadIdx.x / kWave;
-  const int pside = icgn_patch_side(st.maxM, slack);
+  const int pside = icgn_patch_side(gmaxM, slack);
   LdsPatch<PP> patch;
   patch.buf = lds + (size_t)wid * pside * PP;
   patch.side = pside;
 
   for (;;) {
-    const int item = wave_next_item(&st.counters[kCtrIcgn]);
-    if (item >= st.N) break;
-    const int g = uniform(st.work[item]);
+    const int item = wave_next_item(&st.counters[ctr]);
+    if (item >= count) break;
+    const int g = uniform(work[item]);
     const DevPair P = st.pairs[uniform(st.poi_pair[g])];
     const RefRec* R = st.recs + g;
     const int x0 = uniform(poi[2 * g]), y0 = uniform(poi[2 * g + 1]);
@@ -92,9 +145,15 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
       const int64_t corner = (int64_t)(y0 - M) * W + (x0 - M);
       const float* gx = st.grads + P.grad_off + corner;
       const float* gy = gx + (int64_t)W * H;
-      float fxs[MAXS], fys[MAXS];
-      half2v dxy[MAXS];
-      load_slots<MAXS>(M, n, gx, gy, W, dxy, fxs, fys);
+      float fxs[MAXS], fys[MAXS], fxp = 0.f, fyp = 0.f;
+      half2v dxy[R2 ? 1 : MAXS];
+      R2Lane L2{};
+      if constexpr (R2) {
+        L2 = r2_lane(M);
+        load_slots_r2<MAXS>(M, L2, gx, gy, W, fxs, fys, fxp, fyp);
+      } else {
+        load_slots<MAXS>(M, n, gx, gy, W, dxy, fxs, fys);
+      }
       const float c0 = deformed_centre(gimg, W, H, p, x0, y0);
       const double df = R->df;
       const double nn = (double)n;
@@ -110,13 +169,18 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
           break;
         }
         float K[8];
+        const auto pass = [&](const auto& smp) {
+          if constexpr (R2)
+            iter_pass_r2<MAXS>(smp, M, L2, w, fxs, fys, fxp, fyp, K);
+          else
+            iter_pass<MAXS>(smp, n, w, fxs, fys, dxy, K);
+        };
         if constexpr (IM == kInterpBicubicLut)
-          iter_pass<MAXS>(LutSampler{glut, W, H, w.bx, w.by, c0}, n, w, fxs, fys, dxy, K);
+          pass(LutSampler{glut, W, H, w.bx, w.by, c0});
         else if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
-          iter_pass<MAXS>(patch.template sampler<IM>(w.bx, w.by), n, w, fxs, fys, dxy, K);
+          pass(patch.template sampler<IM>(w.bx, w.by));
         else
-          iter_pass<MAXS>(ImageSampler<IM>{gimg, W, H, w.bx, w.by, c0}, n, w, fxs, fys,
-                          dxy, K);
+          pass(ImageSampler<IM>{gimg, W, H, w.bx, w.by, c0});
         double S[8];
         wave_sums_f32<8>(K, S);
         if (!isfinite(S[0]) || !isfinite(S[1])) {
@@ -155,13 +219,18 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
             return tm[__mul24((int)dy, tp) + (int)dx];
           };
           float K[3];
+          const auto fpass = [&](const auto& smp) {
+            if constexpr (R2)
+              final_pass_r2<MAXS>(smp, M, L2, w, tval, K);
+            else
+              final_pass<MAXS>(smp, n, w, dxy, tval, K);
+          };
           if constexpr (IM == kInterpBicubicLut)
-            final_pass<MAXS>(LutSampler{glut, W, H, w.bx, w.by, c0}, n, w, dxy, tval, K);
+            fpass(LutSampler{glut, W, H, w.bx, w.by, c0});
           else if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
-            final_pass<MAXS>(patch.template sampler<IM>(w.bx, w.by), n, w, dxy, tval, K);
+            fpass(patch.template sampler<IM>(w.bx, w.by));
           else
-            final_pass<MAXS>(ImageSampler<IM>{gimg, W, H, w.bx, w.by, c0}, n, w, dxy,
-                             tval, K);
+            fpass(ImageSampler<IM>{gimg, W, H, w.bx, w.by, c0});
           double S[3];
           wave_sums_f32<3>(K, S);
           if (!isfinite(S[0]) || !isfinite(S[1])) {
@@ -188,68 +257,89 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
   }
 }
 
-template <int MAXS, int IM>
-static hipError_t launch_icgn_f32_t(const DevState& st, const dic_tuning_t& tu, const float* def,
+template <int MAXS, int IM, bool R2 = false>
+static hipError_t launch_icgn_f32_t(const DevState& st, const dic_tuning_t& tu,
+                                    const RefineGroup& gr, int ctr, const float* def,
                                     const int32_t* poi, const int32_t* uv_init,
                                     const int32_t* status_in, const double* p_init, double* p_out,
                                     float* zncc, int32_t* iters, int32_t* status, int num_cu,
                                     hipStream_t s) {
   const int threads = tu.icgn_waves * kWave;
+  const int slack = R2 ? min(tu.icgn_slack, kR2MaxSlack) : tu.icgn_slack;
   // the table form reads no LDS patch
   const size_t lds = IM == kInterpBicubicLut
                          ? 0
-                         : refine_lds_bytes(refine_patch_pitch(MAXS),
-                                            icgn_patch_side(st.maxM, tu.icgn_slack), tu.icgn_waves);
+                         : refine_lds_bytes(R2 ? kR2Pitch : refine_patch_pitch(MAXS),
+                                            icgn_patch_side(gr.maxM, slack), tu.icgn_waves);
+  const void* fn = reinterpret_cast<const void*>(&icgn_f32_kernel<MAXS, IM, R2>);
   if (lds > 65536) {
-    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&icgn_f32_kernel<MAXS, IM>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ea != hipSuccess) return ea;
   }
   int occ = 0;
-  hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, icgn_f32_kernel<MAXS, IM>, threads, lds);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, icgn_f32_kernel<MAXS, IM, R2>,
+                                                              threads, lds);
   if (e != hipSuccess) return e;
   if (occ < 1) return hipErrorInvalidConfiguration;
   int64_t blocks = (int64_t)occ * num_cu;
-  const int64_t need = (st.N + tu.icgn_waves - 1) / tu.icgn_waves;
+  const int64_t need = (gr.count + tu.icgn_waves - 1) / tu.icgn_waves;
   if (blocks > need) blocks = need;
-  hipLaunchKernelGGL((icgn_f32_kernel<MAXS, IM>), dim3((unsigned)blocks), dim3(threads), lds, s, st,
-                     tu.icgn_slack, def, poi, uv_init, status_in, p_init, p_out, zncc, iters,
-                     status);
+  hipLaunchKernelGGL((icgn_f32_kernel<MAXS, IM, R2>), dim3((unsigned)blocks), dim3(threads), lds,
+                     s, st, st.work + gr.begin, gr.count, ctr, gr.maxM, slack, def, poi, uv_init,
+                     status_in, p_init, p_out, zncc, iters, status);
   return hipGetLastError();
 }
 
-hipError_t launch_icgn_f32(const DevState& st, const dic_tuning_t& tu, const float* /*ref*/,
-                           const float* def, const int32_t* poi, const int32_t* uv_init,
-                           const int32_t* status_in, const double* p_init, double* p_out,
-                           float* zncc, int32_t* iters, int32_t* status, int num_cu,
-                           hipStream_t s, int interp) {
-  if (st.N == 0) return hipSuccess;
-  const int n = (2 * st.maxM + 1) * (2 * st.maxM + 1);
-  const int need = (n + kWave - 1) / kWave;
-#define DIC_ICGN_CASE(S_)                                                                       \
-  if (need <= S_) {                                                                             \
-    if (interp == kInterpBilinear)                                                              \
-      return launch_icgn_f32_t<S_, kInterpBilinear>(st, tu, def, poi, uv_init, status_in, p_init,  \
-                                                    p_out, zncc, iters, status, num_cu, s);      \
-    if (interp == kInterpBSpline)                                                               \
-      return launch_icgn_f32_t<S_, kInterpBSpline>(st, tu, def, poi, uv_init, status_in,        \
-                                                    p_init, p_out, zncc, iters, status, num_cu, s);\
-    if (interp == kInterpBicubicLut)                                                            \
-      return launch_icgn_f32_t<S_, kInterpBicubicLut>(st, tu, def, poi, uv_init, status_in,     \
-                                                      p_init, p_out, zncc, iters, status, num_cu, \
-                                                      s);                                       \
-    return launch_icgn_f32_t<S_, kInterpBicubic>(st, tu, def, poi, uv_init, status_in, p_init,   \
-                                                 p_out, zncc, iters, status, num_cu, s);         \
+// One group: the kernel its subset size runs in.
+template <int IM>
+static hipError_t launch_icgn_f32_group(const DevState& st, const dic_tuning_t& tu,
+                                     const RefineGroup& gr, int ctr, const float* def,
+                                     const int32_t* poi, const int32_t* uv_init,
+                                     const int32_t* status_in, const double* p_init,
+                                     double* p_out, float* zncc, int32_t* iters,
+                                     int32_t* status, int num_cu, hipStream_t s) {
+#define DIC_REFINE_ARGS st, tu, gr, ctr, def, poi, uv_init, status_in, p_init, p_out, zncc, iters, \
+                        status, num_cu, s
+  if (refine_two_rows(gr.maxM)) return launch_icgn_f32_t<16, IM, true>(DIC_REFINE_ARGS);
+  switch (refine_slots(gr.maxM)) {
+    case 4: return launch_icgn_f32_t<4, IM>(DIC_REFINE_ARGS);
+    case 8: return launch_icgn_f32_t<8, IM>(DIC_REFINE_ARGS);
+    case 12: return launch_icgn_f32_t<12, IM>(DIC_REFINE_ARGS);
+    case 16: return launch_icgn_f32_t<16, IM>(DIC_REFINE_ARGS);
+    case 20: return launch_icgn_f32_t<20, IM>(DIC_REFINE_ARGS);
+    case 28: return launch_icgn_f32_t<28, IM>(DIC_REFINE_ARGS);
+    default: return hipErrorInvalidValue;
   }
-  DIC_ICGN_CASE(4)
-  DIC_ICGN_CASE(8)
-  DIC_ICGN_CASE(12)
-  DIC_ICGN_CASE(16)
-  DIC_ICGN_CASE(20)
-  DIC_ICGN_CASE(28)
-#undef DIC_ICGN_CASE
-  return hipErrorInvalidValue;
+#undef DIC_REFINE_ARGS
+}
+
+hipError_t launch_icgn_f32(const DevState& st, const dic_tuning_t& tu, const RefineGroup* groups,
+                           int ngroups, const float* def, const int32_t* poi,
+                           const int32_t* uv_init, const int32_t* status_in,
+                           const double* p_init, double* p_out, float* zncc, int32_t* iters,
+                           int32_t* status, int num_cu, hipStream_t s, int interp) {
+  if (ngroups > kMaxRefineGroups) return hipErrorInvalidValue;
+  for (int k = 0; k < ngroups; ++k) {
+    const RefineGroup& gr = groups[k];
+    if (gr.count == 0) continue;
+    const int ctr = kCtrIcgn + k;
+    hipError_t e;
+    if (interp == kInterpBilinear)
+      e = launch_icgn_f32_group<kInterpBilinear>(st, tu, gr, ctr, def, poi, uv_init, status_in,
+                                               p_init, p_out, zncc, iters, status, num_cu, s);
+    else if (interp == kInterpBSpline)
+      e = launch_icgn_f32_group<kInterpBSpline>(st, tu, gr, ctr, def, poi, uv_init, status_in,
+                                              p_init, p_out, zncc, iters, status, num_cu, s);
+    else if (interp == kInterpBicubicLut)
+      e = launch_icgn_f32_group<kInterpBicubicLut>(st, tu, gr, ctr, def, poi, uv_init,
+                                                 status_in, p_init, p_out, zncc, iters, status,
+                                                 num_cu, s);
+    else
+      e = launch_icgn_f32_group<kInterpBicubic>(st, tu, gr, ctr, def, poi, uv_init, status_in,
+                                              p_init, p_out, zncc, iters, status, num_cu, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

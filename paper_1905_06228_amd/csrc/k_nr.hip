@@ -67,27 +67,138 @@ __device__ __forceinline__ void nr_pass(const Smp& smp, int n, const Warp32& w, 
   }
 }
 
+// nr_pass in the two-rows layout of IC-GN (subsets of 29 and 31 columns):
+// with the lane's column offset dx fixed and the row offset dy = 2k + (l /
+// 32 - M), every sum over J = (gx, gx dx, gx dy, gy, gy dx, gy dy) is a
+// lane constant times one of 24 sums over gx, gy and their products weighted
+// by 1, 2k and (2k)^2; they are expanded into the 42 sums of nr_pass per
+// lane before the cross-lane reduction.  `tv` holds the lane's template
+// values in the same layout (slot M: the last row, zero in the upper half).
+template <int MAXS, class Smp>
+__device__ __forceinline__ void nr_pass_r2(const Smp& smp, int M, const R2Lane& L, const Warp32& w,
+                                           const float* tv, float tvp, NrSums& A) {
+  const int Mu = __builtin_amdgcn_readfirstlane(M);
+  const float bx = fmaf(w.ax, L.dx, fmaf(w.uy, L.hm, w.uf));
+  const float by = fmaf(w.vx, L.dx, fmaf(w.ay, L.hm, w.vf));
+  float sg = 0.f, sgg = 0.f, sfg = 0.f;
+  float ax0 = 0.f, ax1 = 0.f, ay0 = 0.f, ay1 = 0.f;       // gx, gy (x 1, 2k)
+  float fx0 = 0.f, fx1 = 0.f, fy0 = 0.f, fy1 = 0.f;       // gx t, gy t
+  float gx0 = 0.f, gx1 = 0.f, gy0 = 0.f, gy1 = 0.f;       // gx g, gy g
+  float xx0 = 0.f, xx1 = 0.f, xx2 = 0.f;                  // gx^2 (x 1, 2k, 4k^2)
+  float xy0 = 0.f, xy1 = 0.f, xy2 = 0.f;                  // gx gy
+  float yy0 = 0.f, yy1 = 0.f, yy2 = 0.f;                  // gy^2
+  const auto add = [&](float gs, float gx, float gy, float t, float dk) {
+    const float dk2 = dk * dk;
+    sg += gs;
+    sgg = fmaf(gs, gs, sgg);
+    sfg = fmaf(t, gs, sfg);
+    ax0 += gx;
+    ax1 = fmaf(gx, dk, ax1);
+    ay0 += gy;
+    ay1 = fmaf(gy, dk, ay1);
+    const float xt = gx * t, yt = gy * t, xg = gx * gs, yg = gy * gs;
+    fx0 += xt;
+    fx1 = fmaf(xt, dk, fx1);
+    fy0 += yt;
+    fy1 = fmaf(yt, dk, fy1);
+    gx0 += xg;
+    gx1 = fmaf(xg, dk, gx1);
+    gy0 += yg;
+    gy1 = fmaf(yg, dk, gy1);
+    const float qx = gx * gx, qxy = gx * gy, qy = gy * gy;
+    xx0 += qx;
+    xx1 = fmaf(qx, dk, xx1);
+    xx2 = fmaf(qx, dk2, xx2);
+    xy0 += qxy;
+    xy1 = fmaf(qxy, dk, xy1);
+    xy2 = fmaf(qxy, dk2, xy2);
+    yy0 += qy;
+    yy1 = fmaf(qy, dk, yy1);
+    yy2 = fmaf(qy, dk2, yy2);
+  };
+#pragma unroll
+  for (int k = 0; k < MAXS - 1; ++k) {
+    if (k >= Mu) continue;
+    const float dk = (float)(2 * k);
+    float v, gx, gy;
+    sample_value_grad(smp, fmaf(w.uy, dk, bx), fmaf(w.ay, dk, by), v, gx, gy);
+    add(v, gx, gy, tv[k], dk);
+  }
+  {
+    // the last row, read by both half-waves at the lower one's positions and
+    // counted once (the upper half's value and gradient are zeroed)
+    const float dm = (float)Mu;
+    float v, gx, gy;
+    sample_value_grad(smp, fmaf(w.ax, L.dx, fmaf(w.uy, dm, w.uf)),
+                      fmaf(w.vx, L.dx, fmaf(w.ay, dm, w.vf)), v, gx, gy);
+    const bool on = !L.upper;
+    add(on ? v : 0.f, on ? gx : 0.f, on ? gy : 0.f, tvp, 2.f * dm);
+  }
+  // columns outside the subset: their value sums are cleared (their
+  // template values are zero, and gradients below are zeroed with them)
+  const float cm = L.colok ? 1.f : 0.f;
+  sg *= cm;
+  sgg *= cm;
+  ax0 *= cm; ax1 *= cm; ay0 *= cm; ay1 *= cm;
+  gx0 *= cm; gx1 *= cm; gy0 *= cm; gy1 *= cm;
+  xx0 *= cm; xx1 *= cm; xx2 *= cm;
+  xy0 *= cm; xy1 *= cm; xy2 *= cm;
+  yy0 *= cm; yy1 *= cm; yy2 *= cm;
+  // sums weighted by dy = 2k + hm and dy^2
+  const float h = L.hm, h2 = L.hm * L.hm, d = L.dx, d2 = L.dx * L.dx;
+  const float AX1 = fmaf(h, ax0, ax1), AY1 = fmaf(h, ay0, ay1);
+  const float FX1 = fmaf(h, fx0, fx1), FY1 = fmaf(h, fy0, fy1);
+  const float GX1 = fmaf(h, gx0, gx1), GY1 = fmaf(h, gy0, gy1);
+  const float X1 = fmaf(h, xx0, xx1), X2 = fmaf(h2, xx0, fmaf(2.f * h, xx1, xx2));
+  const float XY1 = fmaf(h, xy0, xy1), XY2 = fmaf(h2, xy0, fmaf(2.f * h, xy1, xy2));
+  const float Y1 = fmaf(h, yy0, yy1), Y2 = fmaf(h2, yy0, fmaf(2.f * h, yy1, yy2));
+  A.g = sg;
+  A.gg = sgg;
+  A.fg = sfg;
+  const float J[6] = {ax0, d * ax0, AX1, ay0, d * ay0, AY1};
+  const float Jf[6] = {fx0, d * fx0, FX1, fy0, d * fy0, FY1};
+  const float Jg[6] = {gx0, d * gx0, GX1, gy0, d * gy0, GY1};
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    A.J[a] = J[a];
+    A.Jf[a] = Jf[a];
+    A.Jg[a] = Jg[a];
+  }
+  // J J^T, packed rows (a >= b)
+  const float JJ[21] = {xx0,                                          // (0,0)
+                        d * xx0, d2 * xx0,                            // (1,0) (1,1)
+                        X1, d * X1, X2,                               // (2,0..2)
+                        xy0, d * xy0, XY1, yy0,                       // (3,0..3)
+                        d * xy0, d2 * xy0, d * XY1, d * yy0, d2 * yy0,  // (4,0..4)
+                        XY1, d * XY1, XY2, Y1, d * Y1, Y2};           // (5,0..5)
+#pragma unroll
+  for (int a = 0; a < 21; ++a) A.JJ[a] = JJ[a];
+}
+
 }  // namespace
 
-template <int MAXS, int IM>
-__global__ void __launch_bounds__(512) nr_f32_kernel(
-    DevState st, int slack, const float* __restrict__ def, const int32_t* __restrict__ poi,
+// The two-rows kernels run at three waves per SIMD.
+template <int MAXS, int IM, bool R2>
+__global__ void __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(R2 ? 3 : 1))) nr_f32_kernel(
+    DevState st, const int32_t* __restrict__ work, int64_t count, int ctr, int gmaxM, int slack,
+    const float* __restrict__ def, const int32_t* __restrict__ poi,
     const int32_t* __restrict__ uv_init, const int32_t* __restrict__ status_in,
     const double* __restrict__ p_init, double* __restrict__ p_out, float* __restrict__ zncc_out,
     int32_t* __restrict__ iters_out, int32_t* __restrict__ status_out) {
-  constexpr int PP = refine_patch_pitch(MAXS);
+  constexpr int PP = R2 ? kR2Pitch : refine_patch_pitch(MAXS);
   constexpr int NT = interp_taps(IM);
   extern __shared__ float lds[];
   const int wid = threadIdx.x / kWave;
-  const int pside = icgn_patch_side(st.maxM, slack);
+  const int pside = icgn_patch_side(gmaxM, slack);
   LdsPatch<PP> patch;
   patch.buf = lds + (size_t)wid * pside * PP;
   patch.side = pside;
 
   for (;;) {
-    const int item = wave_next_item(&st.counters[kCtrIcgn]);
-    if (item >= st.N) break;
-    const int g = uniform(st.work[item]);
+    const int item = wave_next_item(&st.counters[ctr]);
+    if (item >= count) break;
+    const int g = uniform(work[item]);
     const DevPair P = st.pairs[uniform(st.poi_pair[g])];
     const RefRec* R = st.recs + g;
     const int x0 = uniform(poi[2 * g]), y0 = uniform(poi[2 * g + 1]);
@@ -112,9 +223,15 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
       const float4* glut = reinterpret_cast<const float4*>(st.lut) + P.lut_off;
       const int tp = P.tmpl_pitch;
       const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * tp;
-      float tv[MAXS];
-      half2v dxy[MAXS];
-      load_slots<MAXS>(M, n, tm, nullptr, tp, dxy, tv, nullptr);
+      float tv[MAXS], tvp = 0.f, unused = 0.f;
+      half2v dxy[R2 ? 1 : MAXS];
+      R2Lane L2{};
+      if constexpr (R2) {
+        L2 = r2_lane(M);
+        load_slots_r2<MAXS>(M, L2, tm, nullptr, tp, tv, nullptr, tvp, unused);
+      } else {
+        load_slots<MAXS>(M, n, tm, nullptr, tp, dxy, tv, nullptr);
+      }
       const float c0 = deformed_centre(gimg, W, H, p, x0, y0);
       const double df = R->df, tsum = (double)R->tsum;
       const double nn = (double)n;
@@ -130,12 +247,18 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
           break;
         }
         NrSums A;
+        const auto pass = [&](const auto& smp) {
+          if constexpr (R2)
+            nr_pass_r2<MAXS>(smp, M, L2, w, tv, tvp, A);
+          else
+            nr_pass<MAXS>(smp, n, w, tv, dxy, A);
+        };
         if constexpr (IM == kInterpBicubicLut)
-          nr_pass<MAXS>(LutSampler{glut, W, H, w.bx, w.by, c0}, n, w, tv, dxy, A);
+          pass(LutSampler{glut, W, H, w.bx, w.by, c0});
         else if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
-          nr_pass<MAXS>(patch.template sampler<IM>(w.bx, w.by), n, w, tv, dxy, A);
+          pass(patch.template sampler<IM>(w.bx, w.by));
         else
-          nr_pass<MAXS>(ImageSampler<IM>{gimg, W, H, w.bx, w.by, c0}, n, w, tv, dxy, A);
+          pass(ImageSampler<IM>{gimg, W, H, w.bx, w.by, c0});
         // all 42 sums in one reduction, in struct order
         static_assert(sizeof(NrSums) == 42 * sizeof(float), "NrSums layout");
         double S[42];
@@ -191,15 +314,26 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
         if (xl < 0 || xh > W - 1 || yl < 0 || yh > H - 1) {
           status = DIC_POI_OUT_OF_BOUNDS;
         } else {
-          const auto tval = [&](int k, float, float) { return tv[k]; };
           float K[3];
+          const auto fpass = [&](const auto& smp) {
+            if constexpr (R2) {
+              // the template value at offset (dx, dy) from the subset centre
+              const float* tmc = tm + (int64_t)M * tp + M;
+              const auto tval = [&](int, float dx, float dy) {
+                return tmc[__mul24((int)dy, tp) + (int)dx];
+              };
+              final_pass_r2<MAXS>(smp, M, L2, w, tval, K);
+            } else {
+              const auto tval = [&](int k, float, float) { return tv[k]; };
+              final_pass<MAXS>(smp, n, w, dxy, tval, K);
+            }
+          };
           if constexpr (IM == kInterpBicubicLut)
-            final_pass<MAXS>(LutSampler{glut, W, H, w.bx, w.by, c0}, n, w, dxy, tval, K);
+            fpass(LutSampler{glut, W, H, w.bx, w.by, c0});
           else if (patch.ensure(gimg, W, H, xl, xh, yl, yh, c0))
-            final_pass<MAXS>(patch.template sampler<IM>(w.bx, w.by), n, w, dxy, tval, K);
+            fpass(patch.template sampler<IM>(w.bx, w.by));
           else
-            final_pass<MAXS>(ImageSampler<IM>{gimg, W, H, w.bx, w.by, c0}, n, w, dxy,
-                             tval, K);
+            fpass(ImageSampler<IM>{gimg, W, H, w.bx, w.by, c0});
           double S[3];
           wave_sums_f32<3>(K, S);
           if (!isfinite(S[0]) || !isfinite(S[1])) {
@@ -226,67 +360,89 @@ __global__ void __launch_bounds__(512) nr_f32_kernel(
   }
 }
 
-template <int MAXS, int IM>
-static hipError_t launch_nr_f32_t(const DevState& st, const dic_tuning_t& tu, const float* def,
+template <int MAXS, int IM, bool R2 = false>
+static hipError_t launch_nr_f32_t(const DevState& st, const dic_tuning_t& tu,
+                                  const RefineGroup& gr, int ctr, const float* def,
                                   const int32_t* poi, const int32_t* uv_init,
                                   const int32_t* status_in, const double* p_init, double* p_out,
                                   float* zncc, int32_t* iters, int32_t* status, int num_cu,
                                   hipStream_t s) {
   const int threads = tu.icgn_waves * kWave;
+  const int slack = R2 ? min(tu.icgn_slack, kR2MaxSlack) : tu.icgn_slack;
   // the table form reads no LDS patch
   const size_t lds = IM == kInterpBicubicLut
                          ? 0
-                         : refine_lds_bytes(refine_patch_pitch(MAXS),
-                                            icgn_patch_side(st.maxM, tu.icgn_slack), tu.icgn_waves);
+                         : refine_lds_bytes(R2 ? kR2Pitch : refine_patch_pitch(MAXS),
+                                            icgn_patch_side(gr.maxM, slack), tu.icgn_waves);
+  const void* fn = reinterpret_cast<const void*>(&nr_f32_kernel<MAXS, IM, R2>);
   if (lds > 65536) {
-    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&nr_f32_kernel<MAXS, IM>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ea != hipSuccess) return ea;
   }
   int occ = 0;
-  hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, nr_f32_kernel<MAXS, IM>, threads, lds);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, nr_f32_kernel<MAXS, IM, R2>,
+                                                              threads, lds);
   if (e != hipSuccess) return e;
   if (occ < 1) return hipErrorInvalidConfiguration;
   int64_t blocks = (int64_t)occ * num_cu;
-  const int64_t need = (st.N + tu.icgn_waves - 1) / tu.icgn_waves;
+  const int64_t need = (gr.count + tu.icgn_waves - 1) / tu.icgn_waves;
   if (blocks > need) blocks = need;
-  hipLaunchKernelGGL((nr_f32_kernel<MAXS, IM>), dim3((unsigned)blocks), dim3(threads), lds, s, st,
-                     tu.icgn_slack, def, poi, uv_init, status_in, p_init, p_out, zncc, iters,
-                     status);
+  hipLaunchKernelGGL((nr_f32_kernel<MAXS, IM, R2>), dim3((unsigned)blocks), dim3(threads), lds,
+                     s, st, st.work + gr.begin, gr.count, ctr, gr.maxM, slack, def, poi, uv_init,
+                     status_in, p_init, p_out, zncc, iters, status);
   return hipGetLastError();
 }
 
-hipError_t launch_nr_f32(const DevState& st, const dic_tuning_t& tu, const float* def,
-                         const int32_t* poi, const int32_t* uv_init, const int32_t* status_in,
-                         const double* p_init, double* p_out, float* zncc, int32_t* iters,
-                         int32_t* status, int num_cu, hipStream_t s, int interp) {
-  if (st.N == 0) return hipSuccess;
-  const int n = (2 * st.maxM + 1) * (2 * st.maxM + 1);
-  const int need = (n + kWave - 1) / kWave;
-#define DIC_NR_CASE(S_)                                                                       \
-  if (need <= S_) {                                                                           \
-    if (interp == kInterpBilinear)                                                            \
-      return launch_nr_f32_t<S_, kInterpBilinear>(st, tu, def, poi, uv_init, status_in, p_init,  \
-                                                  p_out, zncc, iters, status, num_cu, s);      \
-    if (interp == kInterpBSpline)                                                             \
-      return launch_nr_f32_t<S_, kInterpBSpline>(st, tu, def, poi, uv_init, status_in,        \
-                                                  p_init, p_out, zncc, iters, status, num_cu, s);\
-    if (interp == kInterpBicubicLut)                                                          \
-      return launch_nr_f32_t<S_, kInterpBicubicLut>(st, tu, def, poi, uv_init, status_in,     \
-                                                    p_init, p_out, zncc, iters, status, num_cu, \
-                                                    s);                                       \
-    return launch_nr_f32_t<S_, kInterpBicubic>(st, tu, def, poi, uv_init, status_in, p_init,   \
-                                               p_out, zncc, iters, status, num_cu, s);         \
+// One group: the kernel its subset size runs in.
+template <int IM>
+static hipError_t launch_nr_f32_group(const DevState& st, const dic_tuning_t& tu,
+                                     const RefineGroup& gr, int ctr, const float* def,
+                                     const int32_t* poi, const int32_t* uv_init,
+                                     const int32_t* status_in, const double* p_init,
+                                     double* p_out, float* zncc, int32_t* iters,
+                                     int32_t* status, int num_cu, hipStream_t s) {
+#define DIC_REFINE_ARGS st, tu, gr, ctr, def, poi, uv_init, status_in, p_init, p_out, zncc, iters, \
+                        status, num_cu, s
+  if (refine_two_rows(gr.maxM)) return launch_nr_f32_t<16, IM, true>(DIC_REFINE_ARGS);
+  switch (refine_slots(gr.maxM)) {
+    case 4: return launch_nr_f32_t<4, IM>(DIC_REFINE_ARGS);
+    case 8: return launch_nr_f32_t<8, IM>(DIC_REFINE_ARGS);
+    case 12: return launch_nr_f32_t<12, IM>(DIC_REFINE_ARGS);
+    case 16: return launch_nr_f32_t<16, IM>(DIC_REFINE_ARGS);
+    case 20: return launch_nr_f32_t<20, IM>(DIC_REFINE_ARGS);
+    case 28: return launch_nr_f32_t<28, IM>(DIC_REFINE_ARGS);
+    default: return hipErrorInvalidValue;
   }
-  DIC_NR_CASE(4)
-  DIC_NR_CASE(8)
-  DIC_NR_CASE(12)
-  DIC_NR_CASE(16)
-  DIC_NR_CASE(20)
-  DIC_NR_CASE(28)
-#undef DIC_NR_CASE
-  return hipErrorInvalidValue;
+#undef DIC_REFINE_ARGS
+}
+
+hipError_t launch_nr_f32(const DevState& st, const dic_tuning_t& tu, const RefineGroup* groups,
+                           int ngroups, const float* def, const int32_t* poi,
+                           const int32_t* uv_init, const int32_t* status_in,
+                           const double* p_init, double* p_out, float* zncc, int32_t* iters,
+                           int32_t* status, int num_cu, hipStream_t s, int interp) {
+  if (ngroups > kMaxRefineGroups) return hipErrorInvalidValue;
+  for (int k = 0; k < ngroups; ++k) {
+    const RefineGroup& gr = groups[k];
+    if (gr.count == 0) continue;
+    const int ctr = kCtrIcgn + k;
+    hipError_t e;
+    if (interp == kInterpBilinear)
+      e = launch_nr_f32_group<kInterpBilinear>(st, tu, gr, ctr, def, poi, uv_init, status_in,
+                                               p_init, p_out, zncc, iters, status, num_cu, s);
+    else if (interp == kInterpBSpline)
+      e = launch_nr_f32_group<kInterpBSpline>(st, tu, gr, ctr, def, poi, uv_init, status_in,
+                                              p_init, p_out, zncc, iters, status, num_cu, s);
+    else if (interp == kInterpBicubicLut)
+      e = launch_nr_f32_group<kInterpBicubicLut>(st, tu, gr, ctr, def, poi, uv_init,
+                                                 status_in, p_init, p_out, zncc, iters, status,
+                                                 num_cu, s);
+    else
+      e = launch_nr_f32_group<kInterpBicubic>(st, tu, gr, ctr, def, poi, uv_init, status_in,
+                                              p_init, p_out, zncc, iters, status, num_cu, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

@@ -376,12 +376,13 @@ __device__ __forceinline__ void write_bad_record(RefRec* R, int status, int lane
 __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
                                                            const float* __restrict__ ref,
                                                            const int32_t* __restrict__ poi) {
-  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  // the POI of this wave, wave-uniform: its pointers stay in scalar registers
+  const int g = uniform((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave));
   if (g >= st.N) return;
   const int lane = lane_id();
-  const DevPair P = st.pairs[st.poi_pair[g]];
+  const DevPair P = st.pairs[uniform(st.poi_pair[g])];
   RefRec* R = st.recs + g;
-  const int x0 = poi[2 * g], y0 = poi[2 * g + 1];
+  const int x0 = uniform(poi[2 * g]), y0 = uniform(poi[2 * g + 1]);
   const int M = P.M, n1 = 2 * M + 1, n = n1 * n1, W = P.width;
   if (!poi_inside(x0, y0, M, P.width, P.height)) {
     write_bad_record(R, DIC_POI_OUT_OF_BOUNDS, lane);
@@ -419,8 +420,9 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
   int bad = 0;
   {
     int r = lane / n1, c = lane - r * n1;
+#pragma unroll 4
     for (int k = lane; k < n; k += kWave) {
-      const int o = r * W + c;
+      const unsigned o = (unsigned)(r * W + c);   // 32-bit offset from a scalar base
       const float v = f[o];
       bad |= !isfinite(v);
       s1 += (double)v;
@@ -453,8 +455,9 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
   for (int a = 0; a < 21; ++a) kh[a] = 0.f;
   {
     int r = lane / n1, c = lane - r * n1;
+#pragma unroll 4
     for (int k = lane; k < n; k += kWave) {
-      const int o = r * W + c;
+      const unsigned o = (unsigned)(r * W + c);   // 32-bit offset from a scalar base
       const float v = f[o];
       const double d = (double)v - fbar;
       q += d * d;

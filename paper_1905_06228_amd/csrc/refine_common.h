@@ -208,7 +208,9 @@ struct PatchSampler {
     interp_weights<IM>(tx, wx);
     interp_weights<IM>(ty, wy);
     constexpr int first = NT == 4 ? 0 : P + 1;   // the 2x2 neighbourhood starts at (0, 0)
-    return q0 + (first + __mul24((int)fy, P) + (int)fx);
+    // fy P + fx is a small integer, exact in FP32: one multiply-add and one
+    // conversion instead of two conversions and an integer multiply-add
+    return q0 + (first + (int)fmaf(fy, (float)P, fx));
   }
   static constexpr int pitch() { return P; }
   static constexpr int ntaps() { return NT; }
@@ -425,6 +427,99 @@ __device__ __forceinline__ void final_pass(const Smp& smp, int n, const Warp32& 
     K[1] = fmaf(gs, gs, K[1]);
     K[2] = fmaf(tval(k, dx, dy), gs, K[2]);
   }
+}
+
+// Two-rows-per-slot layout, for subsets of at most 31 columns: lane l holds
+// column c = l mod 32 (clamped to the subset; lanes past it carry zero
+// gradients and have their two value sums cleared after the pass) of row
+// 2k + l / 32 in slot k < M, and slot M holds the last row 2M in the lower
+// half-wave (the upper half repeats it, masked).  A lane's column offset dx
+// is then fixed, so its x position advances by 2 uy per slot from one base,
+// sum SD g dx is dx times sum SD g, and the dy-weighted sums take the slot's
+// even row offset 2k as a constant plus (l / 32 - M) times the plain sum:
+// fewer operations per sample than the general layout and no per-slot
+// offsets in registers.  The two-rows kernels' LDS patch pitch is sized for
+// radius 15 and a slack of at most kR2MaxSlack pixels (a larger tuned slack
+// is clamped: the slack changes when the patch is restaged, not the
+// results), so that four waves' patches fit a CU's LDS.
+constexpr int kR2MaxSlack = 6;
+constexpr int kR2Pitch = (2 * 15 + 4 + 2 * kR2MaxSlack) | 1;
+static_assert(3 * kR2Pitch + 3 <= 255, "tap offsets exceed the LDS read2 range");
+
+struct R2Lane {
+  float dx;      // column offset of this lane (clamped into the subset)
+  float hm;      // l / 32 - M: the row offset of slot 0
+  bool colok;    // the column lies in the subset
+  bool upper;    // l / 32 == 1
+};
+
+__device__ __forceinline__ R2Lane r2_lane(int M) {
+  const int lane = lane_id(), c = lane & 31, h = lane >> 5, n1 = 2 * M + 1;
+  R2Lane L;
+  L.colok = c < n1;
+  L.dx = (float)((L.colok ? c : n1 - 1) - M);
+  L.hm = (float)(h - M);
+  L.upper = h != 0;
+  return L;
+}
+
+// Per-sample reference values of the lane in the two-rows layout: slots
+// k < M, then the last row's value (zero for the upper half and for columns
+// outside the subset).  `a` (and `b`, nullable) address the subset's
+// top-left sample with row pitch `pitch`.
+template <int MAXS>
+__device__ __forceinline__ void load_slots_r2(int M, const R2Lane& L, const float* __restrict__ a,
+                                              const float* __restrict__ b, int pitch, float* va,
+                                              float* vb, float& pa, float& pb) {
+  const int c = (int)L.dx + M, h = L.upper ? 1 : 0;
+#pragma unroll
+  for (int k = 0; k < MAXS - 1; ++k) {
+    va[k] = 0.f;
+    if (b) vb[k] = 0.f;
+    if (k < M && L.colok) {
+      const int o = __umul24(2 * k + h, pitch) + c;
+      va[k] = a[o];
+      if (b) vb[k] = b[o];
+    }
+  }
+  pa = pb = 0.f;
+  if (L.colok && !L.upper) {
+    const int o = __umul24(2 * M, pitch) + c;
+    pa = a[o];
+    if (b) pb = b[o];
+  }
+}
+
+// final_pass in the two-rows layout: sum (g - c0), sum (g - c0)^2 and
+// sum (f - fbar)(g - c0), the template value at (dx, dy) from tval.
+template <int MAXS, class Smp, class TV>
+__device__ __forceinline__ void final_pass_r2(const Smp& smp, int M, const R2Lane& L,
+                                              const Warp32& w, const TV& tval, float* K) {
+  const int Mu = __builtin_amdgcn_readfirstlane(M);
+  const float bx = fmaf(w.ax, L.dx, fmaf(w.uy, L.hm, w.uf));
+  const float by = fmaf(w.vx, L.dx, fmaf(w.ay, L.hm, w.vf));
+  float k0 = 0.f, k1 = 0.f, k2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < MAXS - 1; ++k) {
+    if (k >= Mu) continue;
+    const float dk = (float)(2 * k);
+    const float gs = sample_value(smp, fmaf(w.uy, dk, bx), fmaf(w.ay, dk, by));
+    k0 += gs;
+    k1 = fmaf(gs, gs, k1);
+    k2 = fmaf(tval(0, L.dx, dk + L.hm), gs, k2);
+  }
+  {
+    const float dm = (float)Mu;
+    const float v = sample_value(smp, fmaf(w.ax, L.dx, fmaf(w.uy, dm, w.uf)),
+                                 fmaf(w.vx, L.dx, fmaf(w.ay, dm, w.vf)));
+    const float gs = L.upper ? 0.f : v;
+    k0 += gs;
+    k1 = fmaf(gs, gs, k1);
+    k2 = fmaf(tval(0, L.dx, dm), gs, k2);
+  }
+  K[0] = L.colok ? k0 : 0.f;
+  K[1] = L.colok ? k1 : 0.f;
+  K[2] = L.colok ? k2 : 0.f;
 }
 
 // Per-wave LDS patch of the deformed image: `side` rows of pitch P holding
