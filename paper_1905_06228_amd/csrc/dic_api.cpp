@@ -94,6 +94,7 @@ struct dic_plan_s {
   int num_cu = 0;
   DevState st{};
   bool ref_valid = false;
+  bool ref_tmpl = false;   // the cached reference preparation wrote the FP32 template
   const void* ref_img = nullptr;
   const void* ref_poi = nullptr;
   bool def_valid = false;
@@ -263,18 +264,24 @@ dic_status_t attach_workspace(dic_plan_t p, void* ws, hipStream_t s) {
   return DIC_SUCCESS;
 }
 
+// The reference side.  The FP32 search template is written only when the
+// vector-ALU search form (which reads it) may run: its tuning, or `tmpl`
+// (the autotuner, which tries every form); a cached preparation without it
+// is redone when a form that needs it comes.
 dic_status_t prepare(dic_plan_t p, const float* ref, const int32_t* poi, hipStream_t s,
-                     bool force) {
+                     bool force, bool tmpl = false) {
+  const bool need_tmpl = tmpl || p->tuning.search_block != kMfmaBlock;
   if (!force && (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->ref_valid && p->ref_img == ref &&
-      p->ref_poi == poi)
+      p->ref_poi == poi && (p->ref_tmpl || !need_tmpl || !p->fp32()))
     return DIC_SUCCESS;
   if (p->fp32()) {
     DIC_HIP(launch_gradients(p->st, ref, s));
-    DIC_HIP(launch_ref_prep_f32(p->st, ref, poi, s));
+    DIC_HIP(launch_ref_prep_f32(p->st, ref, poi, need_tmpl, s));
   } else {
     DIC_HIP(launch_ref_prep_f64(p->st, p->dpairs.data(), ref, poi, s));
   }
   p->ref_valid = true;
+  p->ref_tmpl = need_tmpl;
   p->ref_img = ref;
   p->ref_poi = poi;
   return DIC_SUCCESS;
@@ -357,11 +364,13 @@ dic_status_t enqueue_refine(dic_plan_t p, const float* ref, const float* def, co
     DIC_HIP(launch_reset_counters(p->st, s));
     const int ng = (int)p->rgroups.size();
     if (nr)
-      DIC_HIP(launch_nr_f32(p->st, p->tuning, p->rgroups.data(), ng, def, poi, uv, status_in,
-                            p_init, p_out, zn, iters, status, p->num_cu, s, p->interp()));
+      DIC_HIP(launch_nr_f32(p->st, p->tuning, p->rgroups.data(), ng, ref, def, poi, uv,
+                            status_in, p_init, p_out, zn, iters, status, p->num_cu, s,
+                            p->interp()));
     else
-      DIC_HIP(launch_icgn_f32(p->st, p->tuning, p->rgroups.data(), ng, def, poi, uv, status_in,
-                              p_init, p_out, zn, iters, status, p->num_cu, s, p->interp()));
+      DIC_HIP(launch_icgn_f32(p->st, p->tuning, p->rgroups.data(), ng, ref, def, poi, uv,
+                              status_in, p_init, p_out, zn, iters, status, p->num_cu, s,
+                              p->interp()));
   } else if (nr) {
     DIC_HIP(launch_nr_f64(p->st, p->dpairs.data(), ref, def, poi, uv, status_in, p_init, p_out,
                           zn, iters, status, s));
@@ -793,6 +802,7 @@ dic_status_t dic_correlate(dic_plan_t p, const float* ref, const float* def, con
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (!(p->desc.flags & DIC_FLAG_USE_GRAPH)) return enqueue_correlate(p, a, s);
   const bool cached_ref = (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->ref_valid &&
+                          (p->ref_tmpl || p->tuning.search_block == kMfmaBlock || !p->fp32()) &&
                           p->ref_img == ref && p->ref_poi == poi && p->def_valid &&
                           p->def_img == def &&
                           (!p->table() || (p->lut_valid && p->lut_img == def));
@@ -850,12 +860,12 @@ dic_status_t dic_correlate_noalloc(dic_plan_t p, const float* ref, const float* 
   // (workspace, caches, graphs) is put back afterwards, untouched.
   struct Saved {
     void* ws;
-    bool bound, ref_valid, def_valid, lut_valid;
+    bool bound, ref_valid, ref_tmpl, def_valid, lut_valid;
     const void *ref_img, *ref_poi, *def_img, *lut_img;
     DevState st;
     int num_cu;
-  } sv{p->ws, p->bound, p->ref_valid, p->def_valid, p->lut_valid, p->ref_img, p->ref_poi,
-       p->def_img, p->lut_img, p->st, p->num_cu};
+  } sv{p->ws,      p->bound,   p->ref_valid, p->ref_tmpl, p->def_valid, p->lut_valid,
+       p->ref_img, p->ref_poi, p->def_img,   p->lut_img,  p->st,        p->num_cu};
   r = attach_workspace(p, base, s);
   if (r == DIC_SUCCESS) {
     char* b = static_cast<char*>(base);
@@ -868,6 +878,7 @@ dic_status_t dic_correlate_noalloc(dic_plan_t p, const float* ref, const float* 
   p->ws = sv.ws;
   p->bound = sv.bound;
   p->ref_valid = sv.ref_valid;
+  p->ref_tmpl = sv.ref_tmpl;
   p->def_valid = sv.def_valid;
   p->lut_valid = sv.lut_valid;
   p->ref_img = sv.ref_img;
@@ -940,7 +951,7 @@ dic_status_t dic_plan_autotune(dic_plan_t p, const float* ref, const float* def,
   if (!ref || !def || !poi || !uv || !fs || !is || !ps)
     return fail(DIC_ERR_INVALID_ARGUMENT, "null pointer");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  r = prepare(p, ref, poi, s, true);
+  r = prepare(p, ref, poi, s, true, true);   // every search form may be timed
   if (r) return r;
   r = prepare_deformed(p, def, s, true);
   if (r) return r;

@@ -70,7 +70,7 @@ struct DevState {
   int32_t* counters;        // persistent-launch work counters
   float* grads;             // gradient arena
   RefRec* recs;             // [N]
-  float* tmpl;              // template arena
+  float* tmpl;              // template arena (written for the vector-ALU search form)
   double* box;              // box-sum arena (deformed images)
   float* lut;               // bicubic coefficient tables (16 floats per pixel) or B-spline
                             // coefficient images (1 float per pixel, then 1 of scratch) of
@@ -130,8 +130,10 @@ hipError_t launch_pso(const DevState& st, bool modified, const float* ref, const
                       const int32_t* poi, const int32_t* seed, const float* rand, int32_t* uv,
                       float* zn, int32_t* status, int32_t* gens, int32_t* evals, int num_cu,
                       hipStream_t s);
+// write_tmpl: also store the FP32 search template (read by the vector-ALU
+// search form only).
 hipError_t launch_ref_prep_f32(const DevState& st, const float* ref, const int32_t* poi,
-                               hipStream_t s);
+                               bool write_tmpl, hipStream_t s);
 hipError_t launch_ref_prep_f64(const DevState& st, const DevPair* host_pairs,
                                const float* ref, const int32_t* poi, hipStream_t s);
 hipError_t launch_search_f32(const DevState& st, const dic_tuning_t& tu,
@@ -162,13 +164,13 @@ hipError_t launch_search_f64(const DevState& st, const DevPair* host_pairs, cons
                              const float* def, const int32_t* poi, const int32_t* seed,
                              int32_t* uv, float* zncc, int32_t* status, hipStream_t s);
 hipError_t launch_icgn_f32(const DevState& st, const dic_tuning_t& tu,
-                           const RefineGroup* groups, int ngroups, const float* def,
-                           const int32_t* poi, const int32_t* uv_init,
+                           const RefineGroup* groups, int ngroups, const float* ref,
+                           const float* def, const int32_t* poi, const int32_t* uv_init,
                            const int32_t* status_in, const double* p_init, double* p_out,
                            float* zncc, int32_t* iters, int32_t* status, int num_cu,
                            hipStream_t s, int interp);
 hipError_t launch_nr_f32(const DevState& st, const dic_tuning_t& tu, const RefineGroup* groups,
-                         int ngroups, const float* def, const int32_t* poi,
+                         int ngroups, const float* ref, const float* def, const int32_t* poi,
                          const int32_t* uv_init, const int32_t* status_in,
                          const double* p_init, double* p_out, float* zncc, int32_t* iters,
                          int32_t* status, int num_cu, hipStream_t s, int interp);

@@ -105,7 +105,7 @@ template <int MAXS, int IM, bool R2>
 __global__ void __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
     DevState st, const int32_t* __restrict__ work, int64_t count, int ctr, int gmaxM, int slack,
-    const float* __restrict__ def, const int32_t* __restrict__ poi,
+    const float* __restrict__ ref, const float* __restrict__ def, const int32_t* __restrict__ poi,
     const int32_t* __restrict__ uv_init, const int32_t* __restrict__ status_in,
     const double* __restrict__ p_init, double* __restrict__ p_out, float* __restrict__ zncc_out,
     int32_t* __restrict__ iters_out, int32_t* __restrict__ status_out) {
@@ -212,11 +212,12 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
         if (xl < 0 || xh > W - 1 || yl < 0 || yh > H - 1) {
           status = DIC_POI_OUT_OF_BOUNDS;
         } else {
-          const int tp = P.tmpl_pitch;
-          const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * tp +
-                            (int64_t)M * tp + M;
+          // the template value f - fbar at offset (dx, dy), rounded as the
+          // record's tsum counts it
+          const float* fc = ref + P.ref_off + (int64_t)y0 * W + x0;
+          const float fb = (float)R->fbar;
           const auto tval = [&](int, float dx, float dy) {
-            return tm[__mul24((int)dy, tp) + (int)dx];
+            return fc[(int)dy * W + (int)dx] - fb;
           };
           float K[3];
           const auto fpass = [&](const auto& smp) {
@@ -259,7 +260,8 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
 
 template <int MAXS, int IM, bool R2 = false>
 static hipError_t launch_icgn_f32_t(const DevState& st, const dic_tuning_t& tu,
-                                    const RefineGroup& gr, int ctr, const float* def,
+                                    const RefineGroup& gr, int ctr, const float* ref,
+                                    const float* def,
                                     const int32_t* poi, const int32_t* uv_init,
                                     const int32_t* status_in, const double* p_init, double* p_out,
                                     float* zncc, int32_t* iters, int32_t* status, int num_cu,
@@ -285,7 +287,7 @@ static hipError_t launch_icgn_f32_t(const DevState& st, const dic_tuning_t& tu,
   const int64_t need = (gr.count + tu.icgn_waves - 1) / tu.icgn_waves;
   if (blocks > need) blocks = need;
   hipLaunchKernelGGL((icgn_f32_kernel<MAXS, IM, R2>), dim3((unsigned)blocks), dim3(threads), lds,
-                     s, st, st.work + gr.begin, gr.count, ctr, gr.maxM, slack, def, poi, uv_init,
+                     s, st, st.work + gr.begin, gr.count, ctr, gr.maxM, slack, ref, def, poi, uv_init,
                      status_in, p_init, p_out, zncc, iters, status);
   return hipGetLastError();
 }
@@ -293,12 +295,13 @@ static hipError_t launch_icgn_f32_t(const DevState& st, const dic_tuning_t& tu,
 // One group: the kernel its subset size runs in.
 template <int IM>
 static hipError_t launch_icgn_f32_group(const DevState& st, const dic_tuning_t& tu,
-                                     const RefineGroup& gr, int ctr, const float* def,
+                                     const RefineGroup& gr, int ctr, const float* ref,
+                                    const float* def,
                                      const int32_t* poi, const int32_t* uv_init,
                                      const int32_t* status_in, const double* p_init,
                                      double* p_out, float* zncc, int32_t* iters,
                                      int32_t* status, int num_cu, hipStream_t s) {
-#define DIC_REFINE_ARGS st, tu, gr, ctr, def, poi, uv_init, status_in, p_init, p_out, zncc, iters, \
+#define DIC_REFINE_ARGS st, tu, gr, ctr, ref, def, poi, uv_init, status_in, p_init, p_out, zncc, iters, \
                         status, num_cu, s
   if (refine_two_rows(gr.maxM)) return launch_icgn_f32_t<16, IM, true>(DIC_REFINE_ARGS);
   switch (refine_slots(gr.maxM)) {
@@ -314,7 +317,7 @@ static hipError_t launch_icgn_f32_group(const DevState& st, const dic_tuning_t& 
 }
 
 hipError_t launch_icgn_f32(const DevState& st, const dic_tuning_t& tu, const RefineGroup* groups,
-                           int ngroups, const float* def, const int32_t* poi,
+                           int ngroups, const float* ref, const float* def, const int32_t* poi,
                            const int32_t* uv_init, const int32_t* status_in,
                            const double* p_init, double* p_out, float* zncc, int32_t* iters,
                            int32_t* status, int num_cu, hipStream_t s, int interp) {
@@ -325,17 +328,17 @@ hipError_t launch_icgn_f32(const DevState& st, const dic_tuning_t& tu, const Ref
     const int ctr = kCtrIcgn + k;
     hipError_t e;
     if (interp == kInterpBilinear)
-      e = launch_icgn_f32_group<kInterpBilinear>(st, tu, gr, ctr, def, poi, uv_init, status_in,
+      e = launch_icgn_f32_group<kInterpBilinear>(st, tu, gr, ctr, ref, def, poi, uv_init, status_in,
                                                p_init, p_out, zncc, iters, status, num_cu, s);
     else if (interp == kInterpBSpline)
-      e = launch_icgn_f32_group<kInterpBSpline>(st, tu, gr, ctr, def, poi, uv_init, status_in,
+      e = launch_icgn_f32_group<kInterpBSpline>(st, tu, gr, ctr, ref, def, poi, uv_init, status_in,
                                               p_init, p_out, zncc, iters, status, num_cu, s);
     else if (interp == kInterpBicubicLut)
-      e = launch_icgn_f32_group<kInterpBicubicLut>(st, tu, gr, ctr, def, poi, uv_init,
+      e = launch_icgn_f32_group<kInterpBicubicLut>(st, tu, gr, ctr, ref, def, poi, uv_init,
                                                  status_in, p_init, p_out, zncc, iters, status,
                                                  num_cu, s);
     else
-      e = launch_icgn_f32_group<kInterpBicubic>(st, tu, gr, ctr, def, poi, uv_init, status_in,
+      e = launch_icgn_f32_group<kInterpBicubic>(st, tu, gr, ctr, ref, def, poi, uv_init, status_in,
                                               p_init, p_out, zncc, iters, status, num_cu, s);
     if (e != hipSuccess) return e;
   }

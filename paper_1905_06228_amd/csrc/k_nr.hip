@@ -182,7 +182,7 @@ template <int MAXS, int IM, bool R2>
 __global__ void __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu(R2 ? 3 : 1))) nr_f32_kernel(
     DevState st, const int32_t* __restrict__ work, int64_t count, int ctr, int gmaxM, int slack,
-    const float* __restrict__ def, const int32_t* __restrict__ poi,
+    const float* __restrict__ ref, const float* __restrict__ def, const int32_t* __restrict__ poi,
     const int32_t* __restrict__ uv_init, const int32_t* __restrict__ status_in,
     const double* __restrict__ p_init, double* __restrict__ p_out, float* __restrict__ zncc_out,
     int32_t* __restrict__ iters_out, int32_t* __restrict__ status_out) {
@@ -221,16 +221,23 @@ __attribute__((amdgpu_waves_per_eu(R2 ? 3 : 1))) nr_f32_kernel(
       const float* gimg =
           IM == kInterpBSpline ? st.lut + 4 * P.lut_off : def + P.def_off;
       const float4* glut = reinterpret_cast<const float4*>(st.lut) + P.lut_off;
-      const int tp = P.tmpl_pitch;
-      const float* tm = st.tmpl + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * tp;
+      // the template values f - fbar of the lane's samples (rounded as the
+      // record's tsum counts them), zero for missing samples
+      const float* fsub = ref + P.ref_off + (int64_t)(y0 - M) * W + (x0 - M);
+      const float fb = (float)R->fbar;
       float tv[MAXS], tvp = 0.f, unused = 0.f;
       half2v dxy[R2 ? 1 : MAXS];
       R2Lane L2{};
       if constexpr (R2) {
         L2 = r2_lane(M);
-        load_slots_r2<MAXS>(M, L2, tm, nullptr, tp, tv, nullptr, tvp, unused);
+        load_slots_r2<MAXS>(M, L2, fsub, nullptr, W, tv, nullptr, tvp, unused);
+#pragma unroll
+        for (int k = 0; k < MAXS - 1; ++k) tv[k] = (k < M && L2.colok) ? tv[k] - fb : 0.f;
+        tvp = (L2.colok && !L2.upper) ? tvp - fb : 0.f;
       } else {
-        load_slots<MAXS>(M, n, tm, nullptr, tp, dxy, tv, nullptr);
+        load_slots<MAXS>(M, n, fsub, nullptr, W, dxy, tv, nullptr);
+#pragma unroll
+        for (int k = 0; k < MAXS; ++k) tv[k] = (lane_id() + kWave * k < n) ? tv[k] - fb : 0.f;
       }
       const float c0 = deformed_centre(gimg, W, H, p, x0, y0);
       const double df = R->df, tsum = (double)R->tsum;
@@ -318,9 +325,9 @@ __attribute__((amdgpu_waves_per_eu(R2 ? 3 : 1))) nr_f32_kernel(
           const auto fpass = [&](const auto& smp) {
             if constexpr (R2) {
               // the template value at offset (dx, dy) from the subset centre
-              const float* tmc = tm + (int64_t)M * tp + M;
+              const float* fc = fsub + (int64_t)M * W + M;
               const auto tval = [&](int, float dx, float dy) {
-                return tmc[__mul24((int)dy, tp) + (int)dx];
+                return fc[(int)dy * W + (int)dx] - fb;
               };
               final_pass_r2<MAXS>(smp, M, L2, w, tval, K);
             } else {
@@ -362,7 +369,8 @@ __attribute__((amdgpu_waves_per_eu(R2 ? 3 : 1))) nr_f32_kernel(
 
 template <int MAXS, int IM, bool R2 = false>
 static hipError_t launch_nr_f32_t(const DevState& st, const dic_tuning_t& tu,
-                                  const RefineGroup& gr, int ctr, const float* def,
+                                  const RefineGroup& gr, int ctr, const float* ref,
+                                  const float* def,
                                   const int32_t* poi, const int32_t* uv_init,
                                   const int32_t* status_in, const double* p_init, double* p_out,
                                   float* zncc, int32_t* iters, int32_t* status, int num_cu,
@@ -388,7 +396,7 @@ static hipError_t launch_nr_f32_t(const DevState& st, const dic_tuning_t& tu,
   const int64_t need = (gr.count + tu.icgn_waves - 1) / tu.icgn_waves;
   if (blocks > need) blocks = need;
   hipLaunchKernelGGL((nr_f32_kernel<MAXS, IM, R2>), dim3((unsigned)blocks), dim3(threads), lds,
-                     s, st, st.work + gr.begin, gr.count, ctr, gr.maxM, slack, def, poi, uv_init,
+                     s, st, st.work + gr.begin, gr.count, ctr, gr.maxM, slack, ref, def, poi, uv_init,
                      status_in, p_init, p_out, zncc, iters, status);
   return hipGetLastError();
 }
@@ -396,12 +404,13 @@ static hipError_t launch_nr_f32_t(const DevState& st, const dic_tuning_t& tu,
 // One group: the kernel its subset size runs in.
 template <int IM>
 static hipError_t launch_nr_f32_group(const DevState& st, const dic_tuning_t& tu,
-                                     const RefineGroup& gr, int ctr, const float* def,
+                                     const RefineGroup& gr, int ctr, const float* ref,
+                                    const float* def,
                                      const int32_t* poi, const int32_t* uv_init,
                                      const int32_t* status_in, const double* p_init,
                                      double* p_out, float* zncc, int32_t* iters,
                                      int32_t* status, int num_cu, hipStream_t s) {
-#define DIC_REFINE_ARGS st, tu, gr, ctr, def, poi, uv_init, status_in, p_init, p_out, zncc, iters, \
+#define DIC_REFINE_ARGS st, tu, gr, ctr, ref, def, poi, uv_init, status_in, p_init, p_out, zncc, iters, \
                         status, num_cu, s
   if (refine_two_rows(gr.maxM)) return launch_nr_f32_t<16, IM, true>(DIC_REFINE_ARGS);
   switch (refine_slots(gr.maxM)) {
@@ -417,10 +426,10 @@ static hipError_t launch_nr_f32_group(const DevState& st, const dic_tuning_t& tu
 }
 
 hipError_t launch_nr_f32(const DevState& st, const dic_tuning_t& tu, const RefineGroup* groups,
-                           int ngroups, const float* def, const int32_t* poi,
-                           const int32_t* uv_init, const int32_t* status_in,
-                           const double* p_init, double* p_out, float* zncc, int32_t* iters,
-                           int32_t* status, int num_cu, hipStream_t s, int interp) {
+                         int ngroups, const float* ref, const float* def, const int32_t* poi,
+                         const int32_t* uv_init, const int32_t* status_in,
+                         const double* p_init, double* p_out, float* zncc, int32_t* iters,
+                         int32_t* status, int num_cu, hipStream_t s, int interp) {
   if (ngroups > kMaxRefineGroups) return hipErrorInvalidValue;
   for (int k = 0; k < ngroups; ++k) {
     const RefineGroup& gr = groups[k];
@@ -428,17 +437,17 @@ hipError_t launch_nr_f32(const DevState& st, const dic_tuning_t& tu, const Refin
     const int ctr = kCtrIcgn + k;
     hipError_t e;
     if (interp == kInterpBilinear)
-      e = launch_nr_f32_group<kInterpBilinear>(st, tu, gr, ctr, def, poi, uv_init, status_in,
+      e = launch_nr_f32_group<kInterpBilinear>(st, tu, gr, ctr, ref, def, poi, uv_init, status_in,
                                                p_init, p_out, zncc, iters, status, num_cu, s);
     else if (interp == kInterpBSpline)
-      e = launch_nr_f32_group<kInterpBSpline>(st, tu, gr, ctr, def, poi, uv_init, status_in,
+      e = launch_nr_f32_group<kInterpBSpline>(st, tu, gr, ctr, ref, def, poi, uv_init, status_in,
                                               p_init, p_out, zncc, iters, status, num_cu, s);
     else if (interp == kInterpBicubicLut)
-      e = launch_nr_f32_group<kInterpBicubicLut>(st, tu, gr, ctr, def, poi, uv_init,
+      e = launch_nr_f32_group<kInterpBicubicLut>(st, tu, gr, ctr, ref, def, poi, uv_init,
                                                  status_in, p_init, p_out, zncc, iters, status,
                                                  num_cu, s);
     else
-      e = launch_nr_f32_group<kInterpBicubic>(st, tu, gr, ctr, def, poi, uv_init, status_in,
+      e = launch_nr_f32_group<kInterpBicubic>(st, tu, gr, ctr, ref, def, poi, uv_init, status_in,
                                               p_init, p_out, zncc, iters, status, num_cu, s);
     if (e != hipSuccess) return e;
   }

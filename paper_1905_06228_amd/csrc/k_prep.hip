@@ -372,10 +372,13 @@ __device__ __forceinline__ void write_bad_record(RefRec* R, int status, int lane
 // images (the Hessian, no cancellation left) and the six sum SD (f - fbar)
 // in FP32 per lane with fused multiply-adds (at most a few tens of terms),
 // added across lanes in a fixed FP32 tree (six levels).  Factorisation and
-// singularity test in FP64.  Also stores the float search template f_i - fbar.
+// singularity test in FP64.  With write_tmpl also stores the float search
+// template f_i - fbar (rounded as f_i - (float)fbar), which only the
+// vector-ALU search reads; the other kernels form those values from f.
 __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
                                                            const float* __restrict__ ref,
-                                                           const int32_t* __restrict__ poi) {
+                                                           const int32_t* __restrict__ poi,
+                                                           int write_tmpl) {
   // the POI of this wave, wave-uniform: its pointers stay in scalar registers
   const int g = uniform((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave));
   if (g >= st.N) return;
@@ -393,10 +396,11 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
   const float* gyi = gxi + (int64_t)P.width * P.height;
   const int tp = P.tmpl_pitch;
   float* tmpl = st.tmpl + P.tmpl_off + (g - P.poi_off) * (int64_t)(n1 * tp);
-  for (int k = lane; k < n1 * (tp - n1); k += kWave) {
-    const int r = k / (tp - n1);
-    tmpl[r * tp + n1 + (k - r * (tp - n1))] = 0.f;   // zero padding of every row
-  }
+  if (write_tmpl)
+    for (int k = lane; k < n1 * (tp - n1); k += kWave) {
+      const int r = k / (tp - n1);
+      tmpl[r * tp + n1 + (k - r * (tp - n1))] = 0.f;   // zero padding of every row
+    }
   const int dr = kWave / n1, dc = kWave - dr * n1;
   auto step = [&](int& r, int& c) {
     c += dc;
@@ -463,7 +467,7 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
       q += d * d;
       sq += (double)v * (double)v;
       const float t = v - fbar_f;
-      tmpl[r * tp + c] = t;
+      if (write_tmpl) tmpl[r * tp + c] = t;
       ts += (double)t;
       float sd[6];
       sd_of(gxi[o], gyi[o], r, c, sd);
@@ -520,10 +524,11 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
 }
 
 hipError_t launch_ref_prep_f32(const DevState& st, const float* ref, const int32_t* poi,
-                               hipStream_t s) {
+                               bool write_tmpl, hipStream_t s) {
   if (st.N == 0) return hipSuccess;
   const int64_t blocks = (st.N + 3) / 4;
-  hipLaunchKernelGGL(ref_prep_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, st, ref, poi);
+  hipLaunchKernelGGL(ref_prep_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, st, ref, poi,
+                     write_tmpl ? 1 : 0);
   return hipGetLastError();
 }
 

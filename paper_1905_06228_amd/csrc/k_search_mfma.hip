@@ -286,8 +286,6 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     const int wx0 = x0 + cu - S - M, wy0 = y0 + cv - S - M;
     const int wn = n1 + side - 1;   // real window side
     const int wrows = n1 + 32 * TT;   // staged rows (a tile reads up to 32 (TT - 1) + n1 + 31)
-    const int tp = P.tmpl_pitch;
-    const float* tm = tmpl_arena + P.tmpl_off + (int64_t)(g - P.poi_off) * n1 * tp;
     const bool two = side == 33;
     ScoreCtx q;
     q.x0 = x0; q.y0 = y0; q.cu = cu; q.cv = cv; q.S = S; q.M = M; q.W = W; q.H = H;
@@ -297,15 +295,35 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     q.rdf = (float)(1.0 / R->df);
     q.nn = (float)nn;
 
-    // 0. the FP32 template as 4-column groups (rows of pitch tp, 16-byte
-    //    aligned; groups past tp are zero), requested at once
-    const int tq = tp / 4;
+    // 0. the template t = f - fbar of the reference subset (rounded as
+    //    f - (float)fbar, the values whose sum is the record's tsum), as
+    //    4-column groups of its rows, requested at once; columns past the
+    //    subset are zero.  A group whose four pixels lie in the image row is
+    //    one 16-byte load; one reaching past the image's last column (only
+    //    past the subset's) loads its subset columns alone.
+    const float fb = (float)R->fbar;
+    const float* fsub = fimg + (int64_t)(y0 - M) * W + (x0 - M);
     float4 tv[TQL];
 #pragma unroll
     for (int k = 0; k < TQL; ++k) {
-      const int idx = lane + k * kWave, r = idx / TQ, qq = idx - r * TQ;
-      const bool in = idx < n1 * TQ && qq < tq;
-      tv[k] = reinterpret_cast<const float4*>(tm)[in ? r * tq + qq : 0];
+      const int idx = lane + k * kWave, r = idx / TQ, qq = idx - r * TQ, c = 4 * qq;
+      const bool in = idx < n1 * TQ && c < n1;
+      const float* src = fsub + (int64_t)(in ? r : 0) * W + (in ? c : 0);
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (in) {
+        if (x0 - M + c + 3 <= W - 1) {
+          const f32x4u a = *reinterpret_cast<const f32x4u*>(src);
+          v = make_float4(a.x, a.y, a.z, a.w);
+        } else {
+          v.x = src[0];
+          if (c + 1 < n1) v.y = src[1];
+          if (c + 2 < n1) v.z = src[2];
+          if (c + 3 < n1) v.w = src[3];
+        }
+      }
+      tv[k] = make_float4(c < n1 ? v.x - fb : 0.f, c + 1 < n1 ? v.y - fb : 0.f,
+                          c + 2 < n1 ? v.z - fb : 0.f, c + 3 < n1 ? v.w - fb : 0.f);
+      if (!in) tv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 
     wave_lds_sync();   // the previous POI's LDS reads are complete
@@ -316,13 +334,11 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
 #pragma unroll
     for (int k = 0; k < TQL; ++k) {
       const int idx = lane + k * kWave, r = idx / TQ, qq = idx - r * TQ;
-      const bool in = idx < n1 * TQ && qq < tq;
-      const float4 v = in ? tv[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 v = tv[k];
       float nxt = __builtin_bit_cast(
           float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v.x), 0x130, 0xF, 0xF, true));
       if (k + 1 < TQL) {
-        const int idx1 = (k + 1) * kWave, r1 = idx1 / TQ, q1 = idx1 - r1 * TQ;
-        const float x1 = (idx1 < n1 * TQ && q1 < tq) ? tv[k + 1 < TQL ? k + 1 : k].x : 0.f;
+        const float x1 = tv[k + 1 < TQL ? k + 1 : k].x;
         const float lane0 = __builtin_bit_cast(
             float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x1), 0));
         if (lane == kWave - 1) nxt = lane0;
