@@ -144,3 +144,29 @@ def test_wide_windows_border_nan_and_ties():
     ref = oracle_search(f, f, tp, 8, 24)
     assert np.all(ref["uv"][:, 0] == -24)
     both_forms(f, f, tp, 8, 24, ref, "wide ties")
+
+
+def test_cached_reference_then_vector_alu_form():
+    """A plan that caches its reference preparation: the matrix-core search
+    reads the template from the reference image, so the cached preparation
+    holds none; switching the plan to the vector-ALU form (which reads the
+    stored template) must prepare it, and both forms give the oracle's
+    results, then the matrix-core form again."""
+    pr = dicgen.affine_pair_1024(size=160, M=10, S=8, step=9, tag=81)
+    pois = pr.pois[:: max(1, len(pr.pois) // 40)]
+    print(f"case cached reference, form switch N={len(pois)}", flush=True)
+    ref = oracle_search(pr.ref, pr.defm, pois, 10, 8)
+    plan = dic.single_pair_plan(160, 160, 10, 8, len(pois), flags=dic.FLAG_CACHE_REF_PREP)
+    F, G, Q = to_dev(pr.ref), to_dev(pr.defm), to_dev(pois)
+    t = plan.tuning
+    outs = []
+    for block in (MFMA, VALU, 4, MFMA):
+        plan.tuning = (block, t[1], t[2], t[3])
+        uv, zn, st = plan.integer_search(F, G, Q)
+        torch.cuda.synchronize()
+        got = {"uv": uv.cpu().numpy(), "zncc": zn.cpu().numpy(), "status": st.cpu().numpy()}
+        check(got, ref, f"cached/{block}")
+        outs.append(got)
+    for o in outs[1:]:
+        for k in o:
+            np.testing.assert_array_equal(o[k], outs[0][k], err_msg=k)
