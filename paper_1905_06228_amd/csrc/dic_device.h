@@ -14,6 +14,15 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// The lane index as a value the compiler cannot hoist out of a loop: the
+// lane-dependent quantities derived from it inside a persistent loop are
+// recomputed per item instead of being held (and spilled) across the loop.
+__device__ __forceinline__ int opaque_lane() {
+  int l = lane_id();
+  __asm__ volatile("" : "+v"(l));
+  return l;
+}
+
 // Next item of a work counter shared by persistent waves, the same in every
 // lane.  Every lane takes part in one atomic (lane 0 adds 1, the others 0) and
 // the wave reads lane 0's result, so no lane-dependent branch surrounds the

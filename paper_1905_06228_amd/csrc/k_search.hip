@@ -320,7 +320,8 @@ __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
         const int rr = cand / G.side, cc = cand - rr * G.side;
         const int xg = x0 + cu - G.S + cc, yg = y0 + cv - G.S + rr;
         double z;
-        rescore_wave<1>(fimg, gimg, W, x0, y0, &xg, &yg, 1, G.M, R->fbar, dfd, s1img, &z);
+        rescore_wave<1>(fimg, gimg, W, x0, y0, &xg, &yg, 1, G.M, R->fbar, dfd, s1img, &z,
+                        lane_id());
         return z;
       };
       int pick = -1;

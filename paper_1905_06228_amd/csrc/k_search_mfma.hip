@@ -16,19 +16,23 @@
 // most (terms) * 2^-24.  With Cauchy-Schwarz,
 // sum |t| |g'| <= df * sqrt(sum g'^2), the approximate coefficient of every
 // candidate is within
-//   E = kappa * sqrt(sum g'^2 / sum (g - gbar)^2)
-// of Eq. (1), kappa = 8.5e-3 covering all of the above with margin.  The
-// exact maximum therefore lies in { c : s_c + E_c >= max_k (s_k - E_k) };
-// those few candidates (about two per POI on speckle) are re-scored in FP64
-// in index order and the tie rule picks the smallest row-major index within
-// 1e-12 of the FP64 maximum: the same decision, and the same coefficient, as
-// the FP64 definition.  Window sums come from the FP64 box-sum images.
+//   kappa * sqrt(sum g'^2 / sum (g - gbar)^2) <= E
+// of Eq. (1), kappa = 8.5e-3 covering all of the above with margin and E its
+// square-root-free upper bound (Scorer below).  The exact maximum therefore
+// lies in { c : s_c + E_c >= max_k (s_k - E_k) }; those few candidates (about
+// two per POI on speckle) are re-scored in FP64 in index order and the tie
+// rule picks the smallest row-major index within 1e-12 of the FP64 maximum:
+// the same decision, and the same coefficient, as the FP64 definition.
+// Window sums come from the FP64 box-sum images.
 //
 // LDS per wave: the window in bf16 (rows padded to 16 KB + 8 elements so the
 // 16-byte reads of 8 consecutive rows hit distinct banks) and the template in
 // bf16 as two copies of dword pairs, even and odd phase, so that the 8
 // consecutive elements a lane needs for its Toeplitz column start at a dword
 // boundary in one of them (the odd copy sits 16 banks away from the even one).
+// A template row is 32 zeros, then the subset row, then zeros, 16 KB elements
+// in all; a Toeplitz read reaches up to 31 elements past its row, into the
+// next row's leading zeros (a zero tail follows the last row).
 #include "search_common.h"
 
 namespace dic {
@@ -43,30 +47,27 @@ typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
 
 constexpr float kBoundRel = 8.5e-3f;
 constexpr int kXcds = 8;   // accelerator complex dies of the MI355X
-constexpr int kMaskWords = 36;        // >= ceil(33 * 33 / 32)
-constexpr int kMaskWordsWide = 128;   // >= ceil(64 * 64 / 32)
 
 // Per-wave LDS layout for K-block count KB and subsets up to nmax wide; TT
 // tiles of 32 candidates per direction (TT = 2: the window is 32 rows and
 // columns wider).
 struct MfmaLayout {
   int wpb;     // window row pitch (bf16 elements)
-  int tpd;     // template row pitch (dwords)
-  int win, te, to, mask, edge, total;   // byte offsets / size
+  int tpd;     // template row pitch (dwords; rows overlap, see above)
+  int win, te, to, edge, total;   // byte offsets / size
 };
 
 __host__ __device__ __forceinline__ MfmaLayout mfma_layout(int KB, int nmax, int TT = 1) {
   MfmaLayout L;
   L.wpb = 16 * KB + 32 * (TT - 1) + 8;
-  L.tpd = 8 * KB + 16;
+  L.tpd = 8 * KB;
   L.win = 0;
   const int wrows = nmax + 32 * TT;
   L.te = (wrows * L.wpb * 2 + 127) / 128 * 128;
-  const int tbytes = nmax * L.tpd * 4;
+  const int tbytes = (nmax * L.tpd + 16) * 4;   // rows, then the zero tail
   // odd copy 16 banks (64 bytes) past a 128-byte boundary after the even one
   L.to = (L.te + tbytes + 127) / 128 * 128 + 64;
-  L.mask = L.to + tbytes;
-  L.edge = L.mask + (TT == 2 ? kMaskWordsWide : kMaskWords) * 4;
+  L.edge = L.to + tbytes;
   L.total = (L.edge + 64 * 4 + 15) / 16 * 16;
   return L;
 }
@@ -77,6 +78,15 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
          ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
 }
 
+// w with lane L (wave-uniform) replaced by the wave-uniform value val
+__device__ __forceinline__ uint32_t put_lane(uint32_t w, uint32_t val, int L) {
+  return __builtin_amdgcn_inverse_ballot_w64(1ull << L) ? val : w;
+}
+
+__device__ __forceinline__ float bf16_bits(uint16_t v) {
+  return __builtin_bit_cast(float, (uint32_t)v << 16);
+}
+
 __device__ __forceinline__ bf16x8 load_frag_aligned(const uint16_t* p) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
 }
@@ -84,12 +94,6 @@ __device__ __forceinline__ bf16x8 load_frag_aligned(const uint16_t* p) {
 __device__ __forceinline__ bf16x8 load_frag_dwords(const uint32_t* p) {
   const u32x4 v = {p[0], p[1], p[2], p[3]};
   return __builtin_bit_cast(bf16x8, v);
-}
-
-// bf16 element x of a template row stored as even-phase dword pairs.
-__device__ __forceinline__ float tmpl_elem(const uint32_t* row, int x) {
-  const uint32_t d = row[x >> 1];
-  return __builtin_bit_cast(float, (x & 1) ? (d & 0xffff0000u) : (d << 16));
 }
 
 // sum_r A_r B_r for tile A (dv, du in [0, 32)) and, with TWO, tile B
@@ -120,8 +124,8 @@ __device__ __forceinline__ void mfma_step(const bf16x8* a, const bf16x8* b, cons
 template <int KB, bool TWO>
 __device__ __forceinline__ void correlate_tiles(const uint16_t* win, const uint32_t* te,
                                                 const uint32_t* to, int n1, int wpb, int tpd,
-                                                f32x16& acc_a, f32x16& acc_b) {
-  const int lane = lane_id(), n = lane & 31, kg = lane >> 5;
+                                                int lane, f32x16& acc_a, f32x16& acc_b) {
+  const int n = lane & 31, kg = lane >> 5;
   const uint16_t* arow = win + n * wpb + 8 * kg;
   const int o0 = 8 * kg - n + 32;   // Toeplitz phase of tile A's column du = n
   const int o1 = o0 - 1;            // tile B: du = n + 1
@@ -157,37 +161,87 @@ __device__ __forceinline__ void correlate_tiles(const uint16_t* win, const uint3
   }
 }
 
-// Approximate coefficient of candidate (dv, du) of the window (row-major in
-// [0, side)^2) from its cross term C and the window statistics st = (mean,
-// 1/sqrt(sum (g - mean)^2)) of the box-sum pass, and its error bound E (the
-// ratio sum g'^2 / sum (g - mean)^2 is 1 + n ((mean - c0) / sd)^2); -inf for
-// an inadmissible or flat candidate.
-struct ScoreCtx {
-  int x0, y0, cu, cv, S, M, W, H, side;
-  float c0, tsum, rdf, nn;
+// Candidates of the window, (dv, du) row-major in [0, side)^2, centred at
+// (bx + du, by + dv); those in [dv_lo, dv_hi] x [du_lo, du_hi] have their
+// subset inside the image; `inside` when that is the whole window.
+struct CandBox {
+  int bx, by, side;
+  int du_lo, du_hi, dv_lo, dv_hi;
+  bool inside;
 };
 
-__device__ __forceinline__ float score_of(const ScoreCtx& q, float C, int dv, int du, float2 st,
-                                          float& E) {
-  const int dua = q.cu - q.S + du, dva = q.cv - q.S + dv;
-  bool ok = dv < q.side && du < q.side && q.x0 + dua - q.M >= 0 && q.x0 + dua + q.M <= q.W - 1 &&
-            q.y0 + dva - q.M >= 0 && q.y0 + dva + q.M <= q.H - 1 && st.y > 0.f;
-  // sum t (g - mean) = sum t (g - c0) - (mean - c0) sum t
-  const float dm = st.x - q.c0;
-  const float sc = fmaf(-dm, q.tsum, C) * st.y * q.rdf;
-  const float z = dm * st.y;
-  ok = ok && isfinite(sc);
-  E = ok ? kBoundRel * sqrtf(fmaf(q.nn * z, z, 1.f)) : 0.f;
-  return ok ? sc : -INFINITY;
+__device__ __forceinline__ CandBox cand_box(int bx, int by, int side, int M, int W, int H) {
+  CandBox c;
+  c.bx = bx;
+  c.by = by;
+  c.side = side;
+  c.du_lo = max(0, M - bx);
+  c.du_hi = min(side - 1, W - 1 - M - bx);
+  c.dv_lo = max(0, M - by);
+  c.dv_hi = min(side - 1, H - 1 - M - by);
+  c.inside = c.du_lo == 0 && c.dv_lo == 0 && c.du_hi == side - 1 && c.dv_hi == side - 1;
+  return c;
 }
 
-// Index of the box-sum pixel of candidate (dv, du), clamped into the image
-// (a clamped candidate is inadmissible and its sums are not used).
-__device__ __forceinline__ int64_t box_index(const ScoreCtx& q, int dv, int du) {
-  const int x = min(max(q.x0 + q.cu - q.S + du, 0), q.W - 1);
-  const int y = min(max(q.y0 + q.cv - q.S + dv, 0), q.H - 1);
-  return (int64_t)y * q.W + x;
+__device__ __forceinline__ bool admissible(const CandBox& c, int dv, int du) {
+  return dv >= c.dv_lo && dv <= c.dv_hi && du >= c.du_lo && du <= c.du_hi;
 }
+
+// Box-sum pixel of candidate (dv, du) of the window, clamped into the image
+// (a clamped candidate is inadmissible and its sums are not used).
+__device__ __forceinline__ int64_t box_index(const CandBox& c, int dv, int du, int W, int H) {
+  const int x = min(max(c.bx + du, 0), W - 1);
+  const int y = min(max(c.by + dv, 0), H - 1);
+  return (int64_t)y * W + x;
+}
+
+// Box-sum statistics of the 16 candidates (a0 + i, b0 + n) a lane holds in a
+// 32 x 32 tile, i = (j & 3) + 8 (j >> 2) + 4 kg; positions past the window
+// read its last row or column.
+__device__ __forceinline__ void tile_stats(const CandBox& c, const float2* __restrict__ stimg,
+                                           int W, int H, int a0, int b0, int lane, float2* out) {
+  const int n = lane & 31, kg = lane >> 5;
+  if (c.inside) {
+    const int du = min(b0 + n, c.side - 1);
+    if (a0 + 32 <= c.side) {
+      // row offsets j -> ((j & 3) + 8 (j >> 2)) W are wave-uniform
+      const float2* sb = stimg + (int64_t)(c.by + a0) * W + (c.bx + du) + 4 * kg * W;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) out[j] = sb[(int64_t)((j & 3) + 8 * (j >> 2)) * W];
+    } else {
+      const float2* sb = stimg + (int64_t)c.by * W + (c.bx + du);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int dv = min(a0 + (j & 3) + 8 * (j >> 2) + 4 * kg, c.side - 1);
+        out[j] = sb[__umul24((uint32_t)dv, (uint32_t)W)];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      out[j] = stimg[box_index(c, a0 + (j & 3) + 8 * (j >> 2) + 4 * kg, b0 + n, W, H)];
+  }
+}
+
+// Approximate coefficient of a candidate from its cross term C and the
+// window statistics st = (mean, 1/sqrt(sum (g - mean)^2)) of the box-sum
+// pass, returned as the interval [lo, hi] = coefficient -+ E that holds the
+// coefficient of Eq. (1).  E = kappa (1 + n1 |mean - c0| st.y) bounds
+// kappa sqrt(sum g'^2 / sum (g - mean)^2) = kappa sqrt(1 + n ((mean - c0) st.y)^2)
+// from above (sqrt(1 + a^2) <= 1 + |a|).  An inadmissible or flat candidate
+// gets lo = hi = -inf.
+struct Scorer {
+  float c0, tsum, rdf, kn1;   // kn1 = kappa n1
+  __device__ __forceinline__ float operator()(float C, float2 st, bool adm, float& hi) const {
+    const float dm = st.x - c0;
+    // sum t (g - mean) = sum t (g - c0) - (mean - c0) sum t
+    const float sc = fmaf(-dm, tsum, C) * st.y * rdf;
+    const float e = fmaf(kn1, fabsf(dm * st.y), kBoundRel);
+    const bool ok = adm && st.y > 0.f && isfinite(sc);
+    hi = ok ? sc + e : -INFINITY;
+    return ok ? sc - e : -INFINITY;
+  }
+};
 
 }  // namespace
 
@@ -200,34 +254,39 @@ size_t search_mfma_wave_lds(int kb, int maxM, bool wide) {
 // window fragments for 33 x 33).  TT = 2: windows of 34..64 per side, covered
 // by 2 x 2 tiles of 32 x 32 candidates at (dv, du) offsets (32a, 32b), each
 // the TT = 1 product on the window shifted by 32a rows and 32b columns.
+//
+// The candidates that may hold the maximum form a bit set in registers: word
+// 2 dv + du / 32 (bit du % 32) sits in lane (2 dv + du / 32) % 64 of word
+// register (2 dv + du / 32) / 64, so the words in register-then-lane order
+// list the candidates in index order.  A tile's ballot of its 16 candidate
+// rows gives whole words.
 template <int KB, int TT>
-__global__ void __launch_bounds__(64, 2) search_mfma_kernel(
+__global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
     DevState st, const int32_t* __restrict__ work, int64_t count, int nmax,
-    const float* __restrict__ tmpl_arena, const double* __restrict__ box,
-    const float* __restrict__ ref, const float* __restrict__ def, const int32_t* __restrict__ poi,
-    const int32_t* __restrict__ seed, int32_t* __restrict__ uv_out, float* __restrict__ zncc_out,
-    int32_t* __restrict__ status_out) {
+    const double* __restrict__ box, const float* __restrict__ ref, const float* __restrict__ def,
+    const int32_t* __restrict__ poi, const int32_t* __restrict__ seed,
+    int32_t* __restrict__ uv_out, float* __restrict__ zncc_out, int32_t* __restrict__ status_out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   const MfmaLayout Ly = mfma_layout(KB, nmax, TT);
   uint16_t* win = reinterpret_cast<uint16_t*>(lds_raw + Ly.win);
   uint32_t* te = reinterpret_cast<uint32_t*>(lds_raw + Ly.te);
   uint32_t* to = reinterpret_cast<uint32_t*>(lds_raw + Ly.to);
-  uint32_t* mask = reinterpret_cast<uint32_t*>(lds_raw + Ly.mask);
   float* edge = reinterpret_cast<float*>(lds_raw + Ly.edge);
-  const int lane = lane_id(), n = lane & 31, kg = lane >> 5;
+  const int lane0 = lane_id();
   constexpr int WC = 16 * KB + 32 * (TT - 1);   // staged window columns
   constexpr int CPR = WC / 8;                   // 8-element chunks per window row
   constexpr int NMAX = 16 * KB - 32;            // widest subset of this K-block count
   constexpr int CH = ((NMAX + 32 * TT) * CPR + kWave - 1) / kWave;   // window chunks per lane
-  constexpr int TPD = 8 * KB + 16;
+  constexpr int TPD = 8 * KB;
   constexpr int TG = (TPD - 16) / 2;   // 4-column groups of a template row past the left pad
   constexpr int TQ = NMAX / 4;         // the groups a template of this K-block count can fill
   constexpr int TQL = (NMAX * TQ + kWave - 1) / kWave;   // such groups per lane
   static_assert(TQ <= TG, "template groups exceed the row");
   const int wpb = Ly.wpb;
-  // both template copies zero, once: the 32 elements left of every row and
-  // the groups past TQ stay zero; a POI rewrites groups 0..TQ-1 of its rows
-  for (int idx = lane; idx < nmax * TPD; idx += kWave) {
+  // both template copies zero, once: the 32 elements left of every row (the
+  // previous row's zeros past its end) and the tail stay zero; a POI rewrites
+  // groups 0..TQ-1 of its rows
+  for (int idx = lane0; idx < nmax * TPD + 16; idx += kWave) {
     te[idx] = 0u;
     to[idx] = 0u;
   }
@@ -249,6 +308,7 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     step = gridDim.x;
   }
   for (; item < end; item += step) {
+    const int lane = opaque_lane(), n = lane & 31, kg = lane >> 5;
     const int g = uniform(work[item]);
     const DevPair P = st.pairs[uniform(st.poi_pair[g])];
     const RefRec* R = st.recs + g;
@@ -265,8 +325,8 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
       }
       continue;
     }
-    const int M = P.M, S = P.S, n1 = 2 * M + 1, nn = n1 * n1, side = 2 * S + 1;
-    const int W = P.width, H = P.height, K = side * side;
+    const int M = P.M, S = P.S, n1 = 2 * M + 1, side = 2 * S + 1;
+    const int W = P.width, H = P.height;
     const float* gimg = def + P.def_off;
     const float* fimg = ref + P.ref_off;
     const int64_t plane = (int64_t)W * H;
@@ -287,13 +347,12 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     const int wn = n1 + side - 1;   // real window side
     const int wrows = n1 + 32 * TT;   // staged rows (a tile reads up to 32 (TT - 1) + n1 + 31)
     const bool two = side == 33;
-    ScoreCtx q;
-    q.x0 = x0; q.y0 = y0; q.cu = cu; q.cv = cv; q.S = S; q.M = M; q.W = W; q.H = H;
-    q.side = side;
-    q.c0 = c0;
-    q.tsum = R->tsum;
-    q.rdf = (float)(1.0 / R->df);
-    q.nn = (float)nn;
+    const CandBox cb = cand_box(x0 + cu - S, y0 + cv - S, side, M, W, H);
+    Scorer sco;
+    sco.c0 = c0;
+    sco.tsum = R->tsum;
+    sco.rdf = (float)(1.0 / R->df);
+    sco.kn1 = kBoundRel * (float)n1;
 
     // 0. the template t = f - fbar of the reference subset (rounded as
     //    f - (float)fbar, the values whose sum is the record's tsum), as
@@ -327,7 +386,94 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     }
 
     wave_lds_sync();   // the previous POI's LDS reads are complete
-    // 1. template rows in bf16 after 32 zeros: element x of row r is
+    // 2. window g - c0 in bf16, chunks of 8 columns.  When the staged rows
+    //    and columns all lie in the image (the usual case) every chunk is two
+    //    16-byte loads and its values are stored as they are: rows and
+    //    columns past the real window only meet zero template entries or
+    //    candidates outside the window.  A non-finite pixel anywhere sends
+    //    the window to the checked form, which stores 0 outside the window or
+    //    the image and for non-finite pixels (their candidates are invalid by
+    //    the box sums) and clamps every element's address into the image.
+    auto store_checked = [&](int k, const float* v) {
+      const int idx = lane + k * kWave;
+      const int rr = idx / CPR, ch = idx - rr * CPR;
+      if (k < CH && rr < wrows) {
+        const int Y = wy0 + rr;
+        const bool rowok = rr < wn && Y >= 0 && Y < H;
+        float w[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int col = ch * 8 + e, X = wx0 + col;
+          const float x = v[e];
+          w[e] = (rowok && col < wn && X >= 0 && X < W && isfinite(x)) ? x - c0 : 0.f;
+        }
+        const u32x4 pk = {pack_bf16(w[0], w[1]), pack_bf16(w[2], w[3]), pack_bf16(w[4], w[5]),
+                          pack_bf16(w[6], w[7])};
+        *reinterpret_cast<u32x4*>(win + rr * wpb + ch * 8) = pk;
+      }
+    };
+    const bool interior = wx0 >= 0 && wx0 + WC <= W && wy0 >= 0 && wy0 + wrows <= H;
+    bool staged = false;
+    if (interior) {
+      // all chunks requested at once when they fit in registers (one memory
+      // round trip)
+      constexpr int CBI = CH <= 8 ? CH : 4;
+      bool bad = false;
+#pragma unroll
+      for (int k0 = 0; k0 < CH; k0 += CBI) {
+        float vw[CBI][8];
+#pragma unroll
+        for (int kk = 0; kk < CBI; ++kk) {
+          const int idx = lane + (k0 + kk) * kWave;
+          const int rr = idx / CPR, ch = idx - rr * CPR;
+          // rows past the staged ones (not stored) read the last staged row
+          const f32x4u* src = reinterpret_cast<const f32x4u*>(
+              gimg + (int64_t)(wy0 + min(rr, wrows - 1)) * W + wx0 + ch * 8);
+          const f32x4u a = src[0], b = src[1];
+          vw[kk][0] = a.x; vw[kk][1] = a.y; vw[kk][2] = a.z; vw[kk][3] = a.w;
+          vw[kk][4] = b.x; vw[kk][5] = b.y; vw[kk][6] = b.z; vw[kk][7] = b.w;
+        }
+#pragma unroll
+        for (int kk = 0; kk < CBI; ++kk) {
+          const int idx = lane + (k0 + kk) * kWave;
+          const int rr = idx / CPR, ch = idx - rr * CPR;
+          if (k0 + kk < CH && rr < wrows) {
+            float w[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              bad |= !isfinite(vw[kk][e]);
+              w[e] = vw[kk][e] - c0;
+            }
+            const u32x4 pk = {pack_bf16(w[0], w[1]), pack_bf16(w[2], w[3]),
+                              pack_bf16(w[4], w[5]), pack_bf16(w[6], w[7])};
+            *reinterpret_cast<u32x4*>(win + rr * wpb + ch * 8) = pk;
+          }
+        }
+      }
+      staged = __ballot(bad) == 0;
+    }
+    if (!staged) {
+      constexpr int CB = 4;
+#pragma unroll 1
+      for (int k0 = 0; k0 < CH; k0 += CB) {
+        float v[CB][8];
+#pragma unroll
+        for (int kk = 0; kk < CB; ++kk) {
+          const int idx = lane + (k0 + kk) * kWave;
+          const int rr = idx / CPR, ch = idx - rr * CPR;
+          const int Yc = min(max(wy0 + rr, 0), H - 1);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int Xc = min(max(wx0 + ch * 8 + e, 0), W - 1);
+            v[kk][e] = gimg[(int64_t)Yc * W + Xc];
+          }
+        }
+#pragma unroll
+        for (int kk = 0; kk < CB; ++kk) store_checked(k0 + kk, v[kk]);
+      }
+    }
+    // 1. (after the window, so the template's loads, issued first, have
+    //    arrived) template rows in bf16 after 32 zeros: element x of row r is
     //    t(r, x - 32); the even copy holds pairs (2i, 2i+1), the odd copy
     //    (2i+1, 2i+2).  A group's odd pair (3, 4) takes element 4 from the
     //    next group, which the next lane holds.
@@ -351,126 +497,57 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
         if (qq == 0) to[base - 1] = pack_bf16(0.f, v.x);
       }
     }
-    if constexpr (TT == 2) {
-      mask[lane] = 0u;
-      mask[lane + kWave] = 0u;
-    } else {
-      if (lane < kMaskWords) mask[lane] = 0u;
-    }
-    // 2. window g - c0 in bf16, CB chunks of 8 columns per lane at a time;
-    //    outside the window or the image, and non-finite pixels, are 0 (their
-    //    candidates are invalid by the box sums).  A window whose staged
-    //    rows and columns all lie in the image (the usual case) is read as
-    //    two 16-byte loads per chunk; otherwise every element's address is
-    //    clamped into the image.
-    const bool interior = wx0 >= 0 && wx0 + WC <= W && wy0 >= 0 && wy0 + wrows <= H;
-    auto store_chunk = [&](int k, const float* v) {
-      const int idx = lane + k * kWave;
-      const int rr = idx / CPR, ch = idx - rr * CPR;
-      if (k < CH && rr < wrows) {
-        const int Y = wy0 + rr;
-        const bool rowok = rr < wn && (interior || (Y >= 0 && Y < H));
-        float w[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int col = ch * 8 + e, X = wx0 + col;
-          const float x = v[e];
-          w[e] = (rowok && col < wn && (interior || (X >= 0 && X < W)) && isfinite(x)) ? x - c0
-                                                                                     : 0.f;
-        }
-        const u32x4 pk = {pack_bf16(w[0], w[1]), pack_bf16(w[2], w[3]), pack_bf16(w[4], w[5]),
-                          pack_bf16(w[6], w[7])};
-        *reinterpret_cast<u32x4*>(win + rr * wpb + ch * 8) = pk;
-      }
-    };
-    // an interior window's chunks are all requested at once when they fit in
-    // registers (one memory round trip)
-    constexpr int CBI = CH <= 8 ? CH : 4;
-    if (interior) {
-#pragma unroll
-      for (int k0 = 0; k0 < CH; k0 += CBI) {
-        float v[CBI][8];
-#pragma unroll
-        for (int kk = 0; kk < CBI; ++kk) {
-          const int idx = lane + (k0 + kk) * kWave;
-          const int rr = idx / CPR, ch = idx - rr * CPR;
-          // rows past the staged ones (not stored) read the last staged row
-          const f32x4u* src = reinterpret_cast<const f32x4u*>(
-              gimg + (int64_t)(wy0 + min(rr, wrows - 1)) * W + wx0 + ch * 8);
-          const f32x4u a = src[0], b = src[1];
-          v[kk][0] = a.x; v[kk][1] = a.y; v[kk][2] = a.z; v[kk][3] = a.w;
-          v[kk][4] = b.x; v[kk][5] = b.y; v[kk][6] = b.z; v[kk][7] = b.w;
-        }
-#pragma unroll
-        for (int kk = 0; kk < CBI; ++kk) store_chunk(k0 + kk, v[kk]);
-      }
-    } else {
-      constexpr int CB = 4;
-#pragma unroll
-      for (int k0 = 0; k0 < CH; k0 += CB) {
-        float v[CB][8];
-#pragma unroll
-        for (int kk = 0; kk < CB; ++kk) {
-          const int idx = lane + (k0 + kk) * kWave;
-          const int rr = idx / CPR, ch = idx - rr * CPR;
-          const int Yc = min(max(wy0 + rr, 0), H - 1);
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int Xc = min(max(wx0 + ch * 8 + e, 0), W - 1);
-            v[kk][e] = gimg[(int64_t)Yc * W + Xc];
-          }
-        }
-#pragma unroll
-        for (int kk = 0; kk < CB; ++kk) store_chunk(k0 + kk, v[kk]);
-      }
-    }
     wave_lds_sync();
 
-    // 3.-5. cross terms on the matrix cores, approximate coefficients and
-    //    their bounds, and the bit set of the candidates that may hold the
-    //    FP64 maximum
+    // 3.-5. cross terms on the matrix cores, the candidates' intervals, and
+    //    the bit set of those whose interval reaches the largest lower end
+    //    (the FP64 maximum is among them)
     float tau = -INFINITY;
+    uint32_t word0 = 0u, word1 = 0u;
     if constexpr (TT == 1) {
-      // 3. cross terms on the matrix cores
       f32x16 acc_a = {}, acc_b = {};
       if (two)
-        correlate_tiles<KB, true>(win, te, to, n1, wpb, TPD, acc_a, acc_b);
+        correlate_tiles<KB, true>(win, te, to, n1, wpb, TPD, lane, acc_a, acc_b);
       else
-        correlate_tiles<KB, false>(win, te, to, n1, wpb, TPD, acc_a, acc_b);
+        correlate_tiles<KB, false>(win, te, to, n1, wpb, TPD, lane, acc_a, acc_b);
       // box sums of every candidate this lane scores, requested at once: 16 of
       // tile A, then one edge candidate of tile B (lanes 0..62) or the two
       // corners (lane 63); their latency overlaps the corner sums below
       float2 sta[16];
-#pragma unroll
-      for (int j = 0; j < 16; ++j) sta[j] = stimg[box_index(q, (j & 3) + 8 * (j >> 2) + 4 * kg, n)];
+      tile_stats(cb, stimg, W, H, 0, 0, lane, sta);
       // edge candidates: lane b < 32 -> (32, b + 1); 32 <= b < 63 -> (b - 31, 32);
       // lane 63 -> corners (32, 0) and (0, 32)
       const int e0v = lane < 32 ? 32 : lane < 63 ? lane - 31 : 32;
       const int e0u = lane < 32 ? lane + 1 : lane < 63 ? 32 : 0;
       const int e1v = 0, e1u = 32;
-      const float2 ste0 = stimg[box_index(q, e0v, e0u)];
-      const float2 ste1 = stimg[box_index(q, e1v, e1u)];
-
-      // the two corners on the vector ALUs
-      float cr1 = 0.f, cr2 = 0.f;   // corners (dv, du) = (32, 0) and (0, 32)
+      float2 ste0 = make_float2(0.f, 0.f), ste1 = make_float2(0.f, 0.f);
       if (two) {
-        double s_a = 0.0, s_b = 0.0;
-        const int dr = kWave / n1, dc = kWave - dr * n1;
-        int r = lane / n1, c = lane - r * n1;
+        ste0 = stimg[box_index(cb, e0v, e0u, W, H)];
+        ste1 = stimg[box_index(cb, e1v, e1u, W, H)];
+      }
+
+      // the two corners on the vector ALUs, (32, 0) in lanes 0..31 and
+      // (0, 32) in lanes 32..63, one template column per lane: products of
+      // bf16 values are exact in FP32, and the FP32 sums stay inside the
+      // accumulation term of the bound
+      float cr1 = 0.f, cr2 = 0.f;
+      if (two) {
+        const uint16_t* tl = reinterpret_cast<const uint16_t*>(te) + 32 + n;
+        const uint16_t* wl = kg ? win + n + 32 : win + 32 * wpb + n;
+        float s = 0.f;
+        for (int c = n; c < n1; c += 32) {
 #pragma unroll 4
-        for (int k = lane; k < nn; k += kWave) {
-          const double t = (double)tmpl_elem(te + r * TPD, c + 32);
-          s_a += t * (double)__builtin_bit_cast(float, (uint32_t)win[(r + 32) * wpb + c] << 16);
-          s_b += t * (double)__builtin_bit_cast(float, (uint32_t)win[r * wpb + c + 32] << 16);
-          c += dc;
-          r += dr;
-          if (c >= n1) {
-            c -= n1;
-            ++r;
-          }
+          for (int r = 0; r < n1; ++r)
+            s = fmaf(bf16_bits(tl[r * 2 * TPD]), bf16_bits(wl[r * wpb]), s);
+          tl += 32;
+          wl += 32;
         }
-        cr1 = (float)wave_sum_dpp(s_a);
-        cr2 = (float)wave_sum_dpp(s_b);
+        s += dpp_f32<0xB1>(s);   // quad_perm [1,0,3,2]
+        s += dpp_f32<0x4E>(s);   // quad_perm [2,3,0,1]
+        s += dpp_f32<0x141>(s);  // row_half_mirror
+        s += dpp_f32<0x140>(s);  // row_mirror
+        cr1 = readlane_f32(s, 0) + readlane_f32(s, 16);
+        cr2 = readlane_f32(s, 32) + readlane_f32(s, 48);
         // tile B's edge row dv = 32 and column du = 32, one value per lane
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
@@ -481,72 +558,84 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
         wave_lds_sync();
       }
 
-      // 4. approximate coefficients, their bounds, and the threshold
-      float sa[16], ea[16];
+      // 4. the intervals and the threshold
+      float hia[16];
       float lo = -INFINITY;
+      const bool du_ok = n >= cb.du_lo && n <= cb.du_hi;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int i = (j & 3) + 8 * (j >> 2) + 4 * kg;
-        sa[j] = score_of(q, acc_a[j], i, n, sta[j], ea[j]);
-        lo = fmaxf(lo, sa[j] - ea[j]);
+        const bool adm = du_ok && i >= cb.dv_lo && i <= cb.dv_hi;
+        lo = fmaxf(lo, sco(acc_a[j], sta[j], adm, hia[j]));
       }
-      float s0 = -INFINITY, e0 = 0.f, s1 = -INFINITY, e1 = 0.f;
+      float hi0 = -INFINITY, hi1 = -INFINITY;
       if (two) {
         const float c_e0 = lane < 63 ? edge[lane] : cr1;
-        s0 = score_of(q, c_e0, e0v, e0u, ste0, e0);
-        if (lane == 63) s1 = score_of(q, cr2, e1v, e1u, ste1, e1);
-        lo = fmaxf(lo, fmaxf(s0 - e0, s1 - e1));
+        lo = fmaxf(lo, sco(c_e0, ste0, admissible(cb, e0v, e0u), hi0));
+        const float l1 = sco(cr2, ste1, lane == 63 && admissible(cb, e1v, e1u), hi1);
+        lo = fmaxf(lo, l1);
       }
       tau = wave_max_dpp(lo);
+      // 5. the bit set: rows i of tile A give words 2 i (columns 0..31);
+      //    column 32 (words 2 i + 1, bit 0) and row 32 (words 64, 65) come
+      //    from the edge candidates
       if (tau > -INFINITY) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (sa[j] + ea[j] >= tau) {
-            const int cand = ((j & 3) + 8 * (j >> 2) + 4 * kg) * side + n;
-            atomicOr(&mask[cand >> 5], 1u << (cand & 31));
-          }
-        if (s0 + e0 >= tau) {
-          const int cand = e0v * side + e0u;
-          atomicOr(&mask[cand >> 5], 1u << (cand & 31));
+        for (int j = 0; j < 16; ++j) {
+          const uint64_t bl = __ballot(hia[j] >= tau);
+          const int i0 = (j & 3) + 8 * (j >> 2);
+          word0 = put_lane(word0, (uint32_t)bl, 2 * i0);
+          word0 = put_lane(word0, (uint32_t)(bl >> 32), 2 * i0 + 8);
         }
-        if (s1 + e1 >= tau) {
-          const int cand = e1v * side + e1u;
-          atomicOr(&mask[cand >> 5], 1u << (cand & 31));
+        if (two) {
+          const uint64_t b0 = __ballot(hi0 >= tau), b1 = __ballot(hi1 >= tau);
+          // bit 31 + i: candidate (i, 32), from lane i + 31 of b0 (i >= 1)
+          // and lane 63 of b1 (i = 0)
+          const uint64_t c32 = (b0 & 0x7FFFFFFF00000000ull) | ((b1 >> 32) & 0x80000000ull);
+          if (lane & 1) word0 = (uint32_t)(c32 >> (31 + (lane >> 1))) & 1u;
+          // row 32: (32, 0) from lane 63, (32, 1..31) from lanes 0..30, (32, 32) from lane 31
+          const uint32_t r32 = ((uint32_t)b0 << 1) | (uint32_t)(b0 >> 63);
+          word1 = put_lane(word1, r32, 0);
+          word1 = put_lane(word1, ((uint32_t)b0 >> 31) & 1u, 1);
         }
       }
     } else {
-      // 2 x 2 tiles, the one holding the window centre first.  The running
-      // threshold only grows, so a tile's bits (set against the threshold
-      // after it) are a superset of those the final threshold selects; the
-      // FP64 re-score decides among them.
+      // 2 x 2 tiles in order.  The running threshold only grows, so a tile's
+      // bits (set against the threshold after it) are a superset of those the
+      // final threshold selects; the FP64 re-score decides among them.
       float lo = -INFINITY;
 #pragma unroll 1
       for (int t = 0; t < 4; ++t) {
         const int a = t >> 1, b = t & 1;
         if (32 * a >= side || 32 * b >= side) continue;
         f32x16 acc = {}, acc_unused = {};
-        correlate_tiles<KB, false>(win + 32 * a * wpb + 32 * b, te, to, n1, wpb, TPD, acc,
+        correlate_tiles<KB, false>(win + 32 * a * wpb + 32 * b, te, to, n1, wpb, TPD, lane, acc,
                                    acc_unused);
         float2 stt[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          stt[j] = stimg[box_index(q, 32 * a + (j & 3) + 8 * (j >> 2) + 4 * kg, 32 * b + n)];
-        float st_s[16], st_e[16];
+        tile_stats(cb, stimg, W, H, 32 * a, 32 * b, lane, stt);
+        float hit[16];
         float l = lo;
+        const int du = 32 * b + n;
+        const bool du_ok = du >= cb.du_lo && du <= cb.du_hi;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           const int i = 32 * a + (j & 3) + 8 * (j >> 2) + 4 * kg;
-          st_s[j] = score_of(q, acc[j], i, 32 * b + n, stt[j], st_e[j]);
-          l = fmaxf(l, st_s[j] - st_e[j]);
+          const bool adm = du_ok && i >= cb.dv_lo && i <= cb.dv_hi;
+          l = fmaxf(l, sco(acc[j], stt[j], adm, hit[j]));
         }
         lo = wave_max_dpp(l);
         if (lo > -INFINITY) {
+          // rows 32 a + i give words 64 a + 2 i + b
+          uint32_t wt = 0u;
 #pragma unroll
-          for (int j = 0; j < 16; ++j)
-            if (st_s[j] + st_e[j] >= lo) {
-              const int cand = (32 * a + (j & 3) + 8 * (j >> 2) + 4 * kg) * side + 32 * b + n;
-              atomicOr(&mask[cand >> 5], 1u << (cand & 31));
-            }
+          for (int j = 0; j < 16; ++j) {
+            const uint64_t bl = __ballot(hit[j] >= lo);
+            const int i0 = (j & 3) + 8 * (j >> 2);
+            wt = put_lane(wt, (uint32_t)bl, 2 * i0 + b);
+            wt = put_lane(wt, (uint32_t)(bl >> 32), 2 * i0 + 8 + b);
+          }
+          if (a == 0) word0 |= wt;
+          else word1 |= wt;
         }
       }
       tau = lo;
@@ -556,97 +645,94 @@ __global__ void __launch_bounds__(64, 2) search_mfma_kernel(
     int pick = -1;
     double best = -INFINITY;
     if (tau > -INFINITY) {
-      wave_lds_sync();
-      constexpr int kHalves = TT == 2 ? 2 : 1;   // mask words per lane
-      const int words = (K + 31) / 32;
-      uint32_t myword[kHalves];
-      uint64_t nonempty[kHalves];
+      const uint32_t myword[2] = {word0, word1};
+      uint64_t nonempty[2];
 #pragma unroll
-      for (int h = 0; h < kHalves; ++h) {
-        const int wi = kWave * h + lane;
-        myword[h] = wi < words ? mask[wi] : 0u;
-        nonempty[h] = __ballot(myword[h] != 0u);
-      }
+      for (int h = 0; h < 2; ++h) nonempty[h] = __ballot(myword[h] != 0u);
+      // candidate of bit `bits`'s lowest set bit in word 64 h + w
+      auto cand_of = [&](int h, int w, uint32_t bits) {
+        const int wi = 64 * h + w;
+        return (wi >> 1) * side + 32 * (wi & 1) + __builtin_ctz(bits);
+      };
       int count = 0, mycand = 0;
 #pragma unroll
-      for (int h = 0; h < kHalves; ++h)
+      for (int h = 0; h < 2; ++h)
         for (uint64_t ws = nonempty[h]; ws; ws &= ws - 1) {
           const int w = __builtin_ctzll(ws);
           for (uint32_t bits = (uint32_t)__builtin_amdgcn_readlane((int)myword[h], w); bits;
                bits &= bits - 1) {
-            if (lane == count) mycand = 32 * (kWave * h + w) + __builtin_ctz(bits);
+            if (lane == count) mycand = cand_of(h, w, bits);
             ++count;
           }
         }
 
-      // 6. FP64 re-score, two candidates per pass over the subset; the
-      //    first candidate in index order within 1e-12 of the maximum wins.
-      //    Members past the 64th (many exact ties) are walked in the bit set.
+      // 6. FP64 re-score of the members in index order, two per pass over the
+      //    subset (one call site, so the pass is inlined once): first all of
+      //    them, for the maximum, keeping the first 64 coefficients one per
+      //    lane; the first member within 1e-12 of the maximum wins, looked for
+      //    among those 64 and, only when none of them is, in a second sweep
+      //    over the rest (many exact ties).
       const double fbar = R->fbar, dfd = R->df;
       auto centre = [&](int cand, int& xg, int& yg) {
         const int rr = cand / side, cc = cand - rr * side;
         xg = x0 + cu - S + cc;
         yg = y0 + cv - S + rr;
       };
-      auto rescore1 = [&](int cand) -> double {
-        int xg, yg;
-        centre(cand, xg, yg);
-        double z;
-        rescore_wave<1>(fimg, gimg, W, x0, y0, &xg, &yg, 1, M, fbar, dfd, s1img, &z);
-        return z;
-      };
-      // calls fn(cand) for the members past the 64th, in index order, while it returns true
-      auto walk_rest = [&](auto&& fn) {
-        int e = 0;
+      // the e-th member (e uniform): a lane of the list, or past the 64th a
+      // walk over the bit set
+      auto nth = [&](int e) -> int {
+        if (e < kWave) return __builtin_amdgcn_readlane(mycand, e);
+        int k = 0;
 #pragma unroll
-        for (int h = 0; h < kHalves; ++h)
+        for (int h = 0; h < 2; ++h)
           for (uint64_t ws = nonempty[h]; ws; ws &= ws - 1) {
             const int w = __builtin_ctzll(ws);
             for (uint32_t bits = (uint32_t)__builtin_amdgcn_readlane((int)myword[h], w); bits;
-                 bits &= bits - 1, ++e)
-              if (e >= kWave && !fn(32 * (kWave * h + w) + __builtin_ctz(bits))) return;
+                 bits &= bits - 1, ++k)
+              if (k == e) return cand_of(h, w, bits);
           }
+        return 0;
       };
       const int listed = min(count, kWave);
       double keep = -INFINITY, cmax = -INFINITY;
-      constexpr int kB = 2;
-      for (int e0 = 0; e0 < listed; e0 += kB) {
-        const int nb = min(kB, listed - e0);
-        int xs[kB], ys[kB];
-#pragma unroll
-        for (int b = 0; b < kB; ++b)
-          centre(__builtin_amdgcn_readlane(mycand, e0 + min(b, nb - 1)), xs[b], ys[b]);
-        double z[kB];
-        rescore_wave<kB>(fimg, gimg, W, x0, y0, xs, ys, nb, M, fbar, dfd, s1img, z);
-#pragma unroll
-        for (int b = 0; b < kB; ++b)
-          if (b < nb) {
-            if (lane == e0 + b) keep = z[b];
-            cmax = fmax(cmax, z[b]);
+      bool sweep = false;   // second sweep: members past the 64th, for the first near-maximum
+      for (int e = 0;;) {
+        if (!sweep && e >= count) {
+          if (cmax == -INFINITY) break;
+          const uint64_t hit = __ballot(lane < listed && keep >= cmax - 1e-12);
+          if (hit) {
+            const int h = __builtin_ctzll(hit);
+            pick = __builtin_amdgcn_readlane(mycand, h);
+            best = readlane_f64(keep, h);
+            break;
           }
-      }
-      if (count > listed)
-        walk_rest([&](int cand) {
-          cmax = fmax(cmax, rescore1(cand));
-          return true;
-        });
-      if (cmax > -INFINITY) {
-        const uint64_t hit = __ballot(lane < listed && keep >= cmax - 1e-12);
-        if (hit) {
-          const int e = __builtin_ctzll(hit);
-          pick = __builtin_amdgcn_readlane(mycand, e);
-          best = readlane_f64(keep, e);
-        } else {
-          walk_rest([&](int cand) {
-            const double z = rescore1(cand);
-            if (z >= cmax - 1e-12) {
-              pick = cand;
-              best = z;
-              return false;
-            }
-            return true;
-          });
+          sweep = true;
+          e = kWave;
         }
+        if (e >= count) break;
+        const int nb = min(2, count - e);
+        int xs[2], ys[2];
+        centre(nth(e), xs[0], ys[0]);
+        centre(nth(e + nb - 1), xs[1], ys[1]);
+        double z[2];
+        rescore_wave<2>(fimg, gimg, W, x0, y0, xs, ys, nb, M, fbar, dfd, s1img, z, lane);
+        if (!sweep) {
+          if (lane == e) keep = z[0];
+          cmax = fmax(cmax, z[0]);
+          if (nb == 2) {
+            if (lane == e + 1) keep = z[1];
+            cmax = fmax(cmax, z[1]);
+          }
+        } else if (z[0] >= cmax - 1e-12) {
+          pick = nth(e);
+          best = z[0];
+          break;
+        } else if (nb == 2 && z[1] >= cmax - 1e-12) {
+          pick = nth(e + 1);
+          best = z[1];
+          break;
+        }
+        e += nb;
       }
     }
     if (lane == 0) {
@@ -688,8 +774,8 @@ static hipError_t launch_search_mfma_kb(const DevState& st, const SearchGroup& g
   if (blocks > gr.count) blocks = gr.count;
   if (blocks >= kXcds) blocks -= blocks % kXcds;
   hipLaunchKernelGGL((search_mfma_kernel<KB, TT>), dim3((unsigned)blocks), dim3(kWave), lds, s,
-                     st, st.work + gr.begin, gr.count, nmax, st.tmpl, st.box, ref, def, poi, seed,
-                     uv, zncc, status);
+                     st, st.work + gr.begin, gr.count, nmax, st.box, ref, def, poi, seed, uv,
+                     zncc, status);
   return hipGetLastError();
 }
 
