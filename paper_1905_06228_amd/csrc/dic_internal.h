@@ -109,7 +109,14 @@ __host__ __device__ constexpr int refine_slots(int M) {
          : ((2 * M + 1) * (2 * M + 1) + 63) / 64 <= 20 ? 20
                                                        : 28;
 }
-__host__ __device__ constexpr bool refine_two_rows(int M) { return M == 14 || M == 15; }
+// The two-rows layout serves M = kR2MinM and kR2MinM + 1.
+constexpr int kR2MinM = 14;
+__host__ __device__ constexpr bool refine_two_rows(int M) { return M == kR2MinM || M == kR2MinM + 1; }
+// The fewest slots a subset of the maxs-slot class fills: one more than the
+// next smaller class holds.  Slots below it need no per-slot test.
+__host__ __device__ constexpr int refine_min_slots(int maxs) {
+  return maxs <= 4 ? 1 : maxs <= 8 ? 5 : maxs <= 12 ? 9 : maxs <= 16 ? 13 : maxs <= 20 ? 17 : 21;
+}
 // the refinement kernel a radius runs in (slots and layout)
 __host__ __device__ constexpr int refine_class(int M) {
   return 2 * refine_slots(M) + (refine_two_rows(M) ? 1 : 0);

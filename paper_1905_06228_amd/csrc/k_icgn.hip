@@ -27,14 +27,18 @@ template <int MAXS, class Smp>
 __device__ __forceinline__ void iter_pass(const Smp& smp, int n, const Warp32& w,
                                           const float* fxs, const float* fys, const half2v* dxy,
                                           float* K) {
+  constexpr int MINS = refine_min_slots(MAXS);
   const Slots sl(n);
 #pragma unroll
   for (int a = 0; a < 8; ++a) K[a] = 0.f;
 #pragma unroll
   for (int k = 0; k < MAXS; ++k) {
-    if (!sl.used(k)) continue;
+    // slots every subset of the class fills run without a test, so the
+    // reads of consecutive slots can overlap
+    if (k >= MINS && !sl.used(k)) continue;
     const float dx = (float)dxy[k].x, dy = (float)dxy[k].y;
-    const float gs = sl.mask(k, sample_value(smp, warp_x(w, dx, dy), warp_y(w, dx, dy)));
+    const float v = sample_value(smp, warp_x(w, dx, dy), warp_y(w, dx, dy));
+    const float gs = k + 1 >= MINS ? sl.mask(k, v) : v;
     const float fg = fxs[k] * gs, hg = fys[k] * gs;
     K[0] += gs;
     K[1] = fmaf(gs, gs, K[1]);
@@ -56,11 +60,8 @@ __device__ __forceinline__ void iter_pass_r2(const Smp& smp, int M, const R2Lane
   const float bx = fmaf(w.ax, L.dx, fmaf(w.uy, L.hm, w.uf));
   const float by = fmaf(w.vx, L.dx, fmaf(w.ay, L.hm, w.vf));
   float k0 = 0.f, k1 = 0.f, k2 = 0.f, k4 = 0.f, k5 = 0.f, k7 = 0.f;
-#pragma unroll
-  for (int k = 0; k < MAXS - 1; ++k) {
-    if (k >= Mu) continue;
+  const auto add = [&](int k, float gs) {
     const float dk = (float)(2 * k);
-    const float gs = sample_value(smp, fmaf(w.uy, dk, bx), fmaf(w.ay, dk, by));
     const float fg = fxs[k] * gs, hg = fys[k] * gs;
     k0 += gs;
     k1 = fmaf(gs, gs, k1);
@@ -68,6 +69,30 @@ __device__ __forceinline__ void iter_pass_r2(const Smp& smp, int M, const R2Lane
     k4 = fmaf(fg, dk, k4);
     k5 += hg;
     k7 = fmaf(hg, dk, k7);
+  };
+  const auto pos_x = [&](int k) { return fmaf(w.uy, (float)(2 * k), bx); };
+  const auto pos_y = [&](int k) { return fmaf(w.ay, (float)(2 * k), by); };
+  if constexpr (!Smp::kLut) {
+    // slots below kR2MinM always hold samples: software-pipelined, the taps
+    // of slot k + 1 requested before slot k's are combined (the scheduling
+    // barrier keeps that order, so the reads' latency overlaps the work)
+    using TS = TapSet<Smp::ntaps()>;
+    TS ta = taps_fetch(smp, pos_x(0), pos_y(0)), tb;
+#pragma unroll
+    for (int k = 0; k < kR2MinM; ++k) {
+      TS& cur = (k & 1) ? tb : ta;
+      TS& nxt = (k & 1) ? ta : tb;
+      if (k + 1 < kR2MinM) nxt = taps_fetch(smp, pos_x(k + 1), pos_y(k + 1));
+      __builtin_amdgcn_sched_barrier(0);
+      add(k, taps_combine(cur));
+    }
+#pragma unroll
+    for (int k = kR2MinM; k < MAXS - 1; ++k)
+      if (k < Mu) add(k, sample_value(smp, pos_x(k), pos_y(k)));
+  } else {
+#pragma unroll
+    for (int k = 0; k < MAXS - 1; ++k)
+      if (k < kR2MinM || k < Mu) add(k, sample_value(smp, pos_x(k), pos_y(k)));
   }
   {
     // the last row (offset M), read by both half-waves at the lower one's

@@ -42,15 +42,19 @@ __device__ __forceinline__ void nr_pass(const Smp& smp, int n, const Warp32& w, 
   for (int a = 0; a < 21; ++a) A.JJ[a] = 0.f;
 #pragma unroll
   for (int k = 0; k < MAXS; ++k) {
-    if (!sl.used(k)) continue;
+    // slots every subset of the class fills run without a test
+    if (k >= refine_min_slots(MAXS) && !sl.used(k)) continue;
     const float dx = (float)dxy[k].x, dy = (float)dxy[k].y;
     float v, gx, gy;
     sample_value_grad(smp, warp_x(w, dx, dy), warp_y(w, dx, dy), v, gx, gy);
     // a missing sample of the partial slot has zero template value and
     // offsets; zeroing its value and gradient removes it from every sum
-    const float gs = sl.mask(k, v);
-    gx = sl.mask(k, gx);
-    gy = sl.mask(k, gy);
+    const bool may_miss = k + 1 >= refine_min_slots(MAXS);   // the partial slot or later
+    const float gs = may_miss ? sl.mask(k, v) : v;
+    if (may_miss) {
+      gx = sl.mask(k, gx);
+      gy = sl.mask(k, gy);
+    }
     const float t = tv[k];
     const float J[6] = {gx, gx * dx, gx * dy, gy, gy * dx, gy * dy};
     A.g += gs;
@@ -118,7 +122,7 @@ __device__ __forceinline__ void nr_pass_r2(const Smp& smp, int M, const R2Lane& 
   };
 #pragma unroll
   for (int k = 0; k < MAXS - 1; ++k) {
-    if (k >= Mu) continue;
+    if (k >= kR2MinM && k >= Mu) continue;   // slots below kR2MinM always hold samples
     const float dk = (float)(2 * k);
     float v, gx, gy;
     sample_value_grad(smp, fmaf(w.uy, dk, bx), fmaf(w.ay, dk, by), v, gx, gy);

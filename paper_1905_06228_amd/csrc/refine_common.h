@@ -330,6 +330,42 @@ __device__ __forceinline__ float sample_value(const Smp& smp, float xs, float ys
   }
 }
 
+// sample_value split in two for software pipelining: the taps and weights of
+// one sample fetched ahead, and their combination later (the same
+// arithmetic in the same order).
+template <int NT>
+struct TapSet {
+  float t[NT * NT];
+  float wx[NT], wy[NT];
+};
+
+template <class Smp>
+__device__ __forceinline__ TapSet<Smp::ntaps()> taps_fetch(const Smp& smp, float xs, float ys) {
+  constexpr int NT = Smp::ntaps();
+  TapSet<NT> s;
+  float tx, ty;
+  const float* q = smp.taps(xs, ys, s.wx, s.wy, tx, ty);
+  const int P = smp.pitch();
+#pragma unroll
+  for (int l = 0; l < NT; ++l)
+#pragma unroll
+    for (int c = 0; c < NT; ++c) s.t[l * NT + c] = smp.tap(q + l * P + c);
+  return s;
+}
+
+template <int NT>
+__device__ __forceinline__ float taps_combine(const TapSet<NT>& s) {
+  float acc = 0.f;
+#pragma unroll
+  for (int l = 0; l < NT; ++l) {
+    float r = s.wx[0] * s.t[l * NT];
+#pragma unroll
+    for (int k = 1; k < NT; ++k) r = fmaf(s.wx[k], s.t[l * NT + k], r);
+    acc = l == 0 ? s.wy[0] * r : fmaf(s.wy[l], r, acc);
+  }
+  return acc;
+}
+
 // g - c0 and the interpolant's gradient (d/dx, d/dy) at local offset (xs, ys).
 template <class Smp>
 __device__ __forceinline__ void sample_value_grad(const Smp& smp, float xs, float ys, float& v,
@@ -413,19 +449,30 @@ struct Slots {
 // Sums over this lane's samples at the final warp: sum (g - c0),
 // sum (g - c0)^2 and sum (f - fbar)(g - c0), with f - fbar of slot k at
 // offsets (dx, dy) given by tval(k, dx, dy).
+// The template values are all requested before the sampling (one memory
+// round trip), and the slots every subset of the class fills run without a
+// per-slot test, so their reads can overlap.
 template <int MAXS, class Smp, class TV>
 __device__ __forceinline__ void final_pass(const Smp& smp, int n, const Warp32& w,
                                            const half2v* dxy, const TV& tval, float* K) {
+  constexpr int MINS = refine_min_slots(MAXS);
   const Slots sl(n);
+  float tv[MAXS];
+#pragma unroll
+  for (int k = 0; k < MAXS; ++k) {
+    tv[k] = 0.f;
+    if (k < MINS || sl.used(k)) tv[k] = tval(k, (float)dxy[k].x, (float)dxy[k].y);
+  }
   K[0] = K[1] = K[2] = 0.f;
 #pragma unroll
   for (int k = 0; k < MAXS; ++k) {
-    if (!sl.used(k)) continue;
+    if (k >= MINS && !sl.used(k)) continue;
     const float dx = (float)dxy[k].x, dy = (float)dxy[k].y;
-    const float gs = sl.mask(k, sample_value(smp, warp_x(w, dx, dy), warp_y(w, dx, dy)));
+    const float v = sample_value(smp, warp_x(w, dx, dy), warp_y(w, dx, dy));
+    const float gs = k + 1 >= MINS ? sl.mask(k, v) : v;
     K[0] += gs;
     K[1] = fmaf(gs, gs, K[1]);
-    K[2] = fmaf(tval(k, dx, dy), gs, K[2]);
+    K[2] = fmaf(tv[k], gs, K[2]);
   }
 }
 
@@ -498,24 +545,33 @@ __device__ __forceinline__ void final_pass_r2(const Smp& smp, int M, const R2Lan
   const int Mu = __builtin_amdgcn_readfirstlane(M);
   const float bx = fmaf(w.ax, L.dx, fmaf(w.uy, L.hm, w.uf));
   const float by = fmaf(w.vx, L.dx, fmaf(w.ay, L.hm, w.vf));
+  // the template values first (one memory round trip); slots below kR2MinM
+  // hold samples for every subset of the layout, so they need no test
+  float tv[MAXS - 1];
+#pragma unroll
+  for (int k = 0; k < MAXS - 1; ++k) {
+    tv[k] = 0.f;
+    if (k < kR2MinM || k < Mu) tv[k] = tval(0, L.dx, (float)(2 * k) + L.hm);
+  }
+  const float dm = (float)Mu;
+  const float tvm = tval(0, L.dx, dm);
   float k0 = 0.f, k1 = 0.f, k2 = 0.f;
 #pragma unroll
   for (int k = 0; k < MAXS - 1; ++k) {
-    if (k >= Mu) continue;
+    if (k >= kR2MinM && k >= Mu) continue;
     const float dk = (float)(2 * k);
     const float gs = sample_value(smp, fmaf(w.uy, dk, bx), fmaf(w.ay, dk, by));
     k0 += gs;
     k1 = fmaf(gs, gs, k1);
-    k2 = fmaf(tval(0, L.dx, dk + L.hm), gs, k2);
+    k2 = fmaf(tv[k], gs, k2);
   }
   {
-    const float dm = (float)Mu;
     const float v = sample_value(smp, fmaf(w.ax, L.dx, fmaf(w.uy, dm, w.uf)),
                                  fmaf(w.vx, L.dx, fmaf(w.ay, dm, w.vf)));
     const float gs = L.upper ? 0.f : v;
     k0 += gs;
     k1 = fmaf(gs, gs, k1);
-    k2 = fmaf(tval(0, L.dx, dm), gs, k2);
+    k2 = fmaf(tvm, gs, k2);
   }
   K[0] = L.colok ? k0 : 0.f;
   K[1] = L.colok ? k1 : 0.f;
