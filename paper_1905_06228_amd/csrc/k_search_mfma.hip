@@ -49,8 +49,8 @@ constexpr float kBoundRel = 8.5e-3f;
 constexpr int kXcds = 8;   // accelerator complex dies of the MI355X
 
 // Per-wave LDS layout for K-block count KB and subsets up to nmax wide; TT
-// tiles of 32 candidates per direction (TT = 2: the window is 32 rows and
-// columns wider).
+// tiles of 32 candidates per direction (TT = 2: the window is 32 columns
+// wider; the rows of one tile row of candidates are staged at a time).
 struct MfmaLayout {
   int wpb;     // window row pitch (bf16 elements)
   int tpd;     // template row pitch (dwords; rows overlap, see above)
@@ -62,7 +62,7 @@ __host__ __device__ __forceinline__ MfmaLayout mfma_layout(int KB, int nmax, int
   L.wpb = 16 * KB + 32 * (TT - 1) + 8;
   L.tpd = 8 * KB;
   L.win = 0;
-  const int wrows = nmax + 32 * TT;
+  const int wrows = nmax + 32;   // one tile row of candidates (see the kernel)
   L.te = (wrows * L.wpb * 2 + 127) / 128 * 128;
   const int tbytes = (nmax * L.tpd + 16) * 4;   // rows, then the zero tail
   // odd copy 16 banks (64 bytes) past a 128-byte boundary after the even one
@@ -253,7 +253,9 @@ size_t search_mfma_wave_lds(int kb, int maxM, bool wide) {
 // TT = 1: windows up to 33 x 33 candidates (one tile, or two sharing their
 // window fragments for 33 x 33).  TT = 2: windows of 34..64 per side, covered
 // by 2 x 2 tiles of 32 x 32 candidates at (dv, du) offsets (32a, 32b), each
-// the TT = 1 product on the window shifted by 32a rows and 32b columns.
+// the TT = 1 product on the window shifted by 32a rows and 32b columns; the
+// window rows of tile row a = 1 replace those of a = 0 in LDS when its
+// first tile starts, so a wave holds n1 + 32 rows, not n1 + 64.
 //
 // The candidates that may hold the maximum form a bit set in registers: word
 // 2 dv + du / 32 (bit du % 32) sits in lane (2 dv + du / 32) % 64 of word
@@ -276,7 +278,7 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
   constexpr int WC = 16 * KB + 32 * (TT - 1);   // staged window columns
   constexpr int CPR = WC / 8;                   // 8-element chunks per window row
   constexpr int NMAX = 16 * KB - 32;            // widest subset of this K-block count
-  constexpr int CH = ((NMAX + 32 * TT) * CPR + kWave - 1) / kWave;   // window chunks per lane
+  constexpr int CH = ((NMAX + 32) * CPR + kWave - 1) / kWave;   // window chunks per lane
   constexpr int TPD = 8 * KB;
   constexpr int TG = (TPD - 16) / 2;   // 4-column groups of a template row past the left pad
   constexpr int TQ = NMAX / 4;         // the groups a template of this K-block count can fill
@@ -345,7 +347,9 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
     }
     const int wx0 = x0 + cu - S - M, wy0 = y0 + cv - S - M;
     const int wn = n1 + side - 1;   // real window side
-    const int wrows = n1 + 32 * TT;   // staged rows (a tile reads up to 32 (TT - 1) + n1 + 31)
+    // staged rows: those of one tile row of candidates (a tile reads n1 + 31);
+    // the 2 x 2 form stages the second tile row's rows when it gets there
+    const int wrows = n1 + 32;
     const bool two = side == 33;
     const CandBox cb = cand_box(x0 + cu - S, y0 + cv - S, side, M, W, H);
     Scorer sco;
@@ -394,84 +398,89 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
     //    the window to the checked form, which stores 0 outside the window or
     //    the image and for non-finite pixels (their candidates are invalid by
     //    the box sums) and clamps every element's address into the image.
-    auto store_checked = [&](int k, const float* v) {
-      const int idx = lane + k * kWave;
-      const int rr = idx / CPR, ch = idx - rr * CPR;
-      if (k < CH && rr < wrows) {
-        const int Y = wy0 + rr;
-        const bool rowok = rr < wn && Y >= 0 && Y < H;
-        float w[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int col = ch * 8 + e, X = wx0 + col;
-          const float x = v[e];
-          w[e] = (rowok && col < wn && X >= 0 && X < W && isfinite(x)) ? x - c0 : 0.f;
-        }
-        const u32x4 pk = {pack_bf16(w[0], w[1]), pack_bf16(w[2], w[3]), pack_bf16(w[4], w[5]),
-                          pack_bf16(w[6], w[7])};
-        *reinterpret_cast<u32x4*>(win + rr * wpb + ch * 8) = pk;
-      }
-    };
-    const bool interior = wx0 >= 0 && wx0 + WC <= W && wy0 >= 0 && wy0 + wrows <= H;
-    bool staged = false;
-    if (interior) {
-      // all chunks requested at once when they fit in registers (one memory
-      // round trip)
-      constexpr int CBI = CH <= 8 ? CH : 4;
-      bool bad = false;
-#pragma unroll
-      for (int k0 = 0; k0 < CH; k0 += CBI) {
-        float vw[CBI][8];
-#pragma unroll
-        for (int kk = 0; kk < CBI; ++kk) {
-          const int idx = lane + (k0 + kk) * kWave;
-          const int rr = idx / CPR, ch = idx - rr * CPR;
-          // rows past the staged ones (not stored) read the last staged row
-          const f32x4u* src = reinterpret_cast<const f32x4u*>(
-              gimg + (int64_t)(wy0 + min(rr, wrows - 1)) * W + wx0 + ch * 8);
-          const f32x4u a = src[0], b = src[1];
-          vw[kk][0] = a.x; vw[kk][1] = a.y; vw[kk][2] = a.z; vw[kk][3] = a.w;
-          vw[kk][4] = b.x; vw[kk][5] = b.y; vw[kk][6] = b.z; vw[kk][7] = b.w;
-        }
-#pragma unroll
-        for (int kk = 0; kk < CBI; ++kk) {
-          const int idx = lane + (k0 + kk) * kWave;
-          const int rr = idx / CPR, ch = idx - rr * CPR;
-          if (k0 + kk < CH && rr < wrows) {
-            float w[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              bad |= !isfinite(vw[kk][e]);
-              w[e] = vw[kk][e] - c0;
-            }
-            const u32x4 pk = {pack_bf16(w[0], w[1]), pack_bf16(w[2], w[3]),
-                              pack_bf16(w[4], w[5]), pack_bf16(w[6], w[7])};
-            *reinterpret_cast<u32x4*>(win + rr * wpb + ch * 8) = pk;
-          }
-        }
-      }
-      staged = __ballot(bad) == 0;
-    }
-    if (!staged) {
-      constexpr int CB = 4;
-#pragma unroll 1
-      for (int k0 = 0; k0 < CH; k0 += CB) {
-        float v[CB][8];
-#pragma unroll
-        for (int kk = 0; kk < CB; ++kk) {
-          const int idx = lane + (k0 + kk) * kWave;
-          const int rr = idx / CPR, ch = idx - rr * CPR;
-          const int Yc = min(max(wy0 + rr, 0), H - 1);
+    //    The window rows r0 .. r0 + wrows - 1 go to LDS rows 0 ..
+    auto stage_window = [&](int r0) {
+      const int wy = wy0 + r0;
+      auto store_checked = [&](int k, const float* v) {
+        const int idx = lane + k * kWave;
+        const int rr = idx / CPR, ch = idx - rr * CPR;
+        if (k < CH && rr < wrows) {
+          const int Y = wy + rr;
+          const bool rowok = r0 + rr < wn && Y >= 0 && Y < H;
+          float w[8];
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
-            const int Xc = min(max(wx0 + ch * 8 + e, 0), W - 1);
-            v[kk][e] = gimg[(int64_t)Yc * W + Xc];
+            const int col = ch * 8 + e, X = wx0 + col;
+            const float x = v[e];
+            w[e] = (rowok && col < wn && X >= 0 && X < W && isfinite(x)) ? x - c0 : 0.f;
+          }
+          const u32x4 pk = {pack_bf16(w[0], w[1]), pack_bf16(w[2], w[3]),
+                            pack_bf16(w[4], w[5]), pack_bf16(w[6], w[7])};
+          *reinterpret_cast<u32x4*>(win + rr * wpb + ch * 8) = pk;
+        }
+      };
+      const bool interior = wx0 >= 0 && wx0 + WC <= W && wy >= 0 && wy + wrows <= H;
+      bool staged = false;
+      if (interior) {
+        // all chunks requested at once when they fit in registers (one memory
+        // round trip)
+        constexpr int CBI = CH <= 8 ? CH : 4;
+        bool bad = false;
+#pragma unroll
+        for (int k0 = 0; k0 < CH; k0 += CBI) {
+          float vw[CBI][8];
+#pragma unroll
+          for (int kk = 0; kk < CBI; ++kk) {
+            const int idx = lane + (k0 + kk) * kWave;
+            const int rr = idx / CPR, ch = idx - rr * CPR;
+            // rows past the staged ones (not stored) read the last staged row
+            const f32x4u* src = reinterpret_cast<const f32x4u*>(
+                gimg + (int64_t)(wy + min(rr, wrows - 1)) * W + wx0 + ch * 8);
+            const f32x4u a = src[0], b = src[1];
+            vw[kk][0] = a.x; vw[kk][1] = a.y; vw[kk][2] = a.z; vw[kk][3] = a.w;
+            vw[kk][4] = b.x; vw[kk][5] = b.y; vw[kk][6] = b.z; vw[kk][7] = b.w;
+          }
+#pragma unroll
+          for (int kk = 0; kk < CBI; ++kk) {
+            const int idx = lane + (k0 + kk) * kWave;
+            const int rr = idx / CPR, ch = idx - rr * CPR;
+            if (k0 + kk < CH && rr < wrows) {
+              float w[8];
+#pragma unroll
+              for (int e = 0; e < 8; ++e) {
+                bad |= !isfinite(vw[kk][e]);
+                w[e] = vw[kk][e] - c0;
+              }
+              const u32x4 pk = {pack_bf16(w[0], w[1]), pack_bf16(w[2], w[3]),
+                                pack_bf16(w[4], w[5]), pack_bf16(w[6], w[7])};
+              *reinterpret_cast<u32x4*>(win + rr * wpb + ch * 8) = pk;
+            }
           }
         }
-#pragma unroll
-        for (int kk = 0; kk < CB; ++kk) store_checked(k0 + kk, v[kk]);
+        staged = __ballot(bad) == 0;
       }
-    }
+      if (!staged) {
+        constexpr int CB = 4;
+#pragma unroll 1
+        for (int k0 = 0; k0 < CH; k0 += CB) {
+          float v[CB][8];
+#pragma unroll
+          for (int kk = 0; kk < CB; ++kk) {
+            const int idx = lane + (k0 + kk) * kWave;
+            const int rr = idx / CPR, ch = idx - rr * CPR;
+            const int Yc = min(max(wy + rr, 0), H - 1);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int Xc = min(max(wx0 + ch * 8 + e, 0), W - 1);
+              v[kk][e] = gimg[(int64_t)Yc * W + Xc];
+            }
+          }
+#pragma unroll
+          for (int kk = 0; kk < CB; ++kk) store_checked(k0 + kk, v[kk]);
+        }
+      }
+    };
+    stage_window(0);
     // 1. (after the window, so the template's loads, issued first, have
     //    arrived) template rows in bf16 after 32 zeros: element x of row r is
     //    t(r, x - 32); the even copy holds pairs (2i, 2i+1), the odd copy
@@ -608,9 +617,14 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
       for (int t = 0; t < 4; ++t) {
         const int a = t >> 1, b = t & 1;
         if (32 * a >= side || 32 * b >= side) continue;
+        if (a == 1 && b == 0) {
+          // the second tile row's window rows, over the first's
+          wave_lds_sync();
+          stage_window(32);
+          wave_lds_sync();
+        }
         f32x16 acc = {}, acc_unused = {};
-        correlate_tiles<KB, false>(win + 32 * a * wpb + 32 * b, te, to, n1, wpb, TPD, lane, acc,
-                                   acc_unused);
+        correlate_tiles<KB, false>(win + 32 * b, te, to, n1, wpb, TPD, lane, acc, acc_unused);
         float2 stt[16];
         tile_stats(cb, stimg, W, H, 32 * a, 32 * b, lane, stt);
         float hit[16];
