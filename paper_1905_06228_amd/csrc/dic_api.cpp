@@ -108,6 +108,9 @@ struct dic_plan_s {
   // reference-side one (forked from and joined back to the caller's stream)
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // the reference side's statistics done (main stream), and its Hessian part
+  // done (side stream, beside the search)
+  hipEvent_t ev_stats = nullptr, ev_ref = nullptr;
 
   bool fp32() const { return desc.precision == DIC_FP32_BATCHED; }
   bool det() const { return (desc.flags & DIC_FLAG_DETERMINISTIC_BWD) != 0; }
@@ -268,22 +271,29 @@ dic_status_t attach_workspace(dic_plan_t p, void* ws, hipStream_t s) {
 // vector-ALU search form (which reads it) may run: its tuning, or `tmpl`
 // (the autotuner, which tries every form); a cached preparation without it
 // is redone when a form that needs it comes.
+bool ref_cached(const dic_plan_s* p, const float* ref, const int32_t* poi, bool need_tmpl) {
+  return (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->ref_valid && p->ref_img == ref &&
+         p->ref_poi == poi && (p->ref_tmpl || !need_tmpl || !p->fp32());
+}
+
+void mark_ref(dic_plan_t p, const float* ref, const int32_t* poi, bool need_tmpl) {
+  p->ref_valid = true;
+  p->ref_tmpl = need_tmpl;
+  p->ref_img = ref;
+  p->ref_poi = poi;
+}
+
 dic_status_t prepare(dic_plan_t p, const float* ref, const int32_t* poi, hipStream_t s,
                      bool force, bool tmpl = false) {
   const bool need_tmpl = tmpl || p->tuning.search_block != kMfmaBlock;
-  if (!force && (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->ref_valid && p->ref_img == ref &&
-      p->ref_poi == poi && (p->ref_tmpl || !need_tmpl || !p->fp32()))
-    return DIC_SUCCESS;
+  if (!force && ref_cached(p, ref, poi, need_tmpl)) return DIC_SUCCESS;
   if (p->fp32()) {
     DIC_HIP(launch_gradients(p->st, ref, s));
     DIC_HIP(launch_ref_prep_f32(p->st, ref, poi, need_tmpl, s));
   } else {
     DIC_HIP(launch_ref_prep_f64(p->st, p->dpairs.data(), ref, poi, s));
   }
-  p->ref_valid = true;
-  p->ref_tmpl = need_tmpl;
-  p->ref_img = ref;
-  p->ref_poi = poi;
+  mark_ref(p, ref, poi, need_tmpl);
   return DIC_SUCCESS;
 }
 
@@ -397,8 +407,12 @@ struct CorrArgs {
 
 // Search then refine.  In the FP32 form the deformed-side box sums and the
 // interpolation table or B-spline coefficients (when not cached) run on the
-// plan's side stream beside the reference-side preparation: the two read
-// different images and write different sections.
+// plan's side stream beside the reference side's statistics: the two read
+// different images and write different sections.  The reference side's
+// gradients, Hessian and factor, which only the refinement reads, then run
+// on the side stream beside the search (enqueued after it, so the search's
+// waves take the device first and the preparation fills what they leave);
+// the refinement waits for them.
 // With `allow_fork` false everything runs in order on `s` (no side stream is
 // created or used).
 dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s,
@@ -406,10 +420,14 @@ dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s,
   const bool fork = allow_fork && p->fp32() &&
                     !((p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->def_valid &&
                       p->def_img == a.def);
+  const bool need_tmpl = p->tuning.search_block != kMfmaBlock;
+  const bool split = fork && !ref_cached(p, a.ref, a.poi, need_tmpl);
   if (fork) {
     if (!p->side_stream) DIC_HIP(hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking));
     if (!p->ev_fork) DIC_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
     if (!p->ev_join) DIC_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+    if (!p->ev_stats) DIC_HIP(hipEventCreateWithFlags(&p->ev_stats, hipEventDisableTiming));
+    if (!p->ev_ref) DIC_HIP(hipEventCreateWithFlags(&p->ev_ref, hipEventDisableTiming));
     DIC_HIP(hipEventRecord(p->ev_fork, s));
     DIC_HIP(hipStreamWaitEvent(p->side_stream, p->ev_fork, 0));
     // the deformed side: box sums, then the refinement's coefficient table
@@ -419,11 +437,25 @@ dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s,
     if (r != DIC_SUCCESS) return r;
     DIC_HIP(hipEventRecord(p->ev_join, p->side_stream));
   }
-  dic_status_t r = prepare(p, a.ref, a.poi, s, false);
+  dic_status_t r = DIC_SUCCESS;
+  if (split) {
+    DIC_HIP(launch_ref_prep_stats(p->st, a.ref, a.poi, need_tmpl, s));
+    DIC_HIP(hipEventRecord(p->ev_stats, s));
+  } else {
+    r = prepare(p, a.ref, a.poi, s, false);
+  }
   if (fork) DIC_HIP(hipStreamWaitEvent(s, p->ev_join, 0));
   if (r != DIC_SUCCESS) return r;
   r = enqueue_search(p, a.ref, a.def, a.poi, a.seed, a.uv, a.zn_int, a.st_int, s, fork);
   if (r != DIC_SUCCESS) return r;
+  if (split) {
+    DIC_HIP(hipStreamWaitEvent(p->side_stream, p->ev_stats, 0));
+    DIC_HIP(launch_gradients(p->st, a.ref, p->side_stream));
+    DIC_HIP(launch_ref_prep_hessian(p->st, a.ref, a.poi, p->side_stream));
+    DIC_HIP(hipEventRecord(p->ev_ref, p->side_stream));
+    DIC_HIP(hipStreamWaitEvent(s, p->ev_ref, 0));
+    mark_ref(p, a.ref, a.poi, need_tmpl);
+  }
   return enqueue_refine(p, a.ref, a.def, a.poi, a.uv, a.st_int, a.p_init, a.p_out, a.zn, a.iters,
                         a.status, s, p->nr(), fork);
 }
@@ -634,6 +666,8 @@ void dic_plan_destroy(dic_plan_t p) {
   if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  if (p->ev_stats) (void)hipEventDestroy(p->ev_stats);
+  if (p->ev_ref) (void)hipEventDestroy(p->ev_ref);
   delete p;
 }
 

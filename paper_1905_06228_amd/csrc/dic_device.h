@@ -14,6 +14,17 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// A record's status, which the reference preparation's Hessian kernel may
+// turn from OK to SINGULAR_HESSIAN while a search reads it: relaxed atomic
+// accesses (a search takes the two alike).
+__device__ __forceinline__ int load_status(const RefRec* R) {
+  return __hip_atomic_load(const_cast<int32_t*>(&R->status), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_status(RefRec* R, int v) {
+  __hip_atomic_store(&R->status, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // The lane index as a value the compiler cannot hoist out of a loop: the
 // lane-dependent quantities derived from it inside a persistent loop are
 // recomputed per item instead of being held (and spilled) across the loop.

@@ -141,6 +141,13 @@ hipError_t launch_pso(const DevState& st, bool modified, const float* ref, const
 // search form only).
 hipError_t launch_ref_prep_f32(const DevState& st, const float* ref, const int32_t* poi,
                                bool write_tmpl, hipStream_t s);
+// The two halves of launch_ref_prep_f32: the statistics the search reads
+// (mean, norm, template sum, status), then the steepest-descent sums,
+// Hessian and factor IC-GN reads (after the gradients).
+hipError_t launch_ref_prep_stats(const DevState& st, const float* ref, const int32_t* poi,
+                                 bool write_tmpl, hipStream_t s);
+hipError_t launch_ref_prep_hessian(const DevState& st, const float* ref, const int32_t* poi,
+                                   hipStream_t s);
 hipError_t launch_ref_prep_f64(const DevState& st, const DevPair* host_pairs,
                                const float* ref, const int32_t* poi, hipStream_t s);
 hipError_t launch_search_f32(const DevState& st, const dic_tuning_t& tu,

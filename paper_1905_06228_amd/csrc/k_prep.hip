@@ -364,21 +364,22 @@ __device__ __forceinline__ void write_bad_record(RefRec* R, int status, int lane
   }
 }
 
-// FP32 form: one wave per POI, two passes over the subset (pixel k on lane
-// k mod 64, its row and column stepped without division).  Pass 1, in FP64:
-// sum f (the mean decides ZERO_VARIANCE exactly as the FP64 definition does)
-// and the six steepest-descent sums sum SD.  Pass 2: sum (f - fbar)^2 and
-// sum f^2 in FP64; the 21 products of the mean-removed steepest-descent
-// images (the Hessian, no cancellation left) and the six sum SD (f - fbar)
-// in FP32 per lane with fused multiply-adds (at most a few tens of terms),
-// added across lanes in a fixed FP32 tree (six levels).  Factorisation and
-// singularity test in FP64.  With write_tmpl also stores the float search
-// template f_i - fbar (rounded as f_i - (float)fbar), which only the
-// vector-ALU search reads; the other kernels form those values from f.
-__global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
-                                                           const float* __restrict__ ref,
-                                                           const int32_t* __restrict__ poi,
-                                                           int write_tmpl) {
+// FP32 form, in two kernels: the statistics the search needs, then (beside
+// the search, in a correlate with a side stream) the steepest-descent sums,
+// the Hessian and its factor that only IC-GN reads.  One wave per POI, two
+// passes over the subset in each (pixel k on lane k mod 64, its row and
+// column stepped without division).
+//
+// Statistics.  Pass 1, in FP64: sum f (the mean decides ZERO_VARIANCE exactly
+// as the FP64 definition does).  Pass 2, in FP64: sum (f - fbar)^2, sum f^2
+// and the sum of the float template f - (float)fbar.  Writes fbar, df, tsum
+// and the status; with write_tmpl also stores the float search template,
+// which only the vector-ALU search reads (the other kernels form those values
+// from f).
+__global__ void __launch_bounds__(256) ref_prep_stats_kernel(DevState st,
+                                                             const float* __restrict__ ref,
+                                                             const int32_t* __restrict__ poi,
+                                                             int write_tmpl) {
   // the POI of this wave, wave-uniform: its pointers stay in scalar registers
   const int g = uniform((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave));
   if (g >= st.N) return;
@@ -392,8 +393,6 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
     return;
   }
   const float* f = ref + P.ref_off + (int64_t)(y0 - M) * W + (x0 - M);
-  const float* gxi = st.grads + P.grad_off + (int64_t)(y0 - M) * W + (x0 - M);
-  const float* gyi = gxi + (int64_t)P.width * P.height;
   const int tp = P.tmpl_pitch;
   float* tmpl = st.tmpl + P.tmpl_off + (g - P.poi_off) * (int64_t)(n1 * tp);
   if (write_tmpl)
@@ -401,6 +400,87 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
       const int r = k / (tp - n1);
       tmpl[r * tp + n1 + (k - r * (tp - n1))] = 0.f;   // zero padding of every row
     }
+  const int dr = kWave / n1, dc = kWave - dr * n1;
+  auto step = [&](int& r, int& c) {
+    c += dc;
+    r += dr;
+    if (c >= n1) {
+      c -= n1;
+      ++r;
+    }
+  };
+
+  double s1 = 0.0;
+  int bad = 0;
+  {
+    int r = lane / n1, c = lane - r * n1;
+#pragma unroll 4
+    for (int k = lane; k < n; k += kWave) {
+      const float v = f[(unsigned)(r * W + c)];   // 32-bit offset from a scalar base
+      bad |= !isfinite(v);
+      s1 += (double)v;
+      step(r, c);
+    }
+  }
+  s1 = wave_sum_dpp(s1);
+  bad = wave_or_int(bad);
+  if (bad) {
+    write_bad_record(R, DIC_POI_NAN_INPUT, lane);
+    return;
+  }
+  const double fbar = s1 / (double)n;
+  const float fbar_f = (float)fbar;
+
+  double q = 0.0, sq = 0.0, ts = 0.0;
+  {
+    int r = lane / n1, c = lane - r * n1;
+#pragma unroll 4
+    for (int k = lane; k < n; k += kWave) {
+      const float v = f[(unsigned)(r * W + c)];
+      const double d = (double)v - fbar;
+      q += d * d;
+      sq += (double)v * (double)v;
+      const float t = v - fbar_f;
+      if (write_tmpl) tmpl[r * tp + c] = t;
+      ts += (double)t;
+      step(r, c);
+    }
+  }
+  q = wave_sum_dpp(q);
+  sq = wave_sum_dpp(sq);
+  ts = wave_sum_dpp(ts);
+  if (lane == 0) {
+    R->fbar = fbar;
+    R->df = sqrt(q);
+    R->tsum = (float)ts;
+    R->status = not_flat(q, sq) ? DIC_POI_OK : DIC_POI_ZERO_VARIANCE;
+  }
+}
+
+// Steepest-descent sums, Hessian and factor, for the POIs the statistics
+// kernel left OK or flat (it has written the record of the others).  Pass 1,
+// in FP64: the six sums sum SD.  Pass 2: the 21 products of the mean-removed
+// steepest-descent images (the Hessian, no cancellation left) and the six
+// sum SD (f - fbar) in FP32 per lane with fused multiply-adds (at most a few
+// tens of terms), added across lanes in a fixed FP32 tree (six levels).
+// Factorisation and singularity test in FP64.  A singular Hessian turns the
+// status to SINGULAR_HESSIAN with an atomic store: a search may read the
+// status meanwhile, and takes OK and SINGULAR_HESSIAN alike.
+__global__ void __launch_bounds__(256) ref_prep_hessian_kernel(DevState st,
+                                                               const float* __restrict__ ref,
+                                                               const int32_t* __restrict__ poi) {
+  const int g = uniform((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave));
+  if (g >= st.N) return;
+  const int lane = lane_id();
+  const DevPair P = st.pairs[uniform(st.poi_pair[g])];
+  RefRec* R = st.recs + g;
+  const int status0 = uniform(load_status(R));
+  if (status0 != DIC_POI_OK && status0 != DIC_POI_ZERO_VARIANCE) return;
+  const int x0 = uniform(poi[2 * g]), y0 = uniform(poi[2 * g + 1]);
+  const int M = P.M, n1 = 2 * M + 1, n = n1 * n1, W = P.width;
+  const float* f = ref + P.ref_off + (int64_t)(y0 - M) * W + (x0 - M);
+  const float* gxi = st.grads + P.grad_off + (int64_t)(y0 - M) * W + (x0 - M);
+  const float* gyi = gxi + (int64_t)P.width * P.height;
   const int dr = kWave / n1, dc = kWave - dr * n1;
   auto step = [&](int& r, int& c) {
     c += dc;
@@ -420,28 +500,18 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
     sd[5] = fy * dy;
   };
 
-  double s1 = 0.0, ssd[6] = {0, 0, 0, 0, 0, 0};
-  int bad = 0;
+  double ssd[6] = {0, 0, 0, 0, 0, 0};
   {
     int r = lane / n1, c = lane - r * n1;
 #pragma unroll 4
     for (int k = lane; k < n; k += kWave) {
       const unsigned o = (unsigned)(r * W + c);   // 32-bit offset from a scalar base
-      const float v = f[o];
-      bad |= !isfinite(v);
-      s1 += (double)v;
       float sd[6];
       sd_of(gxi[o], gyi[o], r, c, sd);
 #pragma unroll
       for (int a = 0; a < 6; ++a) ssd[a] += (double)sd[a];
       step(r, c);
     }
-  }
-  s1 = wave_sum_dpp(s1);
-  bad = wave_or_int(bad);
-  if (bad) {
-    write_bad_record(R, DIC_POI_NAN_INPUT, lane);
-    return;
   }
   double sdsum[6];
   float sdm[6];
@@ -450,10 +520,8 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
     sdsum[a] = wave_sum_dpp(ssd[a]);
     sdm[a] = (float)(sdsum[a] / (double)n);
   }
-  const double fbar = s1 / (double)n;
-  const float fbar_f = (float)fbar;
+  const float fbar_f = (float)R->fbar;
 
-  double q = 0.0, sq = 0.0, ts = 0.0;
   float ksdf[6] = {0, 0, 0, 0, 0, 0}, kh[21];
 #pragma unroll
   for (int a = 0; a < 21; ++a) kh[a] = 0.f;
@@ -461,14 +529,8 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
     int r = lane / n1, c = lane - r * n1;
 #pragma unroll 4
     for (int k = lane; k < n; k += kWave) {
-      const unsigned o = (unsigned)(r * W + c);   // 32-bit offset from a scalar base
-      const float v = f[o];
-      const double d = (double)v - fbar;
-      q += d * d;
-      sq += (double)v * (double)v;
-      const float t = v - fbar_f;
-      if (write_tmpl) tmpl[r * tp + c] = t;
-      ts += (double)t;
+      const unsigned o = (unsigned)(r * W + c);
+      const float t = f[o] - fbar_f;
       float sd[6];
       sd_of(gxi[o], gyi[o], r, c, sd);
 #pragma unroll
@@ -483,18 +545,13 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
       step(r, c);
     }
   }
-  q = wave_sum_dpp(q);
-  sq = wave_sum_dpp(sq);
-  ts = wave_sum_dpp(ts);
   double sdfsum[6], h[21];
   wave_sums_f32<6>(ksdf, sdfsum);
   wave_sums_f32<21>(kh, h);
 
-  int status = DIC_POI_OK;
+  int status = status0;
   double L[21], rd[6];
-  if (!not_flat(q, sq)) {
-    status = DIC_POI_ZERO_VARIANCE;
-  } else {
+  if (status == DIC_POI_OK) {
     // Hessian of the mean-removed steepest-descent images (centred in pass 2
     // by the FP32 rounding of the means: the residual mean m' gives n m' m'^T,
     // which is removed here)
@@ -508,10 +565,6 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
     if (!cholesky6(h, L, rd)) status = DIC_POI_SINGULAR_HESSIAN;
   }
   if (lane == 0) {
-    R->fbar = fbar;
-    R->df = sqrt(q);
-    R->tsum = (float)ts;
-    R->status = status;
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
       R->sd_sum[a] = sdsum[a];
@@ -520,16 +573,33 @@ __global__ void __launch_bounds__(256) ref_prep_f32_kernel(DevState st,
     }
 #pragma unroll
     for (int a = 0; a < 21; ++a) R->L[a] = status == DIC_POI_OK ? L[a] : 0.0;
+    if (status != status0) store_status(R, status);
   }
+}
+
+hipError_t launch_ref_prep_stats(const DevState& st, const float* ref, const int32_t* poi,
+                                 bool write_tmpl, hipStream_t s) {
+  if (st.N == 0) return hipSuccess;
+  const int64_t blocks = (st.N + 3) / 4;
+  hipLaunchKernelGGL(ref_prep_stats_kernel, dim3((unsigned)blocks), dim3(256), 0, s, st, ref,
+                     poi, write_tmpl ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_ref_prep_hessian(const DevState& st, const float* ref, const int32_t* poi,
+                                   hipStream_t s) {
+  if (st.N == 0) return hipSuccess;
+  const int64_t blocks = (st.N + 3) / 4;
+  hipLaunchKernelGGL(ref_prep_hessian_kernel, dim3((unsigned)blocks), dim3(256), 0, s, st, ref,
+                     poi);
+  return hipGetLastError();
 }
 
 hipError_t launch_ref_prep_f32(const DevState& st, const float* ref, const int32_t* poi,
                                bool write_tmpl, hipStream_t s) {
-  if (st.N == 0) return hipSuccess;
-  const int64_t blocks = (st.N + 3) / 4;
-  hipLaunchKernelGGL(ref_prep_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, st, ref, poi,
-                     write_tmpl ? 1 : 0);
-  return hipGetLastError();
+  hipError_t e = launch_ref_prep_stats(st, ref, poi, write_tmpl, s);
+  if (e != hipSuccess) return e;
+  return launch_ref_prep_hessian(st, ref, poi, s);
 }
 
 // FP64 plain form: one 64-thread workgroup per POI of one pair, everything

@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(kSearchMaxThreads) search_f32_kernel(
     const int x0 = uniform(poi[2 * g]), y0 = uniform(poi[2 * g + 1]);
     const int cu = seed ? uniform(seed[2 * g]) : 0;
     const int cv = seed ? uniform(seed[2 * g + 1]) : 0;
-    const int rstat = uniform(R->status);
+    const int rstat = uniform(load_status(R));
     // A singular Hessian does not stop the search; every other record status does.
     if (rstat != DIC_POI_OK && rstat != DIC_POI_SINGULAR_HESSIAN) {
       if (tid == 0) {
