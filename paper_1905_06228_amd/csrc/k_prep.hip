@@ -410,18 +410,27 @@ __global__ void __launch_bounds__(256) ref_prep_stats_kernel(DevState st,
     }
   };
 
-  double s1 = 0.0;
-  int bad = 0;
+  // the lane's pixels, all requested at once and kept for both passes (one
+  // memory round trip); slot j is pixel lane + 64 j
+  constexpr int kSlots = ((2 * kMaxM + 1) * (2 * kMaxM + 1) + kWave - 1) / kWave;
+  float fv[kSlots];
   {
     int r = lane / n1, c = lane - r * n1;
-#pragma unroll 4
-    for (int k = lane; k < n; k += kWave) {
-      const float v = f[(unsigned)(r * W + c)];   // 32-bit offset from a scalar base
-      bad |= !isfinite(v);
-      s1 += (double)v;
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) {
+      fv[j] = 0.f;
+      if (lane + kWave * j < n) fv[j] = f[(unsigned)(r * W + c)];   // 32-bit offset from a scalar base
       step(r, c);
     }
   }
+  double s1 = 0.0;
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < kSlots; ++j)
+    if (lane + kWave * j < n) {
+      bad |= !isfinite(fv[j]);
+      s1 += (double)fv[j];
+    }
   s1 = wave_sum_dpp(s1);
   bad = wave_or_int(bad);
   if (bad) {
@@ -432,17 +441,20 @@ __global__ void __launch_bounds__(256) ref_prep_stats_kernel(DevState st,
   const float fbar_f = (float)fbar;
 
   double q = 0.0, sq = 0.0, ts = 0.0;
-  {
-    int r = lane / n1, c = lane - r * n1;
-#pragma unroll 4
-    for (int k = lane; k < n; k += kWave) {
-      const float v = f[(unsigned)(r * W + c)];
+#pragma unroll
+  for (int j = 0; j < kSlots; ++j)
+    if (lane + kWave * j < n) {
+      const float v = fv[j];
       const double d = (double)v - fbar;
       q += d * d;
       sq += (double)v * (double)v;
-      const float t = v - fbar_f;
-      if (write_tmpl) tmpl[r * tp + c] = t;
-      ts += (double)t;
+      ts += (double)(v - fbar_f);
+    }
+  if (write_tmpl) {
+    int r = lane / n1, c = lane - r * n1;
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) {
+      if (lane + kWave * j < n) tmpl[r * tp + c] = fv[j] - fbar_f;
       step(r, c);
     }
   }
