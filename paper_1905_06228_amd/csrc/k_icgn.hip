@@ -23,9 +23,9 @@ namespace dic {
 
 namespace {
 
-template <int MAXS, class Smp>
+template <int MAXS, class Smp, class OF>
 __device__ __forceinline__ void iter_pass(const Smp& smp, int n, const Warp32& w,
-                                          const float* fxs, const float* fys, const half2v* dxy,
+                                          const float* fxs, const float* fys, const OF& offs,
                                           float* K) {
   constexpr int MINS = refine_min_slots(MAXS);
   const Slots sl(n);
@@ -36,7 +36,8 @@ __device__ __forceinline__ void iter_pass(const Smp& smp, int n, const Warp32& w
     // slots every subset of the class fills run without a test, so the
     // reads of consecutive slots can overlap
     if (k >= MINS && !sl.used(k)) continue;
-    const float dx = (float)dxy[k].x, dy = (float)dxy[k].y;
+    float dx, dy;
+    offs(k, dx, dy);
     const float v = sample_value(smp, warp_x(w, dx, dy), warp_y(w, dx, dy));
     const float gs = k + 1 >= MINS ? sl.mask(k, v) : v;
     const float fg = fxs[k] * gs, hg = fys[k] * gs;
@@ -172,12 +173,20 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
       const float* gy = gx + (int64_t)W * H;
       float fxs[MAXS], fys[MAXS], fxp = 0.f, fyp = 0.f;
       half2v dxy[R2 ? 1 : MAXS];
+      // the 20-slot kernel recomputes the offsets: 3 waves per SIMD instead
+      // of 2 (the 28-slot kernel holds 2 either way and keeps them)
+      const auto offs = [&] {
+        if constexpr (MAXS == 20)
+          return OffsetsComputed(M);
+        else
+          return OffsetsKept{dxy};
+      }();
       R2Lane L2{};
       if constexpr (R2) {
         L2 = r2_lane(M);
         load_slots_r2<MAXS>(M, L2, gx, gy, W, fxs, fys, fxp, fyp);
       } else {
-        load_slots<MAXS>(M, n, gx, gy, W, dxy, fxs, fys);
+        load_slots<MAXS, true>(M, n, gx, gy, W, dxy, fxs, fys);
       }
       const float c0 = deformed_centre(gimg, W, H, p, x0, y0);
       const double df = R->df;
@@ -198,7 +207,7 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
           if constexpr (R2)
             iter_pass_r2<MAXS>(smp, M, L2, w, fxs, fys, fxp, fyp, K);
           else
-            iter_pass<MAXS>(smp, n, w, fxs, fys, dxy, K);
+            iter_pass<MAXS>(smp, n, w, fxs, fys, offs, K);
         };
         if constexpr (IM == kInterpBicubicLut)
           pass(LutSampler{glut, W, H, w.bx, w.by, c0});
@@ -249,7 +258,7 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
             if constexpr (R2)
               final_pass_r2<MAXS>(smp, M, L2, w, tval, K);
             else
-              final_pass<MAXS>(smp, n, w, dxy, tval, K);
+              final_pass<MAXS>(smp, n, w, offs, tval, K);
           };
           if constexpr (IM == kInterpBicubicLut)
             fpass(LutSampler{glut, W, H, w.bx, w.by, c0});

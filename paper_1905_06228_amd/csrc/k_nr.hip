@@ -239,7 +239,7 @@ __attribute__((amdgpu_waves_per_eu(R2 ? 3 : 1))) nr_f32_kernel(
         for (int k = 0; k < MAXS - 1; ++k) tv[k] = (k < M && L2.colok) ? tv[k] - fb : 0.f;
         tvp = (L2.colok && !L2.upper) ? tvp - fb : 0.f;
       } else {
-        load_slots<MAXS>(M, n, fsub, nullptr, W, dxy, tv, nullptr);
+        load_slots<MAXS, false>(M, n, fsub, nullptr, W, dxy, tv, nullptr);
 #pragma unroll
         for (int k = 0; k < MAXS; ++k) tv[k] = (lane_id() + kWave * k < n) ? tv[k] - fb : 0.f;
       }
@@ -336,7 +336,7 @@ __attribute__((amdgpu_waves_per_eu(R2 ? 3 : 1))) nr_f32_kernel(
               final_pass_r2<MAXS>(smp, M, L2, w, tval, K);
             } else {
               const auto tval = [&](int k, float, float) { return tv[k]; };
-              final_pass<MAXS>(smp, n, w, dxy, tval, K);
+              final_pass<MAXS>(smp, n, w, OffsetsKept{dxy}, tval, K);
             }
           };
           if constexpr (IM == kInterpBicubicLut)

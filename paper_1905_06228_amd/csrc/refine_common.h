@@ -398,11 +398,13 @@ __device__ __forceinline__ void sample_value_grad(const Smp& smp, float xs, floa
   }
 }
 
-// Offsets and one per-sample reference value of every slot of this lane,
-// stepping (row, column) of the subset by 64 samples per slot.  `ref`
-// addresses the subset's top-left sample with row pitch `pitch` (nullable:
-// the values are then zero).
-template <int MAXS>
+// Offsets and one or (TWO) two per-sample reference values of every slot of
+// this lane, stepping (row, column) of the subset by 64 samples per slot.
+// ref0 / ref1 address the subset's top-left sample with row pitch `pitch`.
+// (The second array is chosen at compile time: a run-time null test of its
+// pointer keeps the array in scratch memory, a private address of zero being
+// valid.)
+template <int MAXS, bool TWO>
 __device__ __forceinline__ void load_slots(int M, int n, const float* __restrict__ ref0,
                                            const float* __restrict__ ref1, int pitch,
                                            half2v* dxy, float* v0, float* v1) {
@@ -413,11 +415,11 @@ __device__ __forceinline__ void load_slots(int M, int n, const float* __restrict
   for (int k = 0; k < MAXS; ++k) {
     dxy[k] = half2v{(_Float16)0.f, (_Float16)0.f};
     v0[k] = 0.f;
-    if (v1) v1[k] = 0.f;
+    if constexpr (TWO) v1[k] = 0.f;
     if (lane + kWave * k < n) {
       const int o = __umul24(r, pitch) + c;
       v0[k] = ref0[o];
-      if (v1) v1[k] = ref1[o];
+      if constexpr (TWO) v1[k] = ref1[o];
       dxy[k] = half2v{(_Float16)(c - M), (_Float16)(r - M)};
     }
     c += dc;
@@ -446,28 +448,68 @@ struct Slots {
   }
 };
 
+// Subset offsets (dx, dy) of a lane's sample in slot k.  Kept per slot as
+// exact fp16 pairs, or, where registers decide the occupancy, recomputed from the sample index k' = lane + 64 k: row trunc((k' + 1/2) /
+// n1) in FP32 (exact for k' < 4096: the rounding error is far inside the
+// distance 1 / (2 n1) to an integer), column k' - row n1.  A lane past the
+// subset takes its last sample (its values are masked either way).
+struct OffsetsKept {
+  const half2v* dxy;
+  __device__ __forceinline__ void operator()(int k, float& dx, float& dy) const {
+    dx = (float)dxy[k].x;
+    dy = (float)dxy[k].y;
+  }
+};
+struct OffsetsComputed {
+  int lane, M, n1, last;
+  float inv, hinv;
+  __device__ __forceinline__ explicit OffsetsComputed(int M_) {
+    lane = lane_id();
+    M = M_;
+    n1 = 2 * M_ + 1;
+    last = n1 * n1 - 1;
+    inv = 1.0f / (float)n1;
+    hinv = 0.5f * inv;
+  }
+  __device__ __forceinline__ void operator()(int k, float& dx, float& dy) const {
+    // opaque per use, so the offsets are not hoisted out of the iteration
+    // loop into registers again
+    int l = lane;
+    __asm__ volatile("" : "+v"(l));
+    const int t = min(l + kWave * k, last);
+    const int r = (int)fmaf((float)t, inv, hinv);
+    dx = (float)(t - (int)__umul24((uint32_t)r, (uint32_t)n1) - M);
+    dy = (float)(r - M);
+  }
+};
+
 // Sums over this lane's samples at the final warp: sum (g - c0),
 // sum (g - c0)^2 and sum (f - fbar)(g - c0), with f - fbar of slot k at
 // offsets (dx, dy) given by tval(k, dx, dy).
 // The template values are all requested before the sampling (one memory
 // round trip), and the slots every subset of the class fills run without a
 // per-slot test, so their reads can overlap.
-template <int MAXS, class Smp, class TV>
+template <int MAXS, class Smp, class OF, class TV>
 __device__ __forceinline__ void final_pass(const Smp& smp, int n, const Warp32& w,
-                                           const half2v* dxy, const TV& tval, float* K) {
+                                           const OF& offs, const TV& tval, float* K) {
   constexpr int MINS = refine_min_slots(MAXS);
   const Slots sl(n);
   float tv[MAXS];
 #pragma unroll
   for (int k = 0; k < MAXS; ++k) {
     tv[k] = 0.f;
-    if (k < MINS || sl.used(k)) tv[k] = tval(k, (float)dxy[k].x, (float)dxy[k].y);
+    if (k < MINS || sl.used(k)) {
+      float dx, dy;
+      offs(k, dx, dy);
+      tv[k] = tval(k, dx, dy);
+    }
   }
   K[0] = K[1] = K[2] = 0.f;
 #pragma unroll
   for (int k = 0; k < MAXS; ++k) {
     if (k >= MINS && !sl.used(k)) continue;
-    const float dx = (float)dxy[k].x, dy = (float)dxy[k].y;
+    float dx, dy;
+    offs(k, dx, dy);
     const float v = sample_value(smp, warp_x(w, dx, dy), warp_y(w, dx, dy));
     const float gs = k + 1 >= MINS ? sl.mask(k, v) : v;
     K[0] += gs;
