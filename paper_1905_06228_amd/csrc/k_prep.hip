@@ -470,12 +470,12 @@ __global__ void __launch_bounds__(256) ref_prep_stats_kernel(DevState st,
 }
 
 // Steepest-descent sums, Hessian and factor, for the POIs the statistics
-// kernel left OK or flat (it has written the record of the others).  Pass 1,
-// in FP64: the six sums sum SD.  Pass 2: the 21 products of the mean-removed
-// steepest-descent images (the Hessian, no cancellation left) and the six
-// sum SD (f - fbar) in FP32 per lane with fused multiply-adds (at most a few
-// tens of terms), added across lanes in a fixed FP32 tree (six levels).
-// Factorisation and singularity test in FP64.  A singular Hessian turns the
+// kernel left OK or flat (it has written the record of the others).  One
+// pass: the six sums sum SD, the six sum SD (f - fbar) and the 21 products of
+// the shifted steepest-descent images, in FP32 per lane with fused
+// multiply-adds (at most a few tens of terms), added across lanes in a fixed
+// FP32 tree (six levels).  Removal of the shifted mean, factorisation and
+// singularity test in FP64.  A singular Hessian turns the
 // status to SINGULAR_HESSIAN with an atomic store: a search may read the
 // status meanwhile, and takes OK and SINGULAR_HESSIAN alike.
 __global__ void __launch_bounds__(256) ref_prep_hessian_kernel(DevState st,
@@ -512,68 +512,58 @@ __global__ void __launch_bounds__(256) ref_prep_hessian_kernel(DevState st,
     sd[5] = fy * dy;
   };
 
-  double ssd[6] = {0, 0, 0, 0, 0, 0};
+  // One pass.  The steepest-descent images enter the Hessian shifted by
+  // their value at the subset centre, K = (gx, 0, 0, gy, 0, 0) there, and
+  // the shifted mean m' is removed in FP64 afterwards: sum (s - K)(s - K)^T
+  // - n m' m'^T.  K follows the gradients' level (a ramp's constant gradient
+  // cancels exactly; the offset-weighted terms have mean ~0 over the
+  // symmetric subset), so the removal cancels little.
+  const unsigned oc = (unsigned)(M * W + M);
+  const float kx = gxi[oc], ky = gyi[oc];
+  float ks[6] = {0, 0, 0, 0, 0, 0}, ksdf[6] = {0, 0, 0, 0, 0, 0}, kh[21];
+#pragma unroll
+  for (int a = 0; a < 21; ++a) kh[a] = 0.f;
+  const float fbar_f = (float)R->fbar;
   {
     int r = lane / n1, c = lane - r * n1;
 #pragma unroll 4
     for (int k = lane; k < n; k += kWave) {
       const unsigned o = (unsigned)(r * W + c);   // 32-bit offset from a scalar base
-      float sd[6];
-      sd_of(gxi[o], gyi[o], r, c, sd);
-#pragma unroll
-      for (int a = 0; a < 6; ++a) ssd[a] += (double)sd[a];
-      step(r, c);
-    }
-  }
-  double sdsum[6];
-  float sdm[6];
-#pragma unroll
-  for (int a = 0; a < 6; ++a) {
-    sdsum[a] = wave_sum_dpp(ssd[a]);
-    sdm[a] = (float)(sdsum[a] / (double)n);
-  }
-  const float fbar_f = (float)R->fbar;
-
-  float ksdf[6] = {0, 0, 0, 0, 0, 0}, kh[21];
-#pragma unroll
-  for (int a = 0; a < 21; ++a) kh[a] = 0.f;
-  {
-    int r = lane / n1, c = lane - r * n1;
-#pragma unroll 4
-    for (int k = lane; k < n; k += kWave) {
-      const unsigned o = (unsigned)(r * W + c);
       const float t = f[o] - fbar_f;
       float sd[6];
       sd_of(gxi[o], gyi[o], r, c, sd);
 #pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        ksdf[a] = fmaf(sd[a], t, ksdf[a]);
-        sd[a] -= sdm[a];
-      }
+      for (int a = 0; a < 6; ++a) ksdf[a] = fmaf(sd[a], t, ksdf[a]);
+      sd[0] -= kx;
+      sd[3] -= ky;
 #pragma unroll
-      for (int a = 0; a < 6; ++a)
+      for (int a = 0; a < 6; ++a) {
+        ks[a] += sd[a];
 #pragma unroll
         for (int b = 0; b <= a; ++b) kh[tri(a, b)] = fmaf(sd[a], sd[b], kh[tri(a, b)]);
+      }
       step(r, c);
     }
   }
-  double sdfsum[6], h[21];
+  double shs[6], sdfsum[6], h[21], sdsum[6];
+  wave_sums_f32<6>(ks, shs);
   wave_sums_f32<6>(ksdf, sdfsum);
   wave_sums_f32<21>(kh, h);
+#pragma unroll
+  for (int a = 0; a < 6; ++a) sdsum[a] = shs[a];
+  sdsum[0] += (double)n * (double)kx;
+  sdsum[3] += (double)n * (double)ky;
 
   int status = status0;
   double L[21], rd[6];
   if (status == DIC_POI_OK) {
-    // Hessian of the mean-removed steepest-descent images (centred in pass 2
-    // by the FP32 rounding of the means: the residual mean m' gives n m' m'^T,
-    // which is removed here)
-    double mres[6];
+    double m[6];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) mres[a] = sdsum[a] / (double)n - (double)sdm[a];
+    for (int a = 0; a < 6; ++a) m[a] = shs[a] / (double)n;
 #pragma unroll
     for (int a = 0; a < 6; ++a)
 #pragma unroll
-      for (int b = 0; b <= a; ++b) h[tri(a, b)] -= (double)n * mres[a] * mres[b];
+      for (int b = 0; b <= a; ++b) h[tri(a, b)] -= (double)n * m[a] * m[b];
     if (!cholesky6(h, L, rd)) status = DIC_POI_SINGULAR_HESSIAN;
   }
   if (lane == 0) {
