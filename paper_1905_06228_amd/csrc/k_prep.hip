@@ -366,16 +366,17 @@ __device__ __forceinline__ void write_bad_record(RefRec* R, int status, int lane
 
 // FP32 form, in two kernels: the statistics the search needs, then (beside
 // the search, in a correlate with a side stream) the steepest-descent sums,
-// the Hessian and its factor that only IC-GN reads.  One wave per POI, two
-// passes over the subset in each (pixel k on lane k mod 64, its row and
-// column stepped without division).
+// the Hessian and its factor that only IC-GN reads.  One wave per POI
+// (pixel k on lane k mod 64, its row and column stepped without division).
 //
 // Statistics.  Pass 1, in FP64: sum f (the mean decides ZERO_VARIANCE exactly
 // as the FP64 definition does).  Pass 2, in FP64: sum (f - fbar)^2, sum f^2
 // and the sum of the float template f - (float)fbar.  Writes fbar, df, tsum
 // and the status; with write_tmpl also stores the float search template,
 // which only the vector-ALU search reads (the other kernels form those values
-// from f).
+// from f).  NS: pixels kept per lane, at least the plan's largest subset
+// over 64 (fewer registers for small subsets, more waves in flight).
+template <int NS>
 __global__ void __launch_bounds__(256) ref_prep_stats_kernel(DevState st,
                                                              const float* __restrict__ ref,
                                                              const int32_t* __restrict__ poi,
@@ -412,7 +413,7 @@ __global__ void __launch_bounds__(256) ref_prep_stats_kernel(DevState st,
 
   // the lane's pixels, all requested at once and kept for both passes (one
   // memory round trip); slot j is pixel lane + 64 j
-  constexpr int kSlots = ((2 * kMaxM + 1) * (2 * kMaxM + 1) + kWave - 1) / kWave;
+  constexpr int kSlots = NS;
   float fv[kSlots];
   {
     int r = lane / n1, c = lane - r * n1;
@@ -583,8 +584,16 @@ hipError_t launch_ref_prep_stats(const DevState& st, const float* ref, const int
                                  bool write_tmpl, hipStream_t s) {
   if (st.N == 0) return hipSuccess;
   const int64_t blocks = (st.N + 3) / 4;
-  hipLaunchKernelGGL(ref_prep_stats_kernel, dim3((unsigned)blocks), dim3(256), 0, s, st, ref,
-                     poi, write_tmpl ? 1 : 0);
+  const int wt = write_tmpl ? 1 : 0;
+  const dim3 grid((unsigned)blocks), block(256);
+  switch (refine_slots(st.maxM)) {
+    case 4: hipLaunchKernelGGL(ref_prep_stats_kernel<4>, grid, block, 0, s, st, ref, poi, wt); break;
+    case 8: hipLaunchKernelGGL(ref_prep_stats_kernel<8>, grid, block, 0, s, st, ref, poi, wt); break;
+    case 12: hipLaunchKernelGGL(ref_prep_stats_kernel<12>, grid, block, 0, s, st, ref, poi, wt); break;
+    case 16: hipLaunchKernelGGL(ref_prep_stats_kernel<16>, grid, block, 0, s, st, ref, poi, wt); break;
+    case 20: hipLaunchKernelGGL(ref_prep_stats_kernel<20>, grid, block, 0, s, st, ref, poi, wt); break;
+    default: hipLaunchKernelGGL(ref_prep_stats_kernel<28>, grid, block, 0, s, st, ref, poi, wt); break;
+  }
   return hipGetLastError();
 }
 
