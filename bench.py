@@ -293,7 +293,7 @@ def sequence_bench(torch, dic, dicgen, dev, n_frames: int, reference: str = "fir
             "ms_per_frame": round(t_dev * 1e3 / (n_frames - 1), 3),
             "ms_per_frame_with_h2d": round(t_host * 1e3 / (n_frames - 1), 3),
             "frames": n_frames, "pois_per_frame": int(len(pois)),
-            "reference": reference,
+            "reference": reference, "last_frame_status_histogram": dic.status_histogram(st),
             "config": {"workload": "sequence_4096x3000: frames 1..K against "
                                    + ("frame 0" if reference == "first" else "frame k-1")
                                    + ", ~600k blobs, "
@@ -357,6 +357,7 @@ def batched_bench(torch, dic, dicgen, dev, reps: int) -> dict:
             "icgn_pois_per_s": round(N / (t_icgn * 1e-3), 1),
             "mean_iterations": float(iters.mean()) if iters.size else 0.0,
             "ok_fraction": float((stat == 0).mean()),
+            "status_histogram": dic.status_histogram(stat),
             "tuning": list(plan.tuning),
             "roofline_icgn": dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
                                   unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
@@ -802,6 +803,7 @@ def main() -> int:
         "stages_ms": {"reference_prep": round(t_prep, 4), "deformed_box_sums": round(t_box, 4),
                       "search": round(t_search, 4), "icgn": round(t_icgn, 4)},
         "icgn_pois_per_s": round(N / (t_icgn * 1e-3), 1),
+        "status_histogram": dic.status_histogram(got["status"]),
         "fp64_plain": {"pois_per_s": round(N / (ms64 * 1e-3), 1), "ms_per_step": round(ms64, 3),
                        "search_ms": round(t64_search, 3), "icgn_ms": round(t64_icgn, 3),
                        "icgn_pois_per_s": round(N / (t64_icgn * 1e-3), 1)},

@@ -10,5 +10,5 @@ from .dic import (FLAG_BICUBIC_LUT, FLAG_CACHE_REF_PREP, FLAG_DETERMINISTIC_BWD,
                   POI_NOT_CONVERGED, POI_OK, POI_OUT_OF_BOUNDS, POI_SINGULAR_HESSIAN,
                   POI_ZERO_VARIANCE, ZNSSD, DicError, PairSpec, Plan, batch_layout,
                   LatestFrame, LiveCorrelator, correlate, correlate_batch, correlate_sequence,
-                  load_library, poi_grid,
-                  single_pair_plan)
+                  load_library, poi_grid, SequenceCheckpoint, STATUS_NAMES,
+                  single_pair_plan, status_histogram)

@@ -13,6 +13,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "dic.h"
 #include "dic_internal.h"
 
@@ -30,6 +32,16 @@ static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 namespace {
 
 thread_local std::string g_last_error;
+
+// A named range around one stage for rocprofv3's marker trace: it spans the
+// host-side enqueue (or its capture into a graph), not the kernels' run on
+// the device, which the kernel trace times.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 dic_status_t fail(dic_status_t code, const std::string& msg) {
   g_last_error = msg;
@@ -285,6 +297,7 @@ void mark_ref(dic_plan_t p, const float* ref, const int32_t* poi, bool need_tmpl
 
 dic_status_t prepare(dic_plan_t p, const float* ref, const int32_t* poi, hipStream_t s,
                      bool force, bool tmpl = false) {
+  const Range range("dic: reference preparation");
   const bool need_tmpl = tmpl || p->tuning.search_block != kMfmaBlock;
   if (!force && ref_cached(p, ref, poi, need_tmpl)) return DIC_SUCCESS;
   if (p->fp32()) {
@@ -312,6 +325,7 @@ std::vector<SearchGroup> search_groups(const dic_plan_s* p, int block) {
 }
 
 dic_status_t prepare_deformed(dic_plan_t p, const float* def, hipStream_t s, bool force) {
+  const Range range("dic: deformed preparation");
   if (!p->fp32()) return DIC_SUCCESS;
   if (!force && (p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->def_valid && p->def_img == def)
     return DIC_SUCCESS;
@@ -340,6 +354,7 @@ dic_status_t prepare_lut(dic_plan_t p, const float* def, hipStream_t s, bool for
 dic_status_t enqueue_search(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
                             const int32_t* seed, int32_t* uv, float* zn, int32_t* status,
                             hipStream_t s, bool def_ready = false) {
+  const Range range("dic: integer search");
   if (p->fp32()) {
     const std::vector<SearchGroup> groups = search_groups(p, p->tuning.search_block);
     if (!def_ready) {
@@ -366,6 +381,7 @@ dic_status_t enqueue_refine(dic_plan_t p, const float* ref, const float* def, co
                             const int32_t* uv, const int32_t* status_in, const double* p_init,
                             double* p_out, float* zn, int32_t* iters, int32_t* status,
                             hipStream_t s, bool nr, bool table_ready = false) {
+  const Range range(nr ? "dic: Newton-Raphson refinement" : "dic: IC-GN refinement");
   if (p->fp32()) {
     if (!table_ready) {
       dic_status_t r = prepare_lut(p, def, s, false);
@@ -417,6 +433,7 @@ struct CorrArgs {
 // created or used).
 dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s,
                                bool allow_fork = true) {
+  const Range range("dic: correlate");
   const bool fork = allow_fork && p->fp32() &&
                     !((p->desc.flags & DIC_FLAG_CACHE_REF_PREP) && p->def_valid &&
                       p->def_img == a.def);
@@ -439,6 +456,7 @@ dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s,
   }
   dic_status_t r = DIC_SUCCESS;
   if (split) {
+    const Range range("dic: reference statistics");
     DIC_HIP(launch_ref_prep_stats(p->st, a.ref, a.poi, need_tmpl, s));
     DIC_HIP(hipEventRecord(p->ev_stats, s));
   } else {
@@ -449,6 +467,7 @@ dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s,
   r = enqueue_search(p, a.ref, a.def, a.poi, a.seed, a.uv, a.zn_int, a.st_int, s, fork);
   if (r != DIC_SUCCESS) return r;
   if (split) {
+    const Range range("dic: reference gradients and Hessian (side stream)");
     DIC_HIP(hipStreamWaitEvent(p->side_stream, p->ev_stats, 0));
     DIC_HIP(launch_gradients(p->st, a.ref, p->side_stream));
     DIC_HIP(launch_ref_prep_hessian(p->st, a.ref, a.poi, p->side_stream));
@@ -808,6 +827,7 @@ dic_status_t dic_pso_search(dic_plan_t p, const float* ref, const float* def,
     return fail(DIC_ERR_INVALID_ARGUMENT, "modified must be 0 or 1");
   if (!p->fp32())
     return fail(DIC_ERR_UNSUPPORTED, "the swarm search uses the FP32 batched form's box sums");
+  const Range range(modified ? "dic: modified swarm search" : "dic: swarm search");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   r = prepare(p, ref, poi, s, false);
   if (r) return r;
@@ -934,6 +954,7 @@ dic_status_t dic_znssd_backward(dic_plan_t p, const float* ref, const float* def
   if (!ref || !def || !poi || !pw) return fail(DIC_ERR_INVALID_ARGUMENT, "null required pointer");
   if (p->bilinear() || p->bspline())
     return fail(DIC_ERR_UNSUPPORTED, "the ZNSSD adjoint interpolates bicubically only");
+  const Range range("dic: ZNSSD forward and backward");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   r = prepare(p, ref, poi, s, false);
   if (r) return r;

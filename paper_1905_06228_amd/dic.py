@@ -35,6 +35,19 @@ POI_ZERO_VARIANCE = 3
 POI_SINGULAR_HESSIAN = 4
 POI_NO_VALID_CANDIDATE = 5
 POI_NAN_INPUT = 6
+STATUS_NAMES = {POI_OK: "OK", POI_NOT_CONVERGED: "NOT_CONVERGED",
+                POI_OUT_OF_BOUNDS: "OUT_OF_BOUNDS", POI_ZERO_VARIANCE: "ZERO_VARIANCE",
+                POI_SINGULAR_HESSIAN: "SINGULAR_HESSIAN",
+                POI_NO_VALID_CANDIDATE: "NO_VALID_CANDIDATE", POI_NAN_INPUT: "NAN_INPUT"}
+
+
+def status_histogram(status) -> dict:
+    """Count of every per-POI status code in ``status`` (a tensor or array of
+    codes), by name; a code outside the table is counted as ``UNKNOWN_<code>``."""
+    import numpy as np
+    a = status.detach().cpu().numpy() if isinstance(status, torch.Tensor) else np.asarray(status)
+    codes, counts = np.unique(a.astype(np.int64).ravel(), return_counts=True)
+    return {STATUS_NAMES.get(int(c), f"UNKNOWN_{int(c)}"): int(n) for c, n in zip(codes, counts)}
 
 
 class PairDesc(ctypes.Structure):
@@ -468,8 +481,67 @@ class _FrameRing:
         self.released[slot].record()
 
 
+class SequenceCheckpoint:
+    """The state a frame sequence carries from one pair to the next, on disk.
+    After pair k (frame k against its reference) ``save`` writes
+    ``<directory>/frame_<k>.npz`` holding the seeds of the next pair (integer
+    displacement and warp of every POI), pair k's warp and statuses, the
+    reference policy and the POI count.  A file is written under a temporary
+    name and renamed, so one that exists is whole.  To resume after pair k,
+    the reference side is prepared again (a deterministic computation) and
+    the seeds are read back, so the pairs after k come out bit-identical to an
+    uninterrupted run."""
+
+    def __init__(self, directory: str):
+        self.directory = directory
+
+    def path(self, k: int) -> str:
+        return os.path.join(self.directory, f"frame_{k:06d}.npz")
+
+    def frames(self) -> List[int]:
+        """Pairs with a saved state, ascending."""
+        if not os.path.isdir(self.directory):
+            return []
+        out = []
+        for name in os.listdir(self.directory):
+            if name.startswith("frame_") and name.endswith(".npz"):
+                try:
+                    out.append(int(name[6:-4]))
+                except ValueError:
+                    pass
+        return sorted(out)
+
+    def save(self, k: int, reference: str, seed, p_seed, p, status) -> None:
+        import numpy as np
+        os.makedirs(self.directory, exist_ok=True)
+        host = {name: (t.detach().cpu().numpy() if isinstance(t, torch.Tensor) else np.asarray(t))
+                for name, t in (("seed", seed), ("p_seed", p_seed), ("p", p), ("status", status))}
+        tmp = self.path(k) + ".tmp"
+        with open(tmp, "wb") as fh:
+            np.savez(fh, frame=np.int64(k), reference=np.array(reference),
+                     n=np.int64(host["seed"].shape[0]), **host)
+        os.replace(tmp, self.path(k))
+
+    def load(self, k: Optional[int] = None) -> Tuple[int, dict]:
+        """The state saved after pair k (the latest if None)."""
+        import numpy as np
+        if k is None:
+            have = self.frames()
+            if not have:
+                raise DicError(f"no sequence checkpoint in {self.directory}")
+            k = have[-1]
+        if not os.path.exists(self.path(k)):
+            raise DicError(f"no sequence checkpoint for pair {k} in {self.directory}")
+        with np.load(self.path(k), allow_pickle=False) as z:
+            st = {name: z[name] for name in z.files}
+        if int(st["frame"]) != k:
+            raise DicError(f"checkpoint {self.path(k)} holds pair {int(st['frame'])}")
+        return k, st
+
+
 def correlate_sequence(frames: Sequence, pois: torch.Tensor, M: int, S: int,
                        precision: int = FP32_BATCHED, device=None, reference: str = "first",
+                       checkpoint: Optional[str] = None, resume=False,
                        **kw) -> List[dict]:
     """A frame sequence, each pair seeded by the last OK result of its POI
     (search centred on its rounded displacement, refinement starting from its
@@ -480,9 +552,16 @@ def correlate_sequence(frames: Sequence, pois: torch.Tensor, M: int, S: int,
     k - 1 (the reference updated after every evaluation, Sec. 3): the POIs
     are the same pixel positions of every reference and each result is the
     increment between the two frames.  Host frames are copied through pinned
-    memory on a side stream, one frame ahead of the kernels."""
+    memory on a side stream, one frame ahead of the kernels.
+
+    checkpoint: a directory where the state after every pair is saved
+    (SequenceCheckpoint; each save waits for its pair's results).  resume: True (the latest saved pair) or a pair
+    index k: continue after pair k from its saved state; the list then holds
+    the pairs after k only."""
     if reference not in ("first", "previous"):
         raise DicError("reference must be 'first' or 'previous'")
+    if resume is not False and resume is not None and checkpoint is None:
+        raise DicError("resume needs a checkpoint directory")
     device = torch.device(device if device is not None else "cuda")
     if device.index is None:
         device = torch.device("cuda", torch.cuda.current_device())
@@ -504,12 +583,25 @@ def correlate_sequence(frames: Sequence, pois: torch.Tensor, M: int, S: int,
     else:
         def slot(k: int) -> int:
             return k % 3
+    ckpt = SequenceCheckpoint(checkpoint) if checkpoint is not None else None
+    start = 1
+    if resume is not False and resume is not None:
+        k0, st = ckpt.load(None if resume is True else int(resume))
+        if str(st["reference"]) != reference or int(st["n"]) != N:
+            raise DicError(f"checkpoint of pair {k0} is for reference={str(st['reference'])!r}, "
+                           f"{int(st['n'])} POIs, not {reference!r}, {N}")
+        if not 1 <= k0 < len(frames):
+            raise DicError(f"checkpoint of pair {k0} is outside a sequence of {len(frames)} frames")
+        seed.copy_(torch.from_numpy(st["seed"]).to(device))
+        p_seed.copy_(torch.from_numpy(st["p_seed"]).to(device))
+        start = k0 + 1
     results = []
     out = plan.new_outputs()          # fixed buffers: graph replays keep their key
-    ring.stage(slot(0), frames[0])
-    if len(frames) > 1:
-        ring.stage(slot(1), frames[1])
-    for k in range(1, len(frames)):
+    r0 = 0 if reference == "first" else start - 1     # the first pair's reference frame
+    ring.stage(slot(r0), frames[r0])
+    if start < len(frames):
+        ring.stage(slot(start), frames[start])
+    for k in range(start, len(frames)):
         ref = ring.acquire(slot(0) if reference == "first" else slot(k - 1))
         cur = ring.acquire(slot(k))
         if reference == "first":
@@ -519,6 +611,8 @@ def correlate_sequence(frames: Sequence, pois: torch.Tensor, M: int, S: int,
             plan.prepare_deformed(cur)
         o = plan.correlate(ref, cur, pois, seed, p_seed, out=out)
         plan.seed_update(o["p"], o["status"], seed, p_seed)
+        if ckpt is not None:
+            ckpt.save(k, reference, seed, p_seed, o["p"], o["status"])
         ring.release(slot(k) if reference == "first" else slot(k - 1))
         if k + 1 < len(frames):
             ring.stage(slot(k + 1), frames[k + 1])

@@ -149,3 +149,30 @@ def test_first_reference_with_reused_slots_matches_fresh_plans(frames, flag):
         g = host(got[k - 1])
         for key in ref:
             np.testing.assert_array_equal(ref[key], g[key], err_msg=f"frame {k} {key}")
+
+
+@pytest.mark.parametrize("reference", ["first", "previous"])
+def test_sequence_resume_from_checkpoint(frames, tmp_path, reference):
+    """A sequence checkpointed after every pair and resumed after pair 2 (its
+    reference prepared again, the seeds read back) gives the pairs after 2
+    bit-identical to the uninterrupted run."""
+    fr = [torch.from_numpy(f) for f in frames[:6]]
+    pois = to_dev(dicgen.poi_grid(260, 200, M, S, 15))
+    print(f"case sequence resume {reference} N={len(pois)}", flush=True)
+    whole = dic.correlate_sequence(fr, pois, M, S, reference=reference,
+                                   checkpoint=str(tmp_path))
+    assert dic.SequenceCheckpoint(str(tmp_path)).frames() == [1, 2, 3, 4, 5]
+    part = dic.correlate_sequence(fr, pois, M, S, reference=reference,
+                                  checkpoint=str(tmp_path / "again"), resume=False)
+    resumed = dic.correlate_sequence(fr, pois, M, S, reference=reference,
+                                     checkpoint=str(tmp_path), resume=2)
+    assert len(resumed) == 3
+    for a, b in zip(whole[2:], resumed):
+        for key in a:
+            np.testing.assert_array_equal(a[key].cpu().numpy(), b[key].cpu().numpy(), err_msg=key)
+    for a, b in zip(whole, part):
+        np.testing.assert_array_equal(a["p"].cpu().numpy(), b["p"].cpu().numpy())
+    # the saved warp of a pair is that pair's result
+    _, st = dic.SequenceCheckpoint(str(tmp_path)).load(4)
+    np.testing.assert_array_equal(st["p"], whole[3]["p"].cpu().numpy())
+    np.testing.assert_array_equal(st["status"], whole[3]["status"].cpu().numpy())
