@@ -124,12 +124,11 @@ __device__ __forceinline__ void iter_pass_r2(const Smp& smp, int M, const R2Lane
 
 }  // namespace
 
-// Three waves per SIMD (two for the largest subsets); the two-rows kernels
-// fit four, which measured slower (0.54 against 0.52 ms on the 1024^2
-// benchmark pair).
+// Three waves per SIMD; the two-rows kernels fit four, which measured slower
+// (0.54 against 0.52 ms on the 1024^2 benchmark pair).
 template <int MAXS, int IM, bool R2>
 __global__ void __launch_bounds__(512)
-__attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
+__attribute__((amdgpu_waves_per_eu(3))) icgn_f32_kernel(
     DevState st, const int32_t* __restrict__ work, int64_t count, int ctr, int gmaxM, int slack,
     const float* __restrict__ ref, const float* __restrict__ def, const int32_t* __restrict__ poi,
     const int32_t* __restrict__ uv_init, const int32_t* __restrict__ status_in,
@@ -173,10 +172,10 @@ __attribute__((amdgpu_waves_per_eu(MAXS <= 16 ? 3 : 2))) icgn_f32_kernel(
       const float* gy = gx + (int64_t)W * H;
       float fxs[MAXS], fys[MAXS], fxp = 0.f, fyp = 0.f;
       half2v dxy[R2 ? 1 : MAXS];
-      // the 20-slot kernel recomputes the offsets: 3 waves per SIMD instead
-      // of 2 (the 28-slot kernel holds 2 either way and keeps them)
+      // the 20- and 28-slot kernels recompute the offsets, which leaves them
+      // registers for 3 waves per SIMD instead of 2
       const auto offs = [&] {
-        if constexpr (MAXS == 20)
+        if constexpr (MAXS >= 20)
           return OffsetsComputed(M);
         else
           return OffsetsKept{dxy};
@@ -301,7 +300,7 @@ static hipError_t launch_icgn_f32_t(const DevState& st, const dic_tuning_t& tu,
                                     float* zncc, int32_t* iters, int32_t* status, int num_cu,
                                     hipStream_t s) {
   const int threads = tu.icgn_waves * kWave;
-  const int slack = R2 ? min(tu.icgn_slack, kR2MaxSlack) : tu.icgn_slack;
+  const int slack = min(tu.icgn_slack, R2 ? kR2MaxSlack : refine_max_slack(MAXS));
   // the table form reads no LDS patch
   const size_t lds = IM == kInterpBicubicLut
                          ? 0

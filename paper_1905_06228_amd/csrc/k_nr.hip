@@ -380,7 +380,7 @@ static hipError_t launch_nr_f32_t(const DevState& st, const dic_tuning_t& tu,
                                   float* zncc, int32_t* iters, int32_t* status, int num_cu,
                                   hipStream_t s) {
   const int threads = tu.icgn_waves * kWave;
-  const int slack = R2 ? min(tu.icgn_slack, kR2MaxSlack) : tu.icgn_slack;
+  const int slack = min(tu.icgn_slack, R2 ? kR2MaxSlack : refine_max_slack(MAXS));
   // the table form reads no LDS patch
   const size_t lds = IM == kInterpBicubicLut
                          ? 0

@@ -30,12 +30,20 @@ __host__ __device__ constexpr int refine_max_radius(int maxs) {
   return m;
 }
 
+// Largest patch slack of the maxs-slot kernel: the tuning's, except in the
+// 28-slot kernel, whose patch is sized for a slack of at most 6 so that three
+// waves' patches per SIMD fit a CU's LDS (a larger tuned slack is clamped:
+// the slack changes when the patch is restaged, not the results).
+__host__ __device__ constexpr int refine_max_slack(int maxs) {
+  return maxs >= 28 ? 6 : kMaxRefineSlack;
+}
+
 // Row pitch (floats) of the LDS patch of a kernel built for at most 64 * maxs
 // samples per subset: odd, and at least the widest patch side such a subset
 // can need.  A compile-time pitch lets the 16 taps of a sample be read from
 // one address with immediate offsets (at most 3 * pitch + 3 dwords).
 __host__ __device__ constexpr int refine_patch_pitch(int maxs) {
-  return (2 * refine_max_radius(maxs) + 4 + 2 * kMaxRefineSlack) | 1;
+  return (2 * refine_max_radius(maxs) + 4 + 2 * refine_max_slack(maxs)) | 1;
 }
 static_assert(3 * refine_patch_pitch(28) + 3 <= 255, "tap offsets exceed the LDS read2 range");
 static_assert(refine_max_radius(28) >= kMaxM, "largest kernel does not cover kMaxM");
