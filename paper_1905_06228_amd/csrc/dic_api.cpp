@@ -302,7 +302,8 @@ dic_status_t prepare(dic_plan_t p, const float* ref, const int32_t* poi, hipStre
   if (!force && ref_cached(p, ref, poi, need_tmpl)) return DIC_SUCCESS;
   if (p->fp32()) {
     DIC_HIP(launch_gradients(p->st, ref, s));
-    DIC_HIP(launch_ref_prep_f32(p->st, ref, poi, need_tmpl, s));
+    DIC_HIP(launch_ref_prep_f32(p->st, p->rgroups.data(), (int)p->rgroups.size(), ref, poi,
+                                need_tmpl, s));
   } else {
     DIC_HIP(launch_ref_prep_f64(p->st, p->dpairs.data(), ref, poi, s));
   }
@@ -457,7 +458,8 @@ dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s,
   dic_status_t r = DIC_SUCCESS;
   if (split) {
     const Range range("dic: reference statistics");
-    DIC_HIP(launch_ref_prep_stats(p->st, a.ref, a.poi, need_tmpl, s));
+    DIC_HIP(launch_ref_prep_stats(p->st, p->rgroups.data(), (int)p->rgroups.size(), a.ref,
+                                  a.poi, need_tmpl, s));
     DIC_HIP(hipEventRecord(p->ev_stats, s));
   } else {
     r = prepare(p, a.ref, a.poi, s, false);

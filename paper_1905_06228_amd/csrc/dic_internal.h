@@ -138,14 +138,17 @@ hipError_t launch_pso(const DevState& st, bool modified, const float* ref, const
                       float* zn, int32_t* status, int32_t* gens, int32_t* evals, int num_cu,
                       hipStream_t s);
 // write_tmpl: also store the FP32 search template (read by the vector-ALU
-// search form only).
-hipError_t launch_ref_prep_f32(const DevState& st, const float* ref, const int32_t* poi,
-                               bool write_tmpl, hipStream_t s);
+// search form only).  groups: the plan's refinement runs of the work list
+// (the statistics kernel is sized per run).
+hipError_t launch_ref_prep_f32(const DevState& st, const RefineGroup* groups, int ngroups,
+                               const float* ref, const int32_t* poi, bool write_tmpl,
+                               hipStream_t s);
 // The two halves of launch_ref_prep_f32: the statistics the search reads
 // (mean, norm, template sum, status), then the steepest-descent sums,
 // Hessian and factor IC-GN reads (after the gradients).
-hipError_t launch_ref_prep_stats(const DevState& st, const float* ref, const int32_t* poi,
-                                 bool write_tmpl, hipStream_t s);
+hipError_t launch_ref_prep_stats(const DevState& st, const RefineGroup* groups, int ngroups,
+                                 const float* ref, const int32_t* poi, bool write_tmpl,
+                                 hipStream_t s);
 hipError_t launch_ref_prep_hessian(const DevState& st, const float* ref, const int32_t* poi,
                                    hipStream_t s);
 hipError_t launch_ref_prep_f64(const DevState& st, const DevPair* host_pairs,

@@ -374,16 +374,20 @@ __device__ __forceinline__ void write_bad_record(RefRec* R, int status, int lane
 // and the sum of the float template f - (float)fbar.  Writes fbar, df, tsum
 // and the status; with write_tmpl also stores the float search template,
 // which only the vector-ALU search reads (the other kernels form those values
-// from f).  NS: pixels kept per lane, at least the plan's largest subset
+// from f).  One launch per run of the work list that shares a refinement
+// kernel class; NS: pixels kept per lane, at least the run's largest subset
 // over 64 (fewer registers for small subsets, more waves in flight).
 template <int NS>
 __global__ void __launch_bounds__(256) ref_prep_stats_kernel(DevState st,
+                                                             const int32_t* __restrict__ work,
+                                                             int64_t count,
                                                              const float* __restrict__ ref,
                                                              const int32_t* __restrict__ poi,
                                                              int write_tmpl) {
   // the POI of this wave, wave-uniform: its pointers stay in scalar registers
-  const int g = uniform((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave));
-  if (g >= st.N) return;
+  const int64_t item = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (item >= count) return;
+  const int g = uniform(work[item]);
   const int lane = lane_id();
   const DevPair P = st.pairs[uniform(st.poi_pair[g])];
   RefRec* R = st.recs + g;
@@ -580,21 +584,34 @@ __global__ void __launch_bounds__(256) ref_prep_hessian_kernel(DevState st,
   }
 }
 
-hipError_t launch_ref_prep_stats(const DevState& st, const float* ref, const int32_t* poi,
-                                 bool write_tmpl, hipStream_t s) {
-  if (st.N == 0) return hipSuccess;
-  const int64_t blocks = (st.N + 3) / 4;
+hipError_t launch_ref_prep_stats(const DevState& st, const RefineGroup* groups, int ngroups,
+                                 const float* ref, const int32_t* poi, bool write_tmpl,
+                                 hipStream_t s) {
   const int wt = write_tmpl ? 1 : 0;
-  const dim3 grid((unsigned)blocks), block(256);
-  switch (refine_slots(st.maxM)) {
-    case 4: hipLaunchKernelGGL(ref_prep_stats_kernel<4>, grid, block, 0, s, st, ref, poi, wt); break;
-    case 8: hipLaunchKernelGGL(ref_prep_stats_kernel<8>, grid, block, 0, s, st, ref, poi, wt); break;
-    case 12: hipLaunchKernelGGL(ref_prep_stats_kernel<12>, grid, block, 0, s, st, ref, poi, wt); break;
-    case 16: hipLaunchKernelGGL(ref_prep_stats_kernel<16>, grid, block, 0, s, st, ref, poi, wt); break;
-    case 20: hipLaunchKernelGGL(ref_prep_stats_kernel<20>, grid, block, 0, s, st, ref, poi, wt); break;
-    default: hipLaunchKernelGGL(ref_prep_stats_kernel<28>, grid, block, 0, s, st, ref, poi, wt); break;
+  for (int i = 0; i < ngroups; ++i) {
+    const RefineGroup& gr = groups[i];
+    if (gr.count == 0) continue;
+    const dim3 grid((unsigned)((gr.count + 3) / 4)), block(256);
+    const int32_t* w = st.work + gr.begin;
+    switch (refine_slots(gr.maxM)) {
+#define DIC_STATS(NS)                                                                       \
+  case NS:                                                                                  \
+    hipLaunchKernelGGL(ref_prep_stats_kernel<NS>, grid, block, 0, s, st, w, gr.count, ref, \
+                       poi, wt);                                                            \
+    break;
+      DIC_STATS(4)
+      DIC_STATS(8)
+      DIC_STATS(12)
+      DIC_STATS(16)
+      DIC_STATS(20)
+      DIC_STATS(28)
+#undef DIC_STATS
+      default: return hipErrorInvalidValue;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_ref_prep_hessian(const DevState& st, const float* ref, const int32_t* poi,
@@ -606,9 +623,10 @@ hipError_t launch_ref_prep_hessian(const DevState& st, const float* ref, const i
   return hipGetLastError();
 }
 
-hipError_t launch_ref_prep_f32(const DevState& st, const float* ref, const int32_t* poi,
-                               bool write_tmpl, hipStream_t s) {
-  hipError_t e = launch_ref_prep_stats(st, ref, poi, write_tmpl, s);
+hipError_t launch_ref_prep_f32(const DevState& st, const RefineGroup* groups, int ngroups,
+                               const float* ref, const int32_t* poi, bool write_tmpl,
+                               hipStream_t s) {
+  hipError_t e = launch_ref_prep_stats(st, groups, ngroups, ref, poi, write_tmpl, s);
   if (e != hipSuccess) return e;
   return launch_ref_prep_hessian(st, ref, poi, s);
 }
