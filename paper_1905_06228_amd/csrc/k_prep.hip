@@ -61,15 +61,22 @@ __global__ void __launch_bounds__(256) box_cols_kernel(const DevPair* __restrict
   const int y0 = blockIdx.y * kBoxSeg;
   const int W = P.width, H = P.height, M = P.M;
   if (x >= W || y0 >= H) return;
-  const float* g = def + P.def_off;
+  const float* col = def + P.def_off + x;
   const int64_t plane = (int64_t)W * H;
   double* v1 = box + P.box_off;
   double* v2 = v1 + plane;
   const int y1 = min(y0 + kBoxSeg, H);
+  // centres whose subset rows lie in the image: M <= y <= H - 1 - M
+  const int ya = max(y0, M), yb = max(ya, min(y1, H - M));
+  for (int y = y0; y < y1; ++y)
+    if (y < ya || y >= yb) {
+      v1[(int64_t)y * W + x] = 0.0;
+      v2[(int64_t)y * W + x] = -1.0;
+    }
+  if (ya >= yb) return;
   double s1 = 0.0, s2 = 0.0;
   int bad = 0;
-  auto take = [&](int y, int sign) {
-    const float v = g[(int64_t)y * W + x];
+  auto take = [&](float v, int sign) {
     if (isfinite(v)) {
       s1 += sign * (double)v;
       s2 += sign * (double)v * (double)v;
@@ -77,23 +84,45 @@ __global__ void __launch_bounds__(256) box_cols_kernel(const DevPair* __restrict
       bad += sign;
     }
   };
-  bool primed = false;
-  for (int y = y0; y < y1; ++y) {
-    const int64_t o = (int64_t)y * W + x;
-    if (y - M < 0 || y + M > H - 1) {
-      v1[o] = 0.0;
-      v2[o] = -1.0;
-      continue;
+  auto put = [&](int y) {
+    v1[(int64_t)y * W + x] = s1;
+    v2[(int64_t)y * W + x] = bad ? -1.0 : s2;
+  };
+  auto at = [&](int y) { return col[(int64_t)y * W]; };
+  // The first centre's 2M+1 rows, then per centre y the row y + M in and
+  // the row y - M - 1 out, in that order; the rows are requested eight
+  // centres at a time (one memory round trip per eight), the sums run in
+  // the same order as one row at a time.
+  constexpr int kB = 8;
+  int i = ya - M;
+  for (; i + kB <= ya + M + 1; i += kB) {
+    float v[kB];
+#pragma unroll
+    for (int j = 0; j < kB; ++j) v[j] = at(i + j);
+#pragma unroll
+    for (int j = 0; j < kB; ++j) take(v[j], 1);
+  }
+  for (; i <= ya + M; ++i) take(at(i), 1);
+  put(ya);
+  int y = ya + 1;
+  for (; y + kB <= yb; y += kB) {
+    float vi[kB], vo[kB];
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      vi[j] = at(y + j + M);
+      vo[j] = at(y + j - M - 1);
     }
-    if (!primed) {
-      for (int i = y - M; i <= y + M; ++i) take(i, 1);
-      primed = true;
-    } else {
-      take(y + M, 1);
-      take(y - M - 1, -1);
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      take(vi[j], 1);
+      take(vo[j], -1);
+      put(y + j);
     }
-    v1[o] = s1;
-    v2[o] = bad ? -1.0 : s2;
+  }
+  for (; y < yb; ++y) {
+    take(at(y + M), 1);
+    take(at(y - M - 1), -1);
+    put(y);
   }
 }
 
