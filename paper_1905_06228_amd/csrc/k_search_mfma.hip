@@ -110,21 +110,33 @@ struct Frags {
   bf16x8 a[KB], b[KB], bp[KB];
 };
 
+// `last`: the last K block takes part (see correlate_tiles).
 template <int KB, bool TWO>
 __device__ __forceinline__ void mfma_step(const bf16x8* a, const bf16x8* b, const bf16x8* bp,
-                                          bool do_a, bool do_b, f32x16& acc_a, f32x16& acc_b) {
+                                          bool do_a, bool do_b, bool last, f32x16& acc_a,
+                                          f32x16& acc_b) {
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
+    if (kb == KB - 1 && !last) break;
     if (do_a) acc_a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kb], b[kb], acc_a, 0, 0, 0);
     if (TWO && do_b)
       acc_b = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kb], bp[kb], acc_b, 0, 0, 0);
   }
 }
 
-template <int KB, bool TWO>
+// ncols (TRIM): the tile's candidate columns that are used (du < ncols; the
+// others are outside the window).  Column du meets template entries only at
+// window columns du .. du + n1 - 1, so when ncols - 1 + n1 <= 16 (KB - 1)
+// the last K block adds exact zeros to every used column (the staged window
+// is finite) and is skipped, with its fragment reads.  Used for the 2 x 2
+// tile form's second tile column (windows of 35..63 candidates a side);
+// elsewhere the test measured no gain.
+template <int KB, bool TWO, bool TRIM>
 __device__ __forceinline__ void correlate_tiles(const uint16_t* win, const uint32_t* te,
                                                 const uint32_t* to, int n1, int wpb, int tpd,
-                                                int lane, f32x16& acc_a, f32x16& acc_b) {
+                                                int lane, int ncols, f32x16& acc_a,
+                                                f32x16& acc_b) {
+  const bool last = !TRIM || ncols - 1 + n1 > 16 * (KB - 1);
   const int n = lane & 31, kg = lane >> 5;
   const uint16_t* arow = win + n * wpb + 8 * kg;
   const int o0 = 8 * kg - n + 32;   // Toeplitz phase of tile A's column du = n
@@ -135,6 +147,7 @@ __device__ __forceinline__ void correlate_tiles(const uint16_t* win, const uint3
   auto load = [&](Frags<KB>& f, int r, int rb, int rp) {
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
+      if (kb == KB - 1 && !last) break;
       f.a[kb] = load_frag_aligned(arow + r * wpb + 16 * kb);
       f.b[kb] = load_frag_dwords(ba + rb * tpd + 8 * kb);
       if (TWO) f.bp[kb] = load_frag_dwords(bb + rp * tpd + 8 * kb);
@@ -143,21 +156,21 @@ __device__ __forceinline__ void correlate_tiles(const uint16_t* win, const uint3
   Frags<KB> x, y;
   load(x, 0, 0, 0);
   load(y, 1, min(1, n1 - 1), 0);
-  mfma_step<KB, TWO>(x.a, x.b, x.bp, true, false, acc_a, acc_b);   // step 0
+  mfma_step<KB, TWO>(x.a, x.b, x.bp, true, false, last, acc_a, acc_b);   // step 0
   // entering step r: y = (A(r), B(r), B'(r - 1))
   int r = 1;
   for (; r + 1 < n1; r += 2) {
     load(x, r + 1, r + 1, r);
-    mfma_step<KB, TWO>(y.a, y.b, y.bp, true, true, acc_a, acc_b);
+    mfma_step<KB, TWO>(y.a, y.b, y.bp, true, true, last, acc_a, acc_b);
     load(y, r + 2, min(r + 2, n1 - 1), r + 1);
-    mfma_step<KB, TWO>(x.a, x.b, x.bp, true, true, acc_a, acc_b);
+    mfma_step<KB, TWO>(x.a, x.b, x.bp, true, true, last, acc_a, acc_b);
   }
   if (r < n1) {   // r == n1 - 1: one full step, then the last tile-B step
     load(x, n1, n1 - 1, n1 - 1);
-    mfma_step<KB, TWO>(y.a, y.b, y.bp, true, true, acc_a, acc_b);
-    mfma_step<KB, TWO>(x.a, x.b, x.bp, false, true, acc_a, acc_b);
+    mfma_step<KB, TWO>(y.a, y.b, y.bp, true, true, last, acc_a, acc_b);
+    mfma_step<KB, TWO>(x.a, x.b, x.bp, false, true, last, acc_a, acc_b);
   } else {        // r == n1: y = (A(n1), -, B'(n1 - 1))
-    mfma_step<KB, TWO>(y.a, y.b, y.bp, false, true, acc_a, acc_b);
+    mfma_step<KB, TWO>(y.a, y.b, y.bp, false, true, last, acc_a, acc_b);
   }
 }
 
@@ -517,9 +530,9 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
     if constexpr (TT == 1) {
       f32x16 acc_a = {}, acc_b = {};
       if (two)
-        correlate_tiles<KB, true>(win, te, to, n1, wpb, TPD, lane, acc_a, acc_b);
+        correlate_tiles<KB, true, false>(win, te, to, n1, wpb, TPD, lane, 33, acc_a, acc_b);
       else
-        correlate_tiles<KB, false>(win, te, to, n1, wpb, TPD, lane, acc_a, acc_b);
+        correlate_tiles<KB, false, false>(win, te, to, n1, wpb, TPD, lane, side, acc_a, acc_b);
       // box sums of every candidate this lane scores, requested at once: 16 of
       // tile A, then one edge candidate of tile B (lanes 0..62) or the two
       // corners (lane 63); their latency overlaps the corner sums below
@@ -625,7 +638,8 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
           wave_lds_sync();
         }
         f32x16 acc = {}, acc_unused = {};
-        correlate_tiles<KB, false>(win + 32 * b, te, to, n1, wpb, TPD, lane, acc, acc_unused);
+        correlate_tiles<KB, false, true>(win + 32 * b, te, to, n1, wpb, TPD, lane,
+                                         min(32, side - 32 * b), acc, acc_unused);
         float2 stt[16];
         tile_stats(cb, stimg, W, H, 32 * a, 32 * b, lane, stt);
         float hit[16];
