@@ -412,13 +412,13 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
     //    the window to the checked form, which stores 0 outside the window or
     //    the image and for non-finite pixels (their candidates are invalid by
     //    the box sums) and clamps every element's address into the image.
-    //    The window rows r0 .. r0 + wrows - 1 go to LDS rows 0 ..
-    auto stage_window = [&](int r0) {
+    //    The window rows r0 .. r0 + rows - 1 go to LDS rows 0 ..
+    auto stage_window = [&](int r0, int rows) {
       const int wy = wy0 + r0;
       auto store_checked = [&](int k, const float* v) {
         const int idx = lane + k * kWave;
         const int rr = idx / CPR, ch = idx - rr * CPR;
-        if (k < CH && rr < wrows) {
+        if (k < CH && rr < rows) {
           const int Y = wy + rr;
           const bool rowok = r0 + rr < wn && Y >= 0 && Y < H;
           float w[8];
@@ -433,7 +433,7 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
           *reinterpret_cast<u32x4*>(win + rr * wpb + ch * 8) = pk;
         }
       };
-      const bool interior = wx0 >= 0 && wx0 + WC <= W && wy >= 0 && wy + wrows <= H;
+      const bool interior = wx0 >= 0 && wx0 + WC <= W && wy >= 0 && wy + rows <= H;
       bool staged = false;
       if (interior) {
         // all chunks requested at once when they fit in registers (one memory
@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
             const int rr = idx / CPR, ch = idx - rr * CPR;
             // rows past the staged ones (not stored) read the last staged row
             const f32x4u* src = reinterpret_cast<const f32x4u*>(
-                gimg + (int64_t)(wy + min(rr, wrows - 1)) * W + wx0 + ch * 8);
+                gimg + (int64_t)(wy + min(rr, rows - 1)) * W + wx0 + ch * 8);
             const f32x4u a = src[0], b = src[1];
             vw[kk][0] = a.x; vw[kk][1] = a.y; vw[kk][2] = a.z; vw[kk][3] = a.w;
             vw[kk][4] = b.x; vw[kk][5] = b.y; vw[kk][6] = b.z; vw[kk][7] = b.w;
@@ -458,7 +458,7 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
           for (int kk = 0; kk < CBI; ++kk) {
             const int idx = lane + (k0 + kk) * kWave;
             const int rr = idx / CPR, ch = idx - rr * CPR;
-            if (k0 + kk < CH && rr < wrows) {
+            if (k0 + kk < CH && rr < rows) {
               float w[8];
 #pragma unroll
               for (int e = 0; e < 8; ++e) {
@@ -494,7 +494,7 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
         }
       }
     };
-    stage_window(0);
+    stage_window(0, wrows);
     // 1. (after the window, so the template's loads, issued first, have
     //    arrived) template rows in bf16 after 32 zeros: element x of row r is
     //    t(r, x - 32); the even copy holds pairs (2i, 2i+1), the odd copy
@@ -634,7 +634,9 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
         if (a == 1 && b == 0) {
           // the second tile row's window rows, over the first's
           wave_lds_sync();
-          stage_window(32);
+          // (only the rows the used candidates dv < side reach: the others
+          // keep the first tile row's finite values, met by unused dv only)
+          stage_window(32, min(wrows, n1 + side - 32));
           wave_lds_sync();
         }
         f32x16 acc = {}, acc_unused = {};
