@@ -128,9 +128,9 @@ __device__ __forceinline__ void mfma_step(const bf16x8* a, const bf16x8* b, cons
 // others are outside the window).  Column du meets template entries only at
 // window columns du .. du + n1 - 1, so when ncols - 1 + n1 <= 16 (KB - 1)
 // the last K block adds exact zeros to every used column (the staged window
-// is finite) and is skipped, with its fragment reads.  Used for the 2 x 2
-// tile form's second tile column (windows of 35..63 candidates a side);
-// elsewhere the test measured no gain.
+// is finite) and is skipped, with its fragment reads.  Used for a single
+// tile (windows up to 32 candidates a side) and the 2 x 2 tile form's second
+// tile column; the two-tile 33 x 33 form needs every block.
 template <int KB, bool TWO, bool TRIM>
 __device__ __forceinline__ void correlate_tiles(const uint16_t* win, const uint32_t* te,
                                                 const uint32_t* to, int n1, int wpb, int tpd,
@@ -532,7 +532,7 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
       if (two)
         correlate_tiles<KB, true, false>(win, te, to, n1, wpb, TPD, lane, 33, acc_a, acc_b);
       else
-        correlate_tiles<KB, false, false>(win, te, to, n1, wpb, TPD, lane, side, acc_a, acc_b);
+        correlate_tiles<KB, false, true>(win, te, to, n1, wpb, TPD, lane, side, acc_a, acc_b);
       // box sums of every candidate this lane scores, requested at once: 16 of
       // tile A, then one edge candidate of tile B (lanes 0..62) or the two
       // corners (lane 63); their latency overlaps the corner sums below
