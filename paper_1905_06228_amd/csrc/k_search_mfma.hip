@@ -496,8 +496,9 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
     };
     // one tile of up to 32 candidates a side meets window rows below
     // n1 + side - 1 only in its used rows dv < side: the rows past them are
-    // not staged (they hold earlier values, met only by unused dv, whose
-    // products the scores drop)
+    // not staged (whatever they hold, an earlier POI's values or nothing
+    // yet, reaches only the accumulators of unused dv, which the scores
+    // drop by a select)
     stage_window(0, (TT == 1 && !two) ? n1 + side - 1 : wrows);
     // 1. (after the window, so the template's loads, issued first, have
     //    arrived) template rows in bf16 after 32 zeros: element x of row r is
