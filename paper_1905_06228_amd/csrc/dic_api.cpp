@@ -381,14 +381,15 @@ dic_status_t enqueue_search(dic_plan_t p, const float* ref, const float* def, co
 dic_status_t enqueue_refine(dic_plan_t p, const float* ref, const float* def, const int32_t* poi,
                             const int32_t* uv, const int32_t* status_in, const double* p_init,
                             double* p_out, float* zn, int32_t* iters, int32_t* status,
-                            hipStream_t s, bool nr, bool table_ready = false) {
+                            hipStream_t s, bool nr, bool table_ready = false,
+                            bool counters_ready = false) {
   const Range range(nr ? "dic: Newton-Raphson refinement" : "dic: IC-GN refinement");
   if (p->fp32()) {
     if (!table_ready) {
       dic_status_t r = prepare_lut(p, def, s, false);
       if (r) return r;
     }
-    DIC_HIP(launch_reset_counters(p->st, s));
+    if (!counters_ready) DIC_HIP(launch_reset_counters(p->st, s));
     const int ng = (int)p->rgroups.size();
     if (nr)
       DIC_HIP(launch_nr_f32(p->st, p->tuning, p->rgroups.data(), ng, ref, def, poi, uv,
@@ -477,8 +478,11 @@ dic_status_t enqueue_correlate(dic_plan_t p, const CorrArgs& a, hipStream_t s,
     DIC_HIP(hipStreamWaitEvent(s, p->ev_ref, 0));
     mark_ref(p, a.ref, a.poi, need_tmpl);
   }
+  // the FP32 searches leave the refinement's counters at zero (the
+  // matrix-core form zeroes them, the vector-ALU form's reset before it
+  // covers them and it uses only its own)
   return enqueue_refine(p, a.ref, a.def, a.poi, a.uv, a.st_int, a.p_init, a.p_out, a.zn, a.iters,
-                        a.status, s, p->nr(), fork);
+                        a.status, s, p->nr(), fork, p->fp32());
 }
 
 }  // namespace

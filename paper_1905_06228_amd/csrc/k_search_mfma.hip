@@ -288,6 +288,10 @@ __global__ void __launch_bounds__(64, KB == 3 ? 3 : 2) search_mfma_kernel(
   uint32_t* to = reinterpret_cast<uint32_t*>(lds_raw + Ly.to);
   float* edge = reinterpret_cast<float*>(lds_raw + Ly.edge);
   const int lane0 = lane_id();
+  // the refinement's work counters, zeroed here for the refinement that
+  // follows in a correlate, which then needs no reset launch of its own
+  // (every lane stores; lanes past the counters repeat the first ones)
+  if (blockIdx.x == 0) st.counters[kCtrIcgn + (lane0 & (kMaxRefineGroups - 1))] = 0;
   constexpr int WC = 16 * KB + 32 * (TT - 1);   // staged window columns
   constexpr int CPR = WC / 8;                   // 8-element chunks per window row
   constexpr int NMAX = 16 * KB - 32;            // widest subset of this K-block count
