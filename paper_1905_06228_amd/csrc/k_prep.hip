@@ -505,8 +505,9 @@ __global__ void __launch_bounds__(256) ref_prep_stats_kernel(DevState st,
 
 // Steepest-descent sums, Hessian and factor, for the POIs the statistics
 // kernel left OK or flat (it has written the record of the others).  One
-// pass: the six sums sum SD, the six sum SD (f - fbar) and the 21 products of
-// the shifted steepest-descent images, in FP32 per lane with fused
+// pass: the six sums sum SD in FP64 (they enter IC-GN's right-hand side, so
+// they decide its fixed point), the six sum SD (f - fbar) and the 21 products
+// of the shifted steepest-descent images in FP32 per lane with fused
 // multiply-adds (at most a few tens of terms), added across lanes in a fixed
 // FP32 tree (six levels).  Removal of the shifted mean, factorisation and
 // singularity test in FP64.  A singular Hessian turns the
@@ -554,7 +555,8 @@ __global__ void __launch_bounds__(256) ref_prep_hessian_kernel(DevState st,
   // symmetric subset), so the removal cancels little.
   const unsigned oc = (unsigned)(M * W + M);
   const float kx = gxi[oc], ky = gyi[oc];
-  float ks[6] = {0, 0, 0, 0, 0, 0}, ksdf[6] = {0, 0, 0, 0, 0, 0}, kh[21];
+  double ks[6] = {0, 0, 0, 0, 0, 0};
+  float ksdf[6] = {0, 0, 0, 0, 0, 0}, kh[21];
 #pragma unroll
   for (int a = 0; a < 21; ++a) kh[a] = 0.f;
   const float fbar_f = (float)R->fbar;
@@ -572,7 +574,7 @@ __global__ void __launch_bounds__(256) ref_prep_hessian_kernel(DevState st,
       sd[3] -= ky;
 #pragma unroll
       for (int a = 0; a < 6; ++a) {
-        ks[a] += sd[a];
+        ks[a] += (double)sd[a];
 #pragma unroll
         for (int b = 0; b <= a; ++b) kh[tri(a, b)] = fmaf(sd[a], sd[b], kh[tri(a, b)]);
       }
@@ -580,7 +582,8 @@ __global__ void __launch_bounds__(256) ref_prep_hessian_kernel(DevState st,
     }
   }
   double shs[6], sdfsum[6], h[21], sdsum[6];
-  wave_sums_f32<6>(ks, shs);
+#pragma unroll
+  for (int a = 0; a < 6; ++a) shs[a] = wave_sum_dpp(ks[a]);
   wave_sums_f32<6>(ksdf, sdfsum);
   wave_sums_f32<21>(kh, h);
 #pragma unroll
