@@ -118,8 +118,8 @@ def host_cpu() -> dict:
 
 
 def pool_size() -> int:
-    """Oracle worker processes: the usable cores, at most 16 (a one-GPU machine's
-    CPU share)."""
+    """Oracle worker processes: the usable cores, at most 16 (one GPU's share
+    of the host's cores)."""
     return max(1, min(16, host_cpu()["usable_cores"]))
 
 
