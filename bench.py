@@ -143,6 +143,19 @@ def _pool_correlate(args):
     return O.correlate(f, g, pois, M, S)
 
 
+def _pool_batched(args):
+    """One chunk of the batched workload's sample: renders pair k (the
+    generator's NumPy recipe) and times the oracle on the POIs ``idx`` of its
+    grid (rendering excluded)."""
+    import dicgen
+    from oracle import dic_oracle as O
+    k, idx = args
+    pr = dicgen.sinusoidal_batch(n_pairs=1, size=512, S=8, step=6, first=k)[0]
+    t0 = time.perf_counter()
+    O.correlate(pr.ref, pr.defm, pr.pois[idx], pr.M, pr.S)
+    return time.perf_counter() - t0, len(idx), 2 * pr.M + 1
+
+
 def _pool_znssd(args):
     from oracle import dic_oracle as O
     key, pois, M, P, up = args
@@ -240,7 +253,46 @@ def oracle_other_workloads(pool, procs: int) -> dict:
     dt = time.perf_counter() - t0
     out["differentiation"] = dict(pois=N, seconds=round(dt, 2), pois_per_s=round(N / dt, 1),
                                   cores=procs, what="criterion, dC/dp and dC/dG")
+    out["batched"] = oracle_batched_sample(pool, procs)
     return out
+
+
+def oracle_batched_sample(pool, procs: int, n_pairs: int = 8, per_pair: int = 128) -> dict:
+    """The oracle on 8 seeded pairs of the batched workload (pairs 0..7, which
+    hold all four subset sizes), 128 seeded POIs of each, search and IC-GN;
+    the per-POI time of each subset size, weighted by the 64 pairs' POI
+    counts and divided over the processes, extrapolates the whole workload."""
+    import dicgen
+    rng = np.random.default_rng(43)
+    chunks = []
+    for k in range(n_pairs):
+        sub = dicgen.batch_pair_params(k)[2]
+        n = len(dicgen.poi_grid(512, 512, sub // 2, 8, 6))
+        idx = np.sort(rng.choice(n, per_pair, replace=False))
+        chunks += [(k, c) for c in np.array_split(idx, 2)]
+    t0 = time.perf_counter()
+    res = pool.map(_pool_batched, chunks)
+    wall = time.perf_counter() - t0
+    per = {}
+    for sec, n, sub in res:
+        a = per.setdefault(sub, [0.0, 0])
+        a[0] += sec
+        a[1] += n
+    t_poi = {sub: a[0] / a[1] for sub, a in per.items()}
+    total_s, total_n = 0.0, 0
+    for k in range(64):
+        sub = dicgen.batch_pair_params(k)[2]
+        n = len(dicgen.poi_grid(512, 512, sub // 2, 8, 6))
+        total_n += n
+        total_s += n * t_poi.get(sub, sum(t_poi.values()) / len(t_poi))
+    est = total_s / procs
+    return dict(sample=f"{n_pairs} seeded pairs (0..{n_pairs - 1}), {per_pair} seeded POIs each, "
+                       f"search and IC-GN, {len(chunks)} chunks over {procs} processes "
+                       f"({wall:.1f} s with each chunk's rendering)",
+                pois=n_pairs * per_pair,
+                seconds_per_poi_by_subset={str(k): round(v, 5) for k, v in sorted(t_poi.items())},
+                extrapolated_pois=total_n, extrapolated_seconds=round(est, 1),
+                pois_per_s=round(total_n / est, 1), cores=procs)
 
 
 def sequence_bench(torch, dic, dicgen, dev, n_frames: int, reference: str = "first",

@@ -277,6 +277,16 @@ def affine_pair_1024(size: int = 1024, noise: float = 2.0, M: int = 15, S: int =
 BATCH_SUBSETS = (15, 21, 31, 41)
 
 
+def batch_pair_params(k: int):
+    """(A, lam, subset size) of pair k of the batched workload, drawn from
+    SeedSequence([3, k, 3]) in that order."""
+    prm = rng_for(3, k, 3)
+    A = prm.uniform(0.5, 2.0)
+    lam = prm.uniform(64.0, 256.0)
+    sub = int(BATCH_SUBSETS[prm.integers(0, len(BATCH_SUBSETS))])
+    return A, lam, sub
+
+
 def sinusoidal_batch(n_pairs: int = 64, size: int = 512, S: int = 8, step: int = 6,
                      first: int = 0) -> List[Pair]:
     """Independent speckle pairs with u = A sin(2 pi Y/lam), v = A cos(2 pi X/lam),
@@ -285,10 +295,7 @@ def sinusoidal_batch(n_pairs: int = 64, size: int = 512, S: int = 8, step: int =
     out = []
     n = int(round(2000 * (size / 256.0) ** 2))
     for k in range(first, first + n_pairs):
-        prm = rng_for(3, k, 3)
-        A = prm.uniform(0.5, 2.0)
-        lam = prm.uniform(64.0, 256.0)
-        sub = int(BATCH_SUBSETS[prm.integers(0, len(BATCH_SUBSETS))])
+        A, lam, sub = batch_pair_params(k)
         M = sub // 2
         blobs = make_blobs(rng_for(3, k, 0), n, size, size)
         fld = sinusoidal(A, lam)
@@ -428,10 +435,7 @@ def sinusoidal_batch_torch(n_pairs: int = 64, size: int = 512, S: int = 8, step:
     out = []
     n = int(round(2000 * (size / 256.0) ** 2))
     for k in range(first, first + n_pairs):
-        prm = rng_for(3, k, 3)
-        A = prm.uniform(0.5, 2.0)
-        lam = prm.uniform(64.0, 256.0)
-        sub = int(BATCH_SUBSETS[prm.integers(0, len(BATCH_SUBSETS))])
+        A, lam, sub = batch_pair_params(k)
         M = sub // 2
         blobs = make_blobs(rng_for(3, k, 0), n, size, size)
         f = render_image_torch(blobs, None, size, size, device=device)
