@@ -179,7 +179,10 @@ typedef struct {
   int32_t icgn_waves;      /* waves (POIs in flight) per refinement workgroup
                               1..8 (IC-GN and Newton-Raphson)                 */
   int32_t icgn_slack;      /* extra pixels around the staged deformed patch,
-                              0..16                                           */
+                              0..16; kernels whose patch is sized for less
+                              (subsets of 29 and 31 columns, and of 37 and
+                              more) use at most 6.  It changes when a patch
+                              is restaged, never the results                 */
 } dic_tuning_t;
 
 /* Validate a plan description and build the POI work list (host only, no
