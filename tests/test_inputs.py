@@ -31,3 +31,14 @@ def test_torch_sinusoidal_batch_matches_numpy():
         assert (pa.M, pa.S) == (pb.M, pb.S) and np.array_equal(pa.pois, pb.pois)
         np.testing.assert_allclose(pb.ref.numpy(), pa.ref, rtol=0, atol=1e-4)
         np.testing.assert_allclose(pb.defm.numpy(), pa.defm, rtol=0, atol=1e-4)
+
+
+def test_batch_pair_params_are_the_pairs():
+    """The helper the oracle baseline extrapolates with gives each batched
+    pair's amplitude, wavelength and subset size, and the subset sizes cover
+    all four in the first eight pairs."""
+    pairs = dicgen.sinusoidal_batch(n_pairs=3, size=64, first=2)
+    for k, p in zip(range(2, 5), pairs):
+        A, lam, sub = dicgen.batch_pair_params(k)
+        assert (p.meta["A"], p.meta["lam"], 2 * p.M + 1) == (A, lam, sub)
+    assert {dicgen.batch_pair_params(k)[2] for k in range(8)} == set(dicgen.BATCH_SUBSETS)
