@@ -68,3 +68,31 @@ def test_stale_summary_is_not_used(bench, tmp_path, monkeypatch):
         monkeypatch.setattr(bench, attr, str(p))
     assert bench.measured_traffic("icgn_f32") is None
     assert bench.measured_issue("icgn_f32", 0.5) is None
+
+
+def test_batched_oracle_extrapolation(bench):
+    """The batched oracle sample weights each subset size's per-POI time by
+    the 64 pairs' POI counts and divides over the processes (a stand-in pool
+    returns a known time per POI and subset size)."""
+    import dicgen
+
+    per_poi = {15: 0.004, 21: 0.005, 31: 0.006, 41: 0.008}
+
+    class Pool:
+        def map(self, fn, chunks):
+            out = []
+            for k, idx in chunks:
+                sub = dicgen.batch_pair_params(k)[2]
+                out.append((per_poi[sub] * len(idx), len(idx), sub))
+            return out
+
+    r = bench.oracle_batched_sample(Pool(), 16)
+    n_total, t_total = 0, 0.0
+    for k in range(64):
+        sub = dicgen.batch_pair_params(k)[2]
+        n = len(dicgen.poi_grid(512, 512, sub // 2, 8, 6))
+        n_total += n
+        t_total += n * per_poi[sub]
+    assert r["pois"] == 8 * 128 and r["extrapolated_pois"] == n_total
+    assert r["pois_per_s"] == pytest.approx(n_total / (t_total / 16), rel=1e-3)
+    assert r["seconds_per_poi_by_subset"] == {str(k): v for k, v in per_poi.items()}
